@@ -1,0 +1,345 @@
+"""FP64 direct-sum oracle of the FFT polyspectrum estimator (TEST INFRASTRUCTURE).
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this module.  It shares no code with the HIP path.
+
+What it computes (Watkinson et al. 2017, arXiv:1705.06284, Section 2):
+
+* Delta_fft(m) = sum_n delta(n) exp(-2 pi i m.n / N), the unnormalised forward
+  DFT of Eq. (DeltaFFTtoDelta), evaluated as three matrix products with the
+  DFT matrix (twiddle angle from the exactly reduced integer (m n) mod N).
+* Shells: bin b holds the modes with lo_b^2 <= |m|^2 < hi_b^2, m != 0, every
+  component in [-N/2, N/2) (the spherical-shell reading of the bin rule of
+  Eq. gen_Nspec3; Nyquist modes never qualify because hi_b <= N/2,
+  Eq. nyqvist).
+* The bispectrum of Eq. (Jeong_BI) equals the direct sum over ordered closed
+  triples (Kronecker delta taken modulo N, the phase-sum identity before
+  Eq. gen_Nspec4):
+
+      S_t = sum_{m1 in S_i, m2 in S_j, m3 in S_k, m1+m2+m3 = 0 mod N} D1 D2 D3
+      N_t = the same sum with every amplitude set to 1
+      B_t = (V^2 / N_pix^3) Re S_t / N_t
+
+* Power spectrum (Eq. Jeong_PS; by Parseval the shell average of |Delta|^2):
+      P_b = (V / N_pix^2) sum_{m in S_b} |Delta(m)|^2 / M_b
+* p = 4 (Eq. Jeong_gen with four fields):
+      T_q = (V^3 / N_pix^4) Re S_q / N_q
+
+The closed-triplet loops run in ``direct.c``; everything else is numpy.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "direct.c")
+_LIB = os.path.join(_HERE, "_direct.so")
+_NACC = 7
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile ``direct.c`` into ``_direct.so`` with gcc (-O2, OpenMP)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-o", tmp, _SRC])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        build(force=False)
+        lib = ctypes.CDLL(_LIB)
+        dp = ctypes.POINTER(ctypes.c_double)
+        ip = ctypes.POINTER(ctypes.c_int32)
+        up = ctypes.POINTER(ctypes.c_uint64)
+        lib.orc_pair_sums.argtypes = [ctypes.c_int, dp, dp, ctypes.c_int, ip, ctypes.c_int, ip,
+                                      up, ctypes.c_int64, ctypes.c_uint64, ctypes.c_int, dp]
+        lib.orc_pair_sums.restype = ctypes.c_int
+        lib.orc_triple_sums.argtypes = [ctypes.c_int, dp, dp, ctypes.c_int, ip, ctypes.c_int, ip,
+                                        ctypes.c_int, ip, up, ctypes.c_int64, ctypes.c_uint64,
+                                        ctypes.c_int, dp]
+        lib.orc_triple_sums.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def _ptr(a, ctype):
+    if a is None:
+        return ctypes.POINTER(ctype)()
+    return a.ctypes.data_as(ctypes.POINTER(ctype))
+
+
+# ----------------------------------------------------------------------------
+# Bins and shells (Eq. gen_Nspec3 with the spherical-shell reading)
+# ----------------------------------------------------------------------------
+
+def squared_edges(k_lo, k_hi):
+    """FP64 squared bin edges, in units of the fundamental mode k_f."""
+    lo = np.asarray(k_lo, dtype=np.float64)
+    hi = np.asarray(k_hi, dtype=np.float64)
+    return lo * lo, hi * hi
+
+
+def freq(n: int) -> np.ndarray:
+    """Signed integer frequency of each DFT index: 0..N/2-1, -N/2..-1."""
+    i = np.arange(n)
+    return np.where(i < n // 2, i, i - n)
+
+
+def bin_mask_table(n: int, k_lo, k_hi) -> np.ndarray:
+    """uint64 bit mask per integer |m|^2: bit b set iff lo_b^2 <= |m|^2 < hi_b^2.
+
+    |m|^2 = 0 (the mean) belongs to no bin.
+    """
+    lo2, hi2 = squared_edges(k_lo, k_hi)
+    assert len(lo2) <= 64
+    r2max = 3 * (n // 2) ** 2
+    r2 = np.arange(r2max + 1, dtype=np.float64)
+    mask = np.zeros(r2max + 1, dtype=np.uint64)
+    for b in range(len(lo2)):
+        sel = (r2 >= lo2[b]) & (r2 < hi2[b])
+        sel[0] = False
+        mask[sel] |= np.uint64(1) << np.uint64(b)
+    return mask
+
+
+def shell_modes(n: int, k_lo, k_hi, b: int) -> np.ndarray:
+    """All mode vectors (mz, my, mx) of bin b as an int32 array [M_b, 3]."""
+    lo2, hi2 = squared_edges(k_lo, k_hi)
+    h = min(int(np.ceil(np.sqrt(hi2[b]))) + 1, n // 2)
+    f = np.arange(-h, h + 1) if h < n // 2 else freq(n)
+    f = f[(f >= -(n // 2)) & (f < n // 2)]
+    mz, my, mx = np.meshgrid(f, f, f, indexing="ij")
+    r2 = (mz.astype(np.int64) ** 2 + my.astype(np.int64) ** 2 + mx.astype(np.int64) ** 2)
+    sel = (r2 > 0) & (r2.astype(np.float64) >= lo2[b]) & (r2.astype(np.float64) < hi2[b])
+    return np.ascontiguousarray(np.stack([mz[sel], my[sel], mx[sel]], axis=1).astype(np.int32))
+
+
+def mode_counts(n: int, k_lo, k_hi) -> np.ndarray:
+    """M_b: number of modes in each shell."""
+    return np.array([len(shell_modes(n, k_lo, k_hi, b)) for b in range(len(k_lo))], dtype=np.int64)
+
+
+# ----------------------------------------------------------------------------
+# Forward DFT (Eq. DeltaFFTtoDelta)
+# ----------------------------------------------------------------------------
+
+def dft_matrix(n: int) -> np.ndarray:
+    """W[m, j] = exp(-2 pi i ((m j) mod N) / N), the argument reduced exactly."""
+    j = np.arange(n, dtype=np.int64)
+    red = np.outer(j, j) % n
+    ang = (-2.0 * np.pi / n) * red.astype(np.float64)
+    return np.cos(ang) + 1j * np.sin(ang)
+
+
+def dft3(delta: np.ndarray) -> np.ndarray:
+    """Unnormalised 3D DFT of a real [z][y][x] grid, as three matrix products."""
+    d = np.asarray(delta, dtype=np.float64)
+    n = d.shape[0]
+    assert d.shape == (n, n, n)
+    w = dft_matrix(n)
+    a = d @ w.T                                   # x axis
+    a = np.matmul(w, a)                           # y axis (batched over z)
+    a = (w @ a.reshape(n, n * n)).reshape(n, n, n)  # z axis
+    return a
+
+
+def prepare(delta32) -> np.ndarray:
+    """Promote the FP32 input exactly to FP64 and subtract the FP64 mean."""
+    d = np.asarray(delta32).astype(np.float64)
+    return d - d.mean()
+
+
+# ----------------------------------------------------------------------------
+# Direct sums
+# ----------------------------------------------------------------------------
+
+@dataclass
+class Spectrum:
+    """Per-configuration direct sums and the normalised estimate."""
+    value: np.ndarray        # B, T or P in the paper's normalisation
+    s: np.ndarray            # complex numerator sum S
+    count: np.ndarray        # N_t (or N_q, M_b): ordered closed tuples, mod N
+    s_strict: np.ndarray     # numerator restricted to tuples closed in Z^3
+    count_strict: np.ndarray
+    noise: np.ndarray        # norm * sqrt(sum |product|^2) / count
+
+
+def _volume(n: int, box_len):
+    L = float(n) if (box_len is None or box_len <= 0) else float(box_len)
+    return L ** 3
+
+
+def _grid_parts(delta_k):
+    if delta_k is None:
+        return None, None
+    re = np.ascontiguousarray(delta_k.real, dtype=np.float64)
+    im = np.ascontiguousarray(delta_k.imag, dtype=np.float64)
+    return re, im
+
+
+def _pair_sums(n, re, im, ma, mb, mask, want_bits, n_bins):
+    lib = _load()
+    out = np.zeros((n_bins, _NACC), dtype=np.float64)
+    rc = lib.orc_pair_sums(n, _ptr(re, ctypes.c_double), _ptr(im, ctypes.c_double),
+                           len(ma), _ptr(ma, ctypes.c_int32), len(mb), _ptr(mb, ctypes.c_int32),
+                           _ptr(mask, ctypes.c_uint64), len(mask), ctypes.c_uint64(want_bits),
+                           n_bins, _ptr(out, ctypes.c_double))
+    assert rc == 0, rc
+    return out
+
+
+def _triple_sums(n, re, im, ma, mb, mc, mask, want_bits, n_bins):
+    lib = _load()
+    out = np.zeros((n_bins, _NACC), dtype=np.float64)
+    rc = lib.orc_triple_sums(n, _ptr(re, ctypes.c_double), _ptr(im, ctypes.c_double),
+                             len(ma), _ptr(ma, ctypes.c_int32), len(mb), _ptr(mb, ctypes.c_int32),
+                             len(mc), _ptr(mc, ctypes.c_int32),
+                             _ptr(mask, ctypes.c_uint64), len(mask), ctypes.c_uint64(want_bits),
+                             n_bins, _ptr(out, ctypes.c_double))
+    assert rc == 0, rc
+    return out
+
+
+def _tuple_sums(n, delta_k, k_lo, k_hi, tuples, order):
+    """Direct sums for each tuple of bins (length ``order`` = 3 or 4).
+
+    The sum over ordered slot assignments is symmetric in the slots, so the
+    loops run over the (order-1) shells with the fewest modes and the last
+    slot is closed by the modulo-N reduction.
+    """
+    tuples = np.asarray(tuples, dtype=np.int64).reshape(-1, order)
+    n_bins = len(k_lo)
+    mask = bin_mask_table(n, k_lo, k_hi)
+    modes = {}
+
+    def sh(b):
+        if b not in modes:
+            modes[b] = shell_modes(n, k_lo, k_hi, b)
+        return modes[b]
+
+    counts = np.array([len(sh(b)) for b in range(n_bins)])
+    re, im = _grid_parts(delta_k)
+    groups = {}
+    for t, tup in enumerate(tuples):
+        srt = sorted(int(b) for b in tup)
+        srt.sort(key=lambda b: (counts[b], b))
+        key = tuple(srt[:-1])
+        groups.setdefault(key, []).append((t, srt[-1]))
+    acc = np.zeros((len(tuples), _NACC))
+    for key, items in groups.items():
+        want = 0
+        for _, last in items:
+            want |= 1 << last
+        if order == 3:
+            out = _pair_sums(n, re, im, sh(key[0]), sh(key[1]), mask, want, n_bins)
+        else:
+            out = _triple_sums(n, re, im, sh(key[0]), sh(key[1]), sh(key[2]), mask, want, n_bins)
+        for t, last in items:
+            acc[t] = out[last]
+    return acc
+
+
+def _finish(acc, norm):
+    s = acc[:, 0] + 1j * acc[:, 1]
+    cnt = acc[:, 2]
+    ss = acc[:, 3] + 1j * acc[:, 4]
+    cs = acc[:, 5]
+    with np.errstate(invalid="ignore", divide="ignore"):
+        val = norm * s.real / cnt
+        noise = norm * np.sqrt(acc[:, 6]) / cnt
+    return Spectrum(value=val, s=s, count=cnt.astype(np.int64), s_strict=ss,
+                    count_strict=cs.astype(np.int64), noise=noise)
+
+
+def bispectrum(delta, k_lo, k_hi, triplets, box_len=None, delta_k=None) -> Spectrum:
+    """Direct-sum bispectrum of Eq. (Jeong_BI) for each triplet of bin indices."""
+    d = prepare(delta)
+    n = d.shape[0]
+    if delta_k is None:
+        delta_k = dft3(d)
+    acc = _tuple_sums(n, delta_k, k_lo, k_hi, triplets, 3)
+    vol = _volume(n, box_len)
+    npix = float(n) ** 3
+    return _finish(acc, vol ** 2 / npix ** 3)
+
+
+def trispectrum(delta, k_lo, k_hi, quads, box_len=None, delta_k=None) -> Spectrum:
+    """Direct-sum p = 4 polyspectrum of Eq. (Jeong_gen) for each quad of bins."""
+    d = prepare(delta)
+    n = d.shape[0]
+    if delta_k is None:
+        delta_k = dft3(d)
+    acc = _tuple_sums(n, delta_k, k_lo, k_hi, quads, 4)
+    vol = _volume(n, box_len)
+    npix = float(n) ** 3
+    return _finish(acc, vol ** 3 / npix ** 4)
+
+
+def triangle_counts(n, k_lo, k_hi, triplets):
+    """N_t: ordered closed triples (mod N) of each triplet, and the strict count."""
+    acc = _tuple_sums(n, None, k_lo, k_hi, triplets, 3)
+    return acc[:, 2].astype(np.int64), acc[:, 5].astype(np.int64)
+
+
+def quad_counts(n, k_lo, k_hi, quads):
+    acc = _tuple_sums(n, None, k_lo, k_hi, quads, 4)
+    return acc[:, 2].astype(np.int64), acc[:, 5].astype(np.int64)
+
+
+def power_spectrum(delta, k_lo, k_hi, box_len=None, delta_k=None):
+    """P_b of Eq. (Jeong_PS) as the shell average of |Delta|^2 (Parseval)."""
+    d = prepare(delta)
+    n = d.shape[0]
+    if delta_k is None:
+        delta_k = dft3(d)
+    vol = _volume(n, box_len)
+    npix = float(n) ** 3
+    out = np.zeros(len(k_lo))
+    m = np.zeros(len(k_lo), dtype=np.int64)
+    for b in range(len(k_lo)):
+        md = shell_modes(n, k_lo, k_hi, b)
+        v = delta_k[md[:, 0] % n, md[:, 1] % n, md[:, 2] % n]
+        m[b] = len(md)
+        out[b] = vol / npix ** 2 * np.sum(np.abs(v) ** 2) / len(md) if len(md) else np.nan
+    return out, m
+
+
+# ----------------------------------------------------------------------------
+# Configuration sets (readings of the paper's silent points)
+# ----------------------------------------------------------------------------
+
+def candidate_triplets(k_lo, k_hi):
+    """i <= j <= k whose shells admit a strict triangle: each lower edge is
+    below the sum of the other two upper edges (necessary for closure in Z^3)."""
+    lo = np.asarray(k_lo, dtype=np.float64)
+    hi = np.asarray(k_hi, dtype=np.float64)
+    nb = len(lo)
+    out = []
+    for i in range(nb):
+        for j in range(i, nb):
+            for k in range(j, nb):
+                if lo[k] < hi[i] + hi[j] and lo[j] < hi[i] + hi[k] and lo[i] < hi[j] + hi[k]:
+                    out.append((i, j, k))
+    return np.array(out, dtype=np.int32).reshape(-1, 3)
+
+
+def closed_triplets(n, k_lo, k_hi):
+    """Candidate triplets with a non-zero count N_t (modulo-N closure)."""
+    cand = candidate_triplets(k_lo, k_hi)
+    cnt, _ = triangle_counts(n, k_lo, k_hi, cand)
+    return cand[cnt > 0], cnt[cnt > 0]
+
+
+def collapsed_quads(n_bins):
+    """(a, a, b, b) for a <= b: the collapsed p = 4 configurations."""
+    return np.array([(a, a, b, b) for a in range(n_bins) for b in range(a, n_bins)],
+                    dtype=np.int32).reshape(-1, 4)
