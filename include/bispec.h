@@ -1,0 +1,167 @@
+/*
+ * bispec.h -- C ABI of the MI355X FFT polyspectrum estimator.
+ *
+ * Implements the estimator of Watkinson, Majumdar, Pritchard & Mondal (2017),
+ * "A fast estimator for the bispectrum and beyond", arXiv:1705.06284,
+ * Section 2:
+ *
+ *   Delta_fft(m) = sum_n delta(n) exp(-2 pi i m.n/N)          Eq. (DeltaFFTtoDelta)
+ *   F_b(n)       = sum_{m in S_b} Delta_fft(m) exp(+2 pi i m.n/N)   Eq. (delta_nr), first line
+ *   I_b(n)       = sum_{m in S_b} exp(+2 pi i m.n/N)                Eq. (delta_nr), second line
+ *   P_b          = V/N_pix^2   sum_n F_b^2       / sum_n I_b^2      Eq. (Jeong_PS)
+ *   B_ijk        = V^2/N_pix^3 sum_n F_i F_j F_k / sum_n I_i I_j I_k  Eq. (Jeong_BI)
+ *   T_abcd       = V^3/N_pix^4 sum_n F_a F_b F_c F_d / sum_n I_a I_b I_c I_d
+ *                                                               Eq. (Jeong_gen), p = 4
+ *
+ * with V = L^3 the box volume, N_pix = N^3, and S_b the spherical shell of
+ * bin b: the integer mode vectors m (components in [-N/2, N/2)) with
+ * k_lo[b]^2 <= |m|^2 < k_hi[b]^2, m != 0, edges in units of k_f = 2 pi / L
+ * (the bin rule of Eq. gen_Nspec3 read as a spherical shell; the mean mode is
+ * never in a shell, and k_hi <= N/2 keeps every Nyquist mode out, Eq. nyqvist).
+ *
+ * The denominators sum_n I...I equal N_pix times the number of ordered closed
+ * tuples (closure modulo N, the phase-sum identity before Eq. gen_Nspec4).
+ * The plan evaluates them once, in FP64 with the same FFT pipeline, and
+ * stores the exact integer tuple counts.
+ *
+ * Conventions for every call:
+ *  - Real fields are row-major [z][y][x] FP32 arrays of N^3 values on the
+ *    device.  Batched arguments are [batch][...] with maps back to back.
+ *  - All work is enqueued on the plan's stream and is asynchronous; outputs
+ *    are valid once that stream has been synchronised.  bispec_plan itself
+ *    synchronises the stream before it returns.
+ *  - The caller owns every input, output and workspace buffer.  A plan owns
+ *    only host metadata (bins, configuration lists, counts).  bispec_plan
+ *    allocates temporary device memory for the count fields and frees it
+ *    before returning.
+ *  - No exception crosses the ABI.  Errors are negative status codes; on an
+ *    error the outputs are undefined and the plan stays usable.
+ *  - A plan is not thread safe: one plan per stream.  Plans may share a device.
+ */
+#ifndef BISPEC_H
+#define BISPEC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct bispec_plan_s *bispec_plan_t;   /* opaque, owned by the library */
+
+typedef enum {
+    BISPEC_OK = 0,
+    BISPEC_E_INVALID = -1,        /* null pointer, bad index, batch out of range  */
+    BISPEC_E_UNSUPPORTED_N = -2,  /* n_side not a power of two in [8, 512]       */
+    BISPEC_E_BIN_RANGE = -3,      /* need 0 <= k_lo < k_hi <= N/2, finite         */
+    BISPEC_E_EMPTY_BIN = -4,      /* a shell holds no mode                        */
+    BISPEC_E_NO_WORKSPACE = -5,   /* workspace missing or smaller than footprint  */
+    BISPEC_E_OOM = -6,            /* temporary device allocation failed           */
+    BISPEC_E_HIP = -7,            /* a HIP runtime call or kernel launch failed   */
+    BISPEC_E_NUMERIC = -8         /* an FFT count was not within 0.01 of an integer */
+} bispec_status;
+
+/* Arithmetic of the contraction sum_n F_i F_j F_k (and of the P and T sums).
+ * The FFTs are FP32 in every mode; cross-block sums and the normalisation are
+ * FP64 in every mode.  Modes 0 and 1 evaluate the dense product-Gram
+ * G[(i,j),k] = sum_n (F_i F_j) F_k on the matrix cores and need n_bins <= 32;
+ * with more bins they run as mode 2. */
+enum {
+    BISPEC_FP32 = 0,        /* product-Gram, FP32 MFMA, FP32 accumulation            */
+    BISPEC_SPLIT_BF16 = 1,  /* product-Gram, BF16 MFMA on hi/lo splits (3 products),
+                               FP32 accumulation                                      */
+    BISPEC_FP32_VALU = 2    /* only the requested sums, FP32 vector ALU               */
+};
+
+typedef struct {
+    int32_t n_side;        /* N, a power of two, 8..512 (Section 2: 2^n grids)       */
+    double box_len;        /* L; <= 0 means L = N (grid units, H = V/N_pix = 1)      */
+    int32_t n_bins;        /* 1..64                                                   */
+    const double *k_lo;    /* [n_bins] lower shell edges in k_f units (inclusive)     */
+    const double *k_hi;    /* [n_bins] upper shell edges in k_f units (exclusive)     */
+    int32_t n_tri;         /* number of triplets; 0 = every closed triplet i<=j<=k    */
+    const int32_t *tri;    /* [n_tri][3] bin indices, any order; NULL when n_tri = 0  */
+    int32_t n_quad;        /* number of p = 4 configurations; 0 = all (a,a,b,b), a<=b */
+    const int32_t *quad;   /* [n_quad][4] bin indices; NULL when n_quad = 0           */
+    int32_t precision;     /* BISPEC_FP32, BISPEC_SPLIT_BF16 or BISPEC_FP32_VALU      */
+    int32_t max_batch;     /* largest batch any later call will pass, >= 1            */
+    void *stream;          /* hipStream_t for all work of this plan (NULL = default) */
+} bispec_plan_desc;
+
+/* Build a plan: validate the descriptor, tabulate the shells, evaluate the
+ * FFT counts (Eq. Jeong_BI denominator, Section 3: FFT-counted triangles) in
+ * FP64 and, when n_tri = 0, keep every i<=j<=k whose shells admit a triangle
+ * (each lower edge below the sum of the other two upper edges) and whose
+ * count is non-zero.  *out is set only on BISPEC_OK. */
+bispec_status bispec_plan(const bispec_plan_desc *desc, bispec_plan_t *out);
+
+/* Device workspace bytes a call with this batch needs. */
+bispec_status bispec_plan_footprint(bispec_plan_t plan, int32_t batch, size_t *bytes);
+
+/* Attach caller-owned device memory (at least the footprint of max_batch,
+ * 256-byte aligned).  Uploads the plan's small tables into it. */
+bispec_status bispec_set_workspace(bispec_plan_t plan, void *dev_ptr, size_t bytes);
+
+/* Switch the contraction arithmetic of an existing plan; counts and tables
+ * are unchanged. */
+bispec_status bispec_set_precision(bispec_plan_t plan, int32_t precision);
+
+/* Change the stream later calls enqueue on. */
+bispec_status bispec_set_stream(bispec_plan_t plan, void *stream);
+
+/* Triplet list and FFT counts.  Each output pointer may be NULL.
+ * tri_out: [n_tri][3] as stored (canonical i<=j<=k for automatic lists);
+ * counts_out: [n_tri] ordered closed triples N_t (exact integers as double);
+ * quad_counts_out: [n_quad] ordered closed quadruples N_q, rounded to the
+ * nearest integer (exact while the FP64 sum resolves single units; beyond
+ * that accurate to a relative 1e-9). */
+bispec_status bispec_plan_query(bispec_plan_t plan, int32_t *n_tri, int32_t *tri_out,
+                                double *counts_out, double *quad_counts_out);
+
+/* p = 4 configuration list ([n_quad][4]) and the mode count M_b of each shell. */
+bispec_status bispec_plan_query_quads(bispec_plan_t plan, int32_t *n_quad, int32_t *quad_out);
+bispec_status bispec_plan_mode_counts(bispec_plan_t plan, int64_t *modes_out /*[n_bins]*/);
+
+/* The bin fields F_b(n) of Eq. (delta_nr): fields is a device buffer
+ * [batch][n_bins][N^3] FP32 (unnormalised inverse transform, so
+ * sum_n F_b(n)^2 = N_pix sum_{m in S_b} |Delta_fft(m)|^2). */
+bispec_status bispec_bin_fields(bispec_plan_t plan, const float *delta, int32_t batch,
+                                float *fields);
+
+/* Bispectrum of every planned triplet (Eq. Jeong_BI) and, if P != NULL, the
+ * power spectrum of every bin (Eq. Jeong_PS).  delta: device [batch][N^3];
+ * B: device [batch][n_tri] FP64; P: device [batch][n_bins] FP64.
+ * A triplet whose count is zero (explicit lists only) yields NaN. */
+bispec_status bispec_estimate(bispec_plan_t plan, const float *delta, int32_t batch,
+                              double *B, double *P);
+
+/* p = 4 polyspectrum of every planned quad (Eq. Jeong_gen with four fields).
+ * T: device [batch][n_quad] FP64.  T is the raw four-point mean, including
+ * its disconnected part. */
+bispec_status trispec_estimate(bispec_plan_t plan, const float *delta, int32_t batch,
+                               double *T);
+
+/* P, B and T from one set of bin fields (lower orders at no extra FFT cost,
+ * Section 2 after Eq. Jeong_BI).  Any of P, B, T may be NULL. */
+bispec_status polyspec_estimate(bispec_plan_t plan, const float *delta, int32_t batch,
+                                double *P, double *B, double *T);
+
+/* Stage timing (diagnostics).  While enabled, every estimate or bin-field
+ * call records HIP events on the plan's stream at its stage boundaries:
+ * [0] FP64 mean + forward FFT, [1] shell-masked inverse FFTs (all bins),
+ * [2] contraction kernel(s), [3] FP64 cross-block reduction.
+ * bispec_timing_read waits for the recorded events, returns the summed
+ * milliseconds per stage and the number of calls, and clears the record. */
+enum { BISPEC_N_STAGES = 4 };
+bispec_status bispec_timing_enable(bispec_plan_t plan, int32_t on);
+bispec_status bispec_timing_read(bispec_plan_t plan, double *stage_ms /*[BISPEC_N_STAGES]*/,
+                                 int32_t *calls);
+
+bispec_status bispec_destroy(bispec_plan_t plan);
+const char *bispec_status_string(bispec_status status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BISPEC_H */

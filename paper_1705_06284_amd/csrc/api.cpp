@@ -1,0 +1,714 @@
+// api.cpp -- plan construction and the C ABI of libbispec (see include/bispec.h).
+//
+// A plan holds the shells of the bins as integer |m|^2 thresholds, the
+// configuration lists (triplets for Eq. Jeong_BI, bins for Eq. Jeong_PS,
+// quads for Eq. Jeong_gen with p = 4), and their exact FFT counts.  The counts
+// are the denominators of those equations, sum_n I_i I_j ..., evaluated once
+// in FP64 with the same FFT pipeline and divided by N_pix, which makes them
+// integers (the number of ordered closed tuples, closure modulo N).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <limits>
+#include <new>
+#include <vector>
+
+#include "../../include/bispec.h"
+#include "launch.hpp"
+#include "plan.hpp"
+
+using namespace bispec;
+
+namespace {
+
+constexpr int kMeanParts = 512;
+constexpr size_t kAlign = 256;
+
+inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+bool is_pow2_in_range(int n) { return n >= 8 && n <= 512 && (n & (n - 1)) == 0; }
+
+#define CK(call)                                   \
+    do {                                           \
+        if ((call) != hipSuccess) return BISPEC_E_HIP; \
+    } while (0)
+
+int contract_blocks(int64_t npix) {
+    // about 4096 points per block, at most 2048 blocks, at least 1
+    int64_t b = (npix + 4095) / 4096;
+    if (b > 2048) b = 2048;
+    if (b < 1) b = 1;
+    return (int)b;
+}
+
+// ceil(x) for the FP64 squared edges: integer r2 >= lo^2 <=> r2 >= ceil(lo^2)
+// and r2 < hi^2 <=> r2 < ceil(hi^2).
+int ceil_int(double x) { return (int)std::ceil(x); }
+
+}  // namespace
+
+namespace bispec {
+
+Layout make_layout(const bispec_plan_s &p, int batch) {
+    Layout L{};
+    const int64_t vol = (int64_t)p.n * p.n * p.n;
+    size_t off = 0;
+    L.tw = off;           off = align_up(off + sizeof(float2) * p.n);
+    L.terms = off;        off = align_up(off + sizeof(uchar4) * p.terms.size());
+    L.scale = off;        off = align_up(off + sizeof(double) * p.scale.size());
+    L.pg_pairs = off;     off = align_up(off + sizeof(uchar2) * p.pg_pairs.size());
+    L.pg_idx = off;       off = align_up(off + sizeof(int) * p.pg_idx.size());
+    L.mean_partial = off; off = align_up(off + sizeof(double) * kMeanParts * batch);
+    L.mean = off;         off = align_up(off + sizeof(double) * batch);
+    L.spec = off;         off = align_up(off + sizeof(float2) * vol * batch);
+    L.scratch = off;      off = align_up(off + sizeof(float2) * vol * batch);
+    L.fields = off;       off = align_up(off + sizeof(float) * vol * p.nb * batch);
+    L.partial = off;      off = align_up(off + sizeof(double) * (size_t)p.nblk * p.terms.size() * batch);
+    L.pg_partial = off;
+    if (p.mfma_ok) off = align_up(off + sizeof(double) * pgram_partial_doubles(p.n_mtile, true) * p.nblk_pg * batch);
+    L.total = off;
+    return L;
+}
+
+}  // namespace bispec
+
+bispec_plan_s::~bispec_plan_s() {
+    for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+    for (hipEvent_t e : ev_rec) (void)hipEventDestroy(e);
+}
+
+namespace {
+
+// Stage stamps: stamp(p, 0) opens a record, stamp(p, 1..4) close stages.
+hipEvent_t take_event(bispec_plan_s &p) {
+    if (!p.ev_pool.empty()) {
+        hipEvent_t e = p.ev_pool.back();
+        p.ev_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+void stamp(bispec_plan_s &p, int k) {
+    if (!p.timing) return;
+    if (k == 0)
+        for (int i = 0; i < 5; ++i) p.ev_cur[i] = nullptr;
+    hipEvent_t e = take_event(p);
+    if (!e) return;
+    (void)hipEventRecord(e, p.stream);
+    p.ev_cur[k] = e;
+    if (k == 4) {
+        bool whole = true;
+        for (int i = 0; i < 5; ++i) whole = whole && p.ev_cur[i];
+        if (whole)
+            for (int i = 0; i < 5; ++i) p.ev_rec.push_back(p.ev_cur[i]);
+    }
+}
+
+// Close the stages not yet closed in this call at the current point.
+void stamp_rest(bispec_plan_s &p, int from) {
+    if (!p.timing) return;
+    for (int k = from; k <= 4; ++k)
+        if (!p.ev_cur[k]) stamp(p, k);
+}
+
+// Rows of the product-Gram: pairs (i,j), i <= j, ordered by j then i; then
+// (b, ONE) rows; padding rows (ZERO, ZERO) up to a multiple of 32.  A term's
+// dense index in a block's tiles is tile*1024 + row_in_tile*32 + column.
+void build_pgram_tables(bispec_plan_s &p) {
+    const int nb = p.nb;
+    p.mfma_ok = nb <= 32;
+    p.pg_pairs.clear();
+    p.pg_idx.clear();
+    if (!p.mfma_ok) return;
+    std::vector<int> row_of(nb * nb, -1), row_one(nb, -1);
+    for (int j = 0; j < nb; ++j)
+        for (int i = 0; i <= j; ++i) {
+            row_of[i * nb + j] = (int)p.pg_pairs.size();
+            p.pg_pairs.push_back(uchar2{(unsigned char)i, (unsigned char)j});
+        }
+    for (int b = 0; b < nb; ++b) {
+        row_one[b] = (int)p.pg_pairs.size();
+        p.pg_pairs.push_back(uchar2{(unsigned char)b, (unsigned char)PG_ROW_ONE});
+    }
+    while (p.pg_pairs.size() % 32) p.pg_pairs.push_back(uchar2{(unsigned char)PG_ROW_ZERO, (unsigned char)PG_ROW_ZERO});
+    p.n_mtile = (int)p.pg_pairs.size() / 32;
+    auto dense = [](int row, int c) { return (row / 32) * 1024 + (row % 32) * 32 + c; };
+    const int ntri = (int)p.tri.size() / 3;
+    for (int t = 0; t < ntri; ++t) {
+        int a[3] = {p.tri[3 * t], p.tri[3 * t + 1], p.tri[3 * t + 2]};
+        std::sort(a, a + 3);
+        p.pg_idx.push_back(dense(row_of[a[0] * nb + a[1]], a[2]));
+    }
+    for (int b = 0; b < nb; ++b) p.pg_idx.push_back(dense(row_one[b], b));
+    const int nq = (int)p.quad.size() / 4;
+    p.quads_collapsed = true;
+    for (int q = 0; q < nq; ++q) {
+        int a[4] = {p.quad[4 * q], p.quad[4 * q + 1], p.quad[4 * q + 2], p.quad[4 * q + 3]};
+        std::sort(a, a + 4);
+        if (a[0] != a[1] || a[2] != a[3]) {
+            p.quads_collapsed = false;
+            p.pg_idx.push_back(-1);
+        } else {
+            p.pg_idx.push_back(p.n_mtile * 1024 + a[0] * 32 + a[2]);
+        }
+    }
+}
+
+void build_terms(bispec_plan_s &p) {
+    p.terms.clear();
+    p.scale.clear();
+    const double npix = (double)p.n * p.n * p.n;
+    const double V = p.box_len * p.box_len * p.box_len;
+    const double nan = std::numeric_limits<double>::quiet_NaN();
+    const int ntri = (int)p.tri.size() / 3;
+    for (int t = 0; t < ntri; ++t) {
+        p.terms.push_back(uchar4{(unsigned char)p.tri[3 * t], (unsigned char)p.tri[3 * t + 1],
+                                 (unsigned char)p.tri[3 * t + 2], 0xFF});
+        const double c = p.tri_count.empty() ? 0.0 : p.tri_count[t];
+        p.scale.push_back(c > 0 ? V * V / (npix * npix * npix) / (npix * c) : nan);
+    }
+    for (int b = 0; b < p.nb; ++b) {
+        p.terms.push_back(uchar4{(unsigned char)b, (unsigned char)b, 0xFF, 0xFF});
+        p.scale.push_back(V / (npix * npix) / (npix * (double)p.modes[b]));
+    }
+    const int nq = (int)p.quad.size() / 4;
+    for (int q = 0; q < nq; ++q) {
+        p.terms.push_back(uchar4{(unsigned char)p.quad[4 * q], (unsigned char)p.quad[4 * q + 1],
+                                 (unsigned char)p.quad[4 * q + 2], (unsigned char)p.quad[4 * q + 3]});
+        const double c = p.quad_count.empty() ? 0.0 : p.quad_count[q];
+        p.scale.push_back(c > 0 ? V * V * V / (npix * npix * npix * npix) / (npix * c) : nan);
+    }
+    build_pgram_tables(p);
+}
+
+// Triangle inequality on the shells: each lower edge below the sum of the
+// other two upper edges (necessary for a triangle closed in Z^3).
+bool admits_triangle(const bispec_plan_s &p, int i, int j, int k) {
+    return p.lo[k] < p.hi[i] + p.hi[j] && p.lo[j] < p.hi[i] + p.hi[k] && p.lo[i] < p.hi[j] + p.hi[k];
+}
+
+// FP64 count fields I_b and their product sums, evaluated on the device.
+bispec_status compute_counts(bispec_plan_s &p, std::vector<int> &cand_tri, std::vector<double> &tri_cnt,
+                             std::vector<double> &quad_cnt) {
+    const int n = p.n, nb = p.nb;
+    const int64_t vol = (int64_t)n * n * n;
+    hipStream_t st = p.stream;
+
+    // term list: candidate triplets, (b,b) for the mode-count check, quads
+    std::vector<uchar4> terms;
+    const int ntri = (int)cand_tri.size() / 3;
+    for (int t = 0; t < ntri; ++t)
+        terms.push_back(uchar4{(unsigned char)cand_tri[3 * t], (unsigned char)cand_tri[3 * t + 1],
+                               (unsigned char)cand_tri[3 * t + 2], 0xFF});
+    for (int b = 0; b < nb; ++b) terms.push_back(uchar4{(unsigned char)b, (unsigned char)b, 0xFF, 0xFF});
+    const int nq = (int)p.quad.size() / 4;
+    for (int q = 0; q < nq; ++q)
+        terms.push_back(uchar4{(unsigned char)p.quad[4 * q], (unsigned char)p.quad[4 * q + 1],
+                               (unsigned char)p.quad[4 * q + 2], (unsigned char)p.quad[4 * q + 3]});
+    const int nterm = (int)terms.size();
+    const int nblk = contract_blocks(vol);
+
+    std::vector<double2> tw(n);
+    for (int i = 0; i < n; ++i) {
+        const double a = 2.0 * M_PI * (double)i / (double)n;
+        tw[i] = double2{std::cos(a), -std::sin(a)};
+    }
+
+    size_t off = 0;
+    const size_t o_tw = off;      off = align_up(off + sizeof(double2) * n);
+    const size_t o_terms = off;   off = align_up(off + sizeof(uchar4) * nterm);
+    const size_t o_ones = off;    off = align_up(off + sizeof(double) * nterm);
+    const size_t o_sums = off;    off = align_up(off + sizeof(double) * nterm);
+    const size_t o_partial = off; off = align_up(off + sizeof(double) * (size_t)nblk * nterm);
+    const size_t o_scratch = off; off = align_up(off + sizeof(double2) * vol);
+    const size_t o_fields = off;  off = align_up(off + sizeof(double) * vol * nb);
+    char *mem = nullptr;
+    if (hipMalloc((void **)&mem, off) != hipSuccess) {
+        (void)hipGetLastError();
+        return BISPEC_E_OOM;
+    }
+    struct Free {
+        char *m;
+        ~Free() { (void)hipFree(m); }
+    } guard{mem};
+
+    std::vector<double> ones(nterm, 1.0);
+    CK(hipMemcpyAsync(mem + o_tw, tw.data(), sizeof(double2) * n, hipMemcpyHostToDevice, st));
+    CK(hipMemcpyAsync(mem + o_terms, terms.data(), sizeof(uchar4) * nterm, hipMemcpyHostToDevice, st));
+    CK(hipMemcpyAsync(mem + o_ones, ones.data(), sizeof(double) * nterm, hipMemcpyHostToDevice, st));
+    double *fields = (double *)(mem + o_fields);
+    for (int b = 0; b < nb; b += 2) {
+        const bool two = b + 1 < nb;
+        CK(launch_inverse_pair_unit_f64(n, (const double2 *)(mem + o_tw), p.ilo2[b], p.ihi2[b],
+                                        two ? p.ilo2[b + 1] : 0, two ? p.ihi2[b + 1] : 0,
+                                        (double2 *)(mem + o_scratch), fields + (int64_t)b * vol,
+                                        two ? fields + (int64_t)(b + 1) * vol : nullptr, st));
+    }
+    CK(launch_contract_terms_f64(fields, vol, nb, (const uchar4 *)(mem + o_terms), nterm, nblk,
+                                 (double *)(mem + o_partial), st));
+    CK(launch_finalize((const double *)(mem + o_partial), nblk, nterm, 1, (const double *)(mem + o_ones),
+                       (double *)(mem + o_sums), nterm, nullptr, 0, nullptr, 0, st));
+    std::vector<double> sums(nterm);
+    CK(hipMemcpyAsync(sums.data(), mem + o_sums, sizeof(double) * nterm, hipMemcpyDeviceToHost, st));
+    CK(hipStreamSynchronize(st));
+
+    auto to_count = [&](double s, double *out) -> bool {
+        const double c = s / (double)vol;
+        const double r = std::nearbyint(c);
+        *out = r;
+        return std::fabs(c - r) <= 0.01;
+    };
+    tri_cnt.assign(ntri, 0.0);
+    for (int t = 0; t < ntri; ++t)
+        if (!to_count(sums[t], &tri_cnt[t])) return BISPEC_E_NUMERIC;
+    for (int b = 0; b < nb; ++b) {
+        double m;
+        if (!to_count(sums[ntri + b], &m) || m != (double)p.modes[b]) return BISPEC_E_NUMERIC;
+    }
+    // p = 4 counts grow like M^3 and outrun what an FP64 sum resolves to one
+    // unit once N_pix N_q passes ~2^53 ulp-scale: they are rounded to the
+    // nearest integer and checked to a relative 1e-9.
+    quad_cnt.assign(nq, 0.0);
+    for (int q = 0; q < nq; ++q) {
+        const double c = sums[ntri + nb + q] / (double)vol;
+        quad_cnt[q] = std::nearbyint(c);
+        if (std::fabs(c - quad_cnt[q]) > std::max(0.01, 1e-9 * std::fabs(c))) return BISPEC_E_NUMERIC;
+    }
+    return BISPEC_OK;
+}
+
+bispec_status plan_impl(const bispec_plan_desc *d, bispec_plan_t *out) {
+    if (!d || !out) return BISPEC_E_INVALID;
+    if (!is_pow2_in_range(d->n_side)) return BISPEC_E_UNSUPPORTED_N;
+    if (d->n_bins < 1 || d->n_bins > 64 || !d->k_lo || !d->k_hi) return BISPEC_E_INVALID;
+    if (d->precision < BISPEC_FP32 || d->precision > BISPEC_FP32_VALU) return BISPEC_E_INVALID;
+    if (d->max_batch < 1) return BISPEC_E_INVALID;
+    if (d->n_tri < 0 || (d->n_tri > 0 && !d->tri)) return BISPEC_E_INVALID;
+    if (d->n_quad < 0 || (d->n_quad > 0 && !d->quad)) return BISPEC_E_INVALID;
+    const int n = d->n_side, nb = d->n_bins;
+    for (int b = 0; b < nb; ++b) {
+        const double lo = d->k_lo[b], hi = d->k_hi[b];
+        if (!std::isfinite(lo) || !std::isfinite(hi) || lo < 0.0 || lo >= hi || hi > 0.5 * n)
+            return BISPEC_E_BIN_RANGE;
+    }
+    for (int t = 0; t < 3 * d->n_tri; ++t)
+        if (d->tri[t] < 0 || d->tri[t] >= nb) return BISPEC_E_INVALID;
+    for (int t = 0; t < 4 * d->n_quad; ++t)
+        if (d->quad[t] < 0 || d->quad[t] >= nb) return BISPEC_E_INVALID;
+
+    bispec_plan_s *p = new bispec_plan_s();
+    p->n = n;
+    p->box_len = d->box_len > 0 ? d->box_len : (double)n;
+    p->nb = nb;
+    p->lo.assign(d->k_lo, d->k_lo + nb);
+    p->hi.assign(d->k_hi, d->k_hi + nb);
+    p->precision = d->precision;
+    p->max_batch = d->max_batch;
+    p->stream = (hipStream_t)d->stream;
+    for (int b = 0; b < nb; ++b) {
+        p->ilo2.push_back(std::max(1, ceil_int(p->lo[b] * p->lo[b])));
+        p->ihi2.push_back(ceil_int(p->hi[b] * p->hi[b]));
+    }
+    struct Owner {
+        bispec_plan_s *p;
+        bool keep = false;
+        ~Owner() { if (!keep) delete p; }
+    } own{p};
+
+    // modes per shell
+    {
+        int *thr = nullptr;
+        unsigned long long *cnt = nullptr;
+        if (hipMalloc((void **)&thr, sizeof(int) * 2 * nb) != hipSuccess ||
+            hipMalloc((void **)&cnt, sizeof(unsigned long long) * nb) != hipSuccess) {
+            (void)hipFree(thr);
+            (void)hipGetLastError();
+            return BISPEC_E_OOM;
+        }
+        std::vector<int> th(p->ilo2);
+        th.insert(th.end(), p->ihi2.begin(), p->ihi2.end());
+        std::vector<unsigned long long> hc(nb, 0);
+        bool ok = hipMemcpyAsync(thr, th.data(), sizeof(int) * 2 * nb, hipMemcpyHostToDevice, p->stream) == hipSuccess &&
+                  hipMemsetAsync(cnt, 0, sizeof(unsigned long long) * nb, p->stream) == hipSuccess &&
+                  launch_shell_hist(n, nb, thr, thr + nb, cnt, p->stream) == hipSuccess &&
+                  hipMemcpyAsync(hc.data(), cnt, sizeof(unsigned long long) * nb, hipMemcpyDeviceToHost,
+                                 p->stream) == hipSuccess &&
+                  hipStreamSynchronize(p->stream) == hipSuccess;
+        (void)hipFree(thr);
+        (void)hipFree(cnt);
+        if (!ok) return BISPEC_E_HIP;
+        for (int b = 0; b < nb; ++b) {
+            p->modes.push_back((int64_t)hc[b]);
+            if (hc[b] == 0) return BISPEC_E_EMPTY_BIN;
+        }
+    }
+
+    // configuration lists
+    std::vector<int> cand;
+    const bool auto_tri = d->n_tri == 0;
+    if (auto_tri) {
+        for (int i = 0; i < nb; ++i)
+            for (int j = i; j < nb; ++j)
+                for (int k = j; k < nb; ++k)
+                    if (admits_triangle(*p, i, j, k)) {
+                        cand.push_back(i);
+                        cand.push_back(j);
+                        cand.push_back(k);
+                    }
+    } else {
+        cand.assign(d->tri, d->tri + 3 * d->n_tri);
+    }
+    if (d->n_quad == 0) {
+        for (int a = 0; a < nb; ++a)
+            for (int b = a; b < nb; ++b) {
+                p->quad.push_back(a);
+                p->quad.push_back(a);
+                p->quad.push_back(b);
+                p->quad.push_back(b);
+            }
+    } else {
+        p->quad.assign(d->quad, d->quad + 4 * d->n_quad);
+    }
+
+    std::vector<double> tri_cnt, quad_cnt;
+    bispec_status s = compute_counts(*p, cand, tri_cnt, quad_cnt);
+    if (s != BISPEC_OK) return s;
+    if (auto_tri) {
+        for (size_t t = 0; t < tri_cnt.size(); ++t)
+            if (tri_cnt[t] > 0) {
+                p->tri.insert(p->tri.end(), cand.begin() + 3 * t, cand.begin() + 3 * t + 3);
+                p->tri_count.push_back(tri_cnt[t]);
+            }
+    } else {
+        p->tri = cand;
+        p->tri_count = tri_cnt;
+    }
+    p->quad_count = quad_cnt;
+    p->nblk = contract_blocks((int64_t)n * n * n);
+    {
+        // one product-Gram block per CU (about 100 KiB of LDS each), fewer for
+        // small grids: at least 1024 points per block
+        int64_t b = (int64_t)n * n * n / 1024;
+        p->nblk_pg = (int)std::max<int64_t>(1, std::min<int64_t>(256, b));
+    }
+    build_terms(*p);
+    own.keep = true;
+    *out = p;
+    return BISPEC_OK;
+}
+
+bispec_status upload_tables(bispec_plan_s &p) {
+    const Layout L = make_layout(p, p.max_batch);
+    char *ws = (char *)p.ws;
+    std::vector<float2> tw(p.n);
+    for (int i = 0; i < p.n; ++i) {
+        const double a = 2.0 * M_PI * (double)i / (double)p.n;
+        tw[i] = float2{(float)std::cos(a), (float)-std::sin(a)};
+    }
+    CK(hipMemcpyAsync(ws + L.tw, tw.data(), sizeof(float2) * p.n, hipMemcpyHostToDevice, p.stream));
+    CK(hipMemcpyAsync(ws + L.terms, p.terms.data(), sizeof(uchar4) * p.terms.size(), hipMemcpyHostToDevice,
+                      p.stream));
+    CK(hipMemcpyAsync(ws + L.scale, p.scale.data(), sizeof(double) * p.scale.size(), hipMemcpyHostToDevice,
+                      p.stream));
+    if (p.mfma_ok) {
+        CK(hipMemcpyAsync(ws + L.pg_pairs, p.pg_pairs.data(), sizeof(uchar2) * p.pg_pairs.size(),
+                          hipMemcpyHostToDevice, p.stream));
+        CK(hipMemcpyAsync(ws + L.pg_idx, p.pg_idx.data(), sizeof(int) * p.pg_idx.size(), hipMemcpyHostToDevice,
+                          p.stream));
+    }
+    CK(hipStreamSynchronize(p.stream));
+    return BISPEC_OK;
+}
+
+bispec_status check_call(bispec_plan_s *p, const float *delta, int batch) {
+    if (!p || !delta) return BISPEC_E_INVALID;
+    if (batch < 1 || batch > p->max_batch) return BISPEC_E_INVALID;
+    if (!p->ws) return BISPEC_E_NO_WORKSPACE;
+    return BISPEC_OK;
+}
+
+// mean, forward transform, and all bin fields into `fields` ([batch][nb][N^3]).
+bispec_status run_fields(bispec_plan_s &p, const float *delta, int batch, float *fields) {
+    const Layout L = make_layout(p, p.max_batch);
+    char *ws = (char *)p.ws;
+    const int n = p.n;
+    const int64_t vol = (int64_t)n * n * n;
+    const float2 *tw = (const float2 *)(ws + L.tw);
+    double *mean = (double *)(ws + L.mean);
+    float2 *spec = (float2 *)(ws + L.spec);
+    float2 *scratch = (float2 *)(ws + L.scratch);
+    stamp(p, 0);
+    CK(launch_mean(delta, n, batch, (double *)(ws + L.mean_partial), kMeanParts, mean, p.stream));
+    CK(launch_forward(delta, mean, n, batch, tw, spec, p.stream));
+    stamp(p, 1);
+    for (int b = 0; b < p.nb; b += 2) {
+        const bool two = b + 1 < p.nb;
+        CK(launch_inverse_pair(spec, vol, n, batch, tw, p.ilo2[b], p.ihi2[b], two ? p.ilo2[b + 1] : 0,
+                               two ? p.ihi2[b + 1] : 0, scratch, vol, fields + (int64_t)b * vol,
+                               two ? fields + (int64_t)(b + 1) * vol : nullptr, (int64_t)p.nb * vol, p.stream));
+    }
+    stamp(p, 2);
+    return BISPEC_OK;
+}
+
+// Final FP64 reduction of terms [first, last) into B ([0,ntri)), P
+// ([ntri, ntri+nb)) and T (the rest); gather != 0 reads the dense
+// product-Gram partials at pg_idx.
+bispec_status finalize_range(bispec_plan_s &p, bool gather, const double *partial, int nblk, int64_t blk_stride,
+                             int first, int last, int batch, double *P, double *B, double *T) {
+    const Layout L = make_layout(p, p.max_batch);
+    char *ws = (char *)p.ws;
+    const int ntri = (int)p.tri.size() / 3;
+    const int nterm = last - first;
+    if (nterm <= 0) return BISPEC_OK;
+    const int n0 = std::max(0, std::min(ntri, last) - first);
+    const int n1 = std::max(0, std::min(ntri + p.nb, last) - std::max(first, ntri));
+    const int n2 = std::max(0, last - std::max(first, ntri + p.nb));
+    double *o[3] = {B, P, T};
+    int ns[3] = {n0, n1, n2};
+    double *oo[3] = {nullptr, nullptr, nullptr};
+    int nn[3] = {0, 0, 0};
+    int k = 0;
+    for (int s = 0; s < 3; ++s)
+        if (ns[s] > 0) {
+            oo[k] = o[s];
+            nn[k] = ns[s];
+            ++k;
+        }
+    const double *scale = (const double *)(ws + L.scale) + first;
+    if (p.timing && !p.ev_cur[3]) stamp(p, 3);
+    if (gather) {
+        const int *idx = (const int *)(ws + L.pg_idx) + first;
+        CK(launch_finalize_gather(partial, nblk, blk_stride, idx, nterm, batch, scale, oo[0], nn[0], oo[1], nn[1],
+                                  oo[2], nn[2], p.stream));
+    } else {
+        CK(launch_finalize(partial, nblk, nterm, batch, scale, oo[0], nn[0], oo[1], nn[1], oo[2], nn[2], p.stream));
+    }
+    return BISPEC_OK;
+}
+
+// VALU contraction of terms [first, last) followed by their reduction.
+bispec_status valu_terms(bispec_plan_s &p, const float *fields, int first, int last, int batch, double *P, double *B,
+                         double *T) {
+    const Layout L = make_layout(p, p.max_batch);
+    char *ws = (char *)p.ws;
+    const int64_t vol = (int64_t)p.n * p.n * p.n;
+    const int nterm = last - first;
+    if (nterm <= 0) return BISPEC_OK;
+    double *partial = (double *)(ws + L.partial);
+    CK(launch_contract_terms_f32(fields, vol, p.nb, (int64_t)p.nb * vol, batch, (const uchar4 *)(ws + L.terms) + first,
+                                 nterm, p.nblk, partial, p.stream));
+    return finalize_range(p, false, partial, p.nblk, nterm, first, last, batch, P, B, T);
+}
+
+bispec_status run_estimate_body(bispec_plan_s &p, const float *delta, int batch, double *P, double *B,
+                                double *T) {
+    const Layout L = make_layout(p, p.max_batch);
+    char *ws = (char *)p.ws;
+    const int64_t vol = (int64_t)p.n * p.n * p.n;
+    float *fields = (float *)(ws + L.fields);
+    bispec_status s = run_fields(p, delta, batch, fields);
+    if (s != BISPEC_OK) return s;
+    const int ntri = (int)p.tri.size() / 3, nq = (int)p.quad.size() / 4;
+    const int t_first = ntri + p.nb, t_last = ntri + p.nb + nq;
+    // B and P share the lower term range
+    int first = B ? 0 : ntri, last = P ? ntri + p.nb : ntri;
+    if (!B && !P) first = last = 0;
+    const bool mfma = p.mfma_ok && p.precision != BISPEC_FP32_VALU;
+    if (!mfma) {
+        if (!T) return valu_terms(p, fields, first, last, batch, P, B, T);
+        if (first == last) return valu_terms(p, fields, t_first, t_last, batch, P, B, T);
+        if (last == t_first) return valu_terms(p, fields, first, t_last, batch, P, B, T);
+        s = valu_terms(p, fields, first, last, batch, P, B, T);
+        if (s != BISPEC_OK) return s;
+        return valu_terms(p, fields, t_first, t_last, batch, P, B, T);
+    }
+    const bool t_mfma = T && p.quads_collapsed;
+    if (first < last || t_mfma) {
+        const int mode = p.precision == BISPEC_SPLIT_BF16 ? PG_MODE_SPLIT : PG_MODE_F32;
+        double *pg = (double *)(ws + L.pg_partial);
+        CK(launch_pgram(mode, t_mfma, fields, vol, p.nb, (int64_t)p.nb * vol, batch,
+                        (const uchar2 *)(ws + L.pg_pairs), p.n_mtile, p.nblk_pg, pg, p.stream));
+        const int64_t blk_stride = (int64_t)pgram_partial_doubles(p.n_mtile, t_mfma);
+        if (first < last) {
+            s = finalize_range(p, true, pg, p.nblk_pg, blk_stride, first, last, batch, P, B, T);
+            if (s != BISPEC_OK) return s;
+        }
+        if (t_mfma) {
+            s = finalize_range(p, true, pg, p.nblk_pg, blk_stride, t_first, t_last, batch, P, B, T);
+            if (s != BISPEC_OK) return s;
+        }
+    }
+    if (T && !p.quads_collapsed) return valu_terms(p, fields, t_first, t_last, batch, P, B, T);
+    return BISPEC_OK;
+}
+
+bispec_status run_estimate(bispec_plan_s &p, const float *delta, int batch, double *P, double *B, double *T) {
+    bispec_status s = run_estimate_body(p, delta, batch, P, B, T);
+    stamp_rest(p, 3);
+    return s;
+}
+
+}  // namespace
+
+extern "C" {
+
+bispec_status bispec_plan(const bispec_plan_desc *desc, bispec_plan_t *out) {
+    try {
+        return plan_impl(desc, out);
+    } catch (const std::bad_alloc &) {
+        return BISPEC_E_OOM;
+    } catch (...) {
+        return BISPEC_E_INVALID;
+    }
+}
+
+bispec_status bispec_plan_footprint(bispec_plan_t plan, int32_t batch, size_t *bytes) {
+    if (!plan || !bytes || batch < 1) return BISPEC_E_INVALID;
+    *bytes = make_layout(*plan, batch).total;
+    return BISPEC_OK;
+}
+
+bispec_status bispec_set_workspace(bispec_plan_t plan, void *dev_ptr, size_t bytes) {
+    if (!plan || !dev_ptr) return BISPEC_E_INVALID;
+    if (((uintptr_t)dev_ptr) % kAlign) return BISPEC_E_INVALID;
+    if (bytes < make_layout(*plan, plan->max_batch).total) return BISPEC_E_NO_WORKSPACE;
+    plan->ws = dev_ptr;
+    plan->ws_bytes = bytes;
+    try {
+        bispec_status s = upload_tables(*plan);
+        if (s != BISPEC_OK) plan->ws = nullptr;
+        return s;
+    } catch (...) {
+        plan->ws = nullptr;
+        return BISPEC_E_OOM;
+    }
+}
+
+bispec_status bispec_set_precision(bispec_plan_t plan, int32_t precision) {
+    if (!plan || precision < BISPEC_FP32 || precision > BISPEC_FP32_VALU) return BISPEC_E_INVALID;
+    plan->precision = precision;
+    return BISPEC_OK;
+}
+
+bispec_status bispec_set_stream(bispec_plan_t plan, void *stream) {
+    if (!plan) return BISPEC_E_INVALID;
+    plan->stream = (hipStream_t)stream;
+    return BISPEC_OK;
+}
+
+bispec_status bispec_plan_query(bispec_plan_t plan, int32_t *n_tri, int32_t *tri_out, double *counts_out,
+                                double *quad_counts_out) {
+    if (!plan) return BISPEC_E_INVALID;
+    const int nt = (int)plan->tri.size() / 3;
+    if (n_tri) *n_tri = nt;
+    if (tri_out) std::memcpy(tri_out, plan->tri.data(), sizeof(int32_t) * 3 * nt);
+    if (counts_out) std::memcpy(counts_out, plan->tri_count.data(), sizeof(double) * nt);
+    if (quad_counts_out)
+        std::memcpy(quad_counts_out, plan->quad_count.data(), sizeof(double) * plan->quad_count.size());
+    return BISPEC_OK;
+}
+
+bispec_status bispec_plan_query_quads(bispec_plan_t plan, int32_t *n_quad, int32_t *quad_out) {
+    if (!plan) return BISPEC_E_INVALID;
+    const int nq = (int)plan->quad.size() / 4;
+    if (n_quad) *n_quad = nq;
+    if (quad_out) std::memcpy(quad_out, plan->quad.data(), sizeof(int32_t) * 4 * nq);
+    return BISPEC_OK;
+}
+
+bispec_status bispec_plan_mode_counts(bispec_plan_t plan, int64_t *modes_out) {
+    if (!plan || !modes_out) return BISPEC_E_INVALID;
+    std::memcpy(modes_out, plan->modes.data(), sizeof(int64_t) * plan->nb);
+    return BISPEC_OK;
+}
+
+bispec_status bispec_bin_fields(bispec_plan_t plan, const float *delta, int32_t batch, float *fields) {
+    bispec_status s = check_call(plan, delta, batch);
+    if (s != BISPEC_OK) return s;
+    if (!fields) return BISPEC_E_INVALID;
+    try {
+        bispec_status st = run_fields(*plan, delta, batch, fields);
+        stamp_rest(*plan, 3);
+        return st;
+    } catch (...) {
+        return BISPEC_E_HIP;
+    }
+}
+
+bispec_status polyspec_estimate(bispec_plan_t plan, const float *delta, int32_t batch, double *P, double *B,
+                                double *T) {
+    bispec_status s = check_call(plan, delta, batch);
+    if (s != BISPEC_OK) return s;
+    try {
+        return run_estimate(*plan, delta, batch, P, B, T);
+    } catch (...) {
+        return BISPEC_E_HIP;
+    }
+}
+
+bispec_status bispec_estimate(bispec_plan_t plan, const float *delta, int32_t batch, double *B, double *P) {
+    if (!B) return BISPEC_E_INVALID;
+    return polyspec_estimate(plan, delta, batch, P, B, nullptr);
+}
+
+bispec_status trispec_estimate(bispec_plan_t plan, const float *delta, int32_t batch, double *T) {
+    if (!T) return BISPEC_E_INVALID;
+    return polyspec_estimate(plan, delta, batch, nullptr, nullptr, T);
+}
+
+bispec_status bispec_timing_enable(bispec_plan_t plan, int32_t on) {
+    if (!plan) return BISPEC_E_INVALID;
+    plan->timing = on != 0;
+    return BISPEC_OK;
+}
+
+bispec_status bispec_timing_read(bispec_plan_t plan, double *stage_ms, int32_t *calls) {
+    if (!plan) return BISPEC_E_INVALID;
+    double acc[BISPEC_N_STAGES] = {0, 0, 0, 0};
+    const size_t nrec = plan->ev_rec.size() / 5;
+    bispec_status st = BISPEC_OK;
+    for (size_t r = 0; r < nrec; ++r) {
+        hipEvent_t *e = &plan->ev_rec[5 * r];
+        if (hipEventSynchronize(e[4]) != hipSuccess) st = BISPEC_E_HIP;
+        for (int k = 0; k < BISPEC_N_STAGES; ++k) {
+            float ms = 0.0f;
+            if (hipEventElapsedTime(&ms, e[k], e[k + 1]) != hipSuccess) st = BISPEC_E_HIP;
+            acc[k] += ms;
+        }
+    }
+    plan->ev_pool.insert(plan->ev_pool.end(), plan->ev_rec.begin(), plan->ev_rec.end());
+    plan->ev_rec.clear();
+    if (stage_ms)
+        for (int k = 0; k < BISPEC_N_STAGES; ++k) stage_ms[k] = acc[k];
+    if (calls) *calls = (int32_t)nrec;
+    return st;
+}
+
+bispec_status bispec_destroy(bispec_plan_t plan) {
+    delete plan;
+    return BISPEC_OK;
+}
+
+const char *bispec_status_string(bispec_status s) {
+    switch (s) {
+        case BISPEC_OK: return "ok";
+        case BISPEC_E_INVALID: return "invalid argument";
+        case BISPEC_E_UNSUPPORTED_N: return "n_side must be a power of two in [8, 512]";
+        case BISPEC_E_BIN_RANGE: return "bin edges must satisfy 0 <= k_lo < k_hi <= N/2";
+        case BISPEC_E_EMPTY_BIN: return "a shell contains no mode";
+        case BISPEC_E_NO_WORKSPACE: return "workspace missing or smaller than the footprint";
+        case BISPEC_E_OOM: return "device allocation failed";
+        case BISPEC_E_HIP: return "HIP runtime error";
+        case BISPEC_E_NUMERIC: return "an FFT count was not close to an integer";
+    }
+    return "unknown status";
+}
+
+}  // extern "C"

@@ -1,0 +1,155 @@
+// fft_core.hpp -- LDS-resident Stockham FFT of a group of pencils (gfx950).
+//
+// A block of 256 threads holds G pencils of length N in LDS ([G][N] complex).
+// The transform is a Stockham autosort sequence of radix-8 passes followed by
+// at most one radix-2 or radix-4 pass, so N = 8^p * {1, 2, 4}.  In a pass of
+// radix R over sub-transforms of span Ns, butterfly jj of a pencil reads the R
+// inputs a[jj + t N/R], multiplies input t by w^(t k) with k = jj mod Ns and
+// w = exp(dir 2 pi i / (Ns R)), takes an R-point DFT and writes output u to
+// ((jj / Ns) Ns R + k + u Ns).  Every twiddle is an integer power of
+// W_N = exp(-2 pi i / N) read from a table built on the host in FP64 from the
+// exactly reduced argument; the inverse direction uses the conjugate.
+//
+// Direction: DIR = -1 is the forward transform of Eq. (DeltaFFTtoDelta),
+// DIR = +1 the unnormalised inverse of Eq. (delta_nr).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace bispec {
+
+template <typename R> struct cplx_of;
+template <> struct cplx_of<float> { using type = float2; };
+template <> struct cplx_of<double> { using type = double2; };
+template <typename R> using cplx = typename cplx_of<R>::type;
+
+template <typename C> __device__ __forceinline__ C cadd(C a, C b) { return C{a.x + b.x, a.y + b.y}; }
+template <typename C> __device__ __forceinline__ C csub(C a, C b) { return C{a.x - b.x, a.y - b.y}; }
+template <typename C> __device__ __forceinline__ C cmul(C a, C b) {
+    return C{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+template <typename C> __device__ __forceinline__ C cconj(C a) { return C{a.x, -a.y}; }
+// a * (DIR i)
+template <int DIR, typename C> __device__ __forceinline__ C mul_di(C a) {
+    return DIR > 0 ? C{-a.y, a.x} : C{a.y, -a.x};
+}
+
+template <int DIR, typename C> __device__ __forceinline__ void dft2(C *v) {
+    C a = v[0], b = v[1];
+    v[0] = cadd(a, b);
+    v[1] = csub(a, b);
+}
+
+template <int DIR, typename C> __device__ __forceinline__ void dft4(C *v) {
+    C a0 = cadd(v[0], v[2]), a1 = csub(v[0], v[2]);
+    C a2 = cadd(v[1], v[3]), a3 = mul_di<DIR>(csub(v[1], v[3]));
+    v[0] = cadd(a0, a2);
+    v[2] = csub(a0, a2);
+    v[1] = cadd(a1, a3);
+    v[3] = csub(a1, a3);
+}
+
+// y_u = sum_t x_t w8^(t u), w8 = exp(DIR 2 pi i / 8): split into even/odd
+// outputs, each a 4-point DFT of (x_t +- x_{t+4}) (odd ones twiddled by w8^t).
+template <int DIR, typename C> __device__ __forceinline__ void dft8(C *v) {
+    using R = decltype(v[0].x);
+    const R h = R(0.70710678118654752440084436210484904);
+    C a[4], b[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        a[t] = cadd(v[t], v[t + 4]);
+        b[t] = csub(v[t], v[t + 4]);
+    }
+    // b_t * w8^t : w8 = h (1 + DIR i), w8^2 = DIR i, w8^3 = h (-1 + DIR i)
+    {
+        C x = b[1];
+        C dx = mul_di<DIR>(x);
+        b[1] = C{h * (x.x + dx.x), h * (x.y + dx.y)};
+        b[2] = mul_di<DIR>(b[2]);
+        C y = b[3];
+        C dy = mul_di<DIR>(y);
+        b[3] = C{h * (dy.x - y.x), h * (dy.y - y.y)};
+    }
+    dft4<DIR>(a);
+    dft4<DIR>(b);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        v[2 * u] = a[u];
+        v[2 * u + 1] = b[u];
+    }
+}
+
+template <int RADIX, int DIR, typename C> __device__ __forceinline__ void dft_r(C *v) {
+    if constexpr (RADIX == 8) dft8<DIR>(v);
+    else if constexpr (RADIX == 4) dft4<DIR>(v);
+    else if constexpr (RADIX == 2) dft2<DIR>(v);
+}
+
+constexpr int ilog8_floor(int n) { return n >= 8 ? 1 + ilog8_floor(n / 8) : 0; }
+constexpr int ipow8(int p) { return p == 0 ? 1 : 8 * ipow8(p - 1); }
+
+// One Stockham pass over all G pencils of the block (256 threads).
+template <typename C, int N, int LD, int G, int DIR, int RADIX, int NS>
+__device__ __forceinline__ void stockham_pass(C *s, const C *tw) {
+    constexpr int NB = N / RADIX;          // butterflies per pencil
+    constexpr int TASKS = G * NB;
+    static_assert(TASKS % 256 == 0, "pencil group must fill the block");
+    constexpr int PER = TASKS / 256;
+    constexpr int TSTEP = N / (NS * RADIX);
+    const int tid = threadIdx.x;
+    C v[PER][RADIX];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int task = tid + q * 256;
+        const int p = task / NB, jj = task % NB;
+        const int k = jj % NS;
+#pragma unroll
+        for (int t = 0; t < RADIX; ++t) v[q][t] = s[p * LD + jj + t * NB];
+        if constexpr (NS > 1) {
+#pragma unroll
+            for (int t = 1; t < RADIX; ++t) {
+                C w = tw[(t * k * TSTEP) & (N - 1)];
+                if constexpr (DIR > 0) w = cconj(w);
+                v[q][t] = cmul(v[q][t], w);
+            }
+        }
+        dft_r<RADIX, DIR>(v[q]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int task = tid + q * 256;
+        const int p = task / NB, jj = task % NB;
+        const int k = jj % NS;
+        const int base = (jj / NS) * NS * RADIX + k;
+#pragma unroll
+        for (int u = 0; u < RADIX; ++u) s[p * LD + base + u * NS] = v[q][u];
+    }
+    __syncthreads();
+}
+
+// Full length-N transform of the G pencils held in s (row stride LD).
+// Expects s filled and a __syncthreads() issued by the caller; leaves the
+// result in s (natural order) followed by a barrier.
+template <typename C, int N, int LD, int G, int DIR>
+__device__ __forceinline__ void fft_pencils(C *s, const C *tw) {
+    constexpr int P8 = ilog8_floor(N);
+    constexpr int RL = N / ipow8(P8);
+    if constexpr (P8 >= 1) stockham_pass<C, N, LD, G, DIR, 8, 1>(s, tw);
+    if constexpr (P8 >= 2) stockham_pass<C, N, LD, G, DIR, 8, 8>(s, tw);
+    if constexpr (P8 >= 3) stockham_pass<C, N, LD, G, DIR, 8, 64>(s, tw);
+    if constexpr (P8 >= 4) stockham_pass<C, N, LD, G, DIR, 8, 512>(s, tw);
+    if constexpr (RL > 1) stockham_pass<C, N, LD, G, DIR, RL, ipow8(P8)>(s, tw);
+}
+
+// Pencils per block: at least one butterfly task per thread and at most
+// 64 KiB of LDS for the pencil tile.
+template <typename R, int N> constexpr int pencils_per_block() {
+    constexpr int bytes = (int)sizeof(R) * 2;
+    constexpr int by_lds = 65536 / (N * bytes);
+    constexpr int by_tasks = (2048 + N - 1) / N;
+    constexpr int want = by_tasks > 16 ? by_tasks : 16;
+    return want < by_lds ? want : by_lds;
+}
+
+}  // namespace bispec

@@ -1,0 +1,424 @@
+// kernels.hip -- HIP kernels of the FFT polyspectrum estimator (gfx950).
+//
+// Pipeline for one map (Watkinson et al. 2017, Section 2):
+//   k_sum_f64 / k_mean_final   FP64 mean of the FP32 input
+//   k_fwd_x, k_fft_strided     forward 3D DFT, Eq. (DeltaFFTtoDelta), FP32
+//   k_inv_z_gather             shell mask of two bins fused into the first
+//                              inverse pass (Eq. delta_nr): the two real bin
+//                              fields come out as the real and imaginary
+//                              parts of one complex inverse transform
+//   k_fft_strided, k_inv_x_split  remaining inverse passes; split re/im into
+//                              the two bin fields F_b
+//   k_contract_terms           sum_n of products of 2, 3 or 4 bin fields
+//                              (numerators and denominators of Eqs. Jeong_PS,
+//                              Jeong_BI, Jeong_gen), per-block FP64 partials
+//   k_finalize                 fixed-order FP64 cross-block sum and the
+//                              normalisation H^p / V over the FFT count
+//   k_shell_hist               modes per shell (wave ballot + popcount)
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <type_traits>
+
+#include "fft_core.hpp"
+#include "launch.hpp"
+
+namespace bispec {
+
+// ---------------------------------------------------------------------------
+// FP64 mean (block partials, then one block sums them in fixed order)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__global__ __launch_bounds__(256) void k_sum_f64(const float *__restrict__ x, int64_t n,
+                                                 int64_t map_stride, double *__restrict__ partial) {
+    const float *xm = x + (int64_t)blockIdx.y * map_stride;
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+        acc += (double)xm[i];
+    acc = wave_sum(acc);
+    __shared__ double red[4];
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0)
+        partial[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+__global__ __launch_bounds__(64) void k_mean_final(const double *__restrict__ partial, int nparts,
+                                                   double inv_n, double *__restrict__ mean) {
+    const double *p = partial + (int64_t)blockIdx.x * nparts;
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < nparts; i += 64) acc += p[i];
+    acc = wave_sum(acc);
+    if (threadIdx.x == 0) mean[blockIdx.x] = acc * inv_n;
+}
+
+// ---------------------------------------------------------------------------
+// FFT kernels.  Volumes are [z][y][x] with N^3 entries.
+// ---------------------------------------------------------------------------
+template <typename C, int N>
+__device__ __forceinline__ void load_twiddles(C *tw_s, const C *tw) {
+    for (int i = threadIdx.x; i < N; i += 256) tw_s[i] = tw[i];
+}
+
+// Forward pass along x: real input minus the FP64 mean, complex output.
+template <int N>
+__global__ __launch_bounds__(256) void k_fwd_x(const float *__restrict__ delta, const double *__restrict__ mean,
+                                               const float2 *__restrict__ tw, float2 *__restrict__ spec) {
+    constexpr int G = pencils_per_block<float, N>();
+    __shared__ float2 s[G * N];
+    __shared__ float2 tws[N];
+    load_twiddles<float2, N>(tws, tw);
+    const int64_t vol = (int64_t)N * N * N;
+    const int map = blockIdx.y;
+    const float *src = delta + map * vol;
+    float2 *dst = spec + map * vol;
+    const double mu = mean[map];
+    const int64_t row0 = (int64_t)blockIdx.x * G;
+    for (int e = threadIdx.x; e < G * N; e += 256) {
+        const double v = (double)src[row0 * N + e] - mu;
+        s[e] = float2{(float)v, 0.0f};
+    }
+    __syncthreads();
+    fft_pencils<float2, N, N, G, -1>(s, tws);
+    for (int e = threadIdx.x; e < G * N; e += 256) dst[row0 * N + e] = s[e];
+}
+
+// In-place transform along y (AXIS = 1) or z (AXIS = 2) of a complex volume.
+// A block takes G pencils that are adjacent in x, so every load and store
+// instruction touches contiguous runs of the x-fastest layout.
+template <typename R, int N, int DIR, int AXIS>
+__global__ __launch_bounds__(256) void k_fft_strided(cplx<R> *__restrict__ vol_base, const cplx<R> *__restrict__ tw,
+                                                     int64_t map_stride) {
+    using C = cplx<R>;
+    constexpr int G = pencils_per_block<R, N>();
+    __shared__ C s[G * N];
+    __shared__ C tws[N];
+    load_twiddles<C, N>(tws, tw);
+    C *v = vol_base + (int64_t)blockIdx.y * map_stride;
+    const int64_t p0 = (int64_t)blockIdx.x * G;   // first pencil (c * N + x)
+    const int64_t stride = AXIS == 1 ? N : (int64_t)N * N;
+    for (int e = threadIdx.x; e < G * N; e += 256) {
+        const int p = e % G, i = e / G;
+        const int64_t pl = p0 + p;
+        const int64_t c = pl / N, x = pl % N;
+        const int64_t addr = AXIS == 1 ? c * N * N + i * stride + x : (int64_t)i * stride + pl;
+        s[p * N + i] = v[addr];
+    }
+    __syncthreads();
+    fft_pencils<C, N, N, G, DIR>(s, tws);
+    for (int e = threadIdx.x; e < G * N; e += 256) {
+        const int p = e % G, i = e / G;
+        const int64_t pl = p0 + p;
+        const int64_t c = pl / N, x = pl % N;
+        const int64_t addr = AXIS == 1 ? c * N * N + i * stride + x : (int64_t)i * stride + pl;
+        v[addr] = s[p * N + i];
+    }
+}
+
+__device__ __forceinline__ int signed_freq(int i, int n) { return i < n / 2 ? i : i - n; }
+
+// First inverse pass (along z) with the shell masks of bins (b1, b2) applied
+// on load: value = [m in S_b1] Delta(m) + i [m in S_b2] Delta(m).  Since both
+// masked spectra are Hermitian, the 3D inverse transform is F_b1 + i F_b2.
+// UNIT = true sets Delta = 1 (the count fields I_b of Eq. delta_nr).
+template <typename R, int N, bool UNIT>
+__global__ __launch_bounds__(256) void k_inv_z_gather(const cplx<R> *__restrict__ spec, int64_t spec_stride,
+                                                      cplx<R> *__restrict__ out, int64_t out_stride,
+                                                      const cplx<R> *__restrict__ tw, int lo1, int hi1, int lo2,
+                                                      int hi2) {
+    using C = cplx<R>;
+    constexpr int G = pencils_per_block<R, N>();
+    __shared__ C s[G * N];
+    __shared__ C tws[N];
+    load_twiddles<C, N>(tws, tw);
+    const int map = blockIdx.y;
+    const C *sp = UNIT ? nullptr : spec + map * spec_stride;
+    C *o = out + map * out_stride;
+    const int64_t p0 = (int64_t)blockIdx.x * G;
+    const int64_t nn = (int64_t)N * N;
+    for (int e = threadIdx.x; e < G * N; e += 256) {
+        const int p = e % G, i = e / G;
+        const int64_t pl = p0 + p;
+        const int y = (int)(pl / N), x = (int)(pl % N);
+        const int mz = signed_freq(i, N), my = signed_freq(y, N), mx = signed_freq(x, N);
+        const int r2 = mz * mz + my * my + mx * mx;
+        const R in1 = (r2 >= lo1 && r2 < hi1) ? R(1) : R(0);
+        const R in2 = (r2 >= lo2 && r2 < hi2) ? R(1) : R(0);
+        C d;
+        if constexpr (UNIT) d = C{R(1), R(0)};
+        else d = (in1 != R(0) || in2 != R(0)) ? sp[(int64_t)i * nn + pl] : C{R(0), R(0)};
+        s[p * N + i] = C{d.x * in1 - d.y * in2, d.y * in1 + d.x * in2};
+    }
+    __syncthreads();
+    fft_pencils<C, N, N, G, +1>(s, tws);
+    for (int e = threadIdx.x; e < G * N; e += 256) {
+        const int p = e % G, i = e / G;
+        o[(int64_t)i * nn + p0 + p] = s[p * N + i];
+    }
+}
+
+// Last inverse pass (along x): real part -> F_b1, imaginary part -> F_b2
+// (skipped when f2 is null).
+template <typename R, int N>
+__global__ __launch_bounds__(256) void k_inv_x_split(const cplx<R> *__restrict__ in, int64_t in_stride,
+                                                     const cplx<R> *__restrict__ tw, R *__restrict__ f1,
+                                                     R *__restrict__ f2, int64_t field_stride) {
+    using C = cplx<R>;
+    constexpr int G = pencils_per_block<R, N>();
+    __shared__ C s[G * N];
+    __shared__ C tws[N];
+    load_twiddles<C, N>(tws, tw);
+    const int map = blockIdx.y;
+    const C *src = in + map * in_stride;
+    const int64_t row0 = (int64_t)blockIdx.x * G;
+    for (int e = threadIdx.x; e < G * N; e += 256) s[e] = src[row0 * N + e];
+    __syncthreads();
+    fft_pencils<C, N, N, G, +1>(s, tws);
+    R *d1 = f1 + map * field_stride;
+    for (int e = threadIdx.x; e < G * N; e += 256) d1[row0 * N + e] = s[e].x;
+    if (f2) {
+        R *d2 = f2 + map * field_stride;
+        for (int e = threadIdx.x; e < G * N; e += 256) d2[row0 * N + e] = s[e].y;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Product sums over the grid: term t multiplies the fields named by the four
+// bytes of terms[t] (0xFF = absent).  Block b sums the points
+// [b*chunk, (b+1)*chunk) and writes one FP64 partial per term.
+// FP32 inputs: products and per-tile (64 point) sums in FP32, then FP64.
+// ---------------------------------------------------------------------------
+constexpr int CT_TILE = 64;
+constexpr int CT_MAXT = 16;   // terms per thread per launch
+
+// Neumaier compensated addition: (s, c) += x.
+__device__ __forceinline__ void comp_add(double &s, double &c, double x) {
+    const double t = s + x;
+    c += fabs(s) >= fabs(x) ? (s - t) + x : (x - t) + s;
+    s = t;
+}
+
+// FP32 fields: products and per-tile (64 point) sums in FP32, then FP64.
+// FP64 fields (the count fields of the plan): every product is added with
+// compensated FP64 summation, so sums of integer-valued count products stay
+// exact well beyond 2^53 / N_pix.
+template <typename R>
+__global__ __launch_bounds__(256) void k_contract_terms(const R *__restrict__ fields, int64_t npix, int nb,
+                                                        int64_t map_stride, const uchar4 *__restrict__ terms,
+                                                        int t0, int nterm_launch, int nterm_total,
+                                                        int64_t chunk, double *__restrict__ partial) {
+    constexpr bool F64 = sizeof(R) == 8;
+    extern __shared__ unsigned char smem_raw[];
+    R *tile = reinterpret_cast<R *>(smem_raw);   // [CT_TILE][nb]
+    const int map = blockIdx.y;
+    const R *f = fields + map * map_stride;
+    const int64_t p_begin = (int64_t)blockIdx.x * chunk;
+    const int64_t p_end = p_begin + chunk < npix ? p_begin + chunk : npix;
+    uchar4 my_terms[CT_MAXT];
+    double acc[CT_MAXT], comp[CT_MAXT];
+    int nmine = 0;
+#pragma unroll
+    for (int q = 0; q < CT_MAXT; ++q) {
+        const int t = threadIdx.x + q * 256;
+        acc[q] = 0.0;
+        comp[q] = 0.0;
+        if (t < nterm_launch) {
+            my_terms[q] = terms[t0 + t];
+            nmine = q + 1;
+        } else {
+            my_terms[q] = uchar4{0xFF, 0xFF, 0xFF, 0xFF};
+        }
+    }
+    for (int64_t p = p_begin; p < p_end; p += CT_TILE) {
+        const int cnt = (int)((p_end - p) < CT_TILE ? (p_end - p) : CT_TILE);
+        __syncthreads();
+        for (int e = threadIdx.x; e < CT_TILE * nb; e += 256) {
+            const int b = e / CT_TILE, pt = e % CT_TILE;
+            tile[pt * nb + b] = pt < cnt ? f[(int64_t)b * npix + p + pt] : R(0);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < CT_MAXT; ++q) {
+            if (q >= nmine) break;
+            const uchar4 tm = my_terms[q];
+            R s = R(0);
+            for (int pt = 0; pt < CT_TILE; ++pt) {
+                const R *row = tile + pt * nb;
+                R v = row[tm.x] * row[tm.y];
+                if (tm.z != 0xFF) v *= row[tm.z];
+                if (tm.w != 0xFF) v *= row[tm.w];
+                if constexpr (F64) comp_add(acc[q], comp[q], v);
+                else s += v;
+            }
+            if constexpr (!F64) acc[q] += (double)s;
+        }
+    }
+    double *out = partial + ((int64_t)map * gridDim.x + blockIdx.x) * nterm_total + t0;
+#pragma unroll
+    for (int q = 0; q < CT_MAXT; ++q) {
+        const int t = threadIdx.x + q * 256;
+        if (t < nterm_launch) out[t] = acc[q] + comp[q];
+    }
+}
+
+// Fixed-order compensated FP64 sum over blocks, then scale: out = scale[t] * sum.
+// Terms [0, n0) go to o0, [n0, n0+n1) to o1, [n0+n1, n0+n1+n2) to o2.
+__global__ __launch_bounds__(256) void k_finalize(const double *__restrict__ partial, int nblk, int nterm,
+                                                  const double *__restrict__ scale, double *o0, int n0,
+                                                  double *o1, int n1, double *o2, int n2) {
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    const int map = blockIdx.y;
+    if (t >= nterm) return;
+    const double *p = partial + (int64_t)map * nblk * nterm + t;
+    double acc = 0.0, comp = 0.0;
+    for (int b = 0; b < nblk; ++b) comp_add(acc, comp, p[(int64_t)b * nterm]);
+    const double v = (acc + comp) * scale[t];
+    if (t < n0) {
+        if (o0) o0[(int64_t)map * n0 + t] = v;
+    } else if (t < n0 + n1) {
+        if (o1) o1[(int64_t)map * n1 + (t - n0)] = v;
+    } else if (t < n0 + n1 + n2) {
+        if (o2) o2[(int64_t)map * n2 + (t - n0 - n1)] = v;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Modes per shell: each thread classifies one grid mode; a wave ballot and a
+// popcount give the wave's count per bin, one integer atomic per wave.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_shell_hist(int n, int nb, const int *__restrict__ lo2,
+                                                    const int *__restrict__ hi2,
+                                                    unsigned long long *__restrict__ counts) {
+    const int64_t vol = (int64_t)n * n * n;
+    const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    int r2 = -1;
+    if (g < vol) {
+        const int x = (int)(g % n), y = (int)((g / n) % n), z = (int)(g / ((int64_t)n * n));
+        const int mz = signed_freq(z, n), my = signed_freq(y, n), mx = signed_freq(x, n);
+        r2 = mz * mz + my * my + mx * mx;
+    }
+    for (int b = 0; b < nb; ++b) {
+        const bool in = r2 > 0 && r2 >= lo2[b] && r2 < hi2[b];
+        const unsigned long long m = __ballot(in);
+        if ((threadIdx.x & 63) == 0 && m) atomicAdd(&counts[b], (unsigned long long)__popcll(m));
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Host launchers
+// ---------------------------------------------------------------------------
+
+// Runs f(std::integral_constant<int, N>) for the supported grid sides.
+template <class F> hipError_t dispatch_n(int n, F &&f) {
+    switch (n) {
+        case 8: f(std::integral_constant<int, 8>{}); break;
+        case 16: f(std::integral_constant<int, 16>{}); break;
+        case 32: f(std::integral_constant<int, 32>{}); break;
+        case 64: f(std::integral_constant<int, 64>{}); break;
+        case 128: f(std::integral_constant<int, 128>{}); break;
+        case 256: f(std::integral_constant<int, 256>{}); break;
+        case 512: f(std::integral_constant<int, 512>{}); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_mean(const float *x, int n, int batch, double *partial, int nparts, double *mean,
+                       hipStream_t st) {
+    const int64_t vol = (int64_t)n * n * n;
+    hipLaunchKernelGGL(k_sum_f64, dim3(nparts, batch), dim3(256), 0, st, x, vol, vol, partial);
+    hipLaunchKernelGGL(k_mean_final, dim3(batch), dim3(64), 0, st, partial, nparts, 1.0 / (double)vol, mean);
+    return hipGetLastError();
+}
+
+hipError_t launch_forward(const float *delta, const double *mean, int n, int batch, const float2 *tw,
+                          float2 *spec, hipStream_t st) {
+    const int64_t vol = (int64_t)n * n * n;
+    return dispatch_n(n, [&](auto nc) {
+        constexpr int NN = decltype(nc)::value;
+        constexpr int G = pencils_per_block<float, NN>();
+        const int nblk = NN * NN / G;
+        hipLaunchKernelGGL((k_fwd_x<NN>), dim3(nblk, batch), dim3(256), 0, st, delta, mean, tw, spec);
+        hipLaunchKernelGGL((k_fft_strided<float, NN, -1, 1>), dim3(nblk, batch), dim3(256), 0, st, spec, tw, vol);
+        hipLaunchKernelGGL((k_fft_strided<float, NN, -1, 2>), dim3(nblk, batch), dim3(256), 0, st, spec, tw, vol);
+    });
+}
+
+template <typename R>
+hipError_t launch_inverse_pair_t(const cplx<R> *spec, int64_t spec_stride, int n, int batch, const cplx<R> *tw,
+                                 int lo1, int hi1, int lo2, int hi2, cplx<R> *scratch, int64_t scratch_stride,
+                                 R *f1, R *f2, int64_t field_stride, hipStream_t st) {
+    return dispatch_n(n, [&](auto nc) {
+        constexpr int NN = decltype(nc)::value;
+        constexpr int G = pencils_per_block<R, NN>();
+        const int nblk = NN * NN / G;
+        if (spec)
+            hipLaunchKernelGGL((k_inv_z_gather<R, NN, false>), dim3(nblk, batch), dim3(256), 0, st, spec,
+                               spec_stride, scratch, scratch_stride, tw, lo1, hi1, lo2, hi2);
+        else
+            hipLaunchKernelGGL((k_inv_z_gather<R, NN, true>), dim3(nblk, batch), dim3(256), 0, st, spec,
+                               spec_stride, scratch, scratch_stride, tw, lo1, hi1, lo2, hi2);
+        hipLaunchKernelGGL((k_fft_strided<R, NN, +1, 1>), dim3(nblk, batch), dim3(256), 0, st, scratch, tw,
+                           scratch_stride);
+        hipLaunchKernelGGL((k_inv_x_split<R, NN>), dim3(nblk, batch), dim3(256), 0, st, scratch, scratch_stride,
+                           tw, f1, f2, field_stride);
+    });
+}
+
+hipError_t launch_inverse_pair(const float2 *spec, int64_t spec_stride, int n, int batch, const float2 *tw,
+                               int lo1, int hi1, int lo2, int hi2, float2 *scratch, int64_t scratch_stride,
+                               float *f1, float *f2, int64_t field_stride, hipStream_t st) {
+    return launch_inverse_pair_t<float>(spec, spec_stride, n, batch, tw, lo1, hi1, lo2, hi2, scratch,
+                                        scratch_stride, f1, f2, field_stride, st);
+}
+
+hipError_t launch_inverse_pair_unit_f64(int n, const double2 *tw, int lo1, int hi1, int lo2, int hi2,
+                                        double2 *scratch, double *f1, double *f2, hipStream_t st) {
+    const int64_t vol = (int64_t)n * n * n;
+    return launch_inverse_pair_t<double>(nullptr, 0, n, 1, tw, lo1, hi1, lo2, hi2, scratch, vol, f1, f2, vol, st);
+}
+
+template <typename R>
+hipError_t launch_contract_terms_t(const R *fields, int64_t npix, int nb, int64_t map_stride, int batch,
+                                   const uchar4 *terms, int nterm, int nblk, double *partial, hipStream_t st) {
+    const int64_t chunk = ((npix + nblk - 1) / nblk + CT_TILE - 1) / CT_TILE * CT_TILE;
+    const size_t smem = (size_t)CT_TILE * nb * sizeof(R);
+    for (int t0 = 0; t0 < nterm; t0 += 256 * CT_MAXT) {
+        const int nt = nterm - t0 < 256 * CT_MAXT ? nterm - t0 : 256 * CT_MAXT;
+        hipLaunchKernelGGL(k_contract_terms<R>, dim3(nblk, batch), dim3(256), smem, st, fields, npix, nb, map_stride,
+                           terms, t0, nt, nterm, chunk, partial);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_contract_terms_f32(const float *fields, int64_t npix, int nb, int64_t map_stride, int batch,
+                                     const uchar4 *terms, int nterm, int nblk, double *partial, hipStream_t st) {
+    return launch_contract_terms_t<float>(fields, npix, nb, map_stride, batch, terms, nterm, nblk, partial, st);
+}
+
+hipError_t launch_contract_terms_f64(const double *fields, int64_t npix, int nb, const uchar4 *terms, int nterm,
+                                     int nblk, double *partial, hipStream_t st) {
+    return launch_contract_terms_t<double>(fields, npix, nb, npix * nb, 1, terms, nterm, nblk, partial, st);
+}
+
+hipError_t launch_finalize(const double *partial, int nblk, int nterm, int batch, const double *scale, double *o0,
+                           int n0, double *o1, int n1, double *o2, int n2, hipStream_t st) {
+    hipLaunchKernelGGL(k_finalize, dim3((nterm + 255) / 256, batch), dim3(256), 0, st, partial, nblk, nterm, scale,
+                       o0, n0, o1, n1, o2, n2);
+    return hipGetLastError();
+}
+
+hipError_t launch_shell_hist(int n, int nb, const int *lo2, const int *hi2, unsigned long long *counts,
+                             hipStream_t st) {
+    const int64_t vol = (int64_t)n * n * n;
+    const int nblk = (int)((vol + 255) / 256);
+    hipLaunchKernelGGL(k_shell_hist, dim3(nblk), dim3(256), 0, st, n, nb, lo2, hi2, counts);
+    return hipGetLastError();
+}
+
+}  // namespace bispec

@@ -1,0 +1,50 @@
+// launch.hpp -- host launchers of the estimator kernels (internal to libbispec).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace bispec {
+
+hipError_t launch_mean(const float *x, int n, int batch, double *partial, int nparts, double *mean, hipStream_t st);
+
+// Forward 3D DFT of batch maps (mean subtracted on load) into full complex spectra.
+hipError_t launch_forward(const float *delta, const double *mean, int n, int batch, const float2 *tw,
+                          float2 *spec, hipStream_t st);
+
+// Inverse transform of the shell-masked spectrum of bins (b1, b2) given by
+// integer |m|^2 thresholds [lo, hi); writes F_b1 to f1 and F_b2 to f2 (f2 may
+// be null, then pass lo2 = hi2 = 0).
+hipError_t launch_inverse_pair(const float2 *spec, int64_t spec_stride, int n, int batch, const float2 *tw,
+                               int lo1, int hi1, int lo2, int hi2, float2 *scratch, int64_t scratch_stride,
+                               float *f1, float *f2, int64_t field_stride, hipStream_t st);
+
+// Unit-amplitude (count) fields I_b in FP64.
+hipError_t launch_inverse_pair_unit_f64(int n, const double2 *tw, int lo1, int hi1, int lo2, int hi2,
+                                        double2 *scratch, double *f1, double *f2, hipStream_t st);
+
+hipError_t launch_contract_terms_f32(const float *fields, int64_t npix, int nb, int64_t map_stride, int batch,
+                                     const uchar4 *terms, int nterm, int nblk, double *partial, hipStream_t st);
+hipError_t launch_contract_terms_f64(const double *fields, int64_t npix, int nb, const uchar4 *terms, int nterm,
+                                     int nblk, double *partial, hipStream_t st);
+
+hipError_t launch_finalize(const double *partial, int nblk, int nterm, int batch, const double *scale, double *o0,
+                           int n0, double *o1, int n1, double *o2, int n2, hipStream_t st);
+
+// Product-Gram contraction on MFMA (mfma.hip).  pairs: [n_mtile*32] row
+// factors (field row indices; 32 = zeros, 33 = ones).  partial:
+// [batch][nblk][n_mtile + want_t][32][32] FP64.
+constexpr int PG_MODE_F32 = 0;
+constexpr int PG_MODE_SPLIT = 1;
+constexpr int PG_ROW_ZERO = 32;
+constexpr int PG_ROW_ONE = 33;
+size_t pgram_partial_doubles(int n_mtile, bool want_t);
+hipError_t launch_pgram(int mode, bool want_t, const float *fields, int64_t npix, int nb, int64_t map_stride,
+                        int batch, const uchar2 *pairs, int n_mtile, int nblk, double *partial, hipStream_t st);
+hipError_t launch_finalize_gather(const double *partial, int nblk, int64_t blk_stride, const int *idx, int nterm,
+                                  int batch, const double *scale, double *o0, int n0, double *o1, int n1, double *o2,
+                                  int n2, hipStream_t st);
+
+hipError_t launch_shell_hist(int n, int nb, const int *lo2, const int *hi2, unsigned long long *counts,
+                             hipStream_t st);
+
+}  // namespace bispec

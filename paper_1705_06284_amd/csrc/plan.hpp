@@ -1,0 +1,53 @@
+// plan.hpp -- host-side plan state of libbispec (internal).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <vector>
+
+struct bispec_plan_s {
+    int n = 0;                 // grid side N
+    double box_len = 0;        // L (V = L^3)
+    int nb = 0;                // bins
+    std::vector<double> lo, hi;          // edges in k_f units
+    std::vector<int> ilo2, ihi2;         // member iff ilo2 <= |m|^2 < ihi2 (integers)
+    std::vector<int64_t> modes;          // M_b
+    std::vector<int> tri;                // [n_tri][3]
+    std::vector<double> tri_count;       // N_t (exact integers)
+    std::vector<int> quad;               // [n_quad][4]
+    std::vector<double> quad_count;      // N_q
+    int precision = 0;
+    int max_batch = 1;
+    hipStream_t stream = nullptr;
+    void *ws = nullptr;
+    size_t ws_bytes = 0;
+    int nblk = 1;                        // blocks of the term contraction
+    std::vector<uchar4> terms;           // [triplets | (b,b) | quads]
+    std::vector<double> scale;           // normalisation over the FFT count, per term
+    // product-Gram (MFMA) contraction
+    bool mfma_ok = false;                // n_bins <= 32
+    bool quads_collapsed = false;        // every quad is (a,a,b,b) up to order
+    int n_mtile = 0;                     // 32-row tiles of pair rows
+    int nblk_pg = 1;                     // blocks of the product-Gram kernel
+    std::vector<uchar2> pg_pairs;        // [n_mtile*32] row factors
+    std::vector<int> pg_idx;             // per term: index into a block's dense tiles
+    // stage timing: one event per stage boundary per call
+    bool timing = false;
+    std::vector<hipEvent_t> ev_pool;     // free events
+    std::vector<hipEvent_t> ev_rec;      // 5 per recorded call
+    hipEvent_t ev_cur[5] = {};
+    ~bispec_plan_s();
+};
+
+namespace bispec {
+
+// Byte offsets of the workspace regions (256-byte aligned).
+struct Layout {
+    size_t tw, terms, scale, pg_pairs, pg_idx, mean_partial, mean, spec, scratch, fields, partial, pg_partial,
+        total;
+};
+
+Layout make_layout(const bispec_plan_s &p, int batch);
+
+}  // namespace bispec

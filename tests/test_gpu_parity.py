@@ -1,0 +1,181 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Metric (per result): err = |X_gpu - X_oracle| / max(|X_oracle|, X_noise),
+with X_noise = norm * sqrt(sum |product|^2) / count from the oracle (the
+random-phase noise level of the mean over closed tuples).  FP32 contraction:
+err <= 1e-5; split-BF16 contraction: err <= 1e-4.  P is positive, so plain
+relative error applies.  Tuple counts are integers and must match exactly.
+"""
+import itertools
+import os
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import oracle  # noqa: E402
+from paper_1705_06284_amd import synth  # noqa: E402
+
+TOL = {"fp32": 1e-5, "split_bf16": 1e-4}
+
+
+@pytest.fixture(scope="module")
+def binding():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1705_06284_amd import binding as b
+    return b
+
+
+def _err(got, ref):
+    return np.abs(got - ref.value) / np.maximum(np.abs(ref.value), ref.noise)
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "split_bf16"])
+def test_c1_equilateral_power_32(binding, prec):
+    n = 32
+    lo, hi = synth.unit_bins(1, 8)
+    trip = np.array([(b, b, b) for b in range(8)], np.int32)
+    d = synth.local_quadratic_field(n, 2.0, 0.1, 0.5, seed=1)
+    _say("c1 32^3 equilateral %s" % prec)
+    plan = binding.Plan(n, lo, hi, triplets=trip, precision=prec)
+    B, P = plan.estimate(d)
+    ref = oracle.bispectrum(d, lo, hi, trip)
+    refp, m = oracle.power_spectrum(d, lo, hi)
+    assert np.array_equal(plan.counts.astype(np.int64), ref.count)
+    assert np.array_equal(plan.mode_counts, m)
+    assert np.max(_err(B.cpu().numpy()[0], ref)) <= TOL[prec]
+    assert np.max(np.abs(P.cpu().numpy()[0] - refp) / refp) <= TOL[prec]
+
+
+@pytest.mark.parametrize("n,nb", [(16, 4), (32, 6), (32, 8)])
+def test_auto_triplet_set_and_counts(binding, n, nb):
+    lo, hi = synth.linear_bins(n, nb)
+    _say("auto triplets n=%d nb=%d" % (n, nb))
+    plan = binding.Plan(n, lo, hi, precision="fp32")
+    want, cnt = oracle.closed_triplets(n, lo, hi)
+    got = plan.triplets
+    assert np.array_equal(got, want)
+    assert np.array_equal(plan.counts.astype(np.int64), cnt)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "split_bf16"])
+def test_all_triplets_lognormal_32(binding, prec):
+    n = 32
+    lo, hi = synth.linear_bins(n, 8)
+    d = synth.lognormal_field(n, 1.5, 1.0, seed=12)
+    _say("all triplets 32^3 %s" % prec)
+    plan = binding.Plan(n, lo, hi, precision=prec)
+    P, B, T = plan.polyspec(d)
+    ref = oracle.bispectrum(d, lo, hi, plan.triplets)
+    e = _err(B.cpu().numpy()[0], ref)
+    assert np.max(e) <= TOL[prec], (np.max(e), plan.triplets[np.argmax(e)])
+    refp, _ = oracle.power_spectrum(d, lo, hi)
+    assert np.max(np.abs(P.cpu().numpy()[0] - refp) / refp) <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["fp32", "split_bf16"])
+def test_collapsed_trispectrum_32(binding, prec):
+    n = 32
+    lo, hi = synth.linear_bins(n, 6)
+    d = synth.lognormal_field(n, 1.5, 1.0, seed=5)
+    _say("collapsed trispectrum 32^3 %s" % prec)
+    plan = binding.Plan(n, lo, hi, precision=prec)
+    quads = plan.quads
+    assert len(quads) == 21
+    T = plan.trispec(d).cpu().numpy()[0]
+    sel = [q for q in range(len(quads)) if quads[q][0] <= 1 and quads[q][2] <= 2]
+    ref = oracle.trispectrum(d, lo, hi, quads[sel])
+    assert np.array_equal(plan.quad_counts[sel].astype(np.int64), ref.count)
+    assert np.max(_err(T[sel], ref)) <= TOL[prec]
+
+
+def test_bin_fields_match_masked_inverse_dft(binding):
+    n = 32
+    lo, hi = np.array([1.0, 4.0, 9.0]), np.array([4.0, 9.0, 16.0])     # odd bin count
+    d = synth.lognormal_field(n, 1.0, 0.7, seed=8)
+    _say("bin fields 32^3")
+    plan = binding.Plan(n, lo, hi, precision="fp32")
+    F = plan.bin_fields(d).cpu().numpy()[0].astype(np.float64)
+    D = oracle.dft3(oracle.prepare(d))
+    f = oracle.freq(n)
+    r2 = f[:, None, None] ** 2 + f[None, :, None] ** 2 + f[None, None, :] ** 2
+    for b in range(3):
+        M = (r2 > 0) & (r2 >= lo[b] ** 2) & (r2 < hi[b] ** 2)
+        ref = np.fft.ifftn(D * M).real * n ** 3       # unnormalised inverse
+        assert np.max(np.abs(F[b] - ref)) <= 2e-6 * np.max(np.abs(ref))
+
+
+def test_batch_equals_single_maps(binding):
+    n = 32
+    lo, hi = synth.linear_bins(n, 5)
+    maps = np.stack([synth.lognormal_field(n, 1.5, 1.0, seed=s) for s in (1, 2, 3)])
+    _say("batch of 3 vs single")
+    plan = binding.Plan(n, lo, hi, precision="fp32", max_batch=3)
+    P, B, T = plan.polyspec(maps)
+    for i in range(3):
+        p1, b1, t1 = plan.polyspec(maps[i])
+        assert torch.equal(B[i], b1[0]) and torch.equal(P[i], p1[0]) and torch.equal(T[i], t1[0])
+
+
+def test_overlapping_bins_and_explicit_zero_count(binding):
+    """Squeezed configurations with a one-pixel k3 shell that overlaps bin 0,
+    and an explicit triplet with no closed triangle (NaN)."""
+    n = 64
+    lo, hi = synth.linear_bins(n, 12)
+    lo = np.append(lo, 0.5)
+    hi = np.append(hi, 1.5)
+    sq = 12
+    trip = [(b, b, b) for b in range(12)] + [(b, b, sq) for b in range(12)] + [(0, 0, 11)]
+    d = synth.lognormal_field(n, 1.5, 1.0, seed=5001)
+    _say("squeezed + overlapping bins 64^3")
+    plan = binding.Plan(n, lo, hi, triplets=trip, precision="fp32")
+    B, P = plan.estimate(d)
+    b = B.cpu().numpy()[0]
+    assert np.isnan(b[-1]) and plan.counts[-1] == 0
+    ref = oracle.bispectrum(d, lo, hi, trip[:-1])
+    assert np.max(_err(b[:-1], ref)) <= TOL["fp32"]
+
+
+def _cheap_triplets(n, lo, hi, trip, budget):
+    """Triplets whose direct sum the oracle finishes within `budget` pair steps
+    in total: the oracle loops over the two smallest shells of a triplet, and
+    triplets sharing that pair share one loop."""
+    m = oracle.mode_counts(n, lo, hi)
+    pair = [tuple(sorted(t, key=lambda b: (m[b], b))[:2]) for t in trip]
+    cost = {p: float(m[p[0]]) * float(m[p[1]]) for p in set(pair)}
+    keep, used = set(), 0.0
+    for p in sorted(cost, key=lambda p: cost[p]):
+        if used + cost[p] > budget:
+            break
+        keep.add(p)
+        used += cost[p]
+    return trip[[p in keep for p in pair]]
+
+
+@pytest.mark.parametrize("prec", ["fp32", "split_bf16"])
+def test_c2_lognormal_128_sampled(binding, prec):
+    n = 128
+    lo, hi = synth.workload_bins("c2_128_lognormal")
+    d = synth.workload_field("c2_128_lognormal")
+    _say("c2 128^3 sampled %s" % prec)
+    plan = binding.Plan(n, lo, hi, precision=prec)
+    P, B, T = plan.polyspec(d, want_t=False)
+    trip = plan.triplets
+    assert len(trip) == 508
+    sel = _cheap_triplets(n, lo, hi, trip, 2e9)
+    idx = [int(np.flatnonzero((trip == t).all(1))[0]) for t in sel]
+    Dk = oracle.dft3(oracle.prepare(d))
+    ref = oracle.bispectrum(d, lo, hi, sel, delta_k=Dk)
+    assert np.array_equal(plan.counts[idx].astype(np.int64), ref.count)
+    e = _err(B.cpu().numpy()[0][idx], ref)
+    _say("  %d sampled triplets, max err %.2e" % (len(sel), e.max()))
+    assert np.max(e) <= TOL[prec]
+    refp, _ = oracle.power_spectrum(d, lo, hi, delta_k=Dk)
+    assert np.max(np.abs(P.cpu().numpy()[0] - refp) / refp) <= TOL[prec]
