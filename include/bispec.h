@@ -161,6 +161,10 @@ bispec_status bispec_timing_read(bispec_plan_t plan, double *stage_ms /*[BISPEC_
 bispec_status bispec_destroy(bispec_plan_t plan);
 const char *bispec_status_string(bispec_status status);
 
+/* Text of the last failure seen by the calling thread (the HIP call or
+ * allocation and its runtime message); empty if none. */
+const char *bispec_last_error(void);
+
 #ifdef __cplusplus
 }
 #endif

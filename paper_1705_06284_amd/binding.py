@@ -68,6 +68,8 @@ for _name, _args in _SIGS.items():
     _f.restype = ctypes.c_int
 _lib.bispec_status_string.argtypes = [ctypes.c_int]
 _lib.bispec_status_string.restype = ctypes.c_char_p
+_lib.bispec_last_error.argtypes = []
+_lib.bispec_last_error.restype = ctypes.c_char_p
 
 # The C entry points under their own names.
 bispec_plan = _lib.bispec_plan
@@ -88,13 +90,15 @@ bispec_destroy = _lib.bispec_destroy
 N_STAGES = 4
 STAGES = ("forward", "inverse", "contract", "finalize")
 bispec_status_string = _lib.bispec_status_string
+bispec_last_error = _lib.bispec_last_error
 
 
 class BispecError(RuntimeError):
     def __init__(self, code, where):
         self.code = code
-        super().__init__("%s: %s (%s)" % (where, STATUS.get(code, code),
-                                         bispec_status_string(code).decode()))
+        detail = bispec_last_error().decode()
+        super().__init__("%s: %s (%s)%s" % (where, STATUS.get(code, code), bispec_status_string(code).decode(),
+                                           (" [" + detail + "]") if detail else ""))
 
 
 def check(code, where):
@@ -128,6 +132,10 @@ class Plan:
         import torch
         self._torch = torch
         self.device = torch.device(device)
+        if self.device.type != "cuda":
+            raise ValueError("the estimator runs on a GPU device only")
+        torch.cuda.init()
+        torch.empty(1, device=self.device)        # HIP context current before the library's first call
         self.n = int(n)
         self.k_lo = _arr(k_lo, np.float64)
         self.k_hi = _arr(k_hi, np.float64)

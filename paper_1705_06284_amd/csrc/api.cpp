@@ -11,6 +11,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
+#include <cstdio>
 #include <cstring>
 #include <limits>
 #include <new>
@@ -31,9 +32,18 @@ inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 bool is_pow2_in_range(int n) { return n >= 8 && n <= 512 && (n & (n - 1)) == 0; }
 
-#define CK(call)                                   \
-    do {                                           \
-        if ((call) != hipSuccess) return BISPEC_E_HIP; \
+// Text of the last failure on this thread (bispec_last_error).
+thread_local char g_last_error[512] = "";
+
+bispec_status record(bispec_status s, const char *what, hipError_t e) {
+    std::snprintf(g_last_error, sizeof(g_last_error), "%s: %s", what, hipGetErrorString(e));
+    return s;
+}
+
+#define CK(call)                                                        \
+    do {                                                                \
+        const hipError_t ck_e_ = (call);                                \
+        if (ck_e_ != hipSuccess) return record(BISPEC_E_HIP, #call, ck_e_); \
     } while (0)
 
 int contract_blocks(int64_t npix) {
@@ -61,10 +71,12 @@ Layout make_layout(const bispec_plan_s &p, int batch) {
     L.scale = off;        off = align_up(off + sizeof(double) * p.scale.size());
     L.pg_pairs = off;     off = align_up(off + sizeof(uchar2) * p.pg_pairs.size());
     L.pg_idx = off;       off = align_up(off + sizeof(int) * p.pg_idx.size());
+    L.cols = off;         off = align_up(off + sizeof(int) * p.cols.size());
     L.mean_partial = off; off = align_up(off + sizeof(double) * kMeanParts * batch);
     L.mean = off;         off = align_up(off + sizeof(double) * batch);
     L.spec = off;         off = align_up(off + sizeof(float2) * vol * batch);
-    L.scratch = off;      off = align_up(off + sizeof(float2) * vol * batch);
+    L.abox = off;         off = align_up(off + sizeof(float2) * (size_t)p.n * p.wmax * p.wmax * batch);
+    L.bc = off;           off = align_up(off + sizeof(float2) * (size_t)p.n * p.n * p.wsum * batch);
     L.fields = off;       off = align_up(off + sizeof(float) * vol * p.nb * batch);
     L.partial = off;      off = align_up(off + sizeof(double) * (size_t)p.nblk * p.terms.size() * batch);
     L.pg_partial = off;
@@ -115,6 +127,40 @@ void stamp_rest(bispec_plan_s &p, int from) {
     if (!p.timing) return;
     for (int k = from; k <= 4; ++k)
         if (!p.ev_cur[k]) stamp(p, k);
+}
+
+// Shell pairs (2q, 2q+1) of the pruned inverse transform and the list of
+// z-pass columns (m_y, m_x) with m_y^2 + m_x^2 < hmax of each pair.
+void build_pairs(bispec_plan_s &p) {
+    p.pairs.clear();
+    p.cols.clear();
+    p.col_off.clear();
+    p.col_n.clear();
+    p.bc_off.clear();
+    p.wmax = 1;
+    p.wsum = 0;
+    for (int b = 0; b < p.nb; b += 2) {
+        PairGeom g{};
+        g.lo1 = p.ilo2[b];
+        g.hi1 = p.ihi2[b];
+        const bool two = b + 1 < p.nb;
+        g.lo2 = two ? p.ilo2[b + 1] : 0;
+        g.hi2 = two ? p.ihi2[b + 1] : 0;
+        g.hmax = std::max(g.hi1, g.hi2);
+        int r = 0;
+        while ((int64_t)(r + 1) * (r + 1) < g.hmax) ++r;   // largest r with r^2 < hmax
+        g.R = r;
+        g.W = 2 * r + 1;
+        p.col_off.push_back((int)p.cols.size());
+        for (int my = -r; my <= r; ++my)
+            for (int mx = -r; mx <= r; ++mx)
+                if (my * my + mx * mx < g.hmax) p.cols.push_back((my + r) * g.W + (mx + r));
+        p.col_n.push_back((int)p.cols.size() - p.col_off.back());
+        p.bc_off.push_back(p.wsum);
+        p.wsum += g.W;
+        p.wmax = std::max(p.wmax, g.W);
+        p.pairs.push_back(g);
+    }
 }
 
 // Rows of the product-Gram: pairs (i,j), i <= j, ordered by j then i; then
@@ -226,12 +272,19 @@ bispec_status compute_counts(bispec_plan_s &p, std::vector<int> &cand_tri, std::
     const size_t o_ones = off;    off = align_up(off + sizeof(double) * nterm);
     const size_t o_sums = off;    off = align_up(off + sizeof(double) * nterm);
     const size_t o_partial = off; off = align_up(off + sizeof(double) * (size_t)nblk * nterm);
-    const size_t o_scratch = off; off = align_up(off + sizeof(double2) * vol);
+    const size_t o_cols = off;    off = align_up(off + sizeof(int) * p.cols.size());
+    const size_t o_abox = off;    off = align_up(off + sizeof(double2) * (size_t)n * p.wmax * p.wmax);
+    const size_t o_bc = off;      off = align_up(off + sizeof(double2) * (size_t)n * n * p.wmax);
     const size_t o_fields = off;  off = align_up(off + sizeof(double) * vol * nb);
     char *mem = nullptr;
-    if (hipMalloc((void **)&mem, off) != hipSuccess) {
-        (void)hipGetLastError();
-        return BISPEC_E_OOM;
+    {
+        const hipError_t e = hipMalloc((void **)&mem, off);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            char what[128];
+            std::snprintf(what, sizeof(what), "hipMalloc of %zu bytes for the count fields", off);
+            return record(BISPEC_E_OOM, what, e);
+        }
     }
     struct Free {
         char *m;
@@ -242,13 +295,14 @@ bispec_status compute_counts(bispec_plan_s &p, std::vector<int> &cand_tri, std::
     CK(hipMemcpyAsync(mem + o_tw, tw.data(), sizeof(double2) * n, hipMemcpyHostToDevice, st));
     CK(hipMemcpyAsync(mem + o_terms, terms.data(), sizeof(uchar4) * nterm, hipMemcpyHostToDevice, st));
     CK(hipMemcpyAsync(mem + o_ones, ones.data(), sizeof(double) * nterm, hipMemcpyHostToDevice, st));
+    CK(hipMemcpyAsync(mem + o_cols, p.cols.data(), sizeof(int) * p.cols.size(), hipMemcpyHostToDevice, st));
     double *fields = (double *)(mem + o_fields);
-    for (int b = 0; b < nb; b += 2) {
-        const bool two = b + 1 < nb;
-        CK(launch_inverse_pair_unit_f64(n, (const double2 *)(mem + o_tw), p.ilo2[b], p.ihi2[b],
-                                        two ? p.ilo2[b + 1] : 0, two ? p.ihi2[b + 1] : 0,
-                                        (double2 *)(mem + o_scratch), fields + (int64_t)b * vol,
-                                        two ? fields + (int64_t)(b + 1) * vol : nullptr, st));
+    for (size_t q = 0; q < p.pairs.size(); ++q) {
+        const int b = 2 * (int)q;
+        CK(launch_inverse_unit_f64(n, (const double2 *)(mem + o_tw), p.pairs[q], (const int *)(mem + o_cols) + p.col_off[q],
+                                   p.col_n[q], (double2 *)(mem + o_abox), (double2 *)(mem + o_bc),
+                                   fields + (int64_t)b * vol, b + 1 < nb ? fields + (int64_t)(b + 1) * vol : nullptr,
+                                   st));
     }
     CK(launch_contract_terms_f64(fields, vol, nb, (const uchar4 *)(mem + o_terms), nterm, nblk,
                                  (double *)(mem + o_partial), st));
@@ -325,11 +379,12 @@ bispec_status plan_impl(const bispec_plan_desc *d, bispec_plan_t *out) {
     {
         int *thr = nullptr;
         unsigned long long *cnt = nullptr;
-        if (hipMalloc((void **)&thr, sizeof(int) * 2 * nb) != hipSuccess ||
-            hipMalloc((void **)&cnt, sizeof(unsigned long long) * nb) != hipSuccess) {
+        hipError_t e = hipMalloc((void **)&thr, sizeof(int) * 2 * nb);
+        if (e == hipSuccess) e = hipMalloc((void **)&cnt, sizeof(unsigned long long) * nb);
+        if (e != hipSuccess) {
             (void)hipFree(thr);
             (void)hipGetLastError();
-            return BISPEC_E_OOM;
+            return record(BISPEC_E_OOM, "hipMalloc of the shell tables", e);
         }
         std::vector<int> th(p->ilo2);
         th.insert(th.end(), p->ihi2.begin(), p->ihi2.end());
@@ -342,7 +397,7 @@ bispec_status plan_impl(const bispec_plan_desc *d, bispec_plan_t *out) {
                   hipStreamSynchronize(p->stream) == hipSuccess;
         (void)hipFree(thr);
         (void)hipFree(cnt);
-        if (!ok) return BISPEC_E_HIP;
+        if (!ok) return record(BISPEC_E_HIP, "modes-per-shell pass", hipGetLastError());
         for (int b = 0; b < nb; ++b) {
             p->modes.push_back((int64_t)hc[b]);
             if (hc[b] == 0) return BISPEC_E_EMPTY_BIN;
@@ -376,6 +431,7 @@ bispec_status plan_impl(const bispec_plan_desc *d, bispec_plan_t *out) {
         p->quad.assign(d->quad, d->quad + 4 * d->n_quad);
     }
 
+    build_pairs(*p);
     std::vector<double> tri_cnt, quad_cnt;
     bispec_status s = compute_counts(*p, cand, tri_cnt, quad_cnt);
     if (s != BISPEC_OK) return s;
@@ -416,6 +472,7 @@ bispec_status upload_tables(bispec_plan_s &p) {
                       p.stream));
     CK(hipMemcpyAsync(ws + L.scale, p.scale.data(), sizeof(double) * p.scale.size(), hipMemcpyHostToDevice,
                       p.stream));
+    CK(hipMemcpyAsync(ws + L.cols, p.cols.data(), sizeof(int) * p.cols.size(), hipMemcpyHostToDevice, p.stream));
     if (p.mfma_ok) {
         CK(hipMemcpyAsync(ws + L.pg_pairs, p.pg_pairs.data(), sizeof(uchar2) * p.pg_pairs.size(),
                           hipMemcpyHostToDevice, p.stream));
@@ -433,6 +490,26 @@ bispec_status check_call(bispec_plan_s *p, const float *delta, int batch) {
     return BISPEC_OK;
 }
 
+// Passes Z and Y of every shell pair, leaving the compact rows of all pairs
+// in the workspace ([pair][map][N][N][W]).
+hipError_t run_inverse_zy(bispec_plan_s &p, int batch) {
+    const Layout L = make_layout(p, p.max_batch);
+    char *ws = (char *)p.ws;
+    const int n = p.n;
+    const int64_t vol = (int64_t)n * n * n;
+    const float2 *tw = (const float2 *)(ws + L.tw);
+    const float2 *spec = (const float2 *)(ws + L.spec);
+    for (size_t q = 0; q < p.pairs.size(); ++q) {
+        const PairGeom &g = p.pairs[q];
+        float2 *bc = (float2 *)(ws + L.bc) + p.bc_off[q] * (int64_t)n * n * p.max_batch;
+        hipError_t e = launch_inverse_zy(spec, vol, n, batch, tw, g, (const int *)(ws + L.cols) + p.col_off[q],
+                                         p.col_n[q], (float2 *)(ws + L.abox), (int64_t)n * p.wmax * p.wmax, bc,
+                                         (int64_t)n * n * g.W, p.stream);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
 // mean, forward transform, and all bin fields into `fields` ([batch][nb][N^3]).
 bispec_status run_fields(bispec_plan_s &p, const float *delta, int batch, float *fields) {
     const Layout L = make_layout(p, p.max_batch);
@@ -442,16 +519,17 @@ bispec_status run_fields(bispec_plan_s &p, const float *delta, int batch, float 
     const float2 *tw = (const float2 *)(ws + L.tw);
     double *mean = (double *)(ws + L.mean);
     float2 *spec = (float2 *)(ws + L.spec);
-    float2 *scratch = (float2 *)(ws + L.scratch);
     stamp(p, 0);
     CK(launch_mean(delta, n, batch, (double *)(ws + L.mean_partial), kMeanParts, mean, p.stream));
     CK(launch_forward(delta, mean, n, batch, tw, spec, p.stream));
     stamp(p, 1);
-    for (int b = 0; b < p.nb; b += 2) {
-        const bool two = b + 1 < p.nb;
-        CK(launch_inverse_pair(spec, vol, n, batch, tw, p.ilo2[b], p.ihi2[b], two ? p.ilo2[b + 1] : 0,
-                               two ? p.ihi2[b + 1] : 0, scratch, vol, fields + (int64_t)b * vol,
-                               two ? fields + (int64_t)(b + 1) * vol : nullptr, (int64_t)p.nb * vol, p.stream));
+    CK(run_inverse_zy(p, batch));
+    for (size_t q = 0; q < p.pairs.size(); ++q) {
+        const int b = 2 * (int)q;
+        const PairGeom &g = p.pairs[q];
+        float2 *bc = (float2 *)(ws + L.bc) + p.bc_off[q] * (int64_t)n * n * p.max_batch;
+        CK(launch_inverse_x(bc, (int64_t)n * n * g.W, n, batch, tw, g, fields + (int64_t)b * vol,
+                            b + 1 < p.nb ? fields + (int64_t)(b + 1) * vol : nullptr, (int64_t)p.nb * vol, p.stream));
     }
     stamp(p, 2);
     return BISPEC_OK;
@@ -511,10 +589,7 @@ bispec_status run_estimate_body(bispec_plan_s &p, const float *delta, int batch,
                                 double *T) {
     const Layout L = make_layout(p, p.max_batch);
     char *ws = (char *)p.ws;
-    const int64_t vol = (int64_t)p.n * p.n * p.n;
-    float *fields = (float *)(ws + L.fields);
-    bispec_status s = run_fields(p, delta, batch, fields);
-    if (s != BISPEC_OK) return s;
+    const int n = p.n;
     const int ntri = (int)p.tri.size() / 3, nq = (int)p.quad.size() / 4;
     const int t_first = ntri + p.nb, t_last = ntri + p.nb + nq;
     // B and P share the lower term range
@@ -522,6 +597,9 @@ bispec_status run_estimate_body(bispec_plan_s &p, const float *delta, int batch,
     if (!B && !P) first = last = 0;
     const bool mfma = p.mfma_ok && p.precision != BISPEC_FP32_VALU;
     if (!mfma) {
+        float *fields = (float *)(ws + L.fields);
+        bispec_status s = run_fields(p, delta, batch, fields);
+        if (s != BISPEC_OK) return s;
         if (!T) return valu_terms(p, fields, first, last, batch, P, B, T);
         if (first == last) return valu_terms(p, fields, t_first, t_last, batch, P, B, T);
         if (last == t_first) return valu_terms(p, fields, first, t_last, batch, P, B, T);
@@ -529,12 +607,29 @@ bispec_status run_estimate_body(bispec_plan_s &p, const float *delta, int batch,
         if (s != BISPEC_OK) return s;
         return valu_terms(p, fields, t_first, t_last, batch, P, B, T);
     }
+    // FFT-domain part, then the fused last pass + product-Gram
+    const float2 *tw = (const float2 *)(ws + L.tw);
+    double *mean = (double *)(ws + L.mean);
+    stamp(p, 0);
+    CK(launch_mean(delta, n, batch, (double *)(ws + L.mean_partial), kMeanParts, mean, p.stream));
+    CK(launch_forward(delta, mean, n, batch, tw, (float2 *)(ws + L.spec), p.stream));
+    stamp(p, 1);
+    CK(run_inverse_zy(p, batch));
+    stamp(p, 2);
     const bool t_mfma = T && p.quads_collapsed;
+    bispec_status s = BISPEC_OK;
     if (first < last || t_mfma) {
         const int mode = p.precision == BISPEC_SPLIT_BF16 ? PG_MODE_SPLIT : PG_MODE_F32;
+        TailPairs tp{};
+        tp.npairs = (int)p.pairs.size();
+        for (int q = 0; q < tp.npairs; ++q) {
+            tp.R[q] = p.pairs[q].R;
+            tp.W[q] = p.pairs[q].W;
+            tp.off[q] = p.bc_off[q] * (long long)n * n * p.max_batch;
+        }
         double *pg = (double *)(ws + L.pg_partial);
-        CK(launch_pgram(mode, t_mfma, fields, vol, p.nb, (int64_t)p.nb * vol, batch,
-                        (const uchar2 *)(ws + L.pg_pairs), p.n_mtile, p.nblk_pg, pg, p.stream));
+        CK(launch_tail(mode, t_mfma, (const float2 *)(ws + L.bc), tp, n, p.nb, batch,
+                       (const uchar2 *)(ws + L.pg_pairs), p.n_mtile, tw, p.nblk_pg, pg, p.stream));
         const int64_t blk_stride = (int64_t)pgram_partial_doubles(p.n_mtile, t_mfma);
         if (first < last) {
             s = finalize_range(p, true, pg, p.nblk_pg, blk_stride, first, last, batch, P, B, T);
@@ -545,7 +640,20 @@ bispec_status run_estimate_body(bispec_plan_s &p, const float *delta, int batch,
             if (s != BISPEC_OK) return s;
         }
     }
-    if (T && !p.quads_collapsed) return valu_terms(p, fields, t_first, t_last, batch, P, B, T);
+    if (T && !p.quads_collapsed) {
+        // general quads: bin fields in HBM and the VALU contraction
+        float *fields = (float *)(ws + L.fields);
+        const int64_t vol = (int64_t)n * n * n;
+        for (size_t q = 0; q < p.pairs.size(); ++q) {
+            const int b = 2 * (int)q;
+            const PairGeom &g = p.pairs[q];
+            float2 *bc = (float2 *)(ws + L.bc) + p.bc_off[q] * (int64_t)n * n * p.max_batch;
+            CK(launch_inverse_x(bc, (int64_t)n * n * g.W, n, batch, tw, g, fields + (int64_t)b * vol,
+                                b + 1 < p.nb ? fields + (int64_t)(b + 1) * vol : nullptr, (int64_t)p.nb * vol,
+                                p.stream));
+        }
+        return valu_terms(p, fields, t_first, t_last, batch, P, B, T);
+    }
     return BISPEC_OK;
 }
 
@@ -695,6 +803,8 @@ bispec_status bispec_destroy(bispec_plan_t plan) {
     delete plan;
     return BISPEC_OK;
 }
+
+const char *bispec_last_error(void) { return g_last_error; }
 
 const char *bispec_status_string(bispec_status s) {
     switch (s) {

@@ -1,6 +1,7 @@
 // fft_core.hpp -- LDS-resident Stockham FFT of a group of pencils (gfx950).
 //
-// A block of 256 threads holds G pencils of length N in LDS ([G][N] complex).
+// A block of NT threads (256 unless stated) holds G pencils of length N in
+// LDS ([G][N] complex).
 // The transform is a Stockham autosort sequence of radix-8 passes followed by
 // at most one radix-2 or radix-4 pass, so N = 8^p * {1, 2, 4}.  In a pass of
 // radix R over sub-transforms of span Ns, butterfly jj of a pencil reads the R
@@ -17,6 +18,17 @@
 #include <stdint.h>
 
 namespace bispec {
+
+__device__ __forceinline__ int signed_freq(int i, int n) { return i < n / 2 ? i : i - n; }
+
+// Geometry of one shell pair (b1, b2) of the pruned inverse transform: mode m
+// is in bin b1 iff lo1 <= |m|^2 < hi1 (likewise b2; lo2 = hi2 = 0 for a lone
+// bin); every mode of either shell has components in [-R, R] and
+// |m|^2 < hmax, and the compact intermediates span W = 2R + 1 values.
+struct PairGeom {
+    int lo1, hi1, lo2, hi2;
+    int hmax, R, W, pad;
+};
 
 template <typename R> struct cplx_of;
 template <> struct cplx_of<float> { using type = float2; };
@@ -88,19 +100,22 @@ template <int RADIX, int DIR, typename C> __device__ __forceinline__ void dft_r(
 constexpr int ilog8_floor(int n) { return n >= 8 ? 1 + ilog8_floor(n / 8) : 0; }
 constexpr int ipow8(int p) { return p == 0 ? 1 : 8 * ipow8(p - 1); }
 
-// One Stockham pass over all G pencils of the block (256 threads).
-template <typename C, int N, int LD, int G, int DIR, int RADIX, int NS>
+// One Stockham pass over all G pencils of the block (NT threads).
+template <typename C, int N, int LD, int G, int DIR, int RADIX, int NS, int NT>
 __device__ __forceinline__ void stockham_pass(C *s, const C *tw) {
     constexpr int NB = N / RADIX;          // butterflies per pencil
     constexpr int TASKS = G * NB;
-    static_assert(TASKS % 256 == 0, "pencil group must fill the block");
-    constexpr int PER = TASKS / 256;
+    static_assert(TASKS % NT == 0 || TASKS < NT, "pencil group must fill the block or fit in it");
+    constexpr int PER = TASKS < NT ? 1 : TASKS / NT;
+    constexpr bool PARTIAL = TASKS < NT;   // some threads idle (tiny grids)
     constexpr int TSTEP = N / (NS * RADIX);
     const int tid = threadIdx.x;
     C v[PER][RADIX];
+    const bool active = !PARTIAL || tid < TASKS;
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
-        const int task = tid + q * 256;
+        if (!active) break;
+        const int task = tid + q * NT;
         const int p = task / NB, jj = task % NB;
         const int k = jj % NS;
 #pragma unroll
@@ -118,7 +133,8 @@ __device__ __forceinline__ void stockham_pass(C *s, const C *tw) {
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
-        const int task = tid + q * 256;
+        if (!active) break;
+        const int task = tid + q * NT;
         const int p = task / NB, jj = task % NB;
         const int k = jj % NS;
         const int base = (jj / NS) * NS * RADIX + k;
@@ -131,25 +147,26 @@ __device__ __forceinline__ void stockham_pass(C *s, const C *tw) {
 // Full length-N transform of the G pencils held in s (row stride LD).
 // Expects s filled and a __syncthreads() issued by the caller; leaves the
 // result in s (natural order) followed by a barrier.
-template <typename C, int N, int LD, int G, int DIR>
+template <typename C, int N, int LD, int G, int DIR, int NT = 256>
 __device__ __forceinline__ void fft_pencils(C *s, const C *tw) {
     constexpr int P8 = ilog8_floor(N);
     constexpr int RL = N / ipow8(P8);
-    if constexpr (P8 >= 1) stockham_pass<C, N, LD, G, DIR, 8, 1>(s, tw);
-    if constexpr (P8 >= 2) stockham_pass<C, N, LD, G, DIR, 8, 8>(s, tw);
-    if constexpr (P8 >= 3) stockham_pass<C, N, LD, G, DIR, 8, 64>(s, tw);
-    if constexpr (P8 >= 4) stockham_pass<C, N, LD, G, DIR, 8, 512>(s, tw);
-    if constexpr (RL > 1) stockham_pass<C, N, LD, G, DIR, RL, ipow8(P8)>(s, tw);
+    if constexpr (P8 >= 1) stockham_pass<C, N, LD, G, DIR, 8, 1, NT>(s, tw);
+    if constexpr (P8 >= 2) stockham_pass<C, N, LD, G, DIR, 8, 8, NT>(s, tw);
+    if constexpr (P8 >= 3) stockham_pass<C, N, LD, G, DIR, 8, 64, NT>(s, tw);
+    if constexpr (P8 >= 4) stockham_pass<C, N, LD, G, DIR, 8, 512, NT>(s, tw);
+    if constexpr (RL > 1) stockham_pass<C, N, LD, G, DIR, RL, ipow8(P8), NT>(s, tw);
 }
 
-// Pencils per block: at least one butterfly task per thread and at most
-// 64 KiB of LDS for the pencil tile.
+// Pencils per block: at least one butterfly task per thread, at most 64 KiB
+// of LDS for the pencil tile, and no more than the N^2 pencils of one axis.
 template <typename R, int N> constexpr int pencils_per_block() {
     constexpr int bytes = (int)sizeof(R) * 2;
     constexpr int by_lds = 65536 / (N * bytes);
     constexpr int by_tasks = (2048 + N - 1) / N;
     constexpr int want = by_tasks > 16 ? by_tasks : 16;
-    return want < by_lds ? want : by_lds;
+    constexpr int g = want < by_lds ? want : by_lds;
+    return g < N * N ? g : N * N;
 }
 
 }  // namespace bispec

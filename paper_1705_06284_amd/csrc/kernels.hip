@@ -120,17 +120,30 @@ __global__ __launch_bounds__(256) void k_fft_strided(cplx<R> *__restrict__ vol_b
     }
 }
 
-__device__ __forceinline__ int signed_freq(int i, int n) { return i < n / 2 ? i : i - n; }
-
-// First inverse pass (along z) with the shell masks of bins (b1, b2) applied
-// on load: value = [m in S_b1] Delta(m) + i [m in S_b2] Delta(m).  Since both
-// masked spectra are Hermitian, the 3D inverse transform is F_b1 + i F_b2.
-// UNIT = true sets Delta = 1 (the count fields I_b of Eq. delta_nr).
+// ---------------------------------------------------------------------------
+// Pruned inverse transform of a shell pair (b1, b2), Eq. (delta_nr).
+//
+// Pass Z: only the columns (m_y, m_x) with m_y^2 + m_x^2 < hmax can hold a
+// shell mode.  Each such column gathers [m in S_b1] Delta(m) +
+// i [m in S_b2] Delta(m) along m_z (the shell masks fused into the load),
+// transforms along z and writes the box A[n_z][m_y + R][m_x + R] (W x W per
+// z-plane; entries outside the disk are never written nor read).  Since both
+// masked spectra are Hermitian the 3D transform is F_b1 + i F_b2.
+// UNIT = true sets Delta = 1 (the count fields I_b).
+//
+// Pass Y: each column (n_z, m_x), |m_x| <= R, gathers A along m_y (zero
+// outside the disk), transforms along y and writes the compact rows
+// Bc[n_z][n_y][m_x + R].
+//
+// Pass X (k_inv_x_compact, or fused into the contraction kernel): each row
+// (n_z, n_y) places Bc at m_x mod N, transforms along x, and the real and
+// imaginary parts are F_b1 and F_b2.
+// ---------------------------------------------------------------------------
 template <typename R, int N, bool UNIT>
-__global__ __launch_bounds__(256) void k_inv_z_gather(const cplx<R> *__restrict__ spec, int64_t spec_stride,
-                                                      cplx<R> *__restrict__ out, int64_t out_stride,
-                                                      const cplx<R> *__restrict__ tw, int lo1, int hi1, int lo2,
-                                                      int hi2) {
+__global__ __launch_bounds__(256) void k_inv_z_prune(const cplx<R> *__restrict__ spec, int64_t spec_stride,
+                                                     cplx<R> *__restrict__ abox, int64_t abox_stride,
+                                                     const int *__restrict__ cols, int ncols, PairGeom g,
+                                                     const cplx<R> *__restrict__ tw) {
     using C = cplx<R>;
     constexpr int G = pencils_per_block<R, N>();
     __shared__ C s[G * N];
@@ -138,45 +151,98 @@ __global__ __launch_bounds__(256) void k_inv_z_gather(const cplx<R> *__restrict_
     load_twiddles<C, N>(tws, tw);
     const int map = blockIdx.y;
     const C *sp = UNIT ? nullptr : spec + map * spec_stride;
-    C *o = out + map * out_stride;
-    const int64_t p0 = (int64_t)blockIdx.x * G;
-    const int64_t nn = (int64_t)N * N;
+    C *o = abox + map * abox_stride;
+    const int c0 = blockIdx.x * G;
+    const int W = g.W, Rr = g.R;
     for (int e = threadIdx.x; e < G * N; e += 256) {
         const int p = e % G, i = e / G;
-        const int64_t pl = p0 + p;
-        const int y = (int)(pl / N), x = (int)(pl % N);
-        const int mz = signed_freq(i, N), my = signed_freq(y, N), mx = signed_freq(x, N);
-        const int r2 = mz * mz + my * my + mx * mx;
-        const R in1 = (r2 >= lo1 && r2 < hi1) ? R(1) : R(0);
-        const R in2 = (r2 >= lo2 && r2 < hi2) ? R(1) : R(0);
-        C d;
-        if constexpr (UNIT) d = C{R(1), R(0)};
-        else d = (in1 != R(0) || in2 != R(0)) ? sp[(int64_t)i * nn + pl] : C{R(0), R(0)};
-        s[p * N + i] = C{d.x * in1 - d.y * in2, d.y * in1 + d.x * in2};
+        C v = C{R(0), R(0)};
+        if (c0 + p < ncols) {
+            const int box = cols[c0 + p];            // (m_y + R) * W + (m_x + R)
+            const int my = box / W - Rr, mx = box % W - Rr;
+            const int mz = signed_freq(i, N);
+            const int r2 = mz * mz + my * my + mx * mx;
+            const bool in1 = r2 >= g.lo1 && r2 < g.hi1;
+            const bool in2 = r2 >= g.lo2 && r2 < g.hi2;
+            if (in1 || in2) {
+                C d;
+                if constexpr (UNIT) d = C{R(1), R(0)};
+                else d = sp[((int64_t)i * N + (my & (N - 1))) * N + (mx & (N - 1))];
+                const R a1 = in1 ? R(1) : R(0), a2 = in2 ? R(1) : R(0);
+                v = C{d.x * a1 - d.y * a2, d.y * a1 + d.x * a2};
+            }
+        }
+        s[p * N + i] = v;
     }
     __syncthreads();
     fft_pencils<C, N, N, G, +1>(s, tws);
+    const int64_t plane = (int64_t)W * W;
     for (int e = threadIdx.x; e < G * N; e += 256) {
         const int p = e % G, i = e / G;
-        o[(int64_t)i * nn + p0 + p] = s[p * N + i];
+        if (c0 + p < ncols) o[(int64_t)i * plane + cols[c0 + p]] = s[p * N + i];
     }
 }
 
-// Last inverse pass (along x): real part -> F_b1, imaginary part -> F_b2
-// (skipped when f2 is null).
 template <typename R, int N>
-__global__ __launch_bounds__(256) void k_inv_x_split(const cplx<R> *__restrict__ in, int64_t in_stride,
-                                                     const cplx<R> *__restrict__ tw, R *__restrict__ f1,
-                                                     R *__restrict__ f2, int64_t field_stride) {
+__global__ __launch_bounds__(256) void k_inv_y_prune(const cplx<R> *__restrict__ abox, int64_t abox_stride,
+                                                     cplx<R> *__restrict__ bc, int64_t bc_stride, PairGeom g,
+                                                     const cplx<R> *__restrict__ tw) {
     using C = cplx<R>;
     constexpr int G = pencils_per_block<R, N>();
     __shared__ C s[G * N];
     __shared__ C tws[N];
     load_twiddles<C, N>(tws, tw);
     const int map = blockIdx.y;
-    const C *src = in + map * in_stride;
+    const C *a = abox + map * abox_stride;
+    C *o = bc + map * bc_stride;
+    const int W = g.W, Rr = g.R;
+    const int ncols = N * W;                         // columns (n_z, m_x)
+    const int c0 = blockIdx.x * G;
+    const int64_t plane = (int64_t)W * W;
+    for (int e = threadIdx.x; e < G * N; e += 256) {
+        const int p = e % G, i = e / G;
+        C v = C{R(0), R(0)};
+        const int c = c0 + p;
+        if (c < ncols) {
+            const int nz = c / W, xi = c % W;
+            const int mx = xi - Rr, my = signed_freq(i, N);
+            if (my >= -Rr && my <= Rr && my * my + mx * mx < g.hmax)
+                v = a[(int64_t)nz * plane + (int64_t)(my + Rr) * W + xi];
+        }
+        s[p * N + i] = v;
+    }
+    __syncthreads();
+    fft_pencils<C, N, N, G, +1>(s, tws);
+    for (int e = threadIdx.x; e < G * N; e += 256) {
+        const int p = e % G, i = e / G;
+        const int c = c0 + p;
+        if (c < ncols) {
+            const int nz = c / W, xi = c % W;
+            o[((int64_t)nz * N + i) * W + xi] = s[p * N + i];
+        }
+    }
+}
+
+// Pass X writing the two bin fields (used for bin_fields, the VALU
+// contraction and the FP64 count fields).
+template <typename R, int N>
+__global__ __launch_bounds__(256) void k_inv_x_compact(const cplx<R> *__restrict__ bc, int64_t bc_stride,
+                                                       PairGeom g, const cplx<R> *__restrict__ tw,
+                                                       R *__restrict__ f1, R *__restrict__ f2, int64_t field_stride) {
+    using C = cplx<R>;
+    constexpr int G = pencils_per_block<R, N>();
+    __shared__ C s[G * N];
+    __shared__ C tws[N];
+    load_twiddles<C, N>(tws, tw);
+    const int map = blockIdx.y;
+    const C *src = bc + map * bc_stride;
+    const int W = g.W, Rr = g.R;
     const int64_t row0 = (int64_t)blockIdx.x * G;
-    for (int e = threadIdx.x; e < G * N; e += 256) s[e] = src[row0 * N + e];
+    for (int e = threadIdx.x; e < G * N; e += 256) {
+        const int p = e / N, i = e % N;
+        const int mx = signed_freq(i, N);
+        s[e] = (mx >= -Rr && mx <= Rr) ? src[(row0 + p) * W + mx + Rr] : C{R(0), R(0)};
+    }
     __syncthreads();
     fft_pencils<C, N, N, G, +1>(s, tws);
     R *d1 = f1 + map * field_stride;
@@ -350,37 +416,56 @@ hipError_t launch_forward(const float *delta, const double *mean, int n, int bat
 }
 
 template <typename R>
-hipError_t launch_inverse_pair_t(const cplx<R> *spec, int64_t spec_stride, int n, int batch, const cplx<R> *tw,
-                                 int lo1, int hi1, int lo2, int hi2, cplx<R> *scratch, int64_t scratch_stride,
-                                 R *f1, R *f2, int64_t field_stride, hipStream_t st) {
+hipError_t launch_inverse_zy_t(const cplx<R> *spec, int64_t spec_stride, int n, int batch, const cplx<R> *tw,
+                               const PairGeom &g, const int *cols, int ncols, cplx<R> *abox, int64_t abox_stride,
+                               cplx<R> *bc, int64_t bc_stride, hipStream_t st) {
     return dispatch_n(n, [&](auto nc) {
         constexpr int NN = decltype(nc)::value;
         constexpr int G = pencils_per_block<R, NN>();
-        const int nblk = NN * NN / G;
-        if (spec)
-            hipLaunchKernelGGL((k_inv_z_gather<R, NN, false>), dim3(nblk, batch), dim3(256), 0, st, spec,
-                               spec_stride, scratch, scratch_stride, tw, lo1, hi1, lo2, hi2);
-        else
-            hipLaunchKernelGGL((k_inv_z_gather<R, NN, true>), dim3(nblk, batch), dim3(256), 0, st, spec,
-                               spec_stride, scratch, scratch_stride, tw, lo1, hi1, lo2, hi2);
-        hipLaunchKernelGGL((k_fft_strided<R, NN, +1, 1>), dim3(nblk, batch), dim3(256), 0, st, scratch, tw,
-                           scratch_stride);
-        hipLaunchKernelGGL((k_inv_x_split<R, NN>), dim3(nblk, batch), dim3(256), 0, st, scratch, scratch_stride,
+        const int zblk = (ncols + G - 1) / G;
+        if (zblk > 0) {
+            if (spec)
+                hipLaunchKernelGGL((k_inv_z_prune<R, NN, false>), dim3(zblk, batch), dim3(256), 0, st, spec,
+                                   spec_stride, abox, abox_stride, cols, ncols, g, tw);
+            else
+                hipLaunchKernelGGL((k_inv_z_prune<R, NN, true>), dim3(zblk, batch), dim3(256), 0, st, spec,
+                                   spec_stride, abox, abox_stride, cols, ncols, g, tw);
+        }
+        const int yblk = (NN * g.W + G - 1) / G;
+        hipLaunchKernelGGL((k_inv_y_prune<R, NN>), dim3(yblk, batch), dim3(256), 0, st, abox, abox_stride, bc,
+                           bc_stride, g, tw);
+    });
+}
+
+template <typename R>
+hipError_t launch_inverse_x_t(const cplx<R> *bc, int64_t bc_stride, int n, int batch, const cplx<R> *tw,
+                              const PairGeom &g, R *f1, R *f2, int64_t field_stride, hipStream_t st) {
+    return dispatch_n(n, [&](auto nc) {
+        constexpr int NN = decltype(nc)::value;
+        constexpr int G = pencils_per_block<R, NN>();
+        hipLaunchKernelGGL((k_inv_x_compact<R, NN>), dim3(NN * NN / G, batch), dim3(256), 0, st, bc, bc_stride, g,
                            tw, f1, f2, field_stride);
     });
 }
 
-hipError_t launch_inverse_pair(const float2 *spec, int64_t spec_stride, int n, int batch, const float2 *tw,
-                               int lo1, int hi1, int lo2, int hi2, float2 *scratch, int64_t scratch_stride,
-                               float *f1, float *f2, int64_t field_stride, hipStream_t st) {
-    return launch_inverse_pair_t<float>(spec, spec_stride, n, batch, tw, lo1, hi1, lo2, hi2, scratch,
-                                        scratch_stride, f1, f2, field_stride, st);
+hipError_t launch_inverse_zy(const float2 *spec, int64_t spec_stride, int n, int batch, const float2 *tw,
+                             const PairGeom &g, const int *cols, int ncols, float2 *abox, int64_t abox_stride,
+                             float2 *bc, int64_t bc_stride, hipStream_t st) {
+    return launch_inverse_zy_t<float>(spec, spec_stride, n, batch, tw, g, cols, ncols, abox, abox_stride, bc,
+                                      bc_stride, st);
 }
 
-hipError_t launch_inverse_pair_unit_f64(int n, const double2 *tw, int lo1, int hi1, int lo2, int hi2,
-                                        double2 *scratch, double *f1, double *f2, hipStream_t st) {
+hipError_t launch_inverse_x(const float2 *bc, int64_t bc_stride, int n, int batch, const float2 *tw,
+                            const PairGeom &g, float *f1, float *f2, int64_t field_stride, hipStream_t st) {
+    return launch_inverse_x_t<float>(bc, bc_stride, n, batch, tw, g, f1, f2, field_stride, st);
+}
+
+hipError_t launch_inverse_unit_f64(int n, const double2 *tw, const PairGeom &g, const int *cols, int ncols,
+                                   double2 *abox, double2 *bc, double *f1, double *f2, hipStream_t st) {
     const int64_t vol = (int64_t)n * n * n;
-    return launch_inverse_pair_t<double>(nullptr, 0, n, 1, tw, lo1, hi1, lo2, hi2, scratch, vol, f1, f2, vol, st);
+    hipError_t e = launch_inverse_zy_t<double>(nullptr, 0, n, 1, tw, g, cols, ncols, abox, 0, bc, 0, st);
+    if (e != hipSuccess) return e;
+    return launch_inverse_x_t<double>(bc, 0, n, 1, tw, g, f1, f2, vol, st);
 }
 
 template <typename R>

@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "fft_core.hpp"
+
 namespace bispec {
 
 hipError_t launch_mean(const float *x, int n, int batch, double *partial, int nparts, double *mean, hipStream_t st);
@@ -11,16 +13,18 @@ hipError_t launch_mean(const float *x, int n, int batch, double *partial, int np
 hipError_t launch_forward(const float *delta, const double *mean, int n, int batch, const float2 *tw,
                           float2 *spec, hipStream_t st);
 
-// Inverse transform of the shell-masked spectrum of bins (b1, b2) given by
-// integer |m|^2 thresholds [lo, hi); writes F_b1 to f1 and F_b2 to f2 (f2 may
-// be null, then pass lo2 = hi2 = 0).
-hipError_t launch_inverse_pair(const float2 *spec, int64_t spec_stride, int n, int batch, const float2 *tw,
-                               int lo1, int hi1, int lo2, int hi2, float2 *scratch, int64_t scratch_stride,
-                               float *f1, float *f2, int64_t field_stride, hipStream_t st);
-
-// Unit-amplitude (count) fields I_b in FP64.
-hipError_t launch_inverse_pair_unit_f64(int n, const double2 *tw, int lo1, int hi1, int lo2, int hi2,
-                                        double2 *scratch, double *f1, double *f2, hipStream_t st);
+// Pruned inverse transform of the shell pair g (see k_inv_z_prune):
+// passes Z and Y write the compact rows bc ([batch][N][N][W]); cols lists the
+// ncols active columns ((m_y + R) * W + (m_x + R)) and abox is the [N][W][W]
+// z-pass scratch.  Pass X writes F_b1 to f1 and F_b2 to f2 (f2 may be null).
+hipError_t launch_inverse_zy(const float2 *spec, int64_t spec_stride, int n, int batch, const float2 *tw,
+                             const PairGeom &g, const int *cols, int ncols, float2 *abox, int64_t abox_stride,
+                             float2 *bc, int64_t bc_stride, hipStream_t st);
+hipError_t launch_inverse_x(const float2 *bc, int64_t bc_stride, int n, int batch, const float2 *tw,
+                            const PairGeom &g, float *f1, float *f2, int64_t field_stride, hipStream_t st);
+// Unit-amplitude (count) fields I_b in FP64 (one map).
+hipError_t launch_inverse_unit_f64(int n, const double2 *tw, const PairGeom &g, const int *cols, int ncols,
+                                   double2 *abox, double2 *bc, double *f1, double *f2, hipStream_t st);
 
 hipError_t launch_contract_terms_f32(const float *fields, int64_t npix, int nb, int64_t map_stride, int batch,
                                      const uchar4 *terms, int nterm, int nblk, double *partial, hipStream_t st);
@@ -40,6 +44,16 @@ constexpr int PG_ROW_ONE = 33;
 size_t pgram_partial_doubles(int n_mtile, bool want_t);
 hipError_t launch_pgram(int mode, bool want_t, const float *fields, int64_t npix, int nb, int64_t map_stride,
                         int batch, const uchar2 *pairs, int n_mtile, int nblk, double *partial, hipStream_t st);
+// Fused pass X + product-Gram over the compact rows of all shell pairs.
+struct TailPairs {
+    int R[16];
+    int W[16];
+    long long off[16];      // float2 offset of pair q's compact rows of map 0
+    int npairs;
+};
+hipError_t launch_tail(int mode, bool want_t, const float2 *bc, const TailPairs &tp, int n, int nb, int batch,
+                       const uchar2 *pairs, int n_mtile, const float2 *tw, int nblk, double *partial,
+                       hipStream_t st);
 hipError_t launch_finalize_gather(const double *partial, int nblk, int64_t blk_stride, const int *idx, int nterm,
                                   int batch, const double *scale, double *o0, int n0, double *o1, int n1, double *o2,
                                   int n2, hipStream_t st);

@@ -27,6 +27,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
+#include "fft_core.hpp"
 #include "launch.hpp"
 
 namespace bispec {
@@ -37,12 +40,11 @@ typedef float f32x2 __attribute__((ext_vector_type(2)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 constexpr int PG_TK = 256;                // grid points per LDS tile
-constexpr int PG_THREADS = 512;           // 8 waves
-constexpr int PG_WAVES = PG_THREADS / 64;
-constexpr int PG_MAXT = 3;                // output tiles per wave
-constexpr int PG_FLUSH = 16;              // LDS tiles between FP64 flushes (4096 points)
-constexpr int PG_FS = PG_TK + 4;          // LDS row stride of a field, floats
-constexpr int PG_BS = PG_TK + 8;          // LDS row stride of a bf16 operand row
+// Two block shapes: 16 waves owning one output tile each (up to 16 tiles,
+// half the registers, 4 waves per SIMD) or 8 waves owning up to three.
+constexpr int PG_NT_WIDE = 1024, PG_MAXT_WIDE = 1;
+constexpr int PG_NT_DEEP = 512, PG_MAXT_DEEP = 3;
+constexpr int PG_FLUSH_POINTS = 4096;     // FP32 accumulation span before an FP64 flush
 constexpr int PG_ZERO = PG_ROW_ZERO;      // field row of zeros (padding rows)
 constexpr int PG_ONE = PG_ROW_ONE;        // field row of ones (F_b * 1 rows)
 constexpr int PG_FROWS = 34;
@@ -66,137 +68,269 @@ __device__ __forceinline__ void split8(const float *x, bf16x8 &h, bf16x8 &l) {
     }
 }
 
-template <int MODE, bool WANT_T>
-__global__ __launch_bounds__(PG_THREADS) void k_pgram(const float *__restrict__ fields, int64_t npix, int nb,
+// Per-wave state of the product-Gram: the output tiles this wave owns, the
+// row factors of its lane in each tile, FP32 accumulators and their FP64
+// flush registers.  Tiles [0, n_mtile) are pair rows; tile n_mtile (WANT_T)
+// has rows F_a^2 and columns F_b^2.
+template <int MODE, bool WANT_T, int NT, int MAXT>
+struct PgState {
+    static constexpr int WAVES = NT / 64;
+    int tile_of[MAXT];
+    uchar2 rp[MAXT];
+    f32x16 acc[MAXT];
+    double dacc[MAXT][16];
+
+    __device__ __forceinline__ void init(const uchar2 *__restrict__ pairs, int n_mtile, int nb, int wave, int col) {
+        const int n_out = n_mtile + (WANT_T ? 1 : 0);
+#pragma unroll
+        for (int t = 0; t < MAXT; ++t) {
+            const int tile = wave + t * WAVES;
+            tile_of[t] = tile < n_out ? tile : -1;
+            const unsigned char sq = (unsigned char)(col < nb ? col : PG_ZERO);
+            rp[t] = tile < n_mtile ? pairs[tile * 32 + col] : uchar2{sq, sq};
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                acc[t][r] = 0.0f;
+                dacc[t][r] = 0.0;
+            }
+        }
+    }
+
+    // Contract TK points of the LDS field tile Ft (row stride FS); in split
+    // mode Bh/Bl (row stride BS) hold the bf16 halves of the columns F_k.
+    template <int TK, int FS, int BS>
+    __device__ __forceinline__ void contract(const float *Ft, const __bf16 *Bh, const __bf16 *Bl, int n_mtile,
+                                             int col, int half) {
+        if constexpr (MODE == PG_MODE_SPLIT) {
+#pragma unroll 1
+            for (int s = 0; s < TK / 16; ++s) {
+                const int kp = s * 16 + half * 8;
+                const bf16x8 bh = *reinterpret_cast<const bf16x8 *>(&Bh[col * BS + kp]);
+                const bf16x8 bl = *reinterpret_cast<const bf16x8 *>(&Bl[col * BS + kp]);
+#pragma unroll
+                for (int t = 0; t < MAXT; ++t) {
+                    if (tile_of[t] < 0) continue;
+                    const float4 i0 = *reinterpret_cast<const float4 *>(&Ft[rp[t].x * FS + kp]);
+                    const float4 i1 = *reinterpret_cast<const float4 *>(&Ft[rp[t].x * FS + kp + 4]);
+                    const float4 j0 = *reinterpret_cast<const float4 *>(&Ft[rp[t].y * FS + kp]);
+                    const float4 j1 = *reinterpret_cast<const float4 *>(&Ft[rp[t].y * FS + kp + 4]);
+                    float a[8] = {i0.x * j0.x, i0.y * j0.y, i0.z * j0.z, i0.w * j0.w,
+                                  i1.x * j1.x, i1.y * j1.y, i1.z * j1.z, i1.w * j1.w};
+                    bf16x8 ah, al;
+                    split8(a, ah, al);
+                    if (WANT_T && tile_of[t] == n_mtile) {
+                        // rows and columns are both F_col^2 at this lane's points
+                        acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, ah, acc[t], 0, 0, 0);
+                        acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, al, acc[t], 0, 0, 0);
+                        acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, ah, acc[t], 0, 0, 0);
+                    } else {
+                        acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, acc[t], 0, 0, 0);
+                        acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, acc[t], 0, 0, 0);
+                        acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, acc[t], 0, 0, 0);
+                    }
+                }
+            }
+        } else {
+#pragma unroll 1
+            for (int s = 0; s < TK / 2; ++s) {
+                const int k = 2 * s + half;
+                const float bk = Ft[col * FS + k];
+#pragma unroll
+                for (int t = 0; t < MAXT; ++t) {
+                    if (tile_of[t] < 0) continue;
+                    const float a = Ft[rp[t].x * FS + k] * Ft[rp[t].y * FS + k];
+                    const float b = (WANT_T && tile_of[t] == n_mtile) ? bk * bk : bk;
+                    acc[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc[t], 0, 0, 0);
+                }
+            }
+        }
+    }
+
+    __device__ __forceinline__ void flush() {
+#pragma unroll
+        for (int t = 0; t < MAXT; ++t) {
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                dacc[t][r] += (double)acc[t][r];
+                acc[t][r] = 0.0f;
+            }
+        }
+    }
+
+    __device__ __forceinline__ void write(double *__restrict__ partial, int64_t blk, int n_out, int col, int half) {
+#pragma unroll
+        for (int t = 0; t < MAXT; ++t) {
+            if (tile_of[t] < 0) continue;
+            double *out = partial + (blk * n_out + tile_of[t]) * 1024;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int row = 8 * (r >> 2) + 4 * half + (r & 3);
+                out[row * 32 + col] = dacc[t][r] + (double)acc[t][r];
+            }
+        }
+    }
+};
+
+// Field rows nb..31 and the ZERO row hold 0, the ONE row holds 1.
+template <int FS, int NT>
+__device__ __forceinline__ void init_field_tile(float *Ft, int nb) {
+    for (int e = threadIdx.x; e < (PG_FROWS - nb) * FS; e += NT) {
+        const int row = nb + e / FS;
+        Ft[row * FS + e % FS] = row == PG_ONE ? 1.0f : 0.0f;
+    }
+}
+
+// bf16 halves of the column operands F_k (k < 32) of TK points.
+template <int TK, int FS, int BS, int NT>
+__device__ __forceinline__ void split_columns(const float *Ft, __bf16 *Bh, __bf16 *Bl) {
+    for (int e = threadIdx.x; e < 32 * (TK / 2); e += NT) {
+        const int c = e / (TK / 2), q = 2 * (e % (TK / 2));
+        bf16x2 h, l;
+        split2(Ft[c * FS + q], Ft[c * FS + q + 1], h, l);
+        *reinterpret_cast<bf16x2 *>(&Bh[c * BS + q]) = h;
+        *reinterpret_cast<bf16x2 *>(&Bl[c * BS + q]) = l;
+    }
+}
+
+// Product-Gram over bin fields stored in HBM ([map][nb][npix]).
+template <int MODE, bool WANT_T, int NT = PG_NT_DEEP, int MAXT = PG_MAXT_DEEP>
+__global__ __launch_bounds__(NT) void k_pgram(const float *__restrict__ fields, int64_t npix, int nb,
                                                       int64_t map_stride, const uchar2 *__restrict__ pairs,
                                                       int n_mtile, int64_t chunk, double *__restrict__ partial) {
-    __shared__ float Ft[PG_FROWS * PG_FS];
-    constexpr int BSZ = MODE == PG_MODE_SPLIT ? 32 * PG_BS : 1;
-    constexpr int QSZ = (MODE == PG_MODE_SPLIT && WANT_T) ? 32 * PG_BS : 1;
-    __shared__ __bf16 Bh[BSZ], Bl[BSZ], Qh[QSZ], Ql[QSZ];
-
+    constexpr int TK = PG_TK, FS = TK + 4, BS = TK + 8;
+    __shared__ float Ft[PG_FROWS * FS];
+    constexpr int BSZ = MODE == PG_MODE_SPLIT ? 32 * BS : 1;
+    __shared__ __bf16 Bh[BSZ], Bl[BSZ];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int col = lane & 31, half = lane >> 5;
     const int map = blockIdx.y;
     const float *f = fields + map * map_stride;
     const int64_t p_begin = (int64_t)blockIdx.x * chunk;
     const int64_t p_end = p_begin + chunk < npix ? p_begin + chunk : npix;
-    const int n_out = n_mtile + (WANT_T ? 1 : 0);
-
-    int tile_of[PG_MAXT];
-    uchar2 rp[PG_MAXT];
-#pragma unroll
-    for (int t = 0; t < PG_MAXT; ++t) {
-        const int tile = wave + t * PG_WAVES;
-        tile_of[t] = tile < n_out ? tile : -1;
-        if (tile < n_mtile) rp[t] = pairs[tile * 32 + col];
-        else rp[t] = uchar2{(unsigned char)(col < nb ? col : PG_ZERO), (unsigned char)(col < nb ? col : PG_ZERO)};
-    }
-    f32x16 acc[PG_MAXT];
-    double dacc[PG_MAXT][16];
-#pragma unroll
-    for (int t = 0; t < PG_MAXT; ++t) {
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            acc[t][r] = 0.0f;
-            dacc[t][r] = 0.0;
-        }
-    }
-    // rows nb..31 and the zero row stay 0, the ONE row stays 1
-    for (int e = tid; e < (PG_FROWS - nb) * PG_FS; e += PG_THREADS) {
-        const int row = nb + e / PG_FS;
-        Ft[row * PG_FS + e % PG_FS] = row == PG_ONE ? 1.0f : 0.0f;
-    }
-
+    PgState<MODE, WANT_T, NT, MAXT> st;
+    st.init(pairs, n_mtile, nb, wave, col);
+    init_field_tile<FS, NT>(Ft, nb);
     int since_flush = 0;
-    for (int64_t p = p_begin; p < p_end; p += PG_TK) {
+    for (int64_t p = p_begin; p < p_end; p += TK) {
         __syncthreads();
-        for (int e = tid; e < nb * (PG_TK / 4); e += PG_THREADS) {
-            const int b = e / (PG_TK / 4), q = e % (PG_TK / 4);
+        for (int e = tid; e < nb * (TK / 4); e += NT) {
+            const int b = e / (TK / 4), q = e % (TK / 4);
             const float4 v = *reinterpret_cast<const float4 *>(f + (int64_t)b * npix + p + 4 * q);
-            *reinterpret_cast<float4 *>(&Ft[b * PG_FS + 4 * q]) = v;
+            *reinterpret_cast<float4 *>(&Ft[b * FS + 4 * q]) = v;
         }
         __syncthreads();
         if constexpr (MODE == PG_MODE_SPLIT) {
-            for (int e = tid; e < 32 * (PG_TK / 2); e += PG_THREADS) {
-                const int c = e / (PG_TK / 2), q = 2 * (e % (PG_TK / 2));
-                const float x0 = Ft[c * PG_FS + q], x1 = Ft[c * PG_FS + q + 1];
-                bf16x2 h, l;
-                split2(x0, x1, h, l);
-                *reinterpret_cast<bf16x2 *>(&Bh[c * PG_BS + q]) = h;
-                *reinterpret_cast<bf16x2 *>(&Bl[c * PG_BS + q]) = l;
-                if constexpr (WANT_T) {
-                    split2(x0 * x0, x1 * x1, h, l);
-                    *reinterpret_cast<bf16x2 *>(&Qh[c * PG_BS + q]) = h;
-                    *reinterpret_cast<bf16x2 *>(&Ql[c * PG_BS + q]) = l;
-                }
-            }
+            split_columns<TK, FS, BS, NT>(Ft, Bh, Bl);
             __syncthreads();
-#pragma unroll 1
-            for (int s = 0; s < PG_TK / 16; ++s) {
-                const int kp = s * 16 + half * 8;
-                const bf16x8 bh = *reinterpret_cast<const bf16x8 *>(&Bh[col * PG_BS + kp]);
-                const bf16x8 bl = *reinterpret_cast<const bf16x8 *>(&Bl[col * PG_BS + kp]);
-#pragma unroll
-                for (int t = 0; t < PG_MAXT; ++t) {
-                    if (tile_of[t] < 0) continue;
-                    const bool tq = WANT_T && tile_of[t] == n_mtile;
-                    const float4 i0 = *reinterpret_cast<const float4 *>(&Ft[rp[t].x * PG_FS + kp]);
-                    const float4 i1 = *reinterpret_cast<const float4 *>(&Ft[rp[t].x * PG_FS + kp + 4]);
-                    const float4 j0 = *reinterpret_cast<const float4 *>(&Ft[rp[t].y * PG_FS + kp]);
-                    const float4 j1 = *reinterpret_cast<const float4 *>(&Ft[rp[t].y * PG_FS + kp + 4]);
-                    float a[8] = {i0.x * j0.x, i0.y * j0.y, i0.z * j0.z, i0.w * j0.w,
-                                  i1.x * j1.x, i1.y * j1.y, i1.z * j1.z, i1.w * j1.w};
-                    bf16x8 ah, al;
-                    split8(a, ah, al);
-                    bf16x8 uh = bh, ul = bl;
-                    if (tq) {
-                        uh = *reinterpret_cast<const bf16x8 *>(&Qh[col * PG_BS + kp]);
-                        ul = *reinterpret_cast<const bf16x8 *>(&Ql[col * PG_BS + kp]);
-                    }
-                    acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, uh, acc[t], 0, 0, 0);
-                    acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, ul, acc[t], 0, 0, 0);
-                    acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, uh, acc[t], 0, 0, 0);
-                }
-            }
-        } else {
-#pragma unroll 1
-            for (int s = 0; s < PG_TK / 2; ++s) {
-                const int k = 2 * s + half;
-                const float bk = Ft[(col < nb ? col : PG_ZERO) * PG_FS + k];
-#pragma unroll
-                for (int t = 0; t < PG_MAXT; ++t) {
-                    if (tile_of[t] < 0) continue;
-                    const bool tq = WANT_T && tile_of[t] == n_mtile;
-                    const float a = Ft[rp[t].x * PG_FS + k] * Ft[rp[t].y * PG_FS + k];
-                    const float b = tq ? bk * bk : bk;
-                    acc[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc[t], 0, 0, 0);
-                }
-            }
         }
-        if (++since_flush == PG_FLUSH) {
+        st.template contract<TK, FS, BS>(Ft, Bh, Bl, n_mtile, col, half);
+        since_flush += TK;
+        if (since_flush >= PG_FLUSH_POINTS) {
             since_flush = 0;
+            st.flush();
+        }
+    }
+    st.write(partial, (int64_t)map * gridDim.x + blockIdx.x, n_mtile + (WANT_T ? 1 : 0), col, half);
+}
+
+// Fused last inverse pass + product-Gram.  A tile is TK = max(N, 256) grid
+// points: RT = TK/N consecutive x-rows (n_z, n_y).  For every row and shell
+// pair the compact rows Bc[n_z][n_y][m_x + R] are placed at m_x mod N and
+// transformed along x in LDS; the real and imaginary parts are the bin
+// fields F_2q and F_2q+1 at the tile's points, contracted at once.
+template <int MODE, bool WANT_T, int N, int NT, int MAXT>
+__global__ __launch_bounds__(NT) void k_tail(const float2 *__restrict__ bc, TailPairs tp, int nb,
+                                             const uchar2 *__restrict__ pairs, int n_mtile,
+                                             const float2 *__restrict__ tw, int tiles_per_blk,
+                                             double *__restrict__ partial) {
+    constexpr int TK = N >= PG_TK ? N : PG_TK;
+    constexpr int RT = TK / N;
+    constexpr int G = 16 * RT;                 // pencil slots: RT rows x 16 pairs
+    constexpr int FS = TK + 4, BS = TK + 8;
+    constexpr int FFT_BYTES = G * N * 8;
+    constexpr int SPLIT_BYTES = MODE == PG_MODE_SPLIT ? 2 * 32 * BS * 2 : 0;
+    constexpr int UBYTES = FFT_BYTES > SPLIT_BYTES ? FFT_BYTES : SPLIT_BYTES;
+    constexpr int PF = G * N / NT;             // prefetched elements per thread
+    static_assert((G * N) % NT == 0, "tile loads must divide the block");
+    __shared__ float Ft[PG_FROWS * FS];
+    __shared__ __attribute__((aligned(16))) unsigned char ubuf[UBYTES];
+    __shared__ float2 tws[N];
+    float2 *fb = reinterpret_cast<float2 *>(ubuf);
+    __bf16 *Bh = reinterpret_cast<__bf16 *>(ubuf);
+    __bf16 *Bl = Bh + 32 * BS;
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int col = lane & 31, half = lane >> 5;
+    const int map = blockIdx.y;
+    const int64_t nrow = (int64_t)N * N;
+    const int64_t total = (int64_t)N * N * N / TK;
+    const int64_t t_begin = (int64_t)blockIdx.x * tiles_per_blk;
+    const int64_t t_end = t_begin + tiles_per_blk < total ? t_begin + tiles_per_blk : total;
+    for (int i = tid; i < N; i += NT) tws[i] = tw[i];
+    PgState<MODE, WANT_T, NT, MAXT> st;
+    st.init(pairs, n_mtile, nb, wave, col);
+    init_field_tile<FS, NT>(Ft, nb);
+
+    // Element k of this thread's share of a tile: slot (row r, pair q) and
+    // position i; the compact-row offset is fixed per element, the row varies.
+    int64_t src_off[PF];
+    bool src_ok[PF];
 #pragma unroll
-            for (int t = 0; t < PG_MAXT; ++t) {
-#pragma unroll
-                for (int r = 0; r < 16; ++r) {
-                    dacc[t][r] += (double)acc[t][r];
-                    acc[t][r] = 0.0f;
-                }
+    for (int k = 0; k < PF; ++k) {
+        const int e = tid + k * NT;
+        const int sl = e / N, i = e % N;
+        const int r = sl / 16, q = sl % 16;
+        src_ok[k] = false;
+        src_off[k] = 0;
+        if (q < tp.npairs) {
+            const int mx = signed_freq(i, N), R = tp.R[q], W = tp.W[q];
+            if (mx >= -R && mx <= R) {
+                src_ok[k] = true;
+                src_off[k] = tp.off[q] + (map * nrow + r) * W + mx + R;   // + row0 * W
             }
         }
     }
-    const int64_t blk = (int64_t)map * gridDim.x + blockIdx.x;
+    auto fetch = [&](int64_t tile, float2 *v) {
+        const int64_t row0 = tile * RT;
 #pragma unroll
-    for (int t = 0; t < PG_MAXT; ++t) {
-        if (tile_of[t] < 0) continue;
-        double *out = partial + (blk * n_out + tile_of[t]) * 1024;
+        for (int k = 0; k < PF; ++k) {
+            const int e = tid + k * NT;
+            const int q = (e / N) % 16;
+            v[k] = src_ok[k] ? bc[src_off[k] + row0 * tp.W[q]] : float2{0.0f, 0.0f};
+        }
+    };
+    float2 pre[PF];
+    if (t_begin < t_end) fetch(t_begin, pre);
+    int since_flush = 0;
+    for (int64_t tile = t_begin; tile < t_end; ++tile) {
+        __syncthreads();
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            const int row = 8 * (r >> 2) + 4 * half + (r & 3);
-            out[row * 32 + col] = dacc[t][r] + (double)acc[t][r];
+        for (int k = 0; k < PF; ++k) fb[tid + k * NT] = pre[k];
+        if (tile + 1 < t_end) fetch(tile + 1, pre);    // lands while this tile is processed
+        __syncthreads();
+        fft_pencils<float2, N, N, G, +1, NT>(fb, tws);
+        for (int e = tid; e < G * N; e += NT) {
+            const int sl = e / N, n = e % N;
+            const int r = sl / 16, q = sl % 16;
+            if (q < tp.npairs) {
+                const float2 v = fb[e];
+                Ft[(2 * q) * FS + r * N + n] = v.x;
+                if (2 * q + 1 < nb) Ft[(2 * q + 1) * FS + r * N + n] = v.y;
+            }
+        }
+        __syncthreads();
+        if constexpr (MODE == PG_MODE_SPLIT) {
+            split_columns<TK, FS, BS, NT>(Ft, Bh, Bl);
+            __syncthreads();
+        }
+        st.template contract<TK, FS, BS>(Ft, Bh, Bl, n_mtile, col, half);
+        since_flush += TK;
+        if (since_flush >= PG_FLUSH_POINTS) {
+            since_flush = 0;
+            st.flush();
         }
     }
+    st.write(partial, (int64_t)map * gridDim.x + blockIdx.x, n_mtile + (WANT_T ? 1 : 0), col, half);
 }
 
 // Fixed-order FP64 sum over blocks of the dense tile partials, gathered at
@@ -230,9 +364,9 @@ size_t pgram_partial_doubles(int n_mtile, bool want_t) { return (size_t)(n_mtile
 
 hipError_t launch_pgram(int mode, bool want_t, const float *fields, int64_t npix, int nb, int64_t map_stride,
                         int batch, const uchar2 *pairs, int n_mtile, int nblk, double *partial, hipStream_t st) {
-    if (nb > 32 || n_mtile + (want_t ? 1 : 0) > PG_MAXT * PG_WAVES) return hipErrorInvalidValue;
+    if (nb > 32 || n_mtile + (want_t ? 1 : 0) > PG_MAXT_DEEP * (PG_NT_DEEP / 64)) return hipErrorInvalidValue;
     const int64_t chunk = ((npix + nblk - 1) / nblk + PG_TK - 1) / PG_TK * PG_TK;
-    const dim3 grid(nblk, batch), block(PG_THREADS);
+    const dim3 grid(nblk, batch), block(PG_NT_DEEP);
     if (mode == PG_MODE_SPLIT) {
         if (want_t)
             hipLaunchKernelGGL((k_pgram<PG_MODE_SPLIT, true>), grid, block, 0, st, fields, npix, nb, map_stride, pairs,
@@ -249,6 +383,47 @@ hipError_t launch_pgram(int mode, bool want_t, const float *fields, int64_t npix
                                n_mtile, chunk, partial);
     }
     return hipGetLastError();
+}
+
+template <int MODE, bool WANT_T>
+hipError_t launch_tail_m(const float2 *bc, const TailPairs &tp, int n, int nb, int batch, const uchar2 *pairs,
+                         int n_mtile, const float2 *tw, int nblk, double *partial, hipStream_t st) {
+    const bool wide = n_mtile + (WANT_T ? 1 : 0) <= PG_MAXT_WIDE * (PG_NT_WIDE / 64);
+    auto go = [&](auto nc) {
+        constexpr int NN = decltype(nc)::value;
+        constexpr int TK = NN >= PG_TK ? NN : PG_TK;
+        const int64_t total = (int64_t)NN * NN * NN / TK;
+        const int per = (int)((total + nblk - 1) / nblk);
+        if (wide)
+            hipLaunchKernelGGL((k_tail<MODE, WANT_T, NN, PG_NT_WIDE, PG_MAXT_WIDE>), dim3(nblk, batch),
+                               dim3(PG_NT_WIDE), 0, st, bc, tp, nb, pairs, n_mtile, tw, per, partial);
+        else
+            hipLaunchKernelGGL((k_tail<MODE, WANT_T, NN, PG_NT_DEEP, PG_MAXT_DEEP>), dim3(nblk, batch),
+                               dim3(PG_NT_DEEP), 0, st, bc, tp, nb, pairs, n_mtile, tw, per, partial);
+    };
+    switch (n) {
+        case 8: go(std::integral_constant<int, 8>{}); break;
+        case 16: go(std::integral_constant<int, 16>{}); break;
+        case 32: go(std::integral_constant<int, 32>{}); break;
+        case 64: go(std::integral_constant<int, 64>{}); break;
+        case 128: go(std::integral_constant<int, 128>{}); break;
+        case 256: go(std::integral_constant<int, 256>{}); break;
+        case 512: go(std::integral_constant<int, 512>{}); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_tail(int mode, bool want_t, const float2 *bc, const TailPairs &tp, int n, int nb, int batch,
+                       const uchar2 *pairs, int n_mtile, const float2 *tw, int nblk, double *partial,
+                       hipStream_t st) {
+    if (nb > 32 || tp.npairs > 16 || n_mtile + (want_t ? 1 : 0) > PG_MAXT_DEEP * (PG_NT_DEEP / 64))
+        return hipErrorInvalidValue;
+    if (mode == PG_MODE_SPLIT)
+        return want_t ? launch_tail_m<PG_MODE_SPLIT, true>(bc, tp, n, nb, batch, pairs, n_mtile, tw, nblk, partial, st)
+                      : launch_tail_m<PG_MODE_SPLIT, false>(bc, tp, n, nb, batch, pairs, n_mtile, tw, nblk, partial, st);
+    return want_t ? launch_tail_m<PG_MODE_F32, true>(bc, tp, n, nb, batch, pairs, n_mtile, tw, nblk, partial, st)
+                  : launch_tail_m<PG_MODE_F32, false>(bc, tp, n, nb, batch, pairs, n_mtile, tw, nblk, partial, st);
 }
 
 hipError_t launch_finalize_gather(const double *partial, int nblk, int64_t blk_stride, const int *idx, int nterm,

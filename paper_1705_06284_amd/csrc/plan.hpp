@@ -6,6 +6,8 @@
 #include <cstdint>
 #include <vector>
 
+#include "fft_core.hpp"
+
 struct bispec_plan_s {
     int n = 0;                 // grid side N
     double box_len = 0;        // L (V = L^3)
@@ -22,6 +24,13 @@ struct bispec_plan_s {
     hipStream_t stream = nullptr;
     void *ws = nullptr;
     size_t ws_bytes = 0;
+    // pruned inverse transform: bins paired (2q, 2q+1)
+    std::vector<bispec::PairGeom> pairs;
+    std::vector<int> cols;               // active z-pass columns of all pairs
+    std::vector<int> col_off, col_n;     // per pair: offset into cols, count
+    std::vector<int64_t> bc_off;         // per pair: sum of W of earlier pairs
+    int wmax = 1;                        // largest W
+    int64_t wsum = 0;                    // sum of W over pairs
     int nblk = 1;                        // blocks of the term contraction
     std::vector<uchar4> terms;           // [triplets | (b,b) | quads]
     std::vector<double> scale;           // normalisation over the FFT count, per term
@@ -44,8 +53,8 @@ namespace bispec {
 
 // Byte offsets of the workspace regions (256-byte aligned).
 struct Layout {
-    size_t tw, terms, scale, pg_pairs, pg_idx, mean_partial, mean, spec, scratch, fields, partial, pg_partial,
-        total;
+    size_t tw, terms, scale, pg_pairs, pg_idx, cols, mean_partial, mean, spec, abox, bc, fields, partial,
+        pg_partial, total;
 };
 
 Layout make_layout(const bispec_plan_s &p, int batch);

@@ -179,3 +179,78 @@ def test_c2_lognormal_128_sampled(binding, prec):
     assert np.max(e) <= TOL[prec]
     refp, _ = oracle.power_spectrum(d, lo, hi, delta_k=Dk)
     assert np.max(np.abs(P.cpu().numpy()[0] - refp) / refp) <= TOL[prec]
+
+
+def test_valu_contraction_and_general_quads(binding):
+    """The vector-ALU contraction (mode 2) and non-collapsed p = 4 configurations."""
+    n = 32
+    lo, hi = synth.linear_bins(n, 6)
+    d = synth.lognormal_field(n, 1.5, 1.0, seed=9)
+    trip = np.array([(0, 1, 1), (1, 2, 2), (0, 2, 2), (2, 2, 2)], np.int32)
+    quads = np.array([(0, 1, 1, 2), (0, 0, 1, 1), (1, 1, 1, 1)], np.int32)
+    _say("valu contraction + general quads 32^3")
+    ref_b = oracle.bispectrum(d, lo, hi, trip)
+    ref_t = oracle.trispectrum(d, lo, hi, quads)
+    for prec in ("fp32_valu", "split_bf16"):
+        plan = binding.Plan(n, lo, hi, triplets=trip, quads=quads, precision=prec)
+        P, B, T = plan.polyspec(d)
+        assert np.array_equal(plan.quad_counts.astype(np.int64), ref_t.count)
+        assert np.max(_err(B.cpu().numpy()[0], ref_b)) <= TOL[prec if prec != "fp32_valu" else "fp32"]
+        assert np.max(_err(T.cpu().numpy()[0], ref_t)) <= 1e-5   # general quads always take FP32
+
+
+@pytest.mark.parametrize("n", [8, 16, 128])
+def test_small_and_medium_grids(binding, n):
+    """Every FFT length path (radix 8 with a 2- or 4-point tail) and tiny grids.
+    Linear bins from 0 (from k_f/2 at 8^3, where [0, 1) holds no mode)."""
+    e = np.linspace(0.5 if n == 8 else 0.0, n / 2, 5)
+    lo, hi = e[:-1], e[1:]
+    d = synth.lognormal_field(n, 1.0, 0.8, seed=n)
+    _say("grid %d^3" % n)
+    plan = binding.Plan(n, lo, hi, precision="split_bf16")
+    P, B, T = plan.polyspec(d)
+    trip = plan.triplets
+    sel = _cheap_triplets(n, lo, hi, trip, 5e8)
+    idx = [int(np.flatnonzero((trip == t).all(1))[0]) for t in sel]
+    ref = oracle.bispectrum(d, lo, hi, sel)
+    assert np.array_equal(plan.counts[idx].astype(np.int64), ref.count)
+    assert np.max(_err(B.cpu().numpy()[0][idx], ref)) <= TOL["split_bf16"]
+    refp, _ = oracle.power_spectrum(d, lo, hi)
+    assert np.max(np.abs(P.cpu().numpy()[0] - refp) / refp) <= TOL["split_bf16"]
+
+
+@pytest.mark.parametrize("prec", ["fp32", "split_bf16"])
+def test_c3_bubbles_256_sampled(binding, prec):
+    """The benchmark workload: 256^3 toy-reionisation map, 24 bins, every closed
+    triplet and collapsed quad, in the bench launch configuration (batch 1)."""
+    n = 256
+    wl = "c3_256_bubbles"
+    lo, hi = synth.workload_bins(wl)
+    d = synth.workload_field(wl)
+    _say("c3 256^3 sampled %s" % prec)
+    plan = binding.Plan(n, lo, hi, precision=prec)
+    P, B, T = plan.polyspec(d)
+    trip = plan.triplets
+    assert len(trip) == 1522 and plan.n_quad == 300
+    sel = _cheap_triplets(n, lo, hi, trip, 2e9)
+    idx = [int(np.flatnonzero((trip == t).all(1))[0]) for t in sel]
+    Dk = oracle.dft3(oracle.prepare(d))
+    ref = oracle.bispectrum(d, lo, hi, sel, delta_k=Dk)
+    assert np.array_equal(plan.counts[idx].astype(np.int64), ref.count)
+    e = _err(B.cpu().numpy()[0][idx], ref)
+    _say("  %d sampled triplets, max err %.2e" % (len(sel), e.max()))
+    assert np.max(e) <= TOL[prec]
+    refp, _ = oracle.power_spectrum(d, lo, hi, delta_k=Dk)
+    assert np.max(np.abs(P.cpu().numpy()[0] - refp) / refp) <= TOL[prec]
+    quads = plan.quads
+    qsel = [q for q in range(len(quads)) if quads[q][2] <= 1]
+    reft = oracle.trispectrum(d, lo, hi, quads[qsel], delta_k=Dk)
+    assert np.array_equal(plan.quad_counts[qsel].astype(np.int64), reft.count)
+    assert np.max(_err(T.cpu().numpy()[0][qsel], reft)) <= TOL[prec]
+
+
+def test_empty_shell_is_rejected(binding):
+    """[0, 1) holds only the mean mode, which no shell contains."""
+    with pytest.raises(binding.BispecError) as ei:
+        binding.Plan(8, [0.0, 1.0], [1.0, 2.0])
+    assert ei.value.code == -4
