@@ -96,7 +96,11 @@ typedef struct {
  * count is non-zero.  *out is set only on BISPEC_OK. */
 bispec_status bispec_plan(const bispec_plan_desc *desc, bispec_plan_t *out);
 
-/* Device workspace bytes a call with this batch needs. */
+/* Device workspace bytes a call with this batch needs.  The footprint
+ * depends on the precision mode: BISPEC_FP32_VALU, more than 32 bins or
+ * non-collapsed quads keep all bin fields in HBM (n_bins * N^3 * 4 bytes per
+ * map).  After bispec_set_precision to a mode that needs them, attach a
+ * workspace of the new footprint, or calls return BISPEC_E_NO_WORKSPACE. */
 bispec_status bispec_plan_footprint(bispec_plan_t plan, int32_t batch, size_t *bytes);
 
 /* Attach caller-owned device memory (at least the footprint of max_batch,

@@ -211,6 +211,13 @@ class Plan:
 
     def set_precision(self, precision):
         check(bispec_set_precision(self.handle, _precision(precision)), "bispec_set_precision")
+        sz = ctypes.c_size_t()
+        check(bispec_plan_footprint(self.handle, self.max_batch, ctypes.byref(sz)), "bispec_plan_footprint")
+        if sz.value != self.workspace_bytes:          # the mode needs a different workspace
+            self.workspace = None
+            self.workspace_bytes = sz.value
+            self.workspace = self._torch.empty(sz.value, dtype=self._torch.uint8, device=self.device)
+            check(bispec_set_workspace(self.handle, _ptr(self.workspace), sz.value), "bispec_set_workspace")
 
     def timing(self, on=True):
         check(bispec_timing_enable(self.handle, 1 if on else 0), "bispec_timing_enable")

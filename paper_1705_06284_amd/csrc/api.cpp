@@ -62,6 +62,10 @@ int ceil_int(double x) { return (int)std::ceil(x); }
 
 namespace bispec {
 
+bool needs_fields(const bispec_plan_s &p) {
+    return !p.mfma_ok || !p.quads_collapsed || p.precision == BISPEC_FP32_VALU;
+}
+
 Layout make_layout(const bispec_plan_s &p, int batch) {
     Layout L{};
     const int64_t vol = (int64_t)p.n * p.n * p.n;
@@ -72,15 +76,22 @@ Layout make_layout(const bispec_plan_s &p, int batch) {
     L.pg_pairs = off;     off = align_up(off + sizeof(uchar2) * p.pg_pairs.size());
     L.pg_idx = off;       off = align_up(off + sizeof(int) * p.pg_idx.size());
     L.cols = off;         off = align_up(off + sizeof(int) * p.cols.size());
+    L.pd = off;           off = align_up(off + sizeof(PairDev) * p.pairs.size());
+    L.ztab = off;         off = align_up(off + sizeof(int2) * p.ztab.size());
+    L.ytab = off;         off = align_up(off + sizeof(int2) * p.ytab.size());
     L.mean_partial = off; off = align_up(off + sizeof(double) * kMeanParts * batch);
     L.mean = off;         off = align_up(off + sizeof(double) * batch);
     L.spec = off;         off = align_up(off + sizeof(float2) * vol * batch);
-    L.abox = off;         off = align_up(off + sizeof(float2) * (size_t)p.n * p.wmax * p.wmax * batch);
+    L.abox = off;         off = align_up(off + sizeof(float2) * (size_t)p.n * p.absum * batch);
     L.bc = off;           off = align_up(off + sizeof(float2) * (size_t)p.n * p.n * p.wsum * batch);
-    L.fields = off;       off = align_up(off + sizeof(float) * vol * p.nb * batch);
     L.partial = off;      off = align_up(off + sizeof(double) * (size_t)p.nblk * p.terms.size() * batch);
     L.pg_partial = off;
     if (p.mfma_ok) off = align_up(off + sizeof(double) * pgram_partial_doubles(p.n_mtile, true) * p.nblk_pg * batch);
+    L.pg_dense = off;
+    if (p.mfma_ok) off = align_up(off + sizeof(double) * pgram_partial_doubles(p.n_mtile, true) * batch);
+    // bin fields in HBM: only the vector-ALU contraction and general quads read them
+    L.fields = off;
+    if (needs_fields(p)) off = align_up(off + sizeof(float) * vol * p.nb * batch);
     L.total = off;
     return L;
 }
@@ -137,8 +148,14 @@ void build_pairs(bispec_plan_s &p) {
     p.col_off.clear();
     p.col_n.clear();
     p.bc_off.clear();
+    p.ab_off.clear();
+    p.ztab.clear();
+    p.ytab.clear();
     p.wmax = 1;
+    p.wpmax = 16;
     p.wsum = 0;
+    p.absum = 0;
+    const int G = fft_pencils_per_block(p.n, false);
     for (int b = 0; b < p.nb; b += 2) {
         PairGeom g{};
         g.lo1 = p.ilo2[b];
@@ -151,16 +168,41 @@ void build_pairs(bispec_plan_s &p) {
         while ((int64_t)(r + 1) * (r + 1) < g.hmax) ++r;   // largest r with r^2 < hmax
         g.R = r;
         g.W = 2 * r + 1;
+        g.Wp = (g.W + 15) / 16 * 16;
+        const int q = (int)p.pairs.size();
         p.col_off.push_back((int)p.cols.size());
         for (int my = -r; my <= r; ++my)
             for (int mx = -r; mx <= r; ++mx)
-                if (my * my + mx * mx < g.hmax) p.cols.push_back((my + r) * g.W + (mx + r));
+                if (my * my + mx * mx < g.hmax) p.cols.push_back((my + r) * g.Wp + (mx + r));
         p.col_n.push_back((int)p.cols.size() - p.col_off.back());
+        for (int c0 = 0; c0 < p.col_n.back(); c0 += G) p.ztab.push_back(int2{q, c0});
+        for (int c0 = 0; c0 < p.n * g.Wp; c0 += G) p.ytab.push_back(int2{q, c0});
         p.bc_off.push_back(p.wsum);
-        p.wsum += g.W;
+        p.wsum += g.Wp;
+        p.ab_off.push_back(p.absum);
+        p.absum += (int64_t)g.W * g.Wp;
         p.wmax = std::max(p.wmax, g.W);
+        p.wpmax = std::max(p.wpmax, g.Wp);
         p.pairs.push_back(g);
     }
+}
+
+// Device descriptors of the pairs for the estimate path (all pairs resident).
+std::vector<PairDev> pair_devs(const bispec_plan_s &p) {
+    std::vector<PairDev> v;
+    const long long n = p.n, mb = p.max_batch;
+    for (size_t q = 0; q < p.pairs.size(); ++q) {
+        PairDev d{};
+        d.g = p.pairs[q];
+        d.astride = n * d.g.W * d.g.Wp;
+        d.aoff = p.ab_off[q] * n * mb;
+        d.bstride = n * n * d.g.Wp;
+        d.boff = p.bc_off[q] * n * n * mb;
+        d.col_off = p.col_off[q];
+        d.ncols = p.col_n[q];
+        v.push_back(d);
+    }
+    return v;
 }
 
 // Rows of the product-Gram: pairs (i,j), i <= j, ordered by j then i; then
@@ -273,8 +315,15 @@ bispec_status compute_counts(bispec_plan_s &p, std::vector<int> &cand_tri, std::
     const size_t o_sums = off;    off = align_up(off + sizeof(double) * nterm);
     const size_t o_partial = off; off = align_up(off + sizeof(double) * (size_t)nblk * nterm);
     const size_t o_cols = off;    off = align_up(off + sizeof(int) * p.cols.size());
-    const size_t o_abox = off;    off = align_up(off + sizeof(double2) * (size_t)n * p.wmax * p.wmax);
-    const size_t o_bc = off;      off = align_up(off + sizeof(double2) * (size_t)n * n * p.wmax);
+    const size_t o_abox = off;    off = align_up(off + sizeof(double2) * (size_t)n * p.wmax * p.wpmax);
+    const size_t o_bc = off;      off = align_up(off + sizeof(double2) * (size_t)n * n * p.wpmax);
+    // one pair at a time: a one-entry pair table and its block tables
+    const int G64 = fft_pencils_per_block(n, true);
+    size_t max_tab = 0;
+    for (size_t q = 0; q < p.pairs.size(); ++q)
+        max_tab = std::max(max_tab, (size_t)(p.col_n[q] + G64 - 1) / G64 + (size_t)(n * p.pairs[q].Wp + G64 - 1) / G64);
+    const size_t o_pd = off;      off = align_up(off + sizeof(PairDev) * p.pairs.size());
+    const size_t o_tab = off;     off = align_up(off + sizeof(int2) * max_tab * p.pairs.size());
     const size_t o_fields = off;  off = align_up(off + sizeof(double) * vol * nb);
     char *mem = nullptr;
     {
@@ -297,12 +346,36 @@ bispec_status compute_counts(bispec_plan_s &p, std::vector<int> &cand_tri, std::
     CK(hipMemcpyAsync(mem + o_ones, ones.data(), sizeof(double) * nterm, hipMemcpyHostToDevice, st));
     CK(hipMemcpyAsync(mem + o_cols, p.cols.data(), sizeof(int) * p.cols.size(), hipMemcpyHostToDevice, st));
     double *fields = (double *)(mem + o_fields);
-    for (size_t q = 0; q < p.pairs.size(); ++q) {
-        const int b = 2 * (int)q;
-        CK(launch_inverse_unit_f64(n, (const double2 *)(mem + o_tw), p.pairs[q], (const int *)(mem + o_cols) + p.col_off[q],
-                                   p.col_n[q], (double2 *)(mem + o_abox), (double2 *)(mem + o_bc),
-                                   fields + (int64_t)b * vol, b + 1 < nb ? fields + (int64_t)(b + 1) * vol : nullptr,
-                                   st));
+    {
+        std::vector<PairDev> pd;
+        std::vector<int2> tabs;
+        std::vector<size_t> ztab_at, ytab_at;
+        std::vector<int> nz, ny;
+        for (size_t q = 0; q < p.pairs.size(); ++q) {
+            PairDev d{};
+            d.g = p.pairs[q];
+            d.col_off = p.col_off[q];
+            d.ncols = p.col_n[q];
+            pd.push_back(d);                    // boxes shared by all pairs: offsets 0
+            ztab_at.push_back(tabs.size());
+            for (int c0 = 0; c0 < d.ncols; c0 += G64) tabs.push_back(int2{(int)q, c0});
+            nz.push_back((int)(tabs.size() - ztab_at.back()));
+            ytab_at.push_back(tabs.size());
+            for (int c0 = 0; c0 < n * d.g.Wp; c0 += G64) tabs.push_back(int2{(int)q, c0});
+            ny.push_back((int)(tabs.size() - ytab_at.back()));
+        }
+        CK(hipMemcpyAsync(mem + o_pd, pd.data(), sizeof(PairDev) * pd.size(), hipMemcpyHostToDevice, st));
+        CK(hipMemcpyAsync(mem + o_tab, tabs.data(), sizeof(int2) * tabs.size(), hipMemcpyHostToDevice, st));
+        const int2 *tab = (const int2 *)(mem + o_tab);
+        for (size_t q = 0; q < p.pairs.size(); ++q) {
+            const int b = 2 * (int)q;
+            CK(launch_inverse_unit_f64(n, (const double2 *)(mem + o_tw), (const PairDev *)(mem + o_pd), p.pairs[q],
+                                       tab + ztab_at[q], nz[q], tab + ytab_at[q], ny[q], (const int *)(mem + o_cols),
+                                       (double2 *)(mem + o_abox), (double2 *)(mem + o_bc),
+                                       fields + (int64_t)b * vol,
+                                       b + 1 < nb ? fields + (int64_t)(b + 1) * vol : nullptr, st));
+        }
+        CK(hipStreamSynchronize(st));   // host vectors above must outlive the copies
     }
     CK(launch_contract_terms_f64(fields, vol, nb, (const uchar4 *)(mem + o_terms), nterm, nblk,
                                  (double *)(mem + o_partial), st));
@@ -473,6 +546,10 @@ bispec_status upload_tables(bispec_plan_s &p) {
     CK(hipMemcpyAsync(ws + L.scale, p.scale.data(), sizeof(double) * p.scale.size(), hipMemcpyHostToDevice,
                       p.stream));
     CK(hipMemcpyAsync(ws + L.cols, p.cols.data(), sizeof(int) * p.cols.size(), hipMemcpyHostToDevice, p.stream));
+    const std::vector<PairDev> pd = pair_devs(p);
+    CK(hipMemcpyAsync(ws + L.pd, pd.data(), sizeof(PairDev) * pd.size(), hipMemcpyHostToDevice, p.stream));
+    CK(hipMemcpyAsync(ws + L.ztab, p.ztab.data(), sizeof(int2) * p.ztab.size(), hipMemcpyHostToDevice, p.stream));
+    CK(hipMemcpyAsync(ws + L.ytab, p.ytab.data(), sizeof(int2) * p.ytab.size(), hipMemcpyHostToDevice, p.stream));
     if (p.mfma_ok) {
         CK(hipMemcpyAsync(ws + L.pg_pairs, p.pg_pairs.data(), sizeof(uchar2) * p.pg_pairs.size(),
                           hipMemcpyHostToDevice, p.stream));
@@ -497,17 +574,10 @@ hipError_t run_inverse_zy(bispec_plan_s &p, int batch) {
     char *ws = (char *)p.ws;
     const int n = p.n;
     const int64_t vol = (int64_t)n * n * n;
-    const float2 *tw = (const float2 *)(ws + L.tw);
-    const float2 *spec = (const float2 *)(ws + L.spec);
-    for (size_t q = 0; q < p.pairs.size(); ++q) {
-        const PairGeom &g = p.pairs[q];
-        float2 *bc = (float2 *)(ws + L.bc) + p.bc_off[q] * (int64_t)n * n * p.max_batch;
-        hipError_t e = launch_inverse_zy(spec, vol, n, batch, tw, g, (const int *)(ws + L.cols) + p.col_off[q],
-                                         p.col_n[q], (float2 *)(ws + L.abox), (int64_t)n * p.wmax * p.wmax, bc,
-                                         (int64_t)n * n * g.W, p.stream);
-        if (e != hipSuccess) return e;
-    }
-    return hipSuccess;
+    return launch_inverse_zy((const float2 *)(ws + L.spec), vol, n, batch, (const float2 *)(ws + L.tw),
+                             (const PairDev *)(ws + L.pd), (const int2 *)(ws + L.ztab), (int)p.ztab.size(),
+                             (const int2 *)(ws + L.ytab), (int)p.ytab.size(), (const int *)(ws + L.cols),
+                             (float2 *)(ws + L.abox), (float2 *)(ws + L.bc), p.stream);
 }
 
 // mean, forward transform, and all bin fields into `fields` ([batch][nb][N^3]).
@@ -528,7 +598,7 @@ bispec_status run_fields(bispec_plan_s &p, const float *delta, int batch, float 
         const int b = 2 * (int)q;
         const PairGeom &g = p.pairs[q];
         float2 *bc = (float2 *)(ws + L.bc) + p.bc_off[q] * (int64_t)n * n * p.max_batch;
-        CK(launch_inverse_x(bc, (int64_t)n * n * g.W, n, batch, tw, g, fields + (int64_t)b * vol,
+        CK(launch_inverse_x(bc, (int64_t)n * n * g.Wp, n, batch, tw, g, fields + (int64_t)b * vol,
                             b + 1 < p.nb ? fields + (int64_t)(b + 1) * vol : nullptr, (int64_t)p.nb * vol, p.stream));
     }
     stamp(p, 2);
@@ -596,6 +666,7 @@ bispec_status run_estimate_body(bispec_plan_s &p, const float *delta, int batch,
     int first = B ? 0 : ntri, last = P ? ntri + p.nb : ntri;
     if (!B && !P) first = last = 0;
     const bool mfma = p.mfma_ok && p.precision != BISPEC_FP32_VALU;
+    if ((!mfma || (T && !p.quads_collapsed)) && !p.ws_fields) return BISPEC_E_NO_WORKSPACE;
     if (!mfma) {
         float *fields = (float *)(ws + L.fields);
         bispec_status s = run_fields(p, delta, batch, fields);
@@ -624,19 +695,22 @@ bispec_status run_estimate_body(bispec_plan_s &p, const float *delta, int batch,
         tp.npairs = (int)p.pairs.size();
         for (int q = 0; q < tp.npairs; ++q) {
             tp.R[q] = p.pairs[q].R;
-            tp.W[q] = p.pairs[q].W;
+            tp.W[q] = p.pairs[q].Wp;       // row stride of the compact rows
             tp.off[q] = p.bc_off[q] * (long long)n * n * p.max_batch;
         }
         double *pg = (double *)(ws + L.pg_partial);
+        double *dense = (double *)(ws + L.pg_dense);
         CK(launch_tail(mode, t_mfma, (const float2 *)(ws + L.bc), tp, n, p.nb, batch,
                        (const uchar2 *)(ws + L.pg_pairs), p.n_mtile, tw, p.nblk_pg, pg, p.stream));
-        const int64_t blk_stride = (int64_t)pgram_partial_doubles(p.n_mtile, t_mfma);
+        const int64_t n_dense = (int64_t)pgram_partial_doubles(p.n_mtile, t_mfma);
+        stamp(p, 3);
+        CK(launch_reduce_dense(pg, p.nblk_pg, n_dense, batch, dense, p.stream));
         if (first < last) {
-            s = finalize_range(p, true, pg, p.nblk_pg, blk_stride, first, last, batch, P, B, T);
+            s = finalize_range(p, true, dense, 1, n_dense, first, last, batch, P, B, T);
             if (s != BISPEC_OK) return s;
         }
         if (t_mfma) {
-            s = finalize_range(p, true, pg, p.nblk_pg, blk_stride, t_first, t_last, batch, P, B, T);
+            s = finalize_range(p, true, dense, 1, n_dense, t_first, t_last, batch, P, B, T);
             if (s != BISPEC_OK) return s;
         }
     }
@@ -648,7 +722,7 @@ bispec_status run_estimate_body(bispec_plan_s &p, const float *delta, int batch,
             const int b = 2 * (int)q;
             const PairGeom &g = p.pairs[q];
             float2 *bc = (float2 *)(ws + L.bc) + p.bc_off[q] * (int64_t)n * n * p.max_batch;
-            CK(launch_inverse_x(bc, (int64_t)n * n * g.W, n, batch, tw, g, fields + (int64_t)b * vol,
+            CK(launch_inverse_x(bc, (int64_t)n * n * g.Wp, n, batch, tw, g, fields + (int64_t)b * vol,
                                 b + 1 < p.nb ? fields + (int64_t)(b + 1) * vol : nullptr, (int64_t)p.nb * vol,
                                 p.stream));
         }
@@ -689,6 +763,7 @@ bispec_status bispec_set_workspace(bispec_plan_t plan, void *dev_ptr, size_t byt
     if (bytes < make_layout(*plan, plan->max_batch).total) return BISPEC_E_NO_WORKSPACE;
     plan->ws = dev_ptr;
     plan->ws_bytes = bytes;
+    plan->ws_fields = needs_fields(*plan);
     try {
         bispec_status s = upload_tables(*plan);
         if (s != BISPEC_OK) plan->ws = nullptr;

@@ -24,10 +24,21 @@ __device__ __forceinline__ int signed_freq(int i, int n) { return i < n / 2 ? i 
 // Geometry of one shell pair (b1, b2) of the pruned inverse transform: mode m
 // is in bin b1 iff lo1 <= |m|^2 < hi1 (likewise b2; lo2 = hi2 = 0 for a lone
 // bin); every mode of either shell has components in [-R, R] and
-// |m|^2 < hmax, and the compact intermediates span W = 2R + 1 values.
+// |m|^2 < hmax, and the compact intermediates span W = 2R + 1 values stored
+// with row stride Wp (W rounded up to 16 complex = 128 bytes).
 struct PairGeom {
     int lo1, hi1, lo2, hi2;
-    int hmax, R, W, pad;
+    int hmax, R, W, Wp;
+};
+
+// Where one pair's intermediates live (complex elements).  z-pass box of map
+// m: aoff + m * astride, planes of W x Wp; compact rows of map m:
+// boff + m * bstride, [N][N] rows of stride Wp.  The z-pass columns are
+// cols[col_off .. col_off + ncols), each (m_y + R) * Wp + (m_x + R).
+struct PairDev {
+    PairGeom g;
+    long long aoff, astride, boff, bstride;
+    int col_off, ncols, pad0, pad1;
 };
 
 template <typename R> struct cplx_of;

@@ -139,10 +139,12 @@ __global__ __launch_bounds__(256) void k_fft_strided(cplx<R> *__restrict__ vol_b
 // (n_z, n_y) places Bc at m_x mod N, transforms along x, and the real and
 // imaginary parts are F_b1 and F_b2.
 // ---------------------------------------------------------------------------
+// One launch covers every pair: block b reads (pair q, first column c0) from
+// the block table, so small and large pairs share the machine.
 template <typename R, int N, bool UNIT>
 __global__ __launch_bounds__(256) void k_inv_z_prune(const cplx<R> *__restrict__ spec, int64_t spec_stride,
-                                                     cplx<R> *__restrict__ abox, int64_t abox_stride,
-                                                     const int *__restrict__ cols, int ncols, PairGeom g,
+                                                     cplx<R> *__restrict__ abox, const PairDev *__restrict__ pd,
+                                                     const int2 *__restrict__ ztab, const int *__restrict__ cols,
                                                      const cplx<R> *__restrict__ tw) {
     using C = cplx<R>;
     constexpr int G = pencils_per_block<R, N>();
@@ -150,20 +152,23 @@ __global__ __launch_bounds__(256) void k_inv_z_prune(const cplx<R> *__restrict__
     __shared__ C tws[N];
     load_twiddles<C, N>(tws, tw);
     const int map = blockIdx.y;
+    const int2 ent = ztab[blockIdx.x];
+    const PairDev P = pd[ent.x];
+    const int c0 = ent.y;
     const C *sp = UNIT ? nullptr : spec + map * spec_stride;
-    C *o = abox + map * abox_stride;
-    const int c0 = blockIdx.x * G;
-    const int W = g.W, Rr = g.R;
+    C *o = abox + P.aoff + map * P.astride;
+    const int Wp = P.g.Wp, Rr = P.g.R;
+    const int *cl = cols + P.col_off;
     for (int e = threadIdx.x; e < G * N; e += 256) {
         const int p = e % G, i = e / G;
         C v = C{R(0), R(0)};
-        if (c0 + p < ncols) {
-            const int box = cols[c0 + p];            // (m_y + R) * W + (m_x + R)
-            const int my = box / W - Rr, mx = box % W - Rr;
+        if (c0 + p < P.ncols) {
+            const int box = cl[c0 + p];              // (m_y + R) * Wp + (m_x + R)
+            const int my = box / Wp - Rr, mx = box % Wp - Rr;
             const int mz = signed_freq(i, N);
             const int r2 = mz * mz + my * my + mx * mx;
-            const bool in1 = r2 >= g.lo1 && r2 < g.hi1;
-            const bool in2 = r2 >= g.lo2 && r2 < g.hi2;
+            const bool in1 = r2 >= P.g.lo1 && r2 < P.g.hi1;
+            const bool in2 = r2 >= P.g.lo2 && r2 < P.g.hi2;
             if (in1 || in2) {
                 C d;
                 if constexpr (UNIT) d = C{R(1), R(0)};
@@ -176,16 +181,18 @@ __global__ __launch_bounds__(256) void k_inv_z_prune(const cplx<R> *__restrict__
     }
     __syncthreads();
     fft_pencils<C, N, N, G, +1>(s, tws);
-    const int64_t plane = (int64_t)W * W;
+    const int64_t plane = (int64_t)P.g.W * Wp;
     for (int e = threadIdx.x; e < G * N; e += 256) {
         const int p = e % G, i = e / G;
-        if (c0 + p < ncols) o[(int64_t)i * plane + cols[c0 + p]] = s[p * N + i];
+        if (c0 + p < P.ncols) o[(int64_t)i * plane + cl[c0 + p]] = s[p * N + i];
     }
 }
 
+// Columns (n_z, xi) of a pair are numbered c = n_z * Wp + xi; those with
+// xi >= W are row padding and are skipped.
 template <typename R, int N>
-__global__ __launch_bounds__(256) void k_inv_y_prune(const cplx<R> *__restrict__ abox, int64_t abox_stride,
-                                                     cplx<R> *__restrict__ bc, int64_t bc_stride, PairGeom g,
+__global__ __launch_bounds__(256) void k_inv_y_prune(const cplx<R> *__restrict__ abox, cplx<R> *__restrict__ bc,
+                                                     const PairDev *__restrict__ pd, const int2 *__restrict__ ytab,
                                                      const cplx<R> *__restrict__ tw) {
     using C = cplx<R>;
     constexpr int G = pencils_per_block<R, N>();
@@ -193,21 +200,23 @@ __global__ __launch_bounds__(256) void k_inv_y_prune(const cplx<R> *__restrict__
     __shared__ C tws[N];
     load_twiddles<C, N>(tws, tw);
     const int map = blockIdx.y;
-    const C *a = abox + map * abox_stride;
-    C *o = bc + map * bc_stride;
-    const int W = g.W, Rr = g.R;
-    const int ncols = N * W;                         // columns (n_z, m_x)
-    const int c0 = blockIdx.x * G;
-    const int64_t plane = (int64_t)W * W;
+    const int2 ent = ytab[blockIdx.x];
+    const PairDev P = pd[ent.x];
+    const int c0 = ent.y;
+    const C *a = abox + P.aoff + map * P.astride;
+    C *o = bc + P.boff + map * P.bstride;
+    const int W = P.g.W, Wp = P.g.Wp, Rr = P.g.R;
+    const int ncols = N * Wp;
+    const int64_t plane = (int64_t)W * Wp;
     for (int e = threadIdx.x; e < G * N; e += 256) {
         const int p = e % G, i = e / G;
         C v = C{R(0), R(0)};
         const int c = c0 + p;
-        if (c < ncols) {
-            const int nz = c / W, xi = c % W;
+        const int nz = c / Wp, xi = c % Wp;
+        if (c < ncols && xi < W) {
             const int mx = xi - Rr, my = signed_freq(i, N);
-            if (my >= -Rr && my <= Rr && my * my + mx * mx < g.hmax)
-                v = a[(int64_t)nz * plane + (int64_t)(my + Rr) * W + xi];
+            if (my >= -Rr && my <= Rr && my * my + mx * mx < P.g.hmax)
+                v = a[(int64_t)nz * plane + (int64_t)(my + Rr) * Wp + xi];
         }
         s[p * N + i] = v;
     }
@@ -216,10 +225,8 @@ __global__ __launch_bounds__(256) void k_inv_y_prune(const cplx<R> *__restrict__
     for (int e = threadIdx.x; e < G * N; e += 256) {
         const int p = e % G, i = e / G;
         const int c = c0 + p;
-        if (c < ncols) {
-            const int nz = c / W, xi = c % W;
-            o[((int64_t)nz * N + i) * W + xi] = s[p * N + i];
-        }
+        const int nz = c / Wp, xi = c % Wp;
+        if (c < ncols && xi < W) o[((int64_t)nz * N + i) * Wp + xi] = s[p * N + i];
     }
 }
 
@@ -236,12 +243,12 @@ __global__ __launch_bounds__(256) void k_inv_x_compact(const cplx<R> *__restrict
     load_twiddles<C, N>(tws, tw);
     const int map = blockIdx.y;
     const C *src = bc + map * bc_stride;
-    const int W = g.W, Rr = g.R;
+    const int Wp = g.Wp, Rr = g.R;
     const int64_t row0 = (int64_t)blockIdx.x * G;
     for (int e = threadIdx.x; e < G * N; e += 256) {
         const int p = e / N, i = e % N;
         const int mx = signed_freq(i, N);
-        s[e] = (mx >= -Rr && mx <= Rr) ? src[(row0 + p) * W + mx + Rr] : C{R(0), R(0)};
+        s[e] = (mx >= -Rr && mx <= Rr) ? src[(row0 + p) * Wp + mx + Rr] : C{R(0), R(0)};
     }
     __syncthreads();
     fft_pencils<C, N, N, G, +1>(s, tws);
@@ -417,23 +424,21 @@ hipError_t launch_forward(const float *delta, const double *mean, int n, int bat
 
 template <typename R>
 hipError_t launch_inverse_zy_t(const cplx<R> *spec, int64_t spec_stride, int n, int batch, const cplx<R> *tw,
-                               const PairGeom &g, const int *cols, int ncols, cplx<R> *abox, int64_t abox_stride,
-                               cplx<R> *bc, int64_t bc_stride, hipStream_t st) {
+                               const PairDev *pd, const int2 *ztab, int nz_blk, const int2 *ytab, int ny_blk,
+                               const int *cols, cplx<R> *abox, cplx<R> *bc, hipStream_t st) {
     return dispatch_n(n, [&](auto nc) {
         constexpr int NN = decltype(nc)::value;
-        constexpr int G = pencils_per_block<R, NN>();
-        const int zblk = (ncols + G - 1) / G;
-        if (zblk > 0) {
+        if (nz_blk > 0) {
             if (spec)
-                hipLaunchKernelGGL((k_inv_z_prune<R, NN, false>), dim3(zblk, batch), dim3(256), 0, st, spec,
-                                   spec_stride, abox, abox_stride, cols, ncols, g, tw);
+                hipLaunchKernelGGL((k_inv_z_prune<R, NN, false>), dim3(nz_blk, batch), dim3(256), 0, st, spec,
+                                   spec_stride, abox, pd, ztab, cols, tw);
             else
-                hipLaunchKernelGGL((k_inv_z_prune<R, NN, true>), dim3(zblk, batch), dim3(256), 0, st, spec,
-                                   spec_stride, abox, abox_stride, cols, ncols, g, tw);
+                hipLaunchKernelGGL((k_inv_z_prune<R, NN, true>), dim3(nz_blk, batch), dim3(256), 0, st, spec,
+                                   spec_stride, abox, pd, ztab, cols, tw);
         }
-        const int yblk = (NN * g.W + G - 1) / G;
-        hipLaunchKernelGGL((k_inv_y_prune<R, NN>), dim3(yblk, batch), dim3(256), 0, st, abox, abox_stride, bc,
-                           bc_stride, g, tw);
+        if (ny_blk > 0)
+            hipLaunchKernelGGL((k_inv_y_prune<R, NN>), dim3(ny_blk, batch), dim3(256), 0, st, abox, bc, pd, ytab,
+                               tw);
     });
 }
 
@@ -449,10 +454,10 @@ hipError_t launch_inverse_x_t(const cplx<R> *bc, int64_t bc_stride, int n, int b
 }
 
 hipError_t launch_inverse_zy(const float2 *spec, int64_t spec_stride, int n, int batch, const float2 *tw,
-                             const PairGeom &g, const int *cols, int ncols, float2 *abox, int64_t abox_stride,
-                             float2 *bc, int64_t bc_stride, hipStream_t st) {
-    return launch_inverse_zy_t<float>(spec, spec_stride, n, batch, tw, g, cols, ncols, abox, abox_stride, bc,
-                                      bc_stride, st);
+                             const PairDev *pd, const int2 *ztab, int nz_blk, const int2 *ytab, int ny_blk,
+                             const int *cols, float2 *abox, float2 *bc, hipStream_t st) {
+    return launch_inverse_zy_t<float>(spec, spec_stride, n, batch, tw, pd, ztab, nz_blk, ytab, ny_blk, cols, abox,
+                                      bc, st);
 }
 
 hipError_t launch_inverse_x(const float2 *bc, int64_t bc_stride, int n, int batch, const float2 *tw,
@@ -460,12 +465,23 @@ hipError_t launch_inverse_x(const float2 *bc, int64_t bc_stride, int n, int batc
     return launch_inverse_x_t<float>(bc, bc_stride, n, batch, tw, g, f1, f2, field_stride, st);
 }
 
-hipError_t launch_inverse_unit_f64(int n, const double2 *tw, const PairGeom &g, const int *cols, int ncols,
+hipError_t launch_inverse_unit_f64(int n, const double2 *tw, const PairDev *pd, const PairGeom &g,
+                                   const int2 *ztab, int nz_blk, const int2 *ytab, int ny_blk, const int *cols,
                                    double2 *abox, double2 *bc, double *f1, double *f2, hipStream_t st) {
     const int64_t vol = (int64_t)n * n * n;
-    hipError_t e = launch_inverse_zy_t<double>(nullptr, 0, n, 1, tw, g, cols, ncols, abox, 0, bc, 0, st);
+    hipError_t e = launch_inverse_zy_t<double>(nullptr, 0, n, 1, tw, pd, ztab, nz_blk, ytab, ny_blk, cols, abox, bc,
+                                               st);
     if (e != hipSuccess) return e;
     return launch_inverse_x_t<double>(bc, 0, n, 1, tw, g, f1, f2, vol, st);
+}
+
+int fft_pencils_per_block(int n, bool fp64) {
+    int g = 0;
+    dispatch_n(n, [&](auto nc) {
+        constexpr int NN = decltype(nc)::value;
+        g = fp64 ? pencils_per_block<double, NN>() : pencils_per_block<float, NN>();
+    });
+    return g;
 }
 
 template <typename R>

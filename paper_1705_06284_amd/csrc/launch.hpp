@@ -13,18 +13,22 @@ hipError_t launch_mean(const float *x, int n, int batch, double *partial, int np
 hipError_t launch_forward(const float *delta, const double *mean, int n, int batch, const float2 *tw,
                           float2 *spec, hipStream_t st);
 
-// Pruned inverse transform of the shell pair g (see k_inv_z_prune):
-// passes Z and Y write the compact rows bc ([batch][N][N][W]); cols lists the
-// ncols active columns ((m_y + R) * W + (m_x + R)) and abox is the [N][W][W]
-// z-pass scratch.  Pass X writes F_b1 to f1 and F_b2 to f2 (f2 may be null).
+// Pruned inverse transform (see k_inv_z_prune): passes Z and Y of every pair
+// in pd, one launch each, block tables (pair, first column) in ztab / ytab;
+// the compact rows land in bc at each pair's boff.  Pass X (launch_inverse_x)
+// reads one pair's compact rows (row stride Wp) and writes F_b1 to f1 and
+// F_b2 to f2 (f2 may be null).
 hipError_t launch_inverse_zy(const float2 *spec, int64_t spec_stride, int n, int batch, const float2 *tw,
-                             const PairGeom &g, const int *cols, int ncols, float2 *abox, int64_t abox_stride,
-                             float2 *bc, int64_t bc_stride, hipStream_t st);
+                             const PairDev *pd, const int2 *ztab, int nz_blk, const int2 *ytab, int ny_blk,
+                             const int *cols, float2 *abox, float2 *bc, hipStream_t st);
 hipError_t launch_inverse_x(const float2 *bc, int64_t bc_stride, int n, int batch, const float2 *tw,
                             const PairGeom &g, float *f1, float *f2, int64_t field_stride, hipStream_t st);
-// Unit-amplitude (count) fields I_b in FP64 (one map).
-hipError_t launch_inverse_unit_f64(int n, const double2 *tw, const PairGeom &g, const int *cols, int ncols,
+// Unit-amplitude (count) fields I_b of one pair in FP64 (one map).
+hipError_t launch_inverse_unit_f64(int n, const double2 *tw, const PairDev *pd, const PairGeom &g,
+                                   const int2 *ztab, int nz_blk, const int2 *ytab, int ny_blk, const int *cols,
                                    double2 *abox, double2 *bc, double *f1, double *f2, hipStream_t st);
+// Pencils per block of the FFT kernels (the column-chunk size of the tables).
+int fft_pencils_per_block(int n, bool fp64);
 
 hipError_t launch_contract_terms_f32(const float *fields, int64_t npix, int nb, int64_t map_stride, int batch,
                                      const uchar4 *terms, int nterm, int nblk, double *partial, hipStream_t st);
@@ -47,13 +51,15 @@ hipError_t launch_pgram(int mode, bool want_t, const float *fields, int64_t npix
 // Fused pass X + product-Gram over the compact rows of all shell pairs.
 struct TailPairs {
     int R[16];
-    int W[16];
+    int W[16];              // row stride (Wp) of pair q's compact rows
     long long off[16];      // float2 offset of pair q's compact rows of map 0
     int npairs;
 };
 hipError_t launch_tail(int mode, bool want_t, const float2 *bc, const TailPairs &tp, int n, int nb, int batch,
                        const uchar2 *pairs, int n_mtile, const float2 *tw, int nblk, double *partial,
                        hipStream_t st);
+hipError_t launch_reduce_dense(const double *partial, int nblk, int64_t n_dense, int batch, double *dense,
+                               hipStream_t st);
 hipError_t launch_finalize_gather(const double *partial, int nblk, int64_t blk_stride, const int *idx, int nterm,
                                   int batch, const double *scale, double *o0, int n0, double *o1, int n1, double *o2,
                                   int n2, hipStream_t st);

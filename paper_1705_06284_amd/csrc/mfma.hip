@@ -39,7 +39,8 @@ typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 typedef float f32x2 __attribute__((ext_vector_type(2)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
-constexpr int PG_TK = 256;                // grid points per LDS tile
+constexpr int PG_TK = 256;                // grid points per LDS tile (fields from HBM)
+constexpr int PG_TK_TAIL = 512;           // grid points per LDS tile of the fused tail
 // Two block shapes: 16 waves owning one output tile each (up to 16 tiles,
 // half the registers, 4 waves per SIMD) or 8 waves owning up to three.
 constexpr int PG_NT_WIDE = 1024, PG_MAXT_WIDE = 1;
@@ -49,6 +50,8 @@ constexpr int PG_ZERO = PG_ROW_ZERO;      // field row of zeros (padding rows)
 constexpr int PG_ONE = PG_ROW_ONE;        // field row of ones (F_b * 1 rows)
 constexpr int PG_FROWS = 34;
 
+// x = hi + lo with hi = bf16_rne(x) and lo = bf16_rne(x - hi); x - hi is
+// exact in FP32.
 __device__ __forceinline__ void split2(float x0, float x1, bf16x2 &h, bf16x2 &l) {
     const f32x2 v = {x0, x1};
     h = __builtin_convertvector(v, bf16x2);
@@ -243,7 +246,7 @@ __global__ __launch_bounds__(NT) void k_tail(const float2 *__restrict__ bc, Tail
                                              const uchar2 *__restrict__ pairs, int n_mtile,
                                              const float2 *__restrict__ tw, int tiles_per_blk,
                                              double *__restrict__ partial) {
-    constexpr int TK = N >= PG_TK ? N : PG_TK;
+    constexpr int TK = N >= PG_TK_TAIL ? N : PG_TK_TAIL;
     constexpr int RT = TK / N;
     constexpr int G = 16 * RT;                 // pencil slots: RT rows x 16 pairs
     constexpr int FS = TK + 4, BS = TK + 8;
@@ -271,42 +274,33 @@ __global__ __launch_bounds__(NT) void k_tail(const float2 *__restrict__ bc, Tail
     st.init(pairs, n_mtile, nb, wave, col);
     init_field_tile<FS, NT>(Ft, nb);
 
-    // Element k of this thread's share of a tile: slot (row r, pair q) and
-    // position i; the compact-row offset is fixed per element, the row varies.
-    int64_t src_off[PF];
-    bool src_ok[PF];
-#pragma unroll
-    for (int k = 0; k < PF; ++k) {
-        const int e = tid + k * NT;
-        const int sl = e / N, i = e % N;
-        const int r = sl / 16, q = sl % 16;
-        src_ok[k] = false;
-        src_off[k] = 0;
-        if (q < tp.npairs) {
-            const int mx = signed_freq(i, N), R = tp.R[q], W = tp.W[q];
-            if (mx >= -R && mx <= R) {
-                src_ok[k] = true;
-                src_off[k] = tp.off[q] + (map * nrow + r) * W + mx + R;   // + row0 * W
-            }
-        }
-    }
+    // Element k of this thread's share of a tile is e = tid + k NT: slot
+    // sl = e / N (row r = sl / 16, pair q = sl % 16) at position i = tid % N
+    // (NT is a multiple of N), i.e. at frequency m_x = signed(i).
+    static_assert(NT % N == 0, "block size must be a multiple of the row length");
+    const int mx = signed_freq(tid % N, N);
     auto fetch = [&](int64_t tile, float2 *v) {
         const int64_t row0 = tile * RT;
 #pragma unroll
         for (int k = 0; k < PF; ++k) {
-            const int e = tid + k * NT;
-            const int q = (e / N) % 16;
-            v[k] = src_ok[k] ? bc[src_off[k] + row0 * tp.W[q]] : float2{0.0f, 0.0f};
+            const int sl = tid / N + k * (NT / N);
+            const int r = sl / 16, q = sl % 16;
+            v[k] = float2{0.0f, 0.0f};
+            if (q < tp.npairs) {
+                const int R = tp.R[q];
+                if (mx >= -R && mx <= R) v[k] = bc[tp.off[q] + (map * nrow + row0 + r) * tp.W[q] + mx + R];
+            }
         }
     };
-    float2 pre[PF];
-    if (t_begin < t_end) fetch(t_begin, pre);
     int since_flush = 0;
     for (int64_t tile = t_begin; tile < t_end; ++tile) {
         __syncthreads();
+        {
+            float2 v[PF];
+            fetch(tile, v);
 #pragma unroll
-        for (int k = 0; k < PF; ++k) fb[tid + k * NT] = pre[k];
-        if (tile + 1 < t_end) fetch(tile + 1, pre);    // lands while this tile is processed
+            for (int k = 0; k < PF; ++k) fb[tid + k * NT] = v[k];
+        }
         __syncthreads();
         fft_pencils<float2, N, N, G, +1, NT>(fb, tws);
         for (int e = tid; e < G * N; e += NT) {
@@ -331,6 +325,26 @@ __global__ __launch_bounds__(NT) void k_tail(const float2 *__restrict__ bc, Tail
         }
     }
     st.write(partial, (int64_t)map * gridDim.x + blockIdx.x, n_mtile + (WANT_T ? 1 : 0), col, half);
+}
+
+// Fixed-order compensated FP64 sum over blocks of every dense tile entry:
+// dense[map][e] = sum_b partial[map][b][e].  Consecutive threads read
+// consecutive entries, so every block's partial is read once, coalesced.
+__global__ __launch_bounds__(256) void k_reduce_dense(const double *__restrict__ partial, int nblk, int64_t n_dense,
+                                                      double *__restrict__ dense) {
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int map = blockIdx.y;
+    if (e >= n_dense) return;
+    const double *p = partial + (int64_t)map * nblk * n_dense + e;
+    double acc = 0.0, comp = 0.0;
+#pragma unroll 8
+    for (int b = 0; b < nblk; ++b) {
+        const double x = p[(int64_t)b * n_dense];
+        const double s = acc + x;
+        comp += fabs(acc) >= fabs(x) ? (acc - s) + x : (x - s) + acc;
+        acc = s;
+    }
+    dense[(int64_t)map * n_dense + e] = acc + comp;
 }
 
 // Fixed-order FP64 sum over blocks of the dense tile partials, gathered at
@@ -391,7 +405,7 @@ hipError_t launch_tail_m(const float2 *bc, const TailPairs &tp, int n, int nb, i
     const bool wide = n_mtile + (WANT_T ? 1 : 0) <= PG_MAXT_WIDE * (PG_NT_WIDE / 64);
     auto go = [&](auto nc) {
         constexpr int NN = decltype(nc)::value;
-        constexpr int TK = NN >= PG_TK ? NN : PG_TK;
+        constexpr int TK = NN >= PG_TK_TAIL ? NN : PG_TK_TAIL;
         const int64_t total = (int64_t)NN * NN * NN / TK;
         const int per = (int)((total + nblk - 1) / nblk);
         if (wide)
@@ -424,6 +438,13 @@ hipError_t launch_tail(int mode, bool want_t, const float2 *bc, const TailPairs 
                       : launch_tail_m<PG_MODE_SPLIT, false>(bc, tp, n, nb, batch, pairs, n_mtile, tw, nblk, partial, st);
     return want_t ? launch_tail_m<PG_MODE_F32, true>(bc, tp, n, nb, batch, pairs, n_mtile, tw, nblk, partial, st)
                   : launch_tail_m<PG_MODE_F32, false>(bc, tp, n, nb, batch, pairs, n_mtile, tw, nblk, partial, st);
+}
+
+hipError_t launch_reduce_dense(const double *partial, int nblk, int64_t n_dense, int batch, double *dense,
+                               hipStream_t st) {
+    hipLaunchKernelGGL(k_reduce_dense, dim3((unsigned)((n_dense + 255) / 256), batch), dim3(256), 0, st, partial,
+                       nblk, n_dense, dense);
+    return hipGetLastError();
 }
 
 hipError_t launch_finalize_gather(const double *partial, int nblk, int64_t blk_stride, const int *idx, int nterm,

@@ -24,13 +24,17 @@ struct bispec_plan_s {
     hipStream_t stream = nullptr;
     void *ws = nullptr;
     size_t ws_bytes = 0;
+    bool ws_fields = false;              // workspace holds the bin-field region
     // pruned inverse transform: bins paired (2q, 2q+1)
     std::vector<bispec::PairGeom> pairs;
     std::vector<int> cols;               // active z-pass columns of all pairs
     std::vector<int> col_off, col_n;     // per pair: offset into cols, count
-    std::vector<int64_t> bc_off;         // per pair: sum of W of earlier pairs
-    int wmax = 1;                        // largest W
-    int64_t wsum = 0;                    // sum of W over pairs
+    std::vector<int64_t> bc_off;         // per pair: sum of Wp of earlier pairs
+    std::vector<int64_t> ab_off;         // per pair: sum of W*Wp of earlier pairs
+    int wmax = 1, wpmax = 16;            // largest W and Wp
+    int64_t wsum = 0;                    // sum of Wp over pairs
+    int64_t absum = 0;                   // sum of W*Wp over pairs
+    std::vector<int2> ztab, ytab;        // FP32 pass block tables (pair, first column)
     int nblk = 1;                        // blocks of the term contraction
     std::vector<uchar4> terms;           // [triplets | (b,b) | quads]
     std::vector<double> scale;           // normalisation over the FFT count, per term
@@ -53,10 +57,11 @@ namespace bispec {
 
 // Byte offsets of the workspace regions (256-byte aligned).
 struct Layout {
-    size_t tw, terms, scale, pg_pairs, pg_idx, cols, mean_partial, mean, spec, abox, bc, fields, partial,
-        pg_partial, total;
+    size_t tw, terms, scale, pg_pairs, pg_idx, cols, pd, ztab, ytab, mean_partial, mean, spec, abox, bc, fields,
+        partial, pg_partial, pg_dense, total;
 };
 
 Layout make_layout(const bispec_plan_s &p, int batch);
+bool needs_fields(const bispec_plan_s &p);
 
 }  // namespace bispec
