@@ -25,7 +25,7 @@ using namespace bispec;
 
 namespace {
 
-constexpr int kMeanParts = 512;
+constexpr int kMeanParts = 1024;
 constexpr size_t kAlign = 256;
 
 inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }

@@ -108,6 +108,14 @@ template <int RADIX, int DIR, typename C> __device__ __forceinline__ void dft_r(
     else if constexpr (RADIX == 2) dft2<DIR>(v);
 }
 
+// LDS layout of a pencil group: element i of pencil p sits at
+// p * pencil_ld<N>() + pad_idx(i).  One padding slot per 8 elements breaks
+// the power-of-two strides of the Stockham exchange (stride-8 writes of the
+// first pass hit 16 distinct bank pairs), and the odd pencil stride staggers
+// pencils that are read at the same position.
+template <int N> constexpr int pencil_ld() { return N + N / 8 + 1; }
+__device__ __forceinline__ int pad_idx(int i) { return i + (i >> 3); }
+
 constexpr int ilog8_floor(int n) { return n >= 8 ? 1 + ilog8_floor(n / 8) : 0; }
 constexpr int ipow8(int p) { return p == 0 ? 1 : 8 * ipow8(p - 1); }
 
@@ -130,7 +138,7 @@ __device__ __forceinline__ void stockham_pass(C *s, const C *tw) {
         const int p = task / NB, jj = task % NB;
         const int k = jj % NS;
 #pragma unroll
-        for (int t = 0; t < RADIX; ++t) v[q][t] = s[p * LD + jj + t * NB];
+        for (int t = 0; t < RADIX; ++t) v[q][t] = s[p * LD + pad_idx(jj + t * NB)];
         if constexpr (NS > 1) {
 #pragma unroll
             for (int t = 1; t < RADIX; ++t) {
@@ -150,12 +158,13 @@ __device__ __forceinline__ void stockham_pass(C *s, const C *tw) {
         const int k = jj % NS;
         const int base = (jj / NS) * NS * RADIX + k;
 #pragma unroll
-        for (int u = 0; u < RADIX; ++u) s[p * LD + base + u * NS] = v[q][u];
+        for (int u = 0; u < RADIX; ++u) s[p * LD + pad_idx(base + u * NS)] = v[q][u];
     }
     __syncthreads();
 }
 
-// Full length-N transform of the G pencils held in s (row stride LD).
+// Full length-N transform of the G pencils held in s (pencil stride LD,
+// positions mapped by pad_idx).
 // Expects s filled and a __syncthreads() issued by the caller; leaves the
 // result in s (natural order) followed by a barrier.
 template <typename C, int N, int LD, int G, int DIR, int NT = 256>
@@ -173,10 +182,11 @@ __device__ __forceinline__ void fft_pencils(C *s, const C *tw) {
 // of LDS for the pencil tile, and no more than the N^2 pencils of one axis.
 template <typename R, int N> constexpr int pencils_per_block() {
     constexpr int bytes = (int)sizeof(R) * 2;
-    constexpr int by_lds = 65536 / (N * bytes);
+    constexpr int by_lds = 65536 / (pencil_ld<N>() * bytes);
     constexpr int by_tasks = (2048 + N - 1) / N;
     constexpr int want = by_tasks > 16 ? by_tasks : 16;
-    constexpr int g = want < by_lds ? want : by_lds;
+    constexpr int gl = want < by_lds ? want : by_lds;
+    constexpr int g = 1 << (31 - __builtin_clz(gl));          // power of two
     return g < N * N ? g : N * N;
 }
 

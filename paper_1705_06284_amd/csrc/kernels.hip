@@ -37,9 +37,17 @@ __device__ __forceinline__ double wave_sum(double v) {
 __global__ __launch_bounds__(256) void k_sum_f64(const float *__restrict__ x, int64_t n,
                                                  int64_t map_stride, double *__restrict__ partial) {
     const float *xm = x + (int64_t)blockIdx.y * map_stride;
-    double acc = 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
-        acc += (double)xm[i];
+    double acc = 0.0, acc2 = 0.0;
+    // n = N^3 is a multiple of 512: 16-byte loads, two independent sums
+    const float4 *x4 = reinterpret_cast<const float4 *>(xm);
+    const int64_t n4 = n / 4;
+#pragma unroll 4
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n4; i += (int64_t)gridDim.x * 256) {
+        const float4 v = x4[i];
+        acc += (double)v.x + (double)v.y;
+        acc2 += (double)v.z + (double)v.w;
+    }
+    acc += acc2;
     acc = wave_sum(acc);
     __shared__ double red[4];
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
@@ -70,7 +78,7 @@ template <int N>
 __global__ __launch_bounds__(256) void k_fwd_x(const float *__restrict__ delta, const double *__restrict__ mean,
                                                const float2 *__restrict__ tw, float2 *__restrict__ spec) {
     constexpr int G = pencils_per_block<float, N>();
-    __shared__ float2 s[G * N];
+    __shared__ float2 s[G * pencil_ld<N>()];
     __shared__ float2 tws[N];
     load_twiddles<float2, N>(tws, tw);
     const int64_t vol = (int64_t)N * N * N;
@@ -79,13 +87,14 @@ __global__ __launch_bounds__(256) void k_fwd_x(const float *__restrict__ delta, 
     float2 *dst = spec + map * vol;
     const double mu = mean[map];
     const int64_t row0 = (int64_t)blockIdx.x * G;
+    constexpr int LD = pencil_ld<N>();
     for (int e = threadIdx.x; e < G * N; e += 256) {
         const double v = (double)src[row0 * N + e] - mu;
-        s[e] = float2{(float)v, 0.0f};
+        s[(e / N) * LD + pad_idx(e % N)] = float2{(float)v, 0.0f};
     }
     __syncthreads();
-    fft_pencils<float2, N, N, G, -1>(s, tws);
-    for (int e = threadIdx.x; e < G * N; e += 256) dst[row0 * N + e] = s[e];
+    fft_pencils<float2, N, LD, G, -1>(s, tws);
+    for (int e = threadIdx.x; e < G * N; e += 256) dst[row0 * N + e] = s[(e / N) * LD + pad_idx(e % N)];
 }
 
 // In-place transform along y (AXIS = 1) or z (AXIS = 2) of a complex volume.
@@ -96,7 +105,7 @@ __global__ __launch_bounds__(256) void k_fft_strided(cplx<R> *__restrict__ vol_b
                                                      int64_t map_stride) {
     using C = cplx<R>;
     constexpr int G = pencils_per_block<R, N>();
-    __shared__ C s[G * N];
+    __shared__ C s[G * pencil_ld<N>()];
     __shared__ C tws[N];
     load_twiddles<C, N>(tws, tw);
     C *v = vol_base + (int64_t)blockIdx.y * map_stride;
@@ -107,16 +116,16 @@ __global__ __launch_bounds__(256) void k_fft_strided(cplx<R> *__restrict__ vol_b
         const int64_t pl = p0 + p;
         const int64_t c = pl / N, x = pl % N;
         const int64_t addr = AXIS == 1 ? c * N * N + i * stride + x : (int64_t)i * stride + pl;
-        s[p * N + i] = v[addr];
+        s[p * pencil_ld<N>() + pad_idx(i)] = v[addr];
     }
     __syncthreads();
-    fft_pencils<C, N, N, G, DIR>(s, tws);
+    fft_pencils<C, N, pencil_ld<N>(), G, DIR>(s, tws);
     for (int e = threadIdx.x; e < G * N; e += 256) {
         const int p = e % G, i = e / G;
         const int64_t pl = p0 + p;
         const int64_t c = pl / N, x = pl % N;
         const int64_t addr = AXIS == 1 ? c * N * N + i * stride + x : (int64_t)i * stride + pl;
-        v[addr] = s[p * N + i];
+        v[addr] = s[p * pencil_ld<N>() + pad_idx(i)];
     }
 }
 
@@ -148,7 +157,7 @@ __global__ __launch_bounds__(256) void k_inv_z_prune(const cplx<R> *__restrict__
                                                      const cplx<R> *__restrict__ tw) {
     using C = cplx<R>;
     constexpr int G = pencils_per_block<R, N>();
-    __shared__ C s[G * N];
+    __shared__ C s[G * pencil_ld<N>()];
     __shared__ C tws[N];
     load_twiddles<C, N>(tws, tw);
     const int map = blockIdx.y;
@@ -177,14 +186,14 @@ __global__ __launch_bounds__(256) void k_inv_z_prune(const cplx<R> *__restrict__
                 v = C{d.x * a1 - d.y * a2, d.y * a1 + d.x * a2};
             }
         }
-        s[p * N + i] = v;
+        s[p * pencil_ld<N>() + pad_idx(i)] = v;
     }
     __syncthreads();
-    fft_pencils<C, N, N, G, +1>(s, tws);
+    fft_pencils<C, N, pencil_ld<N>(), G, +1>(s, tws);
     const int64_t plane = (int64_t)P.g.W * Wp;
     for (int e = threadIdx.x; e < G * N; e += 256) {
         const int p = e % G, i = e / G;
-        if (c0 + p < P.ncols) o[(int64_t)i * plane + cl[c0 + p]] = s[p * N + i];
+        if (c0 + p < P.ncols) o[(int64_t)i * plane + cl[c0 + p]] = s[p * pencil_ld<N>() + pad_idx(i)];
     }
 }
 
@@ -196,7 +205,7 @@ __global__ __launch_bounds__(256) void k_inv_y_prune(const cplx<R> *__restrict__
                                                      const cplx<R> *__restrict__ tw) {
     using C = cplx<R>;
     constexpr int G = pencils_per_block<R, N>();
-    __shared__ C s[G * N];
+    __shared__ C s[G * pencil_ld<N>()];
     __shared__ C tws[N];
     load_twiddles<C, N>(tws, tw);
     const int map = blockIdx.y;
@@ -218,15 +227,15 @@ __global__ __launch_bounds__(256) void k_inv_y_prune(const cplx<R> *__restrict__
             if (my >= -Rr && my <= Rr && my * my + mx * mx < P.g.hmax)
                 v = a[(int64_t)nz * plane + (int64_t)(my + Rr) * Wp + xi];
         }
-        s[p * N + i] = v;
+        s[p * pencil_ld<N>() + pad_idx(i)] = v;
     }
     __syncthreads();
-    fft_pencils<C, N, N, G, +1>(s, tws);
+    fft_pencils<C, N, pencil_ld<N>(), G, +1>(s, tws);
     for (int e = threadIdx.x; e < G * N; e += 256) {
         const int p = e % G, i = e / G;
         const int c = c0 + p;
         const int nz = c / Wp, xi = c % Wp;
-        if (c < ncols && xi < W) o[((int64_t)nz * N + i) * Wp + xi] = s[p * N + i];
+        if (c < ncols && xi < W) o[((int64_t)nz * N + i) * Wp + xi] = s[p * pencil_ld<N>() + pad_idx(i)];
     }
 }
 
@@ -238,7 +247,7 @@ __global__ __launch_bounds__(256) void k_inv_x_compact(const cplx<R> *__restrict
                                                        R *__restrict__ f1, R *__restrict__ f2, int64_t field_stride) {
     using C = cplx<R>;
     constexpr int G = pencils_per_block<R, N>();
-    __shared__ C s[G * N];
+    __shared__ C s[G * pencil_ld<N>()];
     __shared__ C tws[N];
     load_twiddles<C, N>(tws, tw);
     const int map = blockIdx.y;
@@ -248,15 +257,16 @@ __global__ __launch_bounds__(256) void k_inv_x_compact(const cplx<R> *__restrict
     for (int e = threadIdx.x; e < G * N; e += 256) {
         const int p = e / N, i = e % N;
         const int mx = signed_freq(i, N);
-        s[e] = (mx >= -Rr && mx <= Rr) ? src[(row0 + p) * Wp + mx + Rr] : C{R(0), R(0)};
+        s[p * pencil_ld<N>() + pad_idx(i)] = (mx >= -Rr && mx <= Rr) ? src[(row0 + p) * Wp + mx + Rr] : C{R(0), R(0)};
     }
     __syncthreads();
-    fft_pencils<C, N, N, G, +1>(s, tws);
+    fft_pencils<C, N, pencil_ld<N>(), G, +1>(s, tws);
     R *d1 = f1 + map * field_stride;
-    for (int e = threadIdx.x; e < G * N; e += 256) d1[row0 * N + e] = s[e].x;
+    for (int e = threadIdx.x; e < G * N; e += 256) d1[row0 * N + e] = s[(e / N) * pencil_ld<N>() + pad_idx(e % N)].x;
     if (f2) {
         R *d2 = f2 + map * field_stride;
-        for (int e = threadIdx.x; e < G * N; e += 256) d2[row0 * N + e] = s[e].y;
+        for (int e = threadIdx.x; e < G * N; e += 256)
+            d2[row0 * N + e] = s[(e / N) * pencil_ld<N>() + pad_idx(e % N)].y;
     }
 }
 

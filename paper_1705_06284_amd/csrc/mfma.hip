@@ -250,7 +250,8 @@ __global__ __launch_bounds__(NT) void k_tail(const float2 *__restrict__ bc, Tail
     constexpr int RT = TK / N;
     constexpr int G = 16 * RT;                 // pencil slots: RT rows x 16 pairs
     constexpr int FS = TK + 4, BS = TK + 8;
-    constexpr int FFT_BYTES = G * N * 8;
+    constexpr int LDP = pencil_ld<N>();
+    constexpr int FFT_BYTES = G * LDP * 8;
     constexpr int SPLIT_BYTES = MODE == PG_MODE_SPLIT ? 2 * 32 * BS * 2 : 0;
     constexpr int UBYTES = FFT_BYTES > SPLIT_BYTES ? FFT_BYTES : SPLIT_BYTES;
     constexpr int PF = G * N / NT;             // prefetched elements per thread
@@ -299,15 +300,18 @@ __global__ __launch_bounds__(NT) void k_tail(const float2 *__restrict__ bc, Tail
             float2 v[PF];
             fetch(tile, v);
 #pragma unroll
-            for (int k = 0; k < PF; ++k) fb[tid + k * NT] = v[k];
+            for (int k = 0; k < PF; ++k) {
+                const int e = tid + k * NT;
+                fb[(e / N) * LDP + pad_idx(e % N)] = v[k];
+            }
         }
         __syncthreads();
-        fft_pencils<float2, N, N, G, +1, NT>(fb, tws);
+        fft_pencils<float2, N, LDP, G, +1, NT>(fb, tws);
         for (int e = tid; e < G * N; e += NT) {
             const int sl = e / N, n = e % N;
             const int r = sl / 16, q = sl % 16;
             if (q < tp.npairs) {
-                const float2 v = fb[e];
+                const float2 v = fb[sl * LDP + pad_idx(n)];
                 Ft[(2 * q) * FS + r * N + n] = v.x;
                 if (2 * q + 1 < nb) Ft[(2 * q + 1) * FS + r * N + n] = v.y;
             }
