@@ -37,6 +37,8 @@ def parse():
     ap.add_argument("--no-compare", action="store_true", help="skip the FP32 comparison paths")
     ap.add_argument("--cpu-budget", type=float, default=1.2e9,
                     help="pair steps of the direct-sum oracle sample")
+    ap.add_argument("--no-serving", action="store_true", help="skip the request-stream measurement")
+    ap.add_argument("--serving-requests", type=int, default=400)
     return ap.parse_args()
 
 
@@ -85,6 +87,45 @@ def cpu_baseline(field, lo, hi, trip, budget):
             "sample": "FP64 direct-sum oracle on the same %d^3 map: its separable DFT plus the %d of %d "
                       "closed triplets with the cheapest closed-pair loops (%.2e pair steps), %.1f s"
                       % (field.shape[0], len(sel), len(trip), used, dt)}
+
+
+def serving_run(n_requests, warmup=50, load=0.7, seed=5):
+    """Poisson stream of 64^3/128^3/256^3 lognormal maps (4:2:1) on one GPU:
+    saturation throughput from a burst, then p50/p99 latency at `load` times
+    that rate.  Each request asks for 12 equilateral + 12 squeezed triplets
+    and P at 12 bins.  Maps come from a pool of 8/4/2 seeded fields per size
+    (seed 5000 + i), pinned in host memory before the run."""
+    import numpy as np
+    from paper_1705_06284_amd import serving, synth
+    sizes = (64, 128, 256)
+    be = serving.GpuBackend()
+    pool = {n: [be.pinned(synth.lognormal_field(n, 1.5, 1.0, 5000 + i)) for i in range(k)]
+            for n, k in zip(sizes, (8, 4, 2))}
+    ns = serving.mixed_sizes(n_requests + warmup, seed)
+
+    def reqs(offset):
+        return [serving.Request(rid=i, n=int(n), field=pool[int(n)][i % len(pool[int(n)])])
+                for i, n in enumerate(ns[offset:], start=offset)]
+
+    srv = serving.Server(be, sizes=sizes, slots_per_size=2, max_batch=4)
+    burst = reqs(0)
+    t0 = time.perf_counter()
+    srv.run(burst, [0.0] * len(burst))
+    sat = len(burst) / (time.perf_counter() - t0)
+    srv.finished.clear()
+    rate = load * sat
+    arr = serving.poisson_arrivals(rate, n_requests + warmup, seed)
+    stream = reqs(0)
+    t0 = time.perf_counter()
+    done = srv.run(stream, list(arr))
+    wall = time.perf_counter() - t0
+    measured = [r for r in done if r.rid >= warmup]
+    summ = serving.latency_summary(measured)
+    ntri = 24
+    summ.update({"rate_maps_per_s": rate, "saturation_maps_per_s": sat, "maps_per_s": len(done) / wall,
+                 "triangles_per_s": len(done) * ntri / wall, "requests": len(measured), "warmup": warmup,
+                 "mix": "64^3:128^3:256^3 = 4:2:1, 12 equilateral + 12 squeezed + P, slots 2/size, batch <= 4"})
+    return summ
 
 
 def main():
@@ -168,6 +209,9 @@ def main():
         out["split_vs_fp32"] = {"end_to_end": out["fp32_path"]["ms_per_step"] / out["ms_per_step"],
                                 "contraction": st32["contract"] / max(stages["contract"], 1e-9)}
         plan.set_precision("split_bf16")
+
+    if not args.no_serving:
+        out["serving"] = serving_run(args.serving_requests)
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(field, lo, hi, plan.triplets, args.cpu_budget)
