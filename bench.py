@@ -198,6 +198,16 @@ def main():
         out["roofline"] = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                            "frac": ach / HBM_PEAK_GBS, "traffic": None, "kernel": "inverse FFT stage"}
 
+    # the same steps replayed from a captured HIP graph (no stage events)
+    plan.set_precision("split_bf16")
+    plan.graph(True)
+    step()
+    torch.cuda.synchronize()
+    wg, latg = timed_steps(torch, step, args.steps, stream)
+    plan.graph(False)
+    out["graph_replay"] = {"value": ntri * bsz * args.steps / wg, "ms_per_step": 1e3 * wg / args.steps,
+                           "latency_ms": {"p50": percentile(latg, 50), "p99": percentile(latg, 99)}}
+
     if not args.no_compare:
         w32, lat32, st32 = run("fp32", args.steps, 2, timing=True)
         wv, latv, stv = run("fp32_valu", max(3, args.steps // 4), 1, timing=True)

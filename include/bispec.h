@@ -162,6 +162,16 @@ bispec_status bispec_timing_enable(bispec_plan_t plan, int32_t on);
 bispec_status bispec_timing_read(bispec_plan_t plan, double *stage_ms /*[BISPEC_N_STAGES]*/,
                                  int32_t *calls);
 
+/* Graph replay.  While enabled, polyspec_estimate (and bispec_estimate,
+ * trispec_estimate) captures its launch sequence on the plan's stream into a
+ * HIP graph the first time it sees a (delta, P, B, T, batch, precision)
+ * combination and replays that graph on later calls with the same
+ * arguments (up to 8 cached; the contents behind the pointers may change
+ * freely).  Calls fall back to direct launches on the legacy NULL stream or
+ * while stage timing is on.  Changing the workspace, precision or stream
+ * discards the captured graphs. */
+bispec_status bispec_graph_enable(bispec_plan_t plan, int32_t on);
+
 bispec_status bispec_destroy(bispec_plan_t plan);
 const char *bispec_status_string(bispec_status status);
 

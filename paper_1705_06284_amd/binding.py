@@ -59,6 +59,7 @@ _SIGS = {
     "trispec_estimate": [_vp, _vp, _i32, _vp],
     "polyspec_estimate": [_vp, _vp, _i32, _vp, _vp, _vp],
     "bispec_timing_enable": [_vp, _i32],
+    "bispec_graph_enable": [_vp, _i32],
     "bispec_timing_read": [_vp, _dp, _ip],
     "bispec_destroy": [_vp],
 }
@@ -85,6 +86,7 @@ bispec_estimate = _lib.bispec_estimate
 trispec_estimate = _lib.trispec_estimate
 polyspec_estimate = _lib.polyspec_estimate
 bispec_timing_enable = _lib.bispec_timing_enable
+bispec_graph_enable = _lib.bispec_graph_enable
 bispec_timing_read = _lib.bispec_timing_read
 bispec_destroy = _lib.bispec_destroy
 N_STAGES = 4
@@ -218,6 +220,9 @@ class Plan:
             self.workspace_bytes = sz.value
             self.workspace = self._torch.empty(sz.value, dtype=self._torch.uint8, device=self.device)
             check(bispec_set_workspace(self.handle, _ptr(self.workspace), sz.value), "bispec_set_workspace")
+
+    def graph(self, on=True):
+        check(bispec_graph_enable(self.handle, 1 if on else 0), "bispec_graph_enable")
 
     def timing(self, on=True):
         check(bispec_timing_enable(self.handle, 1 if on else 0), "bispec_timing_enable")

@@ -98,7 +98,13 @@ Layout make_layout(const bispec_plan_s &p, int batch) {
 
 }  // namespace bispec
 
+void bispec_plan_s::drop_graphs() {
+    for (auto &g : graphs) (void)hipGraphExecDestroy(g.exec);
+    graphs.clear();
+}
+
 bispec_plan_s::~bispec_plan_s() {
+    drop_graphs();
     for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
     for (hipEvent_t e : ev_rec) (void)hipEventDestroy(e);
 }
@@ -761,6 +767,7 @@ bispec_status bispec_set_workspace(bispec_plan_t plan, void *dev_ptr, size_t byt
     if (!plan || !dev_ptr) return BISPEC_E_INVALID;
     if (((uintptr_t)dev_ptr) % kAlign) return BISPEC_E_INVALID;
     if (bytes < make_layout(*plan, plan->max_batch).total) return BISPEC_E_NO_WORKSPACE;
+    plan->drop_graphs();
     plan->ws = dev_ptr;
     plan->ws_bytes = bytes;
     plan->ws_fields = needs_fields(*plan);
@@ -777,12 +784,14 @@ bispec_status bispec_set_workspace(bispec_plan_t plan, void *dev_ptr, size_t byt
 bispec_status bispec_set_precision(bispec_plan_t plan, int32_t precision) {
     if (!plan || precision < BISPEC_FP32 || precision > BISPEC_FP32_VALU) return BISPEC_E_INVALID;
     plan->precision = precision;
+    plan->drop_graphs();
     return BISPEC_OK;
 }
 
 bispec_status bispec_set_stream(bispec_plan_t plan, void *stream) {
     if (!plan) return BISPEC_E_INVALID;
     plan->stream = (hipStream_t)stream;
+    plan->drop_graphs();
     return BISPEC_OK;
 }
 
@@ -830,10 +839,43 @@ bispec_status polyspec_estimate(bispec_plan_t plan, const float *delta, int32_t 
     bispec_status s = check_call(plan, delta, batch);
     if (s != BISPEC_OK) return s;
     try {
-        return run_estimate(*plan, delta, batch, P, B, T);
+        bispec_plan_s &p = *plan;
+        if (!p.use_graph || p.timing || p.stream == nullptr) return run_estimate(p, delta, batch, P, B, T);
+        for (auto &g : p.graphs)
+            if (g.delta == delta && g.P == P && g.B == B && g.T == T && g.batch == batch && g.precision == p.precision) {
+                CK(hipGraphLaunch(g.exec, p.stream));
+                return BISPEC_OK;
+            }
+        // capture the launch sequence once for these arguments
+        hipGraph_t graph = nullptr;
+        CK(hipStreamBeginCapture(p.stream, hipStreamCaptureModeThreadLocal));
+        s = run_estimate(p, delta, batch, P, B, T);
+        const hipError_t e = hipStreamEndCapture(p.stream, &graph);
+        if (s != BISPEC_OK || e != hipSuccess) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return s != BISPEC_OK ? s : record(BISPEC_E_HIP, "hipStreamEndCapture", e);
+        }
+        hipGraphExec_t exec = nullptr;
+        const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (ei != hipSuccess) return record(BISPEC_E_HIP, "hipGraphInstantiate", ei);
+        if (p.graphs.size() >= 8) {
+            (void)hipGraphExecDestroy(p.graphs.front().exec);
+            p.graphs.erase(p.graphs.begin());
+        }
+        p.graphs.push_back({delta, P, B, T, batch, p.precision, exec});
+        CK(hipGraphLaunch(exec, p.stream));
+        return BISPEC_OK;
     } catch (...) {
         return BISPEC_E_HIP;
     }
+}
+
+bispec_status bispec_graph_enable(bispec_plan_t plan, int32_t on) {
+    if (!plan) return BISPEC_E_INVALID;
+    plan->use_graph = on != 0;
+    if (!plan->use_graph) plan->drop_graphs();
+    return BISPEC_OK;
 }
 
 bispec_status bispec_estimate(bispec_plan_t plan, const float *delta, int32_t batch, double *B, double *P) {

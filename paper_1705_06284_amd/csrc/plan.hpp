@@ -50,6 +50,17 @@ struct bispec_plan_s {
     std::vector<hipEvent_t> ev_pool;     // free events
     std::vector<hipEvent_t> ev_rec;      // 5 per recorded call
     hipEvent_t ev_cur[5] = {};
+    // captured launch sequences of polyspec_estimate, keyed by the call's
+    // pointers, batch and precision (replayed with hipGraphLaunch)
+    struct GraphEntry {
+        const void *delta;
+        const void *P, *B, *T;
+        int batch, precision;
+        hipGraphExec_t exec;
+    };
+    bool use_graph = false;
+    std::vector<GraphEntry> graphs;
+    void drop_graphs();
     ~bispec_plan_s();
 };
 

@@ -94,6 +94,7 @@ class GpuBackend:
         torch = self.torch
         stream = torch.cuda.Stream(self.device)
         plan = self._plan(n, max_batch, stream)
+        plan.graph(True)          # the slot's buffers are fixed: replay captured launches
         slot = {
             "n": n, "plan": plan, "stream": stream, "max_batch": max_batch,
             "inp": torch.empty(max_batch, n, n, n, dtype=torch.float32, device=self.device),
