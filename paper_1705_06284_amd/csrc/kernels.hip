@@ -88,9 +88,14 @@ __global__ __launch_bounds__(256) void k_fwd_x(const float *__restrict__ delta, 
     const double mu = mean[map];
     const int64_t row0 = (int64_t)blockIdx.x * G;
     constexpr int LD = pencil_ld<N>();
-    for (int e = threadIdx.x; e < G * N; e += 256) {
-        const double v = (double)src[row0 * N + e] - mu;
-        s[(e / N) * LD + pad_idx(e % N)] = float2{(float)v, 0.0f};
+    constexpr int PER = G * N / 256;
+    float x[PER];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) x[k] = src[row0 * N + threadIdx.x + k * 256];   // all loads in flight
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int e = threadIdx.x + k * 256;
+        s[(e / N) * LD + pad_idx(e % N)] = float2{(float)((double)x[k] - mu), 0.0f};
     }
     __syncthreads();
     fft_pencils<float2, N, LD, G, -1>(s, tws);
@@ -111,12 +116,20 @@ __global__ __launch_bounds__(256) void k_fft_strided(cplx<R> *__restrict__ vol_b
     C *v = vol_base + (int64_t)blockIdx.y * map_stride;
     const int64_t p0 = (int64_t)blockIdx.x * G;   // first pencil (c * N + x)
     const int64_t stride = AXIS == 1 ? N : (int64_t)N * N;
-    for (int e = threadIdx.x; e < G * N; e += 256) {
+    constexpr int PER = G * N / 256;
+    C x[PER];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int e = threadIdx.x + k * 256;
         const int p = e % G, i = e / G;
         const int64_t pl = p0 + p;
-        const int64_t c = pl / N, x = pl % N;
-        const int64_t addr = AXIS == 1 ? c * N * N + i * stride + x : (int64_t)i * stride + pl;
-        s[p * pencil_ld<N>() + pad_idx(i)] = v[addr];
+        const int64_t c = pl / N, xx = pl % N;
+        x[k] = v[AXIS == 1 ? c * N * N + i * stride + xx : (int64_t)i * stride + pl];
+    }
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int e = threadIdx.x + k * 256;
+        s[(e % G) * pencil_ld<N>() + pad_idx(e / G)] = x[k];
     }
     __syncthreads();
     fft_pencils<C, N, pencil_ld<N>(), G, DIR>(s, tws);
@@ -168,25 +181,35 @@ __global__ __launch_bounds__(256) void k_inv_z_prune(const cplx<R> *__restrict__
     C *o = abox + P.aoff + map * P.astride;
     const int Wp = P.g.Wp, Rr = P.g.R;
     const int *cl = cols + P.col_off;
-    for (int e = threadIdx.x; e < G * N; e += 256) {
-        const int p = e % G, i = e / G;
-        C v = C{R(0), R(0)};
-        if (c0 + p < P.ncols) {
-            const int box = cl[c0 + p];              // (m_y + R) * Wp + (m_x + R)
-            const int my = box / Wp - Rr, mx = box % Wp - Rr;
-            const int mz = signed_freq(i, N);
-            const int r2 = mz * mz + my * my + mx * mx;
-            const bool in1 = r2 >= P.g.lo1 && r2 < P.g.hi1;
-            const bool in2 = r2 >= P.g.lo2 && r2 < P.g.hi2;
-            if (in1 || in2) {
-                C d;
-                if constexpr (UNIT) d = C{R(1), R(0)};
-                else d = sp[((int64_t)i * N + (my & (N - 1))) * N + (mx & (N - 1))];
-                const R a1 = in1 ? R(1) : R(0), a2 = in2 ? R(1) : R(0);
-                v = C{d.x * a1 - d.y * a2, d.y * a1 + d.x * a2};
-            }
+    constexpr int PER = G * N / 256;
+    // this thread's column is fixed (p = tid % G since 256 is a multiple of G)
+    const int p = threadIdx.x % G;
+    const bool live = c0 + p < P.ncols;
+    const int box = live ? cl[c0 + p] : 0;           // (m_y + R) * Wp + (m_x + R)
+    const int my = box / Wp - Rr, mx = box % Wp - Rr;
+    const int64_t col_addr = (int64_t)(my & (N - 1)) * N + (mx & (N - 1));
+    C d[PER];
+    unsigned in_mask1 = 0, in_mask2 = 0;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int i = (threadIdx.x + k * 256) / G;
+        const int mz = signed_freq(i, N);
+        const int r2 = mz * mz + my * my + mx * mx;
+        const bool in1 = live && r2 >= P.g.lo1 && r2 < P.g.hi1;
+        const bool in2 = live && r2 >= P.g.lo2 && r2 < P.g.hi2;
+        in_mask1 |= (unsigned)in1 << k;
+        in_mask2 |= (unsigned)in2 << k;
+        d[k] = C{R(0), R(0)};
+        if (in1 || in2) {
+            if constexpr (UNIT) d[k] = C{R(1), R(0)};
+            else d[k] = sp[(int64_t)i * N * N + col_addr];
         }
-        s[p * pencil_ld<N>() + pad_idx(i)] = v;
+    }
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int i = (threadIdx.x + k * 256) / G;
+        const R a1 = (in_mask1 >> k) & 1 ? R(1) : R(0), a2 = (in_mask2 >> k) & 1 ? R(1) : R(0);
+        s[p * pencil_ld<N>() + pad_idx(i)] = C{d[k].x * a1 - d[k].y * a2, d[k].y * a1 + d[k].x * a2};
     }
     __syncthreads();
     fft_pencils<C, N, pencil_ld<N>(), G, +1>(s, tws);
@@ -217,17 +240,23 @@ __global__ __launch_bounds__(256) void k_inv_y_prune(const cplx<R> *__restrict__
     const int W = P.g.W, Wp = P.g.Wp, Rr = P.g.R;
     const int ncols = N * Wp;
     const int64_t plane = (int64_t)W * Wp;
-    for (int e = threadIdx.x; e < G * N; e += 256) {
-        const int p = e % G, i = e / G;
-        C v = C{R(0), R(0)};
+    constexpr int PER = G * N / 256;
+    {
+        const int p = threadIdx.x % G;               // fixed column of this thread
         const int c = c0 + p;
         const int nz = c / Wp, xi = c % Wp;
-        if (c < ncols && xi < W) {
-            const int mx = xi - Rr, my = signed_freq(i, N);
-            if (my >= -Rr && my <= Rr && my * my + mx * mx < P.g.hmax)
-                v = a[(int64_t)nz * plane + (int64_t)(my + Rr) * Wp + xi];
+        const bool live = c < ncols && xi < W;
+        const int mx = xi - Rr;
+        const C *col = a + (int64_t)nz * plane + xi;
+        C v[PER];
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int my = signed_freq((threadIdx.x + k * 256) / G, N);
+            v[k] = C{R(0), R(0)};
+            if (live && my >= -Rr && my <= Rr && my * my + mx * mx < P.g.hmax) v[k] = col[(int64_t)(my + Rr) * Wp];
         }
-        s[p * pencil_ld<N>() + pad_idx(i)] = v;
+#pragma unroll
+        for (int k = 0; k < PER; ++k) s[p * pencil_ld<N>() + pad_idx((threadIdx.x + k * 256) / G)] = v[k];
     }
     __syncthreads();
     fft_pencils<C, N, pencil_ld<N>(), G, +1>(s, tws);
@@ -254,10 +283,18 @@ __global__ __launch_bounds__(256) void k_inv_x_compact(const cplx<R> *__restrict
     const C *src = bc + map * bc_stride;
     const int Wp = g.Wp, Rr = g.R;
     const int64_t row0 = (int64_t)blockIdx.x * G;
-    for (int e = threadIdx.x; e < G * N; e += 256) {
-        const int p = e / N, i = e % N;
-        const int mx = signed_freq(i, N);
-        s[p * pencil_ld<N>() + pad_idx(i)] = (mx >= -Rr && mx <= Rr) ? src[(row0 + p) * Wp + mx + Rr] : C{R(0), R(0)};
+    constexpr int PER = G * N / 256;
+    C v[PER];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int e = threadIdx.x + k * 256;
+        const int p = e / N, mx = signed_freq(e % N, N);
+        v[k] = (mx >= -Rr && mx <= Rr) ? src[(row0 + p) * Wp + mx + Rr] : C{R(0), R(0)};
+    }
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int e = threadIdx.x + k * 256;
+        s[(e / N) * pencil_ld<N>() + pad_idx(e % N)] = v[k];
     }
     __syncthreads();
     fft_pencils<C, N, pencil_ld<N>(), G, +1>(s, tws);

@@ -285,3 +285,29 @@ def test_graph_replay_matches_eager(binding):
         junk.mul_(1.0001).add_(0.5)          # eager work between replays
         torch.cuda.synchronize()
     plan.graph(False)
+
+
+@pytest.mark.parametrize("prec", ["split_bf16"])
+def test_c4_lognormal_512_sampled(binding, prec):
+    """512^3 lognormal field, 32 bins: the full triplet set (3384), P, and the
+    collapsed quads, checked on the triplets the oracle finishes quickly."""
+    n = 512
+    wl = "c4_512_lognormal"
+    lo, hi = synth.workload_bins(wl)
+    d = synth.workload_field(wl)
+    _say("c4 512^3 sampled %s" % prec)
+    plan = binding.Plan(n, lo, hi, precision=prec)
+    P, B, T = plan.polyspec(d)
+    trip = plan.triplets
+    assert len(trip) == 3384 and plan.n_quad == 528
+    sel = _cheap_triplets(n, lo, hi, trip, 1.5e9)
+    idx = [int(np.flatnonzero((trip == t).all(1))[0]) for t in sel]
+    _say("  oracle DFT 512^3")
+    Dk = oracle.dft3(oracle.prepare(d))
+    ref = oracle.bispectrum(d, lo, hi, sel, delta_k=Dk)
+    assert np.array_equal(plan.counts[idx].astype(np.int64), ref.count)
+    e = _err(B.cpu().numpy()[0][idx], ref)
+    _say("  %d sampled triplets, max err %.2e" % (len(sel), e.max()))
+    assert np.max(e) <= TOL[prec]
+    refp, _ = oracle.power_spectrum(d, lo, hi, delta_k=Dk)
+    assert np.max(np.abs(P.cpu().numpy()[0] - refp) / refp) <= TOL[prec]
