@@ -39,7 +39,46 @@ def parse():
                     help="pair steps of the direct-sum oracle sample")
     ap.add_argument("--no-serving", action="store_true", help="skip the request-stream measurement")
     ap.add_argument("--serving-requests", type=int, default=400)
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shape")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="also run a plain device copy of MIB MiB (5 times), the reference kernel "
+                         "for scaling the HBM byte counters of a profiler run")
     return ap.parse_args()
+
+
+TAIL_SOURCES = ("paper_1705_06284_amd/csrc/mfma.hip", "paper_1705_06284_amd/csrc/fft_core.hpp",
+                "paper_1705_06284_amd/csrc/launch.hpp")
+
+
+def tail_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in TAIL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload, nblk, wide):
+    """HBM bytes per launch of the tail kernel from the committed counter
+    summary, if it was taken on the current kernel source with this launch
+    shape; else None."""
+    path = os.path.join(ROOT, "profiles", "k_tail_%s_traffic.txt" % workload)
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    try:
+        if (kv.get("source_sha256") != tail_source_hash() or int(kv["nblk"]) != nblk
+                or int(kv["wide"]) != int(wide)):
+            return None
+        return float(kv["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def timed_steps(torch, step, steps, stream):
@@ -148,6 +187,7 @@ def main():
     bsz = args.batch
     plan = binding.Plan(n, lo, hi, precision="split_bf16", max_batch=bsz, stream=stream, device=dev)
     ntri, nq, nb = plan.n_tri, plan.n_quad, plan.n_bins
+    tuned = plan.autotune() if not args.no_autotune else (None, None)
     d = torch.from_numpy(np.broadcast_to(field, (bsz,) + field.shape).copy()).to(dev)
     P = torch.empty(bsz, nb, dtype=torch.float64, device=dev)
     B = torch.empty(bsz, ntri, dtype=torch.float64, device=dev)
@@ -179,7 +219,7 @@ def main():
            "config": {"workload": wl, "n": n, "bins": nb, "triplets": ntri, "quads": nq, "batch": bsz,
                       "precision": "split_bf16", "outputs": "B, P, T"},
            "latency_ms": {"p50": percentile(lat, 50), "p99": percentile(lat, 99)},
-           "stages_ms": stages}
+           "stages_ms": stages, "tuning": {"tail_blocks": tuned[0], "tail_wide": tuned[1]}}
 
     # dominant kernel and its roofline
     npix = float(n) ** 3
@@ -190,8 +230,11 @@ def main():
     if con_ms >= inv_ms:
         flops = (2.0 * ntri + pairs) * npix          # algorithmic: pair products + one FMA per triplet
         ach = flops / (con_ms * 1e-3) / 1e12
+        traffic = measured_traffic(wl, tuned[0], tuned[1]) if bsz == 1 and tuned[0] else None
         out["roofline"] = {"bound": "mfma", "achieved": ach, "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
-                           "frac": ach / BF16_PEAK_TFLOPS, "traffic": None, "kernel": "k_pgram<split>"}
+                           "frac": ach / BF16_PEAK_TFLOPS, "traffic": traffic,
+                           "kernel": "k_tail<split> (last inverse pass + split-BF16 product-Gram)",
+                           "launch_ms": con_ms, "algorithmic_flop": flops}
     else:
         byts = float(np.sum(modes) * 8 + nb * npix * 4)   # shell modes read + bin fields written
         ach = byts / (inv_ms * 1e-3) / 1e9
@@ -222,6 +265,16 @@ def main():
 
     if not args.no_serving:
         out["serving"] = serving_run(args.serving_requests)
+
+    if args.copy_calibration > 0:
+        cnt = args.copy_calibration * (1 << 18)
+        src = torch.ones(cnt, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_calibration"] = {"bytes_read": 4 * cnt, "bytes_written": 4 * cnt, "launches": 5}
+        del src, dst
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(field, lo, hi, plan.triplets, args.cpu_budget)

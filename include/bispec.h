@@ -162,6 +162,25 @@ bispec_status bispec_timing_enable(bispec_plan_t plan, int32_t on);
 bispec_status bispec_timing_read(bispec_plan_t plan, double *stage_ms /*[BISPEC_N_STAGES]*/,
                                  int32_t *calls);
 
+/* Autotuner: times the fused last-pass + contraction kernel on the attached
+ * workspace (zeroed compact rows) for the default block count per map (one
+ * per CU, and enough that no block contracts more than 64 tiles of
+ * max(N, 512) points) and two and four times it, within the partial buffer
+ * the footprint reserves, and for both block shapes (16 waves with one output
+ * tile each, when the tiles fit, or 8 waves with up to three); keeps the
+ * fastest (a larger count or the deep shape must win by 1.5 %) and reports
+ * it.  Synchronises the stream.  bispec_set_tuning restores a stored choice;
+ * BISPEC_E_INVALID if nblk is below the 64-tile limit or above the buffer. */
+bispec_status bispec_autotune(bispec_plan_t plan, int32_t *nblk_out, int32_t *wide_out);
+bispec_status bispec_set_tuning(bispec_plan_t plan, int32_t nblk, int32_t wide);
+
+/* Condition number of each planned triplet's real-space sum,
+ * kappa_t = sqrt(M_i M_j M_k / (N_pix N_t)) (infinity when N_t = 0): the
+ * factor by which rounding in the FFTs and the contraction is amplified
+ * relative to the random-phase noise level of B_t.  Triplets near the edge
+ * of the triangle inequality with few closed triples have large kappa. */
+bispec_status bispec_plan_condition(bispec_plan_t plan, double *kappa_out /*[n_tri]*/);
+
 /* Graph replay.  While enabled, polyspec_estimate (and bispec_estimate,
  * trispec_estimate) captures its launch sequence on the plan's stream into a
  * HIP graph the first time it sees a (delta, P, B, T, batch, precision)

@@ -60,6 +60,9 @@ _SIGS = {
     "polyspec_estimate": [_vp, _vp, _i32, _vp, _vp, _vp],
     "bispec_timing_enable": [_vp, _i32],
     "bispec_graph_enable": [_vp, _i32],
+    "bispec_autotune": [_vp, _ip, _ip],
+    "bispec_set_tuning": [_vp, _i32, _i32],
+    "bispec_plan_condition": [_vp, _dp],
     "bispec_timing_read": [_vp, _dp, _ip],
     "bispec_destroy": [_vp],
 }
@@ -87,6 +90,9 @@ trispec_estimate = _lib.trispec_estimate
 polyspec_estimate = _lib.polyspec_estimate
 bispec_timing_enable = _lib.bispec_timing_enable
 bispec_graph_enable = _lib.bispec_graph_enable
+bispec_autotune = _lib.bispec_autotune
+bispec_set_tuning = _lib.bispec_set_tuning
+bispec_plan_condition = _lib.bispec_plan_condition
 bispec_timing_read = _lib.bispec_timing_read
 bispec_destroy = _lib.bispec_destroy
 N_STAGES = 4
@@ -220,6 +226,21 @@ class Plan:
             self.workspace_bytes = sz.value
             self.workspace = self._torch.empty(sz.value, dtype=self._torch.uint8, device=self.device)
             check(bispec_set_workspace(self.handle, _ptr(self.workspace), sz.value), "bispec_set_workspace")
+
+    def autotune(self):
+        """Time the contraction kernel's launch shapes; returns (blocks, wide)."""
+        nb, wd = ctypes.c_int32(), ctypes.c_int32()
+        check(bispec_autotune(self.handle, ctypes.byref(nb), ctypes.byref(wd)), "bispec_autotune")
+        return nb.value, bool(wd.value)
+
+    def set_tuning(self, nblk, wide):
+        check(bispec_set_tuning(self.handle, int(nblk), 1 if wide else 0), "bispec_set_tuning")
+
+    @property
+    def condition(self):
+        out = np.zeros(self.n_tri, np.float64)
+        check(bispec_plan_condition(self.handle, out.ctypes.data_as(_dp)), "bispec_plan_condition")
+        return out
 
     def graph(self, on=True):
         check(bispec_graph_enable(self.handle, 1 if on else 0), "bispec_graph_enable")

@@ -86,7 +86,8 @@ Layout make_layout(const bispec_plan_s &p, int batch) {
     L.bc = off;           off = align_up(off + sizeof(float2) * (size_t)p.n * p.n * p.wsum * batch);
     L.partial = off;      off = align_up(off + sizeof(double) * (size_t)p.nblk * p.terms.size() * batch);
     L.pg_partial = off;
-    if (p.mfma_ok) off = align_up(off + sizeof(double) * pgram_partial_doubles(p.n_mtile, true) * p.nblk_pg * batch);
+    if (p.mfma_ok)
+        off = align_up(off + sizeof(double) * pgram_partial_doubles(p.n_mtile, true) * p.nblk_pg_max * batch);
     L.pg_dense = off;
     if (p.mfma_ok) off = align_up(off + sizeof(double) * pgram_partial_doubles(p.n_mtile, true) * batch);
     // bin fields in HBM: only the vector-ALU contraction and general quads read them
@@ -527,10 +528,16 @@ bispec_status plan_impl(const bispec_plan_desc *d, bispec_plan_t *out) {
     p->quad_count = quad_cnt;
     p->nblk = contract_blocks((int64_t)n * n * n);
     {
-        // one product-Gram block per CU (about 100 KiB of LDS each), fewer for
-        // small grids: at least 1024 points per block
-        int64_t b = (int64_t)n * n * n / 1024;
-        p->nblk_pg = (int)std::max<int64_t>(1, std::min<int64_t>(256, b));
+        // Tail blocks: every block contracts at most PG_CHUNK_TILES tiles
+        // (its FP32 accumulation span), and there are at least 256 blocks
+        // (one per CU) when the map has that many tiles.  The tuner may take
+        // up to four times the default, within 2048 blocks.
+        const int64_t tiles = tail_tiles(n);
+        const int64_t need = (tiles + PG_CHUNK_TILES - 1) / PG_CHUNK_TILES;
+        const int64_t lo = std::max<int64_t>(need, std::min<int64_t>(tiles, 256));
+        p->nblk_pg_min = (int)need;
+        p->nblk_pg = (int)lo;
+        p->nblk_pg_max = (int)std::min<int64_t>(tiles, std::max<int64_t>(lo, std::min<int64_t>(4 * lo, 2048)));
     }
     build_terms(*p);
     own.keep = true;
@@ -707,7 +714,7 @@ bispec_status run_estimate_body(bispec_plan_s &p, const float *delta, int batch,
         double *pg = (double *)(ws + L.pg_partial);
         double *dense = (double *)(ws + L.pg_dense);
         CK(launch_tail(mode, t_mfma, (const float2 *)(ws + L.bc), tp, n, p.nb, batch,
-                       (const uchar2 *)(ws + L.pg_pairs), p.n_mtile, tw, p.nblk_pg, pg, p.stream));
+                       (const uchar2 *)(ws + L.pg_pairs), p.n_mtile, tw, p.nblk_pg, pg, p.stream, p.tail_wide));
         const int64_t n_dense = (int64_t)pgram_partial_doubles(p.n_mtile, t_mfma);
         stamp(p, 3);
         CK(launch_reduce_dense(pg, p.nblk_pg, n_dense, batch, dense, p.stream));
@@ -869,6 +876,94 @@ bispec_status polyspec_estimate(bispec_plan_t plan, const float *delta, int32_t 
     } catch (...) {
         return BISPEC_E_HIP;
     }
+}
+
+bispec_status bispec_autotune(bispec_plan_t plan, int32_t *nblk_out, int32_t *wide_out) {
+    if (!plan) return BISPEC_E_INVALID;
+    bispec_plan_s &p = *plan;
+    if (!p.ws) return BISPEC_E_NO_WORKSPACE;
+    if (p.mfma_ok) {
+        try {
+            const Layout L = make_layout(p, p.max_batch);
+            char *ws = (char *)p.ws;
+            const int n = p.n;
+            // well-defined operands: zero compact rows
+            CK(hipMemsetAsync(ws + L.bc, 0, sizeof(float2) * (size_t)n * n * p.wsum * p.max_batch, p.stream));
+            TailPairs tp{};
+            tp.npairs = (int)p.pairs.size();
+            for (int q = 0; q < tp.npairs; ++q) {
+                tp.R[q] = p.pairs[q].R;
+                tp.W[q] = p.pairs[q].Wp;
+                tp.off[q] = p.bc_off[q] * (long long)n * n * p.max_batch;
+            }
+            const int mode = p.precision == BISPEC_SPLIT_BF16 ? PG_MODE_SPLIT : PG_MODE_F32;
+            const bool t = p.quads_collapsed;
+            hipEvent_t e0, e1;
+            CK(hipEventCreate(&e0));
+            CK(hipEventCreate(&e1));
+            // candidates: the default block count and two and four times it;
+            // a larger count or the deep shape must win by 1.5 % to be kept
+            // (fewer partial tiles to write and reduce)
+            float best = 1e30f;
+            int best_nblk = p.nblk_pg;
+            bool best_wide = p.tail_wide;
+            const int base = p.nblk_pg;
+            for (int wide = 1; wide >= 0; --wide) {
+                if (wide && !tail_wide_fits(p.n_mtile, t)) continue;
+                for (int nb : {base, 2 * base, 4 * base}) {
+                    if (nb > p.nblk_pg_max) continue;
+                    float tot = 0.0f;
+                    for (int rep = 0; rep < 3; ++rep) {
+                        CK(hipEventRecord(e0, p.stream));
+                        CK(launch_tail(mode, t, (const float2 *)(ws + L.bc), tp, n, p.nb, 1,
+                                       (const uchar2 *)(ws + L.pg_pairs), p.n_mtile, (const float2 *)(ws + L.tw),
+                                       nb, (double *)(ws + L.pg_partial), p.stream, wide != 0));
+                        CK(hipEventRecord(e1, p.stream));
+                        CK(hipEventSynchronize(e1));
+                        float ms = 0.0f;
+                        CK(hipEventElapsedTime(&ms, e0, e1));
+                        if (rep) tot += ms;        // first run warms up
+                    }
+                    if (tot < best * 0.985f || best >= 1e30f) {
+                        best = tot;
+                        best_nblk = nb;
+                        best_wide = wide != 0;
+                    }
+                }
+            }
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            p.nblk_pg = best_nblk;
+            p.tail_wide = best_wide;
+            p.drop_graphs();
+        } catch (...) {
+            return BISPEC_E_HIP;
+        }
+    }
+    if (nblk_out) *nblk_out = p.nblk_pg;
+    if (wide_out) *wide_out = p.tail_wide ? 1 : 0;
+    return BISPEC_OK;
+}
+
+bispec_status bispec_set_tuning(bispec_plan_t plan, int32_t nblk, int32_t wide) {
+    if (!plan || nblk < plan->nblk_pg_min || nblk > plan->nblk_pg_max) return BISPEC_E_INVALID;
+    plan->nblk_pg = nblk;
+    plan->tail_wide = wide != 0;
+    plan->drop_graphs();
+    return BISPEC_OK;
+}
+
+bispec_status bispec_plan_condition(bispec_plan_t plan, double *kappa_out) {
+    if (!plan || !kappa_out) return BISPEC_E_INVALID;
+    const double npix = (double)plan->n * plan->n * plan->n;
+    const int nt = (int)plan->tri.size() / 3;
+    for (int t = 0; t < nt; ++t) {
+        const double m = (double)plan->modes[plan->tri[3 * t]] * (double)plan->modes[plan->tri[3 * t + 1]] *
+                         (double)plan->modes[plan->tri[3 * t + 2]];
+        const double c = plan->tri_count[t];
+        kappa_out[t] = c > 0 ? std::sqrt(m / (npix * c)) : std::numeric_limits<double>::infinity();
+    }
+    return BISPEC_OK;
 }
 
 bispec_status bispec_graph_enable(bispec_plan_t plan, int32_t on) {

@@ -119,9 +119,10 @@ __device__ __forceinline__ int pad_idx(int i) { return i + (i >> 3); }
 constexpr int ilog8_floor(int n) { return n >= 8 ? 1 + ilog8_floor(n / 8) : 0; }
 constexpr int ipow8(int p) { return p == 0 ? 1 : 8 * ipow8(p - 1); }
 
-// One Stockham pass over all G pencils of the block (NT threads).
+// One Stockham pass over the first g_act of the G pencils of the block (NT
+// threads); the others are left untouched.
 template <typename C, int N, int LD, int G, int DIR, int RADIX, int NS, int NT>
-__device__ __forceinline__ void stockham_pass(C *s, const C *tw) {
+__device__ __forceinline__ void stockham_pass(C *s, const C *tw, int g_act) {
     constexpr int NB = N / RADIX;          // butterflies per pencil
     constexpr int TASKS = G * NB;
     static_assert(TASKS % NT == 0 || TASKS < NT, "pencil group must fill the block or fit in it");
@@ -129,12 +130,12 @@ __device__ __forceinline__ void stockham_pass(C *s, const C *tw) {
     constexpr bool PARTIAL = TASKS < NT;   // some threads idle (tiny grids)
     constexpr int TSTEP = N / (NS * RADIX);
     const int tid = threadIdx.x;
+    const int act_tasks = g_act * NB;
     C v[PER][RADIX];
-    const bool active = !PARTIAL || tid < TASKS;
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
-        if (!active) break;
         const int task = tid + q * NT;
+        if (task >= act_tasks || (PARTIAL && tid >= TASKS)) break;
         const int p = task / NB, jj = task % NB;
         const int k = jj % NS;
 #pragma unroll
@@ -152,8 +153,8 @@ __device__ __forceinline__ void stockham_pass(C *s, const C *tw) {
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
-        if (!active) break;
         const int task = tid + q * NT;
+        if (task >= act_tasks || (PARTIAL && tid >= TASKS)) break;
         const int p = task / NB, jj = task % NB;
         const int k = jj % NS;
         const int base = (jj / NS) * NS * RADIX + k;
@@ -163,19 +164,19 @@ __device__ __forceinline__ void stockham_pass(C *s, const C *tw) {
     __syncthreads();
 }
 
-// Full length-N transform of the G pencils held in s (pencil stride LD,
-// positions mapped by pad_idx).
+// Full length-N transform of the first g_act (default all G) pencils held in
+// s (pencil stride LD, positions mapped by pad_idx).
 // Expects s filled and a __syncthreads() issued by the caller; leaves the
 // result in s (natural order) followed by a barrier.
 template <typename C, int N, int LD, int G, int DIR, int NT = 256>
-__device__ __forceinline__ void fft_pencils(C *s, const C *tw) {
+__device__ __forceinline__ void fft_pencils(C *s, const C *tw, int g_act = G) {
     constexpr int P8 = ilog8_floor(N);
     constexpr int RL = N / ipow8(P8);
-    if constexpr (P8 >= 1) stockham_pass<C, N, LD, G, DIR, 8, 1, NT>(s, tw);
-    if constexpr (P8 >= 2) stockham_pass<C, N, LD, G, DIR, 8, 8, NT>(s, tw);
-    if constexpr (P8 >= 3) stockham_pass<C, N, LD, G, DIR, 8, 64, NT>(s, tw);
-    if constexpr (P8 >= 4) stockham_pass<C, N, LD, G, DIR, 8, 512, NT>(s, tw);
-    if constexpr (RL > 1) stockham_pass<C, N, LD, G, DIR, RL, ipow8(P8), NT>(s, tw);
+    if constexpr (P8 >= 1) stockham_pass<C, N, LD, G, DIR, 8, 1, NT>(s, tw, g_act);
+    if constexpr (P8 >= 2) stockham_pass<C, N, LD, G, DIR, 8, 8, NT>(s, tw, g_act);
+    if constexpr (P8 >= 3) stockham_pass<C, N, LD, G, DIR, 8, 64, NT>(s, tw, g_act);
+    if constexpr (P8 >= 4) stockham_pass<C, N, LD, G, DIR, 8, 512, NT>(s, tw, g_act);
+    if constexpr (RL > 1) stockham_pass<C, N, LD, G, DIR, RL, ipow8(P8), NT>(s, tw, g_act);
 }
 
 // Pencils per block: at least one butterfly task per thread, at most 64 KiB

@@ -45,9 +45,11 @@ constexpr int PG_MODE_F32 = 0;
 constexpr int PG_MODE_SPLIT = 1;
 constexpr int PG_ROW_ZERO = 32;
 constexpr int PG_ROW_ONE = 33;
+// The fused tail works on tiles of max(N, 512) grid points; one block
+// contracts at most PG_CHUNK_TILES of them.
+constexpr int PG_CHUNK_TILES = 64;
+int64_t tail_tiles(int n);
 size_t pgram_partial_doubles(int n_mtile, bool want_t);
-hipError_t launch_pgram(int mode, bool want_t, const float *fields, int64_t npix, int nb, int64_t map_stride,
-                        int batch, const uchar2 *pairs, int n_mtile, int nblk, double *partial, hipStream_t st);
 // Fused pass X + product-Gram over the compact rows of all shell pairs.
 struct TailPairs {
     int R[16];
@@ -55,9 +57,13 @@ struct TailPairs {
     long long off[16];      // float2 offset of pair q's compact rows of map 0
     int npairs;
 };
+// prefer_wide: 16 waves with one tile each when the tiles fit (else 8 waves
+// with up to three).  nblk blocks per map, at least
+// ceil(tail_tiles(n) / PG_CHUNK_TILES) (else hipErrorInvalidValue).
 hipError_t launch_tail(int mode, bool want_t, const float2 *bc, const TailPairs &tp, int n, int nb, int batch,
                        const uchar2 *pairs, int n_mtile, const float2 *tw, int nblk, double *partial,
-                       hipStream_t st);
+                       hipStream_t st, bool prefer_wide);
+bool tail_wide_fits(int n_mtile, bool want_t);
 hipError_t launch_reduce_dense(const double *partial, int nblk, int64_t n_dense, int batch, double *dense,
                                hipStream_t st);
 hipError_t launch_finalize_gather(const double *partial, int nblk, int64_t blk_stride, const int *idx, int nterm,

@@ -16,9 +16,12 @@
 // x_lo = bf16_rne(x - x_hi) (the difference is exact in FP32); the product
 // is A_hi B_hi + A_hi B_lo + A_lo B_hi on v_mfma_f32_32x32x16_bf16 with FP32
 // accumulation.  MODE_F32: the same GEMM on v_mfma_f32_32x32x2f32.
-// In both modes the FP32 accumulators are flushed into FP64 registers every
-// 4096 grid points, and every block writes its FP64 tile partials; a
-// fixed-order FP64 reduction over blocks follows (k_finalize_gather).
+// Every block contracts one chunk of at most PG_CHUNK_TILES tiles and writes
+// its FP64 tile partials; a fixed-order FP64 reduction over chunks follows
+// (k_reduce_dense).  A chunk is at most 2048 split-mode MFMA steps, so the
+// FP32 accumulators of split mode are converted only at the end of a chunk;
+// FP32 mode (two points per step) adds its accumulators into FP64 registers
+// every 4096 points.
 //
 // Lane layouts (checked on the device): for the 32x32x16 bf16 operation lane
 // l holds A[l%32][8(l/32)+j] and B[8(l/32)+j][l%32], j < 8; for 32x32x2 f32
@@ -39,13 +42,12 @@ typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 typedef float f32x2 __attribute__((ext_vector_type(2)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
-constexpr int PG_TK = 256;                // grid points per LDS tile (fields from HBM)
 constexpr int PG_TK_TAIL = 512;           // grid points per LDS tile of the fused tail
 // Two block shapes: 16 waves owning one output tile each (up to 16 tiles,
 // half the registers, 4 waves per SIMD) or 8 waves owning up to three.
 constexpr int PG_NT_WIDE = 1024, PG_MAXT_WIDE = 1;
 constexpr int PG_NT_DEEP = 512, PG_MAXT_DEEP = 3;
-constexpr int PG_FLUSH_POINTS = 4096;     // FP32 accumulation span before an FP64 flush
+constexpr int PG_FLUSH_POINTS = 4096;     // FP32-mode accumulation span before an FP64 flush
 constexpr int PG_ZERO = PG_ROW_ZERO;      // field row of zeros (padding rows)
 constexpr int PG_ONE = PG_ROW_ONE;        // field row of ones (F_b * 1 rows)
 constexpr int PG_FROWS = 34;
@@ -78,10 +80,11 @@ __device__ __forceinline__ void split8(const float *x, bf16x8 &h, bf16x8 &l) {
 template <int MODE, bool WANT_T, int NT, int MAXT>
 struct PgState {
     static constexpr int WAVES = NT / 64;
+    static constexpr int DT = MODE == PG_MODE_F32 ? MAXT : 1;    // FP64 flush registers (FP32 mode)
     int tile_of[MAXT];
     uchar2 rp[MAXT];
     f32x16 acc[MAXT];
-    double dacc[MAXT][16];
+    double dacc[DT][16];
 
     __device__ __forceinline__ void init(const uchar2 *__restrict__ pairs, int n_mtile, int nb, int wave, int col) {
         const int n_out = n_mtile + (WANT_T ? 1 : 0);
@@ -92,11 +95,12 @@ struct PgState {
             const unsigned char sq = (unsigned char)(col < nb ? col : PG_ZERO);
             rp[t] = tile < n_mtile ? pairs[tile * 32 + col] : uchar2{sq, sq};
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                acc[t][r] = 0.0f;
-                dacc[t][r] = 0.0;
-            }
+            for (int r = 0; r < 16; ++r) acc[t][r] = 0.0f;
         }
+#pragma unroll
+        for (int t = 0; t < DT; ++t)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) dacc[t][r] = 0.0;
     }
 
     // Contract TK points of the LDS field tile Ft (row stride FS); in split
@@ -150,12 +154,14 @@ struct PgState {
     }
 
     __device__ __forceinline__ void flush() {
+        if constexpr (MODE == PG_MODE_F32) {
 #pragma unroll
-        for (int t = 0; t < MAXT; ++t) {
+            for (int t = 0; t < MAXT; ++t) {
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                dacc[t][r] += (double)acc[t][r];
-                acc[t][r] = 0.0f;
+                for (int r = 0; r < 16; ++r) {
+                    dacc[t][r] += (double)acc[t][r];
+                    acc[t][r] = 0.0f;
+                }
             }
         }
     }
@@ -168,7 +174,7 @@ struct PgState {
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
                 const int row = 8 * (r >> 2) + 4 * half + (r & 3);
-                out[row * 32 + col] = dacc[t][r] + (double)acc[t][r];
+                out[row * 32 + col] = (MODE == PG_MODE_F32 ? dacc[t < DT ? t : 0][r] : 0.0) + (double)acc[t][r];
             }
         }
     }
@@ -195,47 +201,6 @@ __device__ __forceinline__ void split_columns(const float *Ft, __bf16 *Bh, __bf1
     }
 }
 
-// Product-Gram over bin fields stored in HBM ([map][nb][npix]).
-template <int MODE, bool WANT_T, int NT = PG_NT_DEEP, int MAXT = PG_MAXT_DEEP>
-__global__ __launch_bounds__(NT) void k_pgram(const float *__restrict__ fields, int64_t npix, int nb,
-                                                      int64_t map_stride, const uchar2 *__restrict__ pairs,
-                                                      int n_mtile, int64_t chunk, double *__restrict__ partial) {
-    constexpr int TK = PG_TK, FS = TK + 4, BS = TK + 8;
-    __shared__ float Ft[PG_FROWS * FS];
-    constexpr int BSZ = MODE == PG_MODE_SPLIT ? 32 * BS : 1;
-    __shared__ __bf16 Bh[BSZ], Bl[BSZ];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int col = lane & 31, half = lane >> 5;
-    const int map = blockIdx.y;
-    const float *f = fields + map * map_stride;
-    const int64_t p_begin = (int64_t)blockIdx.x * chunk;
-    const int64_t p_end = p_begin + chunk < npix ? p_begin + chunk : npix;
-    PgState<MODE, WANT_T, NT, MAXT> st;
-    st.init(pairs, n_mtile, nb, wave, col);
-    init_field_tile<FS, NT>(Ft, nb);
-    int since_flush = 0;
-    for (int64_t p = p_begin; p < p_end; p += TK) {
-        __syncthreads();
-        for (int e = tid; e < nb * (TK / 4); e += NT) {
-            const int b = e / (TK / 4), q = e % (TK / 4);
-            const float4 v = *reinterpret_cast<const float4 *>(f + (int64_t)b * npix + p + 4 * q);
-            *reinterpret_cast<float4 *>(&Ft[b * FS + 4 * q]) = v;
-        }
-        __syncthreads();
-        if constexpr (MODE == PG_MODE_SPLIT) {
-            split_columns<TK, FS, BS, NT>(Ft, Bh, Bl);
-            __syncthreads();
-        }
-        st.template contract<TK, FS, BS>(Ft, Bh, Bl, n_mtile, col, half);
-        since_flush += TK;
-        if (since_flush >= PG_FLUSH_POINTS) {
-            since_flush = 0;
-            st.flush();
-        }
-    }
-    st.write(partial, (int64_t)map * gridDim.x + blockIdx.x, n_mtile + (WANT_T ? 1 : 0), col, half);
-}
-
 // Fused last inverse pass + product-Gram.  A tile is TK = max(N, 256) grid
 // points: RT = TK/N consecutive x-rows (n_z, n_y).  For every row and shell
 // pair the compact rows Bc[n_z][n_y][m_x + R] are placed at m_x mod N and
@@ -248,13 +213,13 @@ __global__ __launch_bounds__(NT) void k_tail(const float2 *__restrict__ bc, Tail
                                              double *__restrict__ partial) {
     constexpr int TK = N >= PG_TK_TAIL ? N : PG_TK_TAIL;
     constexpr int RT = TK / N;
-    constexpr int G = 16 * RT;                 // pencil slots: RT rows x 16 pairs
+    constexpr int G = 16 * RT;                 // pencil slots: 16 pairs x RT rows
     constexpr int FS = TK + 4, BS = TK + 8;
     constexpr int LDP = pencil_ld<N>();
     constexpr int FFT_BYTES = G * LDP * 8;
     constexpr int SPLIT_BYTES = MODE == PG_MODE_SPLIT ? 2 * 32 * BS * 2 : 0;
     constexpr int UBYTES = FFT_BYTES > SPLIT_BYTES ? FFT_BYTES : SPLIT_BYTES;
-    constexpr int PF = G * N / NT;             // prefetched elements per thread
+    constexpr int PF = G * N / NT;             // loaded elements per thread and tile
     static_assert((G * N) % NT == 0, "tile loads must divide the block");
     __shared__ float Ft[PG_FROWS * FS];
     __shared__ __attribute__((aligned(16))) unsigned char ubuf[UBYTES];
@@ -275,17 +240,22 @@ __global__ __launch_bounds__(NT) void k_tail(const float2 *__restrict__ bc, Tail
     st.init(pairs, n_mtile, nb, wave, col);
     init_field_tile<FS, NT>(Ft, nb);
 
-    // Element k of this thread's share of a tile is e = tid + k NT: slot
-    // sl = e / N (row r = sl / 16, pair q = sl % 16) at position i = tid % N
-    // (NT is a multiple of N), i.e. at frequency m_x = signed(i).
+    // Slot sl = q RT + r holds pair q of tile row r; only the first
+    // npairs RT slots are loaded, transformed and read.  Element k of this
+    // thread's share of a tile is e = tid + k NT: slot e / N at position
+    // i = tid % N (NT is a multiple of N), i.e. at frequency m_x = signed(i).
+    // A wave covers one slot, or 64/N consecutive rows of one pair, so the
+    // pair index is wave-uniform and its parameters are scalar loads.
     static_assert(NT % N == 0, "block size must be a multiple of the row length");
     const int mx = signed_freq(tid % N, N);
+    const int gact = tp.npairs * RT;
     auto fetch = [&](int64_t tile, float2 *v) {
         const int64_t row0 = tile * RT;
 #pragma unroll
         for (int k = 0; k < PF; ++k) {
             const int sl = tid / N + k * (NT / N);
-            const int r = sl / 16, q = sl % 16;
+            const int q = __builtin_amdgcn_readfirstlane(sl / RT);
+            const int r = sl % RT;
             v[k] = float2{0.0f, 0.0f};
             if (q < tp.npairs) {
                 const int R = tp.R[q];
@@ -293,28 +263,27 @@ __global__ __launch_bounds__(NT) void k_tail(const float2 *__restrict__ bc, Tail
             }
         }
     };
+    // The loads of tile t + 1 are issued right after tile t is stored and
+    // stay in flight through its transform and contraction.
     int since_flush = 0;
+    float2 v[PF];
+    if (t_begin < t_end) fetch(t_begin, v);
     for (int64_t tile = t_begin; tile < t_end; ++tile) {
         __syncthreads();
-        {
-            float2 v[PF];
-            fetch(tile, v);
 #pragma unroll
-            for (int k = 0; k < PF; ++k) {
-                const int e = tid + k * NT;
-                fb[(e / N) * LDP + pad_idx(e % N)] = v[k];
-            }
+        for (int k = 0; k < PF; ++k) {
+            const int e = tid + k * NT;
+            if (e / N < gact) fb[(e / N) * LDP + pad_idx(e % N)] = v[k];
         }
+        if (tile + 1 < t_end) fetch(tile + 1, v);
         __syncthreads();
-        fft_pencils<float2, N, LDP, G, +1, NT>(fb, tws);
-        for (int e = tid; e < G * N; e += NT) {
+        fft_pencils<float2, N, LDP, G, +1, NT>(fb, tws, gact);
+        for (int e = tid; e < gact * N; e += NT) {
             const int sl = e / N, n = e % N;
-            const int r = sl / 16, q = sl % 16;
-            if (q < tp.npairs) {
-                const float2 v = fb[sl * LDP + pad_idx(n)];
-                Ft[(2 * q) * FS + r * N + n] = v.x;
-                if (2 * q + 1 < nb) Ft[(2 * q + 1) * FS + r * N + n] = v.y;
-            }
+            const int q = sl / RT, r = sl % RT;
+            const float2 v = fb[sl * LDP + pad_idx(n)];
+            Ft[(2 * q) * FS + r * N + n] = v.x;
+            if (2 * q + 1 < nb) Ft[(2 * q + 1) * FS + r * N + n] = v.y;
         }
         __syncthreads();
         if constexpr (MODE == PG_MODE_SPLIT) {
@@ -378,70 +347,61 @@ __global__ __launch_bounds__(256) void k_finalize_gather(const double *__restric
     }
 }
 
+int64_t tail_tiles(int n) {
+    const int64_t tk = n >= PG_TK_TAIL ? n : PG_TK_TAIL;
+    return (int64_t)n * n * n / tk;
+}
+
 size_t pgram_partial_doubles(int n_mtile, bool want_t) { return (size_t)(n_mtile + (want_t ? 1 : 0)) * 1024; }
 
-hipError_t launch_pgram(int mode, bool want_t, const float *fields, int64_t npix, int nb, int64_t map_stride,
-                        int batch, const uchar2 *pairs, int n_mtile, int nblk, double *partial, hipStream_t st) {
-    if (nb > 32 || n_mtile + (want_t ? 1 : 0) > PG_MAXT_DEEP * (PG_NT_DEEP / 64)) return hipErrorInvalidValue;
-    const int64_t chunk = ((npix + nblk - 1) / nblk + PG_TK - 1) / PG_TK * PG_TK;
-    const dim3 grid(nblk, batch), block(PG_NT_DEEP);
-    if (mode == PG_MODE_SPLIT) {
-        if (want_t)
-            hipLaunchKernelGGL((k_pgram<PG_MODE_SPLIT, true>), grid, block, 0, st, fields, npix, nb, map_stride, pairs,
-                               n_mtile, chunk, partial);
-        else
-            hipLaunchKernelGGL((k_pgram<PG_MODE_SPLIT, false>), grid, block, 0, st, fields, npix, nb, map_stride,
-                               pairs, n_mtile, chunk, partial);
-    } else {
-        if (want_t)
-            hipLaunchKernelGGL((k_pgram<PG_MODE_F32, true>), grid, block, 0, st, fields, npix, nb, map_stride, pairs,
-                               n_mtile, chunk, partial);
-        else
-            hipLaunchKernelGGL((k_pgram<PG_MODE_F32, false>), grid, block, 0, st, fields, npix, nb, map_stride, pairs,
-                               n_mtile, chunk, partial);
-    }
-    return hipGetLastError();
+bool tail_wide_fits(int n_mtile, bool want_t) {
+    return n_mtile + (want_t ? 1 : 0) <= PG_MAXT_WIDE * (PG_NT_WIDE / 64);
 }
 
 template <int MODE, bool WANT_T>
 hipError_t launch_tail_m(const float2 *bc, const TailPairs &tp, int n, int nb, int batch, const uchar2 *pairs,
-                         int n_mtile, const float2 *tw, int nblk, double *partial, hipStream_t st) {
-    const bool wide = n_mtile + (WANT_T ? 1 : 0) <= PG_MAXT_WIDE * (PG_NT_WIDE / 64);
-    auto go = [&](auto nc) {
+                         int n_mtile, const float2 *tw, int nblk, double *partial, hipStream_t st, bool prefer_wide) {
+    const bool wide = prefer_wide && tail_wide_fits(n_mtile, WANT_T);
+    auto go = [&](auto nc) -> hipError_t {
         constexpr int NN = decltype(nc)::value;
         constexpr int TK = NN >= PG_TK_TAIL ? NN : PG_TK_TAIL;
         const int64_t total = (int64_t)NN * NN * NN / TK;
         const int per = (int)((total + nblk - 1) / nblk);
+        if (nblk < 1 || per > PG_CHUNK_TILES) return hipErrorInvalidValue;
         if (wide)
             hipLaunchKernelGGL((k_tail<MODE, WANT_T, NN, PG_NT_WIDE, PG_MAXT_WIDE>), dim3(nblk, batch),
                                dim3(PG_NT_WIDE), 0, st, bc, tp, nb, pairs, n_mtile, tw, per, partial);
         else
             hipLaunchKernelGGL((k_tail<MODE, WANT_T, NN, PG_NT_DEEP, PG_MAXT_DEEP>), dim3(nblk, batch),
                                dim3(PG_NT_DEEP), 0, st, bc, tp, nb, pairs, n_mtile, tw, per, partial);
+        return hipGetLastError();
     };
     switch (n) {
-        case 8: go(std::integral_constant<int, 8>{}); break;
-        case 16: go(std::integral_constant<int, 16>{}); break;
-        case 32: go(std::integral_constant<int, 32>{}); break;
-        case 64: go(std::integral_constant<int, 64>{}); break;
-        case 128: go(std::integral_constant<int, 128>{}); break;
-        case 256: go(std::integral_constant<int, 256>{}); break;
-        case 512: go(std::integral_constant<int, 512>{}); break;
+        case 8: return go(std::integral_constant<int, 8>{});
+        case 16: return go(std::integral_constant<int, 16>{});
+        case 32: return go(std::integral_constant<int, 32>{});
+        case 64: return go(std::integral_constant<int, 64>{});
+        case 128: return go(std::integral_constant<int, 128>{});
+        case 256: return go(std::integral_constant<int, 256>{});
+        case 512: return go(std::integral_constant<int, 512>{});
         default: return hipErrorInvalidValue;
     }
-    return hipGetLastError();
 }
 
 hipError_t launch_tail(int mode, bool want_t, const float2 *bc, const TailPairs &tp, int n, int nb, int batch,
                        const uchar2 *pairs, int n_mtile, const float2 *tw, int nblk, double *partial,
-                       hipStream_t st) {
+                       hipStream_t st, bool prefer_wide) {
     if (nb > 32 || tp.npairs > 16 || n_mtile + (want_t ? 1 : 0) > PG_MAXT_DEEP * (PG_NT_DEEP / 64))
         return hipErrorInvalidValue;
     if (mode == PG_MODE_SPLIT)
-        return want_t ? launch_tail_m<PG_MODE_SPLIT, true>(bc, tp, n, nb, batch, pairs, n_mtile, tw, nblk, partial, st)
-                      : launch_tail_m<PG_MODE_SPLIT, false>(bc, tp, n, nb, batch, pairs, n_mtile, tw, nblk, partial, st);
-    return want_t ? launch_tail_m<PG_MODE_F32, true>(bc, tp, n, nb, batch, pairs, n_mtile, tw, nblk, partial, st)
-                  : launch_tail_m<PG_MODE_F32, false>(bc, tp, n, nb, batch, pairs, n_mtile, tw, nblk, partial, st);
+        return want_t ? launch_tail_m<PG_MODE_SPLIT, true>(bc, tp, n, nb, batch, pairs, n_mtile, tw, nblk, partial, st,
+                                                           prefer_wide)
+                      : launch_tail_m<PG_MODE_SPLIT, false>(bc, tp, n, nb, batch, pairs, n_mtile, tw, nblk, partial,
+                                                            st, prefer_wide);
+    return want_t ? launch_tail_m<PG_MODE_F32, true>(bc, tp, n, nb, batch, pairs, n_mtile, tw, nblk, partial, st,
+                                                     prefer_wide)
+                  : launch_tail_m<PG_MODE_F32, false>(bc, tp, n, nb, batch, pairs, n_mtile, tw, nblk, partial, st,
+                                                      prefer_wide);
 }
 
 hipError_t launch_reduce_dense(const double *partial, int nblk, int64_t n_dense, int batch, double *dense,

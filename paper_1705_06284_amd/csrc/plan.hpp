@@ -42,7 +42,10 @@ struct bispec_plan_s {
     bool mfma_ok = false;                // n_bins <= 32
     bool quads_collapsed = false;        // every quad is (a,a,b,b) up to order
     int n_mtile = 0;                     // 32-row tiles of pair rows
-    int nblk_pg = 1;                     // blocks of the product-Gram kernel
+    int nblk_pg = 1;                     // blocks of the product-Gram kernel (tuned)
+    int nblk_pg_min = 1;                 // fewest blocks (chunk span limit)
+    int nblk_pg_max = 1;                 // partial buffer capacity in blocks
+    bool tail_wide = true;               // tail block shape (tuned)
     std::vector<uchar2> pg_pairs;        // [n_mtile*32] row factors
     std::vector<int> pg_idx;             // per term: index into a block's dense tiles
     // stage timing: one event per stage boundary per call

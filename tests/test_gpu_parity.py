@@ -287,6 +287,43 @@ def test_graph_replay_matches_eager(binding):
     plan.graph(False)
 
 
+def test_autotune_choices_agree_with_oracle(binding):
+    """Every launch shape the tuner may pick gives oracle parity; the tuner's
+    pick is one of them and out-of-range choices are refused."""
+    n = 64
+    lo, hi = synth.linear_bins(n, 8)
+    d = synth.lognormal_field(n, 1.5, 1.0, seed=81)
+    _say("autotune 64^3")
+    plan = binding.Plan(n, lo, hi, precision="split_bf16")
+    ref = oracle.bispectrum(d, lo, hi, plan.triplets)
+    refp, _ = oracle.power_spectrum(d, lo, hi)
+    nb, wide = plan.autotune()
+    # 512 tiles of 512 points: at least 8 blocks (64 tiles each), default 256, at most 512
+    assert nb in (256, 512) and isinstance(wide, bool)
+    for blocks in (8, 100, 256, 512):
+        for w in (True, False):
+            plan.set_tuning(blocks, w)
+            P, B, T = plan.polyspec(d)
+            assert np.max(_err(B.cpu().numpy()[0], ref)) <= TOL["split_bf16"], (blocks, w)
+            assert np.max(np.abs(P.cpu().numpy()[0] - refp) / refp) <= TOL["split_bf16"], (blocks, w)
+    for bad in (0, 7, 513):
+        with pytest.raises(binding.BispecError) as ei:
+            plan.set_tuning(bad, True)
+        assert ei.value.code == -1
+
+
+def test_condition_numbers_match_counts(binding):
+    """kappa_t = sqrt(M_i M_j M_k / (N_pix N_t)) from the oracle's exact counts."""
+    n = 32
+    lo, hi = synth.linear_bins(n, 8)
+    plan = binding.Plan(n, lo, hi, precision="fp32")
+    m = oracle.mode_counts(n, lo, hi)
+    _, cnt = oracle.closed_triplets(n, lo, hi)
+    t = plan.triplets.astype(np.int64)
+    want = np.sqrt(m[t[:, 0]] * m[t[:, 1]] * m[t[:, 2]] / (float(n) ** 3 * cnt))
+    assert np.allclose(plan.condition, want, rtol=1e-14, atol=0)
+
+
 @pytest.mark.parametrize("prec", ["split_bf16"])
 def test_c4_lognormal_512_sampled(binding, prec):
     """512^3 lognormal field, 32 bins: the full triplet set (3384), P, and the
