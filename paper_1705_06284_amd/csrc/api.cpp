@@ -86,10 +86,20 @@ Layout make_layout(const bispec_plan_s &p, int batch) {
     L.bc = off;           off = align_up(off + sizeof(float2) * (size_t)p.n * p.n * p.wsum * batch);
     L.partial = off;      off = align_up(off + sizeof(double) * (size_t)p.nblk * p.terms.size() * batch);
     L.pg_partial = off;
-    if (p.mfma_ok)
-        off = align_up(off + sizeof(double) * pgram_partial_doubles(p.n_mtile, true) * p.nblk_pg_max * batch);
+    if (p.mfma_ok) {
+        // the largest partial set over both block shapes, with and without T
+        size_t per_blk = 0;
+        for (int t = 0; t < 2; ++t)
+            for (int w = 0; w < 2; ++w)
+                per_blk = std::max(per_blk, pgram_partial_doubles(p.n_mtile, t != 0) *
+                                                (size_t)tail_ksplit(p.n_mtile, t != 0, w != 0));
+        off = align_up(off + sizeof(double) * per_blk * p.nblk_pg_max * batch);
+    }
     L.pg_dense = off;
     if (p.mfma_ok) off = align_up(off + sizeof(double) * pgram_partial_doubles(p.n_mtile, true) * batch);
+    L.pg_tmp = off;
+    if (p.mfma_ok)
+        off = align_up(off + sizeof(double) * pgram_partial_doubles(p.n_mtile, true) * PG_REDUCE_SEGS * batch);
     // bin fields in HBM: only the vector-ALU contraction and general quads read them
     L.fields = off;
     if (needs_fields(p)) off = align_up(off + sizeof(float) * vol * p.nb * batch);
@@ -215,6 +225,13 @@ std::vector<PairDev> pair_devs(const bispec_plan_s &p) {
 // Rows of the product-Gram: pairs (i,j), i <= j, ordered by j then i; then
 // (b, ONE) rows; padding rows (ZERO, ZERO) up to a multiple of 32.  A term's
 // dense index in a block's tiles is tile*1024 + row_in_tile*32 + column.
+// Rows of the product-Gram.  Every (b,b) row is kept; when nb < 32 column nb
+// is a field of ones, so G[(b,b), nb] is the power-spectrum numerator, else
+// rows (b, ONE) are added for it.  A triplet a <= b <= c is read from
+// G[(x,y), z] for one of its three pairs (x,y): a pair already chosen if
+// there is one, else one whose bins have equal parity.  Among three bins two
+// always share a parity, and a repeated bin gives a (b,b) row, so at most the
+// pairs of equal parity are needed (about nb^2/4 rows instead of nb^2/2).
 void build_pgram_tables(bispec_plan_s &p) {
     const int nb = p.nb;
     p.mfma_ok = nb <= 32;
@@ -222,25 +239,40 @@ void build_pgram_tables(bispec_plan_s &p) {
     p.pg_idx.clear();
     if (!p.mfma_ok) return;
     std::vector<int> row_of(nb * nb, -1), row_one(nb, -1);
-    for (int j = 0; j < nb; ++j)
-        for (int i = 0; i <= j; ++i) {
+    auto add = [&](int i, int j) {
+        if (row_of[i * nb + j] < 0) {
             row_of[i * nb + j] = (int)p.pg_pairs.size();
             p.pg_pairs.push_back(uchar2{(unsigned char)i, (unsigned char)j});
         }
-    for (int b = 0; b < nb; ++b) {
-        row_one[b] = (int)p.pg_pairs.size();
-        p.pg_pairs.push_back(uchar2{(unsigned char)b, (unsigned char)PG_ROW_ONE});
+        return row_of[i * nb + j];
+    };
+    for (int b = 0; b < nb; ++b) add(b, b);
+    const bool one_col = nb < 32;
+    if (!one_col)
+        for (int b = 0; b < nb; ++b) {
+            row_one[b] = (int)p.pg_pairs.size();
+            p.pg_pairs.push_back(uchar2{(unsigned char)b, (unsigned char)PG_ROW_ONE});
+        }
+    const int ntri = (int)p.tri.size() / 3;
+    std::vector<int> tri_row(ntri), tri_col(ntri);
+    for (int t = 0; t < ntri; ++t) {
+        int a[3] = {p.tri[3 * t], p.tri[3 * t + 1], p.tri[3 * t + 2]};
+        std::sort(a, a + 3);
+        // candidate (pair, remaining bin): (a0,a1)|a2, (a0,a2)|a1, (a1,a2)|a0
+        const int cand[3][3] = {{a[0], a[1], a[2]}, {a[0], a[2], a[1]}, {a[1], a[2], a[0]}};
+        int pick = -1;
+        for (int c = 0; c < 3 && pick < 0; ++c)
+            if (row_of[cand[c][0] * nb + cand[c][1]] >= 0) pick = c;
+        for (int c = 0; c < 3 && pick < 0; ++c)
+            if ((cand[c][0] & 1) == (cand[c][1] & 1)) pick = c;
+        tri_row[t] = add(cand[pick][0], cand[pick][1]);
+        tri_col[t] = cand[pick][2];
     }
     while (p.pg_pairs.size() % 32) p.pg_pairs.push_back(uchar2{(unsigned char)PG_ROW_ZERO, (unsigned char)PG_ROW_ZERO});
     p.n_mtile = (int)p.pg_pairs.size() / 32;
     auto dense = [](int row, int c) { return (row / 32) * 1024 + (row % 32) * 32 + c; };
-    const int ntri = (int)p.tri.size() / 3;
-    for (int t = 0; t < ntri; ++t) {
-        int a[3] = {p.tri[3 * t], p.tri[3 * t + 1], p.tri[3 * t + 2]};
-        std::sort(a, a + 3);
-        p.pg_idx.push_back(dense(row_of[a[0] * nb + a[1]], a[2]));
-    }
-    for (int b = 0; b < nb; ++b) p.pg_idx.push_back(dense(row_one[b], b));
+    for (int t = 0; t < ntri; ++t) p.pg_idx.push_back(dense(tri_row[t], tri_col[t]));
+    for (int b = 0; b < nb; ++b) p.pg_idx.push_back(one_col ? dense(row_of[b * nb + b], nb) : dense(row_one[b], b));
     const int nq = (int)p.quad.size() / 4;
     p.quads_collapsed = true;
     for (int q = 0; q < nq; ++q) {
@@ -717,7 +749,8 @@ bispec_status run_estimate_body(bispec_plan_s &p, const float *delta, int batch,
                        (const uchar2 *)(ws + L.pg_pairs), p.n_mtile, tw, p.nblk_pg, pg, p.stream, p.tail_wide));
         const int64_t n_dense = (int64_t)pgram_partial_doubles(p.n_mtile, t_mfma);
         stamp(p, 3);
-        CK(launch_reduce_dense(pg, p.nblk_pg, n_dense, batch, dense, p.stream));
+        CK(launch_reduce_dense(pg, p.nblk_pg * tail_ksplit(p.n_mtile, t_mfma, p.tail_wide), n_dense, batch, dense,
+                               (double *)(ws + L.pg_tmp), p.stream));
         if (first < last) {
             s = finalize_range(p, true, dense, 1, n_dense, first, last, batch, P, B, T);
             if (s != BISPEC_OK) return s;

@@ -39,8 +39,9 @@ hipError_t launch_finalize(const double *partial, int nblk, int nterm, int batch
                            int n0, double *o1, int n1, double *o2, int n2, hipStream_t st);
 
 // Product-Gram contraction on MFMA (mfma.hip).  pairs: [n_mtile*32] row
-// factors (field row indices; 32 = zeros, 33 = ones).  partial:
-// [batch][nblk][n_mtile + want_t][32][32] FP64.
+// factors (field row indices; 32 = zeros, 33 = ones); column nb < 32 is a
+// field of ones.  partial: [batch][nblk * ksplit][n_mtile + want_t][32][32]
+// FP64.
 constexpr int PG_MODE_F32 = 0;
 constexpr int PG_MODE_SPLIT = 1;
 constexpr int PG_ROW_ZERO = 32;
@@ -64,8 +65,14 @@ hipError_t launch_tail(int mode, bool want_t, const float2 *bc, const TailPairs 
                        const uchar2 *pairs, int n_mtile, const float2 *tw, int nblk, double *partial,
                        hipStream_t st, bool prefer_wide);
 bool tail_wide_fits(int n_mtile, bool want_t);
+// K parts per output tile of the launched shape: each block writes
+// tail_ksplit(...) partial sets of n_mtile + want_t tiles.
+int tail_ksplit(int n_mtile, bool want_t, bool prefer_wide);
+// dense[map][e] = sum over the nblk partial sets; tmp holds
+// PG_REDUCE_SEGS * n_dense * batch doubles of segment sums (or null: one pass).
+constexpr int PG_REDUCE_SEGS = 32;
 hipError_t launch_reduce_dense(const double *partial, int nblk, int64_t n_dense, int batch, double *dense,
-                               hipStream_t st);
+                               double *tmp, hipStream_t st);
 hipError_t launch_finalize_gather(const double *partial, int nblk, int64_t blk_stride, const int *idx, int nterm,
                                   int batch, const double *scale, double *o0, int n0, double *o1, int n1, double *o2,
                                   int n2, hipStream_t st);

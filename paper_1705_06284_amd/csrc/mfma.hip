@@ -73,24 +73,31 @@ __device__ __forceinline__ void split8(const float *x, bf16x8 &h, bf16x8 &l) {
     }
 }
 
-// Per-wave state of the product-Gram: the output tiles this wave owns, the
-// row factors of its lane in each tile, FP32 accumulators and their FP64
-// flush registers.  Tiles [0, n_mtile) are pair rows; tile n_mtile (WANT_T)
-// has rows F_a^2 and columns F_b^2.
+// Per-wave state of the product-Gram.  The work items are (output tile,
+// K part) pairs: with ksplit K parts, tile u / ksplit takes the 16-point
+// steps s = kpart (mod ksplit) of every LDS tile, kpart = u mod ksplit.
+// Wave w owns items w + t WAVES (t < MAXT); WAVES is a multiple of ksplit, so
+// all items of a wave share one K part.  Tiles [0, n_mtile) are pair rows;
+// tile n_mtile (WANT_T) has rows F_a^2 and columns F_b^2.
 template <int MODE, bool WANT_T, int NT, int MAXT>
 struct PgState {
     static constexpr int WAVES = NT / 64;
     static constexpr int DT = MODE == PG_MODE_F32 ? MAXT : 1;    // FP64 flush registers (FP32 mode)
     int tile_of[MAXT];
+    int kpart, ksplit;
     uchar2 rp[MAXT];
     f32x16 acc[MAXT];
     double dacc[DT][16];
 
-    __device__ __forceinline__ void init(const uchar2 *__restrict__ pairs, int n_mtile, int nb, int wave, int col) {
+    __device__ __forceinline__ void init(const uchar2 *__restrict__ pairs, int n_mtile, int nb, int wave, int col,
+                                         int ks) {
         const int n_out = n_mtile + (WANT_T ? 1 : 0);
+        ksplit = ks;
+        kpart = wave % ks;
 #pragma unroll
         for (int t = 0; t < MAXT; ++t) {
-            const int tile = wave + t * WAVES;
+            const int u = wave + t * WAVES;
+            const int tile = u / ks;
             tile_of[t] = tile < n_out ? tile : -1;
             const unsigned char sq = (unsigned char)(col < nb ? col : PG_ZERO);
             rp[t] = tile < n_mtile ? pairs[tile * 32 + col] : uchar2{sq, sq};
@@ -110,7 +117,7 @@ struct PgState {
                                              int col, int half) {
         if constexpr (MODE == PG_MODE_SPLIT) {
 #pragma unroll 1
-            for (int s = 0; s < TK / 16; ++s) {
+            for (int s = kpart; s < TK / 16; s += ksplit) {
                 const int kp = s * 16 + half * 8;
                 const bf16x8 bh = *reinterpret_cast<const bf16x8 *>(&Bh[col * BS + kp]);
                 const bf16x8 bl = *reinterpret_cast<const bf16x8 *>(&Bl[col * BS + kp]);
@@ -139,7 +146,7 @@ struct PgState {
             }
         } else {
 #pragma unroll 1
-            for (int s = 0; s < TK / 2; ++s) {
+            for (int s = kpart; s < TK / 2; s += ksplit) {
                 const int k = 2 * s + half;
                 const float bk = Ft[col * FS + k];
 #pragma unroll
@@ -166,11 +173,12 @@ struct PgState {
         }
     }
 
+    // Partials of block blk: [ksplit][n_out][32][32].
     __device__ __forceinline__ void write(double *__restrict__ partial, int64_t blk, int n_out, int col, int half) {
 #pragma unroll
         for (int t = 0; t < MAXT; ++t) {
             if (tile_of[t] < 0) continue;
-            double *out = partial + (blk * n_out + tile_of[t]) * 1024;
+            double *out = partial + ((blk * ksplit + kpart) * n_out + tile_of[t]) * 1024;
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
                 const int row = 8 * (r >> 2) + 4 * half + (r & 3);
@@ -180,12 +188,14 @@ struct PgState {
     }
 };
 
-// Field rows nb..31 and the ZERO row hold 0, the ONE row holds 1.
+// Field rows nb..31 and the ZERO row hold 0, the ONE row holds 1; when
+// nb < 32, row nb (a column of the product-Gram) holds 1 as well, so that
+// G[(b,b), nb] = sum_n F_b^2.
 template <int FS, int NT>
 __device__ __forceinline__ void init_field_tile(float *Ft, int nb) {
     for (int e = threadIdx.x; e < (PG_FROWS - nb) * FS; e += NT) {
         const int row = nb + e / FS;
-        Ft[row * FS + e % FS] = row == PG_ONE ? 1.0f : 0.0f;
+        Ft[row * FS + e % FS] = (row == PG_ONE || row == nb) ? 1.0f : 0.0f;
     }
 }
 
@@ -209,7 +219,7 @@ __device__ __forceinline__ void split_columns(const float *Ft, __bf16 *Bh, __bf1
 template <int MODE, bool WANT_T, int N, int NT, int MAXT>
 __global__ __launch_bounds__(NT) void k_tail(const float2 *__restrict__ bc, TailPairs tp, int nb,
                                              const uchar2 *__restrict__ pairs, int n_mtile,
-                                             const float2 *__restrict__ tw, int tiles_per_blk,
+                                             const float2 *__restrict__ tw, int tiles_per_blk, int ksplit,
                                              double *__restrict__ partial) {
     constexpr int TK = N >= PG_TK_TAIL ? N : PG_TK_TAIL;
     constexpr int RT = TK / N;
@@ -237,7 +247,7 @@ __global__ __launch_bounds__(NT) void k_tail(const float2 *__restrict__ bc, Tail
     const int64_t t_end = t_begin + tiles_per_blk < total ? t_begin + tiles_per_blk : total;
     for (int i = tid; i < N; i += NT) tws[i] = tw[i];
     PgState<MODE, WANT_T, NT, MAXT> st;
-    st.init(pairs, n_mtile, nb, wave, col);
+    st.init(pairs, n_mtile, nb, wave, col, ksplit);
     init_field_tile<FS, NT>(Ft, nb);
 
     // Slot sl = q RT + r holds pair q of tile row r; only the first
@@ -300,24 +310,26 @@ __global__ __launch_bounds__(NT) void k_tail(const float2 *__restrict__ bc, Tail
     st.write(partial, (int64_t)map * gridDim.x + blockIdx.x, n_mtile + (WANT_T ? 1 : 0), col, half);
 }
 
-// Fixed-order compensated FP64 sum over blocks of every dense tile entry:
-// dense[map][e] = sum_b partial[map][b][e].  Consecutive threads read
-// consecutive entries, so every block's partial is read once, coalesced.
-__global__ __launch_bounds__(256) void k_reduce_dense(const double *__restrict__ partial, int nblk, int64_t n_dense,
-                                                      double *__restrict__ dense) {
+// Fixed-order compensated FP64 sum over blocks of every dense tile entry,
+// in segments: out[map][z][e] = sum_{b in segment z} partial[map][b][e],
+// segment z = [z seg, min((z+1) seg, nblk)) for z = blockIdx.z.  Consecutive
+// threads read consecutive entries, so every partial is read once, coalesced.
+__global__ __launch_bounds__(256) void k_reduce_dense(const double *__restrict__ partial, int nblk, int seg,
+                                                      int64_t n_dense, double *__restrict__ out) {
     const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const int map = blockIdx.y;
+    const int map = blockIdx.y, z = blockIdx.z;
     if (e >= n_dense) return;
     const double *p = partial + (int64_t)map * nblk * n_dense + e;
+    const int b0 = z * seg, b1 = b0 + seg < nblk ? b0 + seg : nblk;
     double acc = 0.0, comp = 0.0;
 #pragma unroll 8
-    for (int b = 0; b < nblk; ++b) {
+    for (int b = b0; b < b1; ++b) {
         const double x = p[(int64_t)b * n_dense];
         const double s = acc + x;
         comp += fabs(acc) >= fabs(x) ? (acc - s) + x : (x - s) + acc;
         acc = s;
     }
-    dense[(int64_t)map * n_dense + e] = acc + comp;
+    out[((int64_t)map * gridDim.z + z) * n_dense + e] = acc + comp;
 }
 
 // Fixed-order FP64 sum over blocks of the dense tile partials, gathered at
@@ -358,10 +370,21 @@ bool tail_wide_fits(int n_mtile, bool want_t) {
     return n_mtile + (want_t ? 1 : 0) <= PG_MAXT_WIDE * (PG_NT_WIDE / 64);
 }
 
+int tail_ksplit(int n_mtile, bool want_t, bool prefer_wide) {
+    const int n_out = n_mtile + (want_t ? 1 : 0);
+    const bool wide = prefer_wide && tail_wide_fits(n_mtile, want_t);
+    const int waves = (wide ? PG_NT_WIDE : PG_NT_DEEP) / 64;
+    const int cap = (wide ? PG_MAXT_WIDE : PG_MAXT_DEEP) * waves;
+    int k = 1;
+    while (2 * k <= waves && n_out * 2 * k <= cap) k *= 2;
+    return k;
+}
+
 template <int MODE, bool WANT_T>
 hipError_t launch_tail_m(const float2 *bc, const TailPairs &tp, int n, int nb, int batch, const uchar2 *pairs,
                          int n_mtile, const float2 *tw, int nblk, double *partial, hipStream_t st, bool prefer_wide) {
     const bool wide = prefer_wide && tail_wide_fits(n_mtile, WANT_T);
+    const int ks = tail_ksplit(n_mtile, WANT_T, prefer_wide);
     auto go = [&](auto nc) -> hipError_t {
         constexpr int NN = decltype(nc)::value;
         constexpr int TK = NN >= PG_TK_TAIL ? NN : PG_TK_TAIL;
@@ -370,10 +393,10 @@ hipError_t launch_tail_m(const float2 *bc, const TailPairs &tp, int n, int nb, i
         if (nblk < 1 || per > PG_CHUNK_TILES) return hipErrorInvalidValue;
         if (wide)
             hipLaunchKernelGGL((k_tail<MODE, WANT_T, NN, PG_NT_WIDE, PG_MAXT_WIDE>), dim3(nblk, batch),
-                               dim3(PG_NT_WIDE), 0, st, bc, tp, nb, pairs, n_mtile, tw, per, partial);
+                               dim3(PG_NT_WIDE), 0, st, bc, tp, nb, pairs, n_mtile, tw, per, ks, partial);
         else
             hipLaunchKernelGGL((k_tail<MODE, WANT_T, NN, PG_NT_DEEP, PG_MAXT_DEEP>), dim3(nblk, batch),
-                               dim3(PG_NT_DEEP), 0, st, bc, tp, nb, pairs, n_mtile, tw, per, partial);
+                               dim3(PG_NT_DEEP), 0, st, bc, tp, nb, pairs, n_mtile, tw, per, ks, partial);
         return hipGetLastError();
     };
     switch (n) {
@@ -405,9 +428,18 @@ hipError_t launch_tail(int mode, bool want_t, const float2 *bc, const TailPairs 
 }
 
 hipError_t launch_reduce_dense(const double *partial, int nblk, int64_t n_dense, int batch, double *dense,
-                               hipStream_t st) {
-    hipLaunchKernelGGL(k_reduce_dense, dim3((unsigned)((n_dense + 255) / 256), batch), dim3(256), 0, st, partial,
-                       nblk, n_dense, dense);
+                               double *tmp, hipStream_t st) {
+    const unsigned gx = (unsigned)((n_dense + 255) / 256);
+    if (nblk <= 2 * PG_REDUCE_SEGS || !tmp) {
+        hipLaunchKernelGGL(k_reduce_dense, dim3(gx, batch, 1), dim3(256), 0, st, partial, nblk, nblk, n_dense, dense);
+        return hipGetLastError();
+    }
+    // PG_REDUCE_SEGS segment sums, then their sum (both in a fixed order)
+    const int seg = (nblk + PG_REDUCE_SEGS - 1) / PG_REDUCE_SEGS;
+    const int nseg = (nblk + seg - 1) / seg;
+    hipLaunchKernelGGL(k_reduce_dense, dim3(gx, batch, nseg), dim3(256), 0, st, partial, nblk, seg, n_dense, tmp);
+    hipLaunchKernelGGL(k_reduce_dense, dim3(gx, batch, 1), dim3(256), 0, st, (const double *)tmp, nseg, nseg, n_dense,
+                       dense);
     return hipGetLastError();
 }
 
