@@ -59,7 +59,7 @@ def tail_source_hash():
     return h.hexdigest()
 
 
-def measured_traffic(workload, nblk, wide):
+def measured_traffic(workload, nblk, shape):
     """HBM bytes per launch of the tail kernel from the committed counter
     summary, if it was taken on the current kernel source with this launch
     shape; else None."""
@@ -74,7 +74,7 @@ def measured_traffic(workload, nblk, wide):
                 kv[k.strip()] = v.strip()
     try:
         if (kv.get("source_sha256") != tail_source_hash() or int(kv["nblk"]) != nblk
-                or int(kv["wide"]) != int(wide)):
+                or int(kv["shape"]) != int(shape)):
             return None
         return float(kv["traffic_bytes_per_launch"])
     except (KeyError, ValueError):
@@ -219,7 +219,8 @@ def main():
            "config": {"workload": wl, "n": n, "bins": nb, "triplets": ntri, "quads": nq, "batch": bsz,
                       "precision": "split_bf16", "outputs": "B, P, T"},
            "latency_ms": {"p50": percentile(lat, 50), "p99": percentile(lat, 99)},
-           "stages_ms": stages, "tuning": {"tail_blocks": tuned[0], "tail_wide": tuned[1]}}
+           "stages_ms": stages, "tuning": {"tail_blocks": tuned[0], "tail_shape": ["deep", "wide", "twin"][tuned[1]]
+                                            if tuned[1] is not None else None}}
 
     # dominant kernel and its roofline
     npix = float(n) ** 3

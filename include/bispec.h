@@ -162,17 +162,26 @@ bispec_status bispec_timing_enable(bispec_plan_t plan, int32_t on);
 bispec_status bispec_timing_read(bispec_plan_t plan, double *stage_ms /*[BISPEC_N_STAGES]*/,
                                  int32_t *calls);
 
+/* Block shapes of the fused last-pass + contraction kernel. */
+enum {
+    BISPEC_TAIL_DEEP = 0, /* 512 threads, up to three output tiles per wave */
+    BISPEC_TAIL_WIDE = 1, /* 1024 threads, one output tile per wave (<= 16 tiles) */
+    BISPEC_TAIL_TWIN = 2  /* 512 threads, one tile per wave, half the LDS: two
+                             blocks per CU (N <= 256, <= 8 tiles) */
+};
+
 /* Autotuner: times the fused last-pass + contraction kernel on the attached
- * workspace (zeroed compact rows) for the default block count per map (one
- * per CU, and enough that no block contracts more than 64 tiles of
- * max(N, 512) points) and two and four times it, within the partial buffer
- * the footprint reserves, and for both block shapes (16 waves with one output
- * tile each, when the tiles fit, or 8 waves with up to three); keeps the
- * fastest (a larger count or the deep shape must win by 1.5 %) and reports
- * it.  Synchronises the stream.  bispec_set_tuning restores a stored choice;
- * BISPEC_E_INVALID if nblk is below the 64-tile limit or above the buffer. */
-bispec_status bispec_autotune(bispec_plan_t plan, int32_t *nblk_out, int32_t *wide_out);
-bispec_status bispec_set_tuning(bispec_plan_t plan, int32_t nblk, int32_t wide);
+ * workspace (zeroed compact rows) for every shape that fits the plan's
+ * output tiles and for the default block count per map (one per CU, and
+ * enough that no block contracts more than 64 units of 512 points) and two
+ * and four times it, within the partial buffer the footprint reserves; keeps
+ * the fastest (a candidate after the first must win by 1.5 %: wide, twin,
+ * deep, fewer blocks first) and reports it.  Synchronises the stream.
+ * bispec_set_tuning restores a stored choice; BISPEC_E_INVALID if nblk is
+ * below the 64-unit limit or above the buffer, or the shape is unknown.  A
+ * shape that does not fit the tiles of a call runs as wide, else deep. */
+bispec_status bispec_autotune(bispec_plan_t plan, int32_t *nblk_out, int32_t *shape_out);
+bispec_status bispec_set_tuning(bispec_plan_t plan, int32_t nblk, int32_t shape);
 
 /* Condition number of each planned triplet's real-space sum,
  * kappa_t = sqrt(M_i M_j M_k / (N_pix N_t)) (infinity when N_t = 0): the

@@ -28,6 +28,7 @@ BISPEC_OK = 0
 BISPEC_FP32 = 0
 BISPEC_SPLIT_BF16 = 1
 BISPEC_FP32_VALU = 2
+TAIL_DEEP, TAIL_WIDE, TAIL_TWIN = 0, 1, 2        # block shapes of the fused tail kernel
 STATUS = {0: "BISPEC_OK", -1: "BISPEC_E_INVALID", -2: "BISPEC_E_UNSUPPORTED_N", -3: "BISPEC_E_BIN_RANGE",
           -4: "BISPEC_E_EMPTY_BIN", -5: "BISPEC_E_NO_WORKSPACE", -6: "BISPEC_E_OOM", -7: "BISPEC_E_HIP",
           -8: "BISPEC_E_NUMERIC"}
@@ -228,13 +229,14 @@ class Plan:
             check(bispec_set_workspace(self.handle, _ptr(self.workspace), sz.value), "bispec_set_workspace")
 
     def autotune(self):
-        """Time the contraction kernel's launch shapes; returns (blocks, wide)."""
-        nb, wd = ctypes.c_int32(), ctypes.c_int32()
-        check(bispec_autotune(self.handle, ctypes.byref(nb), ctypes.byref(wd)), "bispec_autotune")
-        return nb.value, bool(wd.value)
+        """Time the contraction kernel's launch shapes; returns (blocks, shape),
+        shape one of TAIL_DEEP, TAIL_WIDE, TAIL_TWIN."""
+        nb, sh = ctypes.c_int32(), ctypes.c_int32()
+        check(bispec_autotune(self.handle, ctypes.byref(nb), ctypes.byref(sh)), "bispec_autotune")
+        return nb.value, sh.value
 
-    def set_tuning(self, nblk, wide):
-        check(bispec_set_tuning(self.handle, int(nblk), 1 if wide else 0), "bispec_set_tuning")
+    def set_tuning(self, nblk, shape):
+        check(bispec_set_tuning(self.handle, int(nblk), int(shape)), "bispec_set_tuning")
 
     @property
     def condition(self):

@@ -90,9 +90,9 @@ Layout make_layout(const bispec_plan_s &p, int batch) {
         // the largest partial set over both block shapes, with and without T
         size_t per_blk = 0;
         for (int t = 0; t < 2; ++t)
-            for (int w = 0; w < 2; ++w)
+            for (int sh : {PG_SHAPE_DEEP, PG_SHAPE_WIDE, PG_SHAPE_TWIN})
                 per_blk = std::max(per_blk, pgram_partial_doubles(p.n_mtile, t != 0) *
-                                                (size_t)tail_ksplit(p.n_mtile, t != 0, w != 0));
+                                                (size_t)tail_ksplit(p.n, p.n_mtile, t != 0, sh));
         off = align_up(off + sizeof(double) * per_blk * p.nblk_pg_max * batch);
     }
     L.pg_dense = off;
@@ -564,7 +564,7 @@ bispec_status plan_impl(const bispec_plan_desc *d, bispec_plan_t *out) {
         // (its FP32 accumulation span), and there are at least 256 blocks
         // (one per CU) when the map has that many tiles.  The tuner may take
         // up to four times the default, within 2048 blocks.
-        const int64_t tiles = tail_tiles(n);
+        const int64_t tiles = tail_units(n);
         const int64_t need = (tiles + PG_CHUNK_TILES - 1) / PG_CHUNK_TILES;
         const int64_t lo = std::max<int64_t>(need, std::min<int64_t>(tiles, 256));
         p->nblk_pg_min = (int)need;
@@ -746,10 +746,10 @@ bispec_status run_estimate_body(bispec_plan_s &p, const float *delta, int batch,
         double *pg = (double *)(ws + L.pg_partial);
         double *dense = (double *)(ws + L.pg_dense);
         CK(launch_tail(mode, t_mfma, (const float2 *)(ws + L.bc), tp, n, p.nb, batch,
-                       (const uchar2 *)(ws + L.pg_pairs), p.n_mtile, tw, p.nblk_pg, pg, p.stream, p.tail_wide));
+                       (const uchar2 *)(ws + L.pg_pairs), p.n_mtile, tw, p.nblk_pg, pg, p.stream, p.tail_shape));
         const int64_t n_dense = (int64_t)pgram_partial_doubles(p.n_mtile, t_mfma);
         stamp(p, 3);
-        CK(launch_reduce_dense(pg, p.nblk_pg * tail_ksplit(p.n_mtile, t_mfma, p.tail_wide), n_dense, batch, dense,
+        CK(launch_reduce_dense(pg, p.nblk_pg * tail_ksplit(n, p.n_mtile, t_mfma, p.tail_shape), n_dense, batch, dense,
                                (double *)(ws + L.pg_tmp), p.stream));
         if (first < last) {
             s = finalize_range(p, true, dense, 1, n_dense, first, last, batch, P, B, T);
@@ -911,7 +911,7 @@ bispec_status polyspec_estimate(bispec_plan_t plan, const float *delta, int32_t 
     }
 }
 
-bispec_status bispec_autotune(bispec_plan_t plan, int32_t *nblk_out, int32_t *wide_out) {
+bispec_status bispec_autotune(bispec_plan_t plan, int32_t *nblk_out, int32_t *shape_out) {
     if (!plan) return BISPEC_E_INVALID;
     bispec_plan_s &p = *plan;
     if (!p.ws) return BISPEC_E_NO_WORKSPACE;
@@ -934,15 +934,16 @@ bispec_status bispec_autotune(bispec_plan_t plan, int32_t *nblk_out, int32_t *wi
             hipEvent_t e0, e1;
             CK(hipEventCreate(&e0));
             CK(hipEventCreate(&e1));
-            // candidates: the default block count and two and four times it;
-            // a larger count or the deep shape must win by 1.5 % to be kept
-            // (fewer partial tiles to write and reduce)
+            // candidates: the wide, twin and deep shapes (those that fit the
+            // tile count) at the default block count and two and four times
+            // it; a later candidate must win by 1.5 % to be kept (the first
+            // ones write and reduce fewer partial tiles)
             float best = 1e30f;
             int best_nblk = p.nblk_pg;
-            bool best_wide = p.tail_wide;
+            int best_shape = p.tail_shape;
             const int base = p.nblk_pg;
-            for (int wide = 1; wide >= 0; --wide) {
-                if (wide && !tail_wide_fits(p.n_mtile, t)) continue;
+            for (int sh : {PG_SHAPE_WIDE, PG_SHAPE_TWIN, PG_SHAPE_DEEP}) {
+                if (!tail_shape_fits(n, p.n_mtile, t, sh)) continue;
                 for (int nb : {base, 2 * base, 4 * base}) {
                     if (nb > p.nblk_pg_max) continue;
                     float tot = 0.0f;
@@ -950,7 +951,7 @@ bispec_status bispec_autotune(bispec_plan_t plan, int32_t *nblk_out, int32_t *wi
                         CK(hipEventRecord(e0, p.stream));
                         CK(launch_tail(mode, t, (const float2 *)(ws + L.bc), tp, n, p.nb, 1,
                                        (const uchar2 *)(ws + L.pg_pairs), p.n_mtile, (const float2 *)(ws + L.tw),
-                                       nb, (double *)(ws + L.pg_partial), p.stream, wide != 0));
+                                       nb, (double *)(ws + L.pg_partial), p.stream, sh));
                         CK(hipEventRecord(e1, p.stream));
                         CK(hipEventSynchronize(e1));
                         float ms = 0.0f;
@@ -960,28 +961,33 @@ bispec_status bispec_autotune(bispec_plan_t plan, int32_t *nblk_out, int32_t *wi
                     if (tot < best * 0.985f || best >= 1e30f) {
                         best = tot;
                         best_nblk = nb;
-                        best_wide = wide != 0;
+                        best_shape = sh;
                     }
                 }
             }
             (void)hipEventDestroy(e0);
             (void)hipEventDestroy(e1);
             p.nblk_pg = best_nblk;
-            p.tail_wide = best_wide;
+            p.tail_shape = best_shape;
             p.drop_graphs();
         } catch (...) {
             return BISPEC_E_HIP;
         }
     }
     if (nblk_out) *nblk_out = p.nblk_pg;
-    if (wide_out) *wide_out = p.tail_wide ? 1 : 0;
+    if (shape_out) *shape_out = p.tail_shape;
     return BISPEC_OK;
 }
 
-bispec_status bispec_set_tuning(bispec_plan_t plan, int32_t nblk, int32_t wide) {
+static_assert(BISPEC_TAIL_DEEP == PG_SHAPE_DEEP && BISPEC_TAIL_WIDE == PG_SHAPE_WIDE &&
+                  BISPEC_TAIL_TWIN == PG_SHAPE_TWIN,
+              "public and internal tail shapes agree");
+
+bispec_status bispec_set_tuning(bispec_plan_t plan, int32_t nblk, int32_t shape) {
     if (!plan || nblk < plan->nblk_pg_min || nblk > plan->nblk_pg_max) return BISPEC_E_INVALID;
+    if (shape != BISPEC_TAIL_DEEP && shape != BISPEC_TAIL_WIDE && shape != BISPEC_TAIL_TWIN) return BISPEC_E_INVALID;
     plan->nblk_pg = nblk;
-    plan->tail_wide = wide != 0;
+    plan->tail_shape = shape;
     plan->drop_graphs();
     return BISPEC_OK;
 }

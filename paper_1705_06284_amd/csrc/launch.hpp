@@ -46,10 +46,11 @@ constexpr int PG_MODE_F32 = 0;
 constexpr int PG_MODE_SPLIT = 1;
 constexpr int PG_ROW_ZERO = 32;
 constexpr int PG_ROW_ONE = 33;
-// The fused tail works on tiles of max(N, 512) grid points; one block
-// contracts at most PG_CHUNK_TILES of them.
+// The fused tail's work is counted in units of 512 grid points
+// (tail_units(n) = N^3 / 512 per map); one block contracts at most
+// PG_CHUNK_TILES units.
 constexpr int PG_CHUNK_TILES = 64;
-int64_t tail_tiles(int n);
+int64_t tail_units(int n);
 size_t pgram_partial_doubles(int n_mtile, bool want_t);
 // Fused pass X + product-Gram over the compact rows of all shell pairs.
 struct TailPairs {
@@ -58,16 +59,20 @@ struct TailPairs {
     long long off[16];      // float2 offset of pair q's compact rows of map 0
     int npairs;
 };
-// prefer_wide: 16 waves with one tile each when the tiles fit (else 8 waves
-// with up to three).  nblk blocks per map, at least
-// ceil(tail_tiles(n) / PG_CHUNK_TILES) (else hipErrorInvalidValue).
+// Block shapes of launch_tail (mfma.hip): wide (16 waves, one output tile
+// each), deep (8 waves, up to three), twin (8 waves, one tile, 256-point
+// tiles, two blocks per CU; N <= 256).  A shape that does not fit the tile
+// count falls back to wide, else deep (tail_shape).  nblk blocks per map,
+// at least ceil(tail_units(n) / PG_CHUNK_TILES) (else hipErrorInvalidValue).
+constexpr int PG_SHAPE_DEEP = 0, PG_SHAPE_WIDE = 1, PG_SHAPE_TWIN = 2;
 hipError_t launch_tail(int mode, bool want_t, const float2 *bc, const TailPairs &tp, int n, int nb, int batch,
                        const uchar2 *pairs, int n_mtile, const float2 *tw, int nblk, double *partial,
-                       hipStream_t st, bool prefer_wide);
-bool tail_wide_fits(int n_mtile, bool want_t);
+                       hipStream_t st, int shape);
+bool tail_shape_fits(int n, int n_mtile, bool want_t, int shape);
+int tail_shape(int n, int n_mtile, bool want_t, int shape);
 // K parts per output tile of the launched shape: each block writes
 // tail_ksplit(...) partial sets of n_mtile + want_t tiles.
-int tail_ksplit(int n_mtile, bool want_t, bool prefer_wide);
+int tail_ksplit(int n, int n_mtile, bool want_t, int shape);
 // dense[map][e] = sum over the nblk partial sets; tmp holds
 // PG_REDUCE_SEGS * n_dense * batch doubles of segment sums (or null: one pass).
 constexpr int PG_REDUCE_SEGS = 32;

@@ -43,10 +43,17 @@ typedef float f32x2 __attribute__((ext_vector_type(2)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 constexpr int PG_TK_TAIL = 512;           // grid points per LDS tile of the fused tail
-// Two block shapes: 16 waves owning one output tile each (up to 16 tiles,
-// half the registers, 4 waves per SIMD) or 8 waves owning up to three.
+// Block shapes of the fused tail (threads, output tiles per wave, points per
+// LDS tile; tiles are at least one x-row of N points):
+//   wide: 1024 threads, one tile per wave, 512 points (up to 16 tiles, 4
+//         waves per SIMD);
+//   deep: 512 threads, up to three tiles per wave, 512 points;
+//   twin: 512 threads, one tile per wave, 256 points (N <= 256, up to 8
+//         tiles): half the LDS of the others, so two blocks share a CU and
+//         one block's transforms overlap the other's contraction.
 constexpr int PG_NT_WIDE = 1024, PG_MAXT_WIDE = 1;
 constexpr int PG_NT_DEEP = 512, PG_MAXT_DEEP = 3;
+constexpr int PG_NT_TWIN = 512, PG_MAXT_TWIN = 1, PG_TK_TWIN = 256;
 constexpr int PG_FLUSH_POINTS = 4096;     // FP32-mode accumulation span before an FP64 flush
 constexpr int PG_ZERO = PG_ROW_ZERO;      // field row of zeros (padding rows)
 constexpr int PG_ONE = PG_ROW_ONE;        // field row of ones (F_b * 1 rows)
@@ -211,17 +218,17 @@ __device__ __forceinline__ void split_columns(const float *Ft, __bf16 *Bh, __bf1
     }
 }
 
-// Fused last inverse pass + product-Gram.  A tile is TK = max(N, 256) grid
+// Fused last inverse pass + product-Gram.  A tile is TK = max(N, TKP) grid
 // points: RT = TK/N consecutive x-rows (n_z, n_y).  For every row and shell
 // pair the compact rows Bc[n_z][n_y][m_x + R] are placed at m_x mod N and
 // transformed along x in LDS; the real and imaginary parts are the bin
 // fields F_2q and F_2q+1 at the tile's points, contracted at once.
-template <int MODE, bool WANT_T, int N, int NT, int MAXT>
-__global__ __launch_bounds__(NT) void k_tail(const float2 *__restrict__ bc, TailPairs tp, int nb,
+template <int MODE, bool WANT_T, int N, int NT, int MAXT, int TKP, int MINW>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MINW))) void k_tail(const float2 *__restrict__ bc, TailPairs tp, int nb,
                                              const uchar2 *__restrict__ pairs, int n_mtile,
                                              const float2 *__restrict__ tw, int tiles_per_blk, int ksplit,
                                              double *__restrict__ partial) {
-    constexpr int TK = N >= PG_TK_TAIL ? N : PG_TK_TAIL;
+    constexpr int TK = N >= TKP ? N : TKP;
     constexpr int RT = TK / N;
     constexpr int G = 16 * RT;                 // pencil slots: 16 pairs x RT rows
     constexpr int FS = TK + 4, BS = TK + 8;
@@ -359,22 +366,31 @@ __global__ __launch_bounds__(256) void k_finalize_gather(const double *__restric
     }
 }
 
-int64_t tail_tiles(int n) {
-    const int64_t tk = n >= PG_TK_TAIL ? n : PG_TK_TAIL;
-    return (int64_t)n * n * n / tk;
-}
-
 size_t pgram_partial_doubles(int n_mtile, bool want_t) { return (size_t)(n_mtile + (want_t ? 1 : 0)) * 1024; }
 
-bool tail_wide_fits(int n_mtile, bool want_t) {
-    return n_mtile + (want_t ? 1 : 0) <= PG_MAXT_WIDE * (PG_NT_WIDE / 64);
+int64_t tail_units(int n) { return (int64_t)n * n * n / PG_TK_TAIL; }
+
+bool tail_shape_fits(int n, int n_mtile, bool want_t, int shape) {
+    const int n_out = n_mtile + (want_t ? 1 : 0);
+    switch (shape) {
+        case PG_SHAPE_WIDE: return n_out <= PG_MAXT_WIDE * (PG_NT_WIDE / 64);
+        case PG_SHAPE_DEEP: return n_out <= PG_MAXT_DEEP * (PG_NT_DEEP / 64);
+        case PG_SHAPE_TWIN: return n <= PG_TK_TWIN && n_out <= PG_MAXT_TWIN * (PG_NT_TWIN / 64);
+        default: return false;
+    }
 }
 
-int tail_ksplit(int n_mtile, bool want_t, bool prefer_wide) {
+int tail_shape(int n, int n_mtile, bool want_t, int shape) {
+    if (tail_shape_fits(n, n_mtile, want_t, shape)) return shape;
+    return tail_shape_fits(n, n_mtile, want_t, PG_SHAPE_WIDE) ? PG_SHAPE_WIDE : PG_SHAPE_DEEP;
+}
+
+int tail_ksplit(int n, int n_mtile, bool want_t, int shape) {
     const int n_out = n_mtile + (want_t ? 1 : 0);
-    const bool wide = prefer_wide && tail_wide_fits(n_mtile, want_t);
-    const int waves = (wide ? PG_NT_WIDE : PG_NT_DEEP) / 64;
-    const int cap = (wide ? PG_MAXT_WIDE : PG_MAXT_DEEP) * waves;
+    const int sh = tail_shape(n, n_mtile, want_t, shape);
+    const int nt = sh == PG_SHAPE_WIDE ? PG_NT_WIDE : sh == PG_SHAPE_DEEP ? PG_NT_DEEP : PG_NT_TWIN;
+    const int maxt = sh == PG_SHAPE_WIDE ? PG_MAXT_WIDE : sh == PG_SHAPE_DEEP ? PG_MAXT_DEEP : PG_MAXT_TWIN;
+    const int waves = nt / 64, cap = maxt * waves;
     int k = 1;
     while (2 * k <= waves && n_out * 2 * k <= cap) k *= 2;
     return k;
@@ -382,21 +398,30 @@ int tail_ksplit(int n_mtile, bool want_t, bool prefer_wide) {
 
 template <int MODE, bool WANT_T>
 hipError_t launch_tail_m(const float2 *bc, const TailPairs &tp, int n, int nb, int batch, const uchar2 *pairs,
-                         int n_mtile, const float2 *tw, int nblk, double *partial, hipStream_t st, bool prefer_wide) {
-    const bool wide = prefer_wide && tail_wide_fits(n_mtile, WANT_T);
-    const int ks = tail_ksplit(n_mtile, WANT_T, prefer_wide);
+                         int n_mtile, const float2 *tw, int nblk, double *partial, hipStream_t st, int shape) {
+    const int sh = tail_shape(n, n_mtile, WANT_T, shape);
+    const int ks = tail_ksplit(n, n_mtile, WANT_T, shape);
+    const int64_t units = tail_units(n);
+    const int per = (int)((units + nblk - 1) / nblk);       // 512-point units per block
+    if (nblk < 1 || per > PG_CHUNK_TILES) return hipErrorInvalidValue;
     auto go = [&](auto nc) -> hipError_t {
         constexpr int NN = decltype(nc)::value;
-        constexpr int TK = NN >= PG_TK_TAIL ? NN : PG_TK_TAIL;
-        const int64_t total = (int64_t)NN * NN * NN / TK;
-        const int per = (int)((total + nblk - 1) / nblk);
-        if (nblk < 1 || per > PG_CHUNK_TILES) return hipErrorInvalidValue;
-        if (wide)
-            hipLaunchKernelGGL((k_tail<MODE, WANT_T, NN, PG_NT_WIDE, PG_MAXT_WIDE>), dim3(nblk, batch),
-                               dim3(PG_NT_WIDE), 0, st, bc, tp, nb, pairs, n_mtile, tw, per, ks, partial);
-        else
-            hipLaunchKernelGGL((k_tail<MODE, WANT_T, NN, PG_NT_DEEP, PG_MAXT_DEEP>), dim3(nblk, batch),
-                               dim3(PG_NT_DEEP), 0, st, bc, tp, nb, pairs, n_mtile, tw, per, ks, partial);
+        constexpr int TKW = NN >= PG_TK_TAIL ? NN : PG_TK_TAIL;
+        const int per_w = (int)((int64_t)per * PG_TK_TAIL / TKW);
+        if (sh == PG_SHAPE_WIDE)
+            hipLaunchKernelGGL((k_tail<MODE, WANT_T, NN, PG_NT_WIDE, PG_MAXT_WIDE, PG_TK_TAIL, 4>), dim3(nblk, batch),
+                               dim3(PG_NT_WIDE), 0, st, bc, tp, nb, pairs, n_mtile, tw, per_w, ks, partial);
+        else if (sh == PG_SHAPE_DEEP)
+            hipLaunchKernelGGL((k_tail<MODE, WANT_T, NN, PG_NT_DEEP, PG_MAXT_DEEP, PG_TK_TAIL, 2>), dim3(nblk, batch),
+                               dim3(PG_NT_DEEP), 0, st, bc, tp, nb, pairs, n_mtile, tw, per_w, ks, partial);
+        else if constexpr (NN <= PG_TK_TWIN) {
+            constexpr int TKT = NN >= PG_TK_TWIN ? NN : PG_TK_TWIN;
+            const int per_t = (int)((int64_t)per * PG_TK_TAIL / TKT);
+            hipLaunchKernelGGL((k_tail<MODE, WANT_T, NN, PG_NT_TWIN, PG_MAXT_TWIN, PG_TK_TWIN, 4>), dim3(nblk, batch),
+                               dim3(PG_NT_TWIN), 0, st, bc, tp, nb, pairs, n_mtile, tw, per_t, ks, partial);
+        } else {
+            return hipErrorInvalidValue;
+        }
         return hipGetLastError();
     };
     switch (n) {
@@ -413,18 +438,17 @@ hipError_t launch_tail_m(const float2 *bc, const TailPairs &tp, int n, int nb, i
 
 hipError_t launch_tail(int mode, bool want_t, const float2 *bc, const TailPairs &tp, int n, int nb, int batch,
                        const uchar2 *pairs, int n_mtile, const float2 *tw, int nblk, double *partial,
-                       hipStream_t st, bool prefer_wide) {
-    if (nb > 32 || tp.npairs > 16 || n_mtile + (want_t ? 1 : 0) > PG_MAXT_DEEP * (PG_NT_DEEP / 64))
-        return hipErrorInvalidValue;
+                       hipStream_t st, int shape) {
+    if (nb > 32 || tp.npairs > 16 || !tail_shape_fits(n, n_mtile, want_t, PG_SHAPE_DEEP)) return hipErrorInvalidValue;
     if (mode == PG_MODE_SPLIT)
         return want_t ? launch_tail_m<PG_MODE_SPLIT, true>(bc, tp, n, nb, batch, pairs, n_mtile, tw, nblk, partial, st,
-                                                           prefer_wide)
+                                                           shape)
                       : launch_tail_m<PG_MODE_SPLIT, false>(bc, tp, n, nb, batch, pairs, n_mtile, tw, nblk, partial,
-                                                            st, prefer_wide);
+                                                            st, shape);
     return want_t ? launch_tail_m<PG_MODE_F32, true>(bc, tp, n, nb, batch, pairs, n_mtile, tw, nblk, partial, st,
-                                                     prefer_wide)
+                                                     shape)
                   : launch_tail_m<PG_MODE_F32, false>(bc, tp, n, nb, batch, pairs, n_mtile, tw, nblk, partial, st,
-                                                      prefer_wide);
+                                                      shape);
 }
 
 hipError_t launch_reduce_dense(const double *partial, int nblk, int64_t n_dense, int batch, double *dense,

@@ -45,7 +45,7 @@ struct bispec_plan_s {
     int nblk_pg = 1;                     // blocks of the product-Gram kernel (tuned)
     int nblk_pg_min = 1;                 // fewest blocks (chunk span limit)
     int nblk_pg_max = 1;                 // partial buffer capacity in blocks
-    bool tail_wide = true;               // tail block shape (tuned)
+    int tail_shape = 1;                  // tail block shape, PG_SHAPE_* (tuned; 1 = wide)
     std::vector<uchar2> pg_pairs;        // [n_mtile*32] row factors
     std::vector<int> pg_idx;             // per term: index into a block's dense tiles
     // stage timing: one event per stage boundary per call

@@ -297,18 +297,18 @@ def test_autotune_choices_agree_with_oracle(binding):
     plan = binding.Plan(n, lo, hi, precision="split_bf16")
     ref = oracle.bispectrum(d, lo, hi, plan.triplets)
     refp, _ = oracle.power_spectrum(d, lo, hi)
-    nb, wide = plan.autotune()
-    # 512 tiles of 512 points: at least 8 blocks (64 tiles each), default 256, at most 512
-    assert nb in (256, 512) and isinstance(wide, bool)
+    nb, shape = plan.autotune()
+    # 512 units of 512 points: at least 8 blocks (64 units each), default 256, at most 512
+    assert nb in (256, 512) and shape in (binding.TAIL_WIDE, binding.TAIL_TWIN, binding.TAIL_DEEP)
     for blocks in (8, 100, 256, 512):
-        for w in (True, False):
-            plan.set_tuning(blocks, w)
+        for sh in (binding.TAIL_WIDE, binding.TAIL_TWIN, binding.TAIL_DEEP):
+            plan.set_tuning(blocks, sh)
             P, B, T = plan.polyspec(d)
-            assert np.max(_err(B.cpu().numpy()[0], ref)) <= TOL["split_bf16"], (blocks, w)
-            assert np.max(np.abs(P.cpu().numpy()[0] - refp) / refp) <= TOL["split_bf16"], (blocks, w)
-    for bad in (0, 7, 513):
+            assert np.max(_err(B.cpu().numpy()[0], ref)) <= TOL["split_bf16"], (blocks, sh)
+            assert np.max(np.abs(P.cpu().numpy()[0] - refp) / refp) <= TOL["split_bf16"], (blocks, sh)
+    for bad, sh in ((0, 1), (7, 1), (513, 1), (256, 3), (256, -1)):
         with pytest.raises(binding.BispecError) as ei:
-            plan.set_tuning(bad, True)
+            plan.set_tuning(bad, sh)
         assert ei.value.code == -1
 
 
