@@ -117,40 +117,54 @@ struct PgState {
             for (int r = 0; r < 16; ++r) dacc[t][r] = 0.0;
     }
 
+    // Split-mode steps of this wave's K part.  HAS_T: one of the wave's tiles
+    // is the p = 4 tile (its columns come from the rows, not from Bh/Bl).
+    template <int TK, int FS, int BS, bool HAS_T>
+    __device__ __forceinline__ void contract_split(const float *Ft, const __bf16 *Bh, const __bf16 *Bl, int n_mtile,
+                                                   int col, int half) {
+#pragma unroll 1
+        for (int s = kpart; s < TK / 16; s += ksplit) {
+            const int kp = s * 16 + half * 8;
+            const bf16x8 bh = *reinterpret_cast<const bf16x8 *>(&Bh[col * BS + kp]);
+            const bf16x8 bl = *reinterpret_cast<const bf16x8 *>(&Bl[col * BS + kp]);
+#pragma unroll
+            for (int t = 0; t < MAXT; ++t) {
+                if (tile_of[t] < 0) continue;
+                const float4 i0 = *reinterpret_cast<const float4 *>(&Ft[rp[t].x * FS + kp]);
+                const float4 i1 = *reinterpret_cast<const float4 *>(&Ft[rp[t].x * FS + kp + 4]);
+                const float4 j0 = *reinterpret_cast<const float4 *>(&Ft[rp[t].y * FS + kp]);
+                const float4 j1 = *reinterpret_cast<const float4 *>(&Ft[rp[t].y * FS + kp + 4]);
+                float a[8] = {i0.x * j0.x, i0.y * j0.y, i0.z * j0.z, i0.w * j0.w,
+                              i1.x * j1.x, i1.y * j1.y, i1.z * j1.z, i1.w * j1.w};
+                bf16x8 ah, al;
+                split8(a, ah, al);
+                if (HAS_T && tile_of[t] == n_mtile) {
+                    // rows and columns are both F_col^2 at this lane's points
+                    acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, ah, acc[t], 0, 0, 0);
+                    acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, al, acc[t], 0, 0, 0);
+                    acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, ah, acc[t], 0, 0, 0);
+                } else {
+                    acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, acc[t], 0, 0, 0);
+                    acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, acc[t], 0, 0, 0);
+                    acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, acc[t], 0, 0, 0);
+                }
+            }
+        }
+    }
+
     // Contract TK points of the LDS field tile Ft (row stride FS); in split
     // mode Bh/Bl (row stride BS) hold the bf16 halves of the columns F_k.
     template <int TK, int FS, int BS>
     __device__ __forceinline__ void contract(const float *Ft, const __bf16 *Bh, const __bf16 *Bl, int n_mtile,
                                              int col, int half) {
         if constexpr (MODE == PG_MODE_SPLIT) {
-#pragma unroll 1
-            for (int s = kpart; s < TK / 16; s += ksplit) {
-                const int kp = s * 16 + half * 8;
-                const bf16x8 bh = *reinterpret_cast<const bf16x8 *>(&Bh[col * BS + kp]);
-                const bf16x8 bl = *reinterpret_cast<const bf16x8 *>(&Bl[col * BS + kp]);
+            bool has_t = false;
 #pragma unroll
-                for (int t = 0; t < MAXT; ++t) {
-                    if (tile_of[t] < 0) continue;
-                    const float4 i0 = *reinterpret_cast<const float4 *>(&Ft[rp[t].x * FS + kp]);
-                    const float4 i1 = *reinterpret_cast<const float4 *>(&Ft[rp[t].x * FS + kp + 4]);
-                    const float4 j0 = *reinterpret_cast<const float4 *>(&Ft[rp[t].y * FS + kp]);
-                    const float4 j1 = *reinterpret_cast<const float4 *>(&Ft[rp[t].y * FS + kp + 4]);
-                    float a[8] = {i0.x * j0.x, i0.y * j0.y, i0.z * j0.z, i0.w * j0.w,
-                                  i1.x * j1.x, i1.y * j1.y, i1.z * j1.z, i1.w * j1.w};
-                    bf16x8 ah, al;
-                    split8(a, ah, al);
-                    if (WANT_T && tile_of[t] == n_mtile) {
-                        // rows and columns are both F_col^2 at this lane's points
-                        acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, ah, acc[t], 0, 0, 0);
-                        acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, al, acc[t], 0, 0, 0);
-                        acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, ah, acc[t], 0, 0, 0);
-                    } else {
-                        acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, acc[t], 0, 0, 0);
-                        acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, acc[t], 0, 0, 0);
-                        acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, acc[t], 0, 0, 0);
-                    }
-                }
-            }
+            for (int t = 0; t < MAXT; ++t) has_t = has_t || (WANT_T && tile_of[t] == n_mtile);
+            if (has_t)
+                contract_split<TK, FS, BS, WANT_T>(Ft, Bh, Bl, n_mtile, col, half);
+            else
+                contract_split<TK, FS, BS, false>(Ft, Bh, Bl, n_mtile, col, half);
         } else {
 #pragma unroll 1
             for (int s = kpart; s < TK / 2; s += ksplit) {
@@ -245,7 +259,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MINW))) void
     __bf16 *Bh = reinterpret_cast<__bf16 *>(ubuf);
     __bf16 *Bl = Bh + 32 * BS;
 
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform, kept in SGPRs
     const int col = lane & 31, half = lane >> 5;
     const int map = blockIdx.y;
     const int64_t nrow = (int64_t)N * N;
