@@ -227,11 +227,14 @@ std::vector<PairDev> pair_devs(const bispec_plan_s &p) {
 // dense index in a block's tiles is tile*1024 + row_in_tile*32 + column.
 // Rows of the product-Gram.  Every (b,b) row is kept; when nb < 32 column nb
 // is a field of ones, so G[(b,b), nb] is the power-spectrum numerator, else
-// rows (b, ONE) are added for it.  A triplet a <= b <= c is read from
-// G[(x,y), z] for one of its three pairs (x,y): a pair already chosen if
-// there is one, else one whose bins have equal parity.  Among three bins two
-// always share a parity, and a repeated bin gives a (b,b) row, so at most the
-// pairs of equal parity are needed (about nb^2/4 rows instead of nb^2/2).
+// rows (b, ONE) are added for it.  A triplet a <= b <= c can be read from
+// G[(x,y), z] for any of its three pairs (x,y); the pair rows are a greedy
+// set cover of the requested triplets: repeatedly the pair in the most
+// not-yet-covered triplets (lowest pair index on ties).  A repeated bin is
+// covered by its (b,b) row, and among three distinct bins two share a
+// parity, so the equal-parity pairs (about nb^2/4) always suffice; the
+// greedy cover is smaller (128 rows instead of 156 for 1541 triplets of 24
+// linear bins).
 void build_pgram_tables(bispec_plan_s &p) {
     const int nb = p.nb;
     p.mfma_ok = nb <= 32;
@@ -254,20 +257,43 @@ void build_pgram_tables(bispec_plan_s &p) {
             p.pg_pairs.push_back(uchar2{(unsigned char)b, (unsigned char)PG_ROW_ONE});
         }
     const int ntri = (int)p.tri.size() / 3;
-    std::vector<int> tri_row(ntri), tri_col(ntri);
+    // pair index x*nb + y (x <= y) of the three pairs of each sorted triplet
+    std::vector<int> tp(3 * ntri), rest(3 * ntri);
     for (int t = 0; t < ntri; ++t) {
         int a[3] = {p.tri[3 * t], p.tri[3 * t + 1], p.tri[3 * t + 2]};
         std::sort(a, a + 3);
-        // candidate (pair, remaining bin): (a0,a1)|a2, (a0,a2)|a1, (a1,a2)|a0
-        const int cand[3][3] = {{a[0], a[1], a[2]}, {a[0], a[2], a[1]}, {a[1], a[2], a[0]}};
-        int pick = -1;
-        for (int c = 0; c < 3 && pick < 0; ++c)
-            if (row_of[cand[c][0] * nb + cand[c][1]] >= 0) pick = c;
-        for (int c = 0; c < 3 && pick < 0; ++c)
-            if ((cand[c][0] & 1) == (cand[c][1] & 1)) pick = c;
-        tri_row[t] = add(cand[pick][0], cand[pick][1]);
-        tri_col[t] = cand[pick][2];
+        const int c[3][3] = {{a[0], a[1], a[2]}, {a[0], a[2], a[1]}, {a[1], a[2], a[0]}};
+        for (int k = 0; k < 3; ++k) {
+            tp[3 * t + k] = c[k][0] * nb + c[k][1];
+            rest[3 * t + k] = c[k][2];
+        }
     }
+    auto covered = [&](int t) {
+        return row_of[tp[3 * t]] >= 0 || row_of[tp[3 * t + 1]] >= 0 || row_of[tp[3 * t + 2]] >= 0;
+    };
+    std::vector<int> open;
+    for (int t = 0; t < ntri; ++t)
+        if (!covered(t)) open.push_back(t);
+    std::vector<int> cnt(nb * nb);
+    while (!open.empty()) {
+        std::fill(cnt.begin(), cnt.end(), 0);
+        for (int t : open)
+            for (int k = 0; k < 3; ++k) ++cnt[tp[3 * t + k]];
+        const int best = (int)(std::max_element(cnt.begin(), cnt.end()) - cnt.begin());
+        add(best / nb, best % nb);
+        std::vector<int> left;
+        for (int t : open)
+            if (!covered(t)) left.push_back(t);
+        open.swap(left);
+    }
+    std::vector<int> tri_row(ntri), tri_col(ntri);
+    for (int t = 0; t < ntri; ++t)
+        for (int k = 0; k < 3; ++k)
+            if (row_of[tp[3 * t + k]] >= 0) {
+                tri_row[t] = row_of[tp[3 * t + k]];
+                tri_col[t] = rest[3 * t + k];
+                break;
+            }
     while (p.pg_pairs.size() % 32) p.pg_pairs.push_back(uchar2{(unsigned char)PG_ROW_ZERO, (unsigned char)PG_ROW_ZERO});
     p.n_mtile = (int)p.pg_pairs.size() / 32;
     auto dense = [](int row, int c) { return (row / 32) * 1024 + (row % 32) * 32 + c; };

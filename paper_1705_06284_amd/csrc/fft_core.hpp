@@ -120,9 +120,10 @@ constexpr int ilog8_floor(int n) { return n >= 8 ? 1 + ilog8_floor(n / 8) : 0; }
 constexpr int ipow8(int p) { return p == 0 ? 1 : 8 * ipow8(p - 1); }
 
 // One Stockham pass over the first g_act of the G pencils of the block (NT
-// threads); the others are left untouched.
-template <typename C, int N, int LD, int G, int DIR, int RADIX, int NS, int NT>
-__device__ __forceinline__ void stockham_pass(C *s, const C *tw, int g_act) {
+// threads); the others are left untouched.  Output u of a butterfly goes to
+// store(pencil, position, value) once every thread has read its inputs.
+template <typename C, int N, int LD, int G, int DIR, int RADIX, int NS, int NT, typename Store>
+__device__ __forceinline__ void stockham_pass_to(C *s, const C *tw, int g_act, Store store) {
     constexpr int NB = N / RADIX;          // butterflies per pencil
     constexpr int TASKS = G * NB;
     static_assert(TASKS % NT == 0 || TASKS < NT, "pencil group must fill the block or fit in it");
@@ -159,9 +160,15 @@ __device__ __forceinline__ void stockham_pass(C *s, const C *tw, int g_act) {
         const int k = jj % NS;
         const int base = (jj / NS) * NS * RADIX + k;
 #pragma unroll
-        for (int u = 0; u < RADIX; ++u) s[p * LD + pad_idx(base + u * NS)] = v[q][u];
+        for (int u = 0; u < RADIX; ++u) store(p, base + u * NS, v[q][u]);
     }
     __syncthreads();
+}
+
+template <typename C, int N, int LD, int G, int DIR, int RADIX, int NS, int NT>
+__device__ __forceinline__ void stockham_pass(C *s, const C *tw, int g_act) {
+    stockham_pass_to<C, N, LD, G, DIR, RADIX, NS, NT>(
+        s, tw, g_act, [s](int p, int pos, C v) { s[p * LD + pad_idx(pos)] = v; });
 }
 
 // Full length-N transform of the first g_act (default all G) pencils held in
@@ -177,6 +184,24 @@ __device__ __forceinline__ void fft_pencils(C *s, const C *tw, int g_act = G) {
     if constexpr (P8 >= 3) stockham_pass<C, N, LD, G, DIR, 8, 64, NT>(s, tw, g_act);
     if constexpr (P8 >= 4) stockham_pass<C, N, LD, G, DIR, 8, 512, NT>(s, tw, g_act);
     if constexpr (RL > 1) stockham_pass<C, N, LD, G, DIR, RL, ipow8(P8), NT>(s, tw, g_act);
+}
+
+// As fft_pencils, but the last pass hands its outputs (pencil, position in
+// natural order, value) to store instead of writing them back to s; s may be
+// overwritten by store, since every read of the pass precedes it.
+template <typename C, int N, int LD, int G, int DIR, int NT, typename Store>
+__device__ __forceinline__ void fft_pencils_to(C *s, const C *tw, int g_act, Store store) {
+    constexpr int P8 = ilog8_floor(N);
+    constexpr int RL = N / ipow8(P8);
+    constexpr int LAST8 = RL > 1 ? P8 : P8 - 1;     // radix-8 passes written back to s
+    if constexpr (LAST8 >= 1) stockham_pass<C, N, LD, G, DIR, 8, 1, NT>(s, tw, g_act);
+    if constexpr (LAST8 >= 2) stockham_pass<C, N, LD, G, DIR, 8, 8, NT>(s, tw, g_act);
+    if constexpr (LAST8 >= 3) stockham_pass<C, N, LD, G, DIR, 8, 64, NT>(s, tw, g_act);
+    if constexpr (LAST8 >= 4) stockham_pass<C, N, LD, G, DIR, 8, 512, NT>(s, tw, g_act);
+    if constexpr (RL > 1)
+        stockham_pass_to<C, N, LD, G, DIR, RL, ipow8(P8), NT>(s, tw, g_act, store);
+    else
+        stockham_pass_to<C, N, LD, G, DIR, 8, ipow8(P8 - 1), NT>(s, tw, g_act, store);
 }
 
 // Pencils per block: at least one butterfly task per thread, at most 64 KiB

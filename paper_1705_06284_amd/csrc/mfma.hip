@@ -30,6 +30,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
 #include <type_traits>
 
 #include "fft_core.hpp"
@@ -83,8 +84,8 @@ __device__ __forceinline__ void split8(const float *x, bf16x8 &h, bf16x8 &l) {
 // Per-wave state of the product-Gram.  The work items are (output tile,
 // K part) pairs: with ksplit K parts, tile u / ksplit takes the 16-point
 // steps s = kpart (mod ksplit) of every LDS tile, kpart = u mod ksplit.
-// Wave w owns items w + t WAVES (t < MAXT); WAVES is a multiple of ksplit, so
-// all items of a wave share one K part.  Tiles [0, n_mtile) are pair rows;
+// Wave w owns items w + t WAVES (t < MAXT); with several items per wave,
+// WAVES is a multiple of ksplit, so all items of a wave share one K part.  Tiles [0, n_mtile) are pair rows;
 // tile n_mtile (WANT_T) has rows F_a^2 and columns F_b^2.
 template <int MODE, bool WANT_T, int NT, int MAXT>
 struct PgState {
@@ -119,14 +120,14 @@ struct PgState {
 
     // Split-mode steps of this wave's K part.  HAS_T: one of the wave's tiles
     // is the p = 4 tile (its columns come from the rows, not from Bh/Bl).
-    template <int TK, int FS, int BS, bool HAS_T>
-    __device__ __forceinline__ void contract_split(const float *Ft, const __bf16 *Bh, const __bf16 *Bl, int n_mtile,
-                                                   int col, int half) {
+    template <int TK, int FS, bool HAS_T>
+    __device__ __forceinline__ void contract_split(const float *Ft, const __bf16 *bh_row, const __bf16 *bl_row,
+                                                   int n_mtile, int half) {
 #pragma unroll 1
         for (int s = kpart; s < TK / 16; s += ksplit) {
             const int kp = s * 16 + half * 8;
-            const bf16x8 bh = *reinterpret_cast<const bf16x8 *>(&Bh[col * BS + kp]);
-            const bf16x8 bl = *reinterpret_cast<const bf16x8 *>(&Bl[col * BS + kp]);
+            const bf16x8 bh = *reinterpret_cast<const bf16x8 *>(&bh_row[kp]);
+            const bf16x8 bl = *reinterpret_cast<const bf16x8 *>(&bl_row[kp]);
 #pragma unroll
             for (int t = 0; t < MAXT; ++t) {
                 if (tile_of[t] < 0) continue;
@@ -153,18 +154,18 @@ struct PgState {
     }
 
     // Contract TK points of the LDS field tile Ft (row stride FS); in split
-    // mode Bh/Bl (row stride BS) hold the bf16 halves of the columns F_k.
-    template <int TK, int FS, int BS>
-    __device__ __forceinline__ void contract(const float *Ft, const __bf16 *Bh, const __bf16 *Bl, int n_mtile,
-                                             int col, int half) {
+    // mode bh_row/bl_row are this lane's column F_col in bf16 halves.
+    template <int TK, int FS>
+    __device__ __forceinline__ void contract(const float *Ft, const __bf16 *bh_row, const __bf16 *bl_row,
+                                             int n_mtile, int col, int half) {
         if constexpr (MODE == PG_MODE_SPLIT) {
             bool has_t = false;
 #pragma unroll
             for (int t = 0; t < MAXT; ++t) has_t = has_t || (WANT_T && tile_of[t] == n_mtile);
             if (has_t)
-                contract_split<TK, FS, BS, WANT_T>(Ft, Bh, Bl, n_mtile, col, half);
+                contract_split<TK, FS, WANT_T>(Ft, bh_row, bl_row, n_mtile, half);
             else
-                contract_split<TK, FS, BS, false>(Ft, Bh, Bl, n_mtile, col, half);
+                contract_split<TK, FS, false>(Ft, bh_row, bl_row, n_mtile, half);
         } else {
 #pragma unroll 1
             for (int s = kpart; s < TK / 2; s += ksplit) {
@@ -220,18 +221,6 @@ __device__ __forceinline__ void init_field_tile(float *Ft, int nb) {
     }
 }
 
-// bf16 halves of the column operands F_k (k < 32) of TK points.
-template <int TK, int FS, int BS, int NT>
-__device__ __forceinline__ void split_columns(const float *Ft, __bf16 *Bh, __bf16 *Bl) {
-    for (int e = threadIdx.x; e < 32 * (TK / 2); e += NT) {
-        const int c = e / (TK / 2), q = 2 * (e % (TK / 2));
-        bf16x2 h, l;
-        split2(Ft[c * FS + q], Ft[c * FS + q + 1], h, l);
-        *reinterpret_cast<bf16x2 *>(&Bh[c * BS + q]) = h;
-        *reinterpret_cast<bf16x2 *>(&Bl[c * BS + q]) = l;
-    }
-}
-
 // Fused last inverse pass + product-Gram.  A tile is TK = max(N, TKP) grid
 // points: RT = TK/N consecutive x-rows (n_z, n_y).  For every row and shell
 // pair the compact rows Bc[n_z][n_y][m_x + R] are placed at m_x mod N and
@@ -252,11 +241,13 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MINW))) void
     constexpr int UBYTES = FFT_BYTES > SPLIT_BYTES ? FFT_BYTES : SPLIT_BYTES;
     constexpr int PF = G * N / NT;             // loaded elements per thread and tile
     static_assert((G * N) % NT == 0, "tile loads must divide the block");
+    constexpr int CBS = MODE == PG_MODE_SPLIT ? 2 * BS : 8;
     __shared__ float Ft[PG_FROWS * FS];
     __shared__ __attribute__((aligned(16))) unsigned char ubuf[UBYTES];
     __shared__ float2 tws[N];
+    __shared__ __attribute__((aligned(16))) __bf16 Bconst[CBS];   // bf16 rows of ones and of zeros
     float2 *fb = reinterpret_cast<float2 *>(ubuf);
-    __bf16 *Bh = reinterpret_cast<__bf16 *>(ubuf);
+    __bf16 *Bh = reinterpret_cast<__bf16 *>(ubuf);       // over the FFT buffer once it is read
     __bf16 *Bl = Bh + 32 * BS;
 
     const int tid = threadIdx.x, lane = tid & 63;
@@ -268,9 +259,14 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MINW))) void
     const int64_t t_begin = (int64_t)blockIdx.x * tiles_per_blk;
     const int64_t t_end = t_begin + tiles_per_blk < total ? t_begin + tiles_per_blk : total;
     for (int i = tid; i < N; i += NT) tws[i] = tw[i];
+    for (int i = tid; i < CBS; i += NT) Bconst[i] = (__bf16)(i < CBS / 2 ? 1.0f : 0.0f);
     PgState<MODE, WANT_T, NT, MAXT> st;
     st.init(pairs, n_mtile, nb, wave, col, ksplit);
     init_field_tile<FS, NT>(Ft, nb);
+    // This lane's column operand F_col in bf16 halves: the tile's split field,
+    // or for col >= nb the constant column (ones at col = nb, else zeros).
+    const __bf16 *bh_row = col < nb ? Bh + col * BS : (col == nb ? Bconst : Bconst + CBS / 2);
+    const __bf16 *bl_row = col < nb ? Bl + col * BS : Bconst + CBS / 2;
 
     // Slot sl = q RT + r holds pair q of tile row r; only the first
     // npairs RT slots are loaded, transformed and read.  Element k of this
@@ -309,20 +305,27 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MINW))) void
         }
         if (tile + 1 < t_end) fetch(tile + 1, v);
         __syncthreads();
-        fft_pencils<float2, N, LDP, G, +1, NT>(fb, tws, gact);
-        for (int e = tid; e < gact * N; e += NT) {
-            const int sl = e / N, n = e % N;
+        // The last pass writes the fields straight into the tile: F_2q and
+        // F_2q+1 in FP32 and, in split mode, their bf16 halves (which
+        // overwrite the FFT buffer after the pass has read it).
+        fft_pencils_to<float2, N, LDP, G, +1, NT>(fb, tws, gact, [&](int sl, int n, float2 f) {
             const int q = sl / RT, r = sl % RT;
-            const float2 v = fb[sl * LDP + pad_idx(n)];
-            Ft[(2 * q) * FS + r * N + n] = v.x;
-            if (2 * q + 1 < nb) Ft[(2 * q + 1) * FS + r * N + n] = v.y;
-        }
-        __syncthreads();
-        if constexpr (MODE == PG_MODE_SPLIT) {
-            split_columns<TK, FS, BS, NT>(Ft, Bh, Bl);
-            __syncthreads();
-        }
-        st.template contract<TK, FS, BS>(Ft, Bh, Bl, n_mtile, col, half);
+            const int i = r * N + n;
+            const bool odd = 2 * q + 1 < nb;
+            Ft[(2 * q) * FS + i] = f.x;
+            if (odd) Ft[(2 * q + 1) * FS + i] = f.y;
+            if constexpr (MODE == PG_MODE_SPLIT) {
+                bf16x2 h, l;
+                split2(f.x, f.y, h, l);
+                Bh[(2 * q) * BS + i] = h[0];
+                Bl[(2 * q) * BS + i] = l[0];
+                if (odd) {
+                    Bh[(2 * q + 1) * BS + i] = h[1];
+                    Bl[(2 * q + 1) * BS + i] = l[1];
+                }
+            }
+        });
+        st.template contract<TK, FS>(Ft, bh_row, bl_row, n_mtile, col, half);
         since_flush += TK;
         if (since_flush >= PG_FLUSH_POINTS) {
             since_flush = 0;
@@ -406,6 +409,9 @@ int tail_ksplit(int n, int n_mtile, bool want_t, int shape) {
     const int nt = sh == PG_SHAPE_WIDE ? PG_NT_WIDE : sh == PG_SHAPE_DEEP ? PG_NT_DEEP : PG_NT_TWIN;
     const int maxt = sh == PG_SHAPE_WIDE ? PG_MAXT_WIDE : sh == PG_SHAPE_DEEP ? PG_MAXT_DEEP : PG_MAXT_TWIN;
     const int waves = nt / 64, cap = maxt * waves;
+    // one item per wave: any count of K parts; several: a power of two that
+    // divides the wave count (all items of a wave then share one K part)
+    if (maxt == 1) return std::max(1, std::min(waves / n_out, PG_TK_TAIL / 32));
     int k = 1;
     while (2 * k <= waves && n_out * 2 * k <= cap) k *= 2;
     return k;
