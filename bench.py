@@ -35,11 +35,13 @@ def parse():
     ap.add_argument("--batch", type=int, default=1, help="maps per step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the FP32 comparison paths")
-    ap.add_argument("--cpu-budget", type=float, default=1.2e9,
+    ap.add_argument("--cpu-budget", type=float, default=8e9,
                     help="pair steps of the direct-sum oracle sample")
     ap.add_argument("--no-serving", action="store_true", help="skip the request-stream measurement")
     ap.add_argument("--serving-requests", type=int, default=400)
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shape")
+    ap.add_argument("--all-tunings", action="store_true",
+                    help="also run 3 steps with every tail launch shape the tuner may pick (for counter runs)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="also run a plain device copy of MIB MiB (5 times), the reference kernel "
                          "for scaling the HBM byte counters of a profiler run")
@@ -61,8 +63,8 @@ def tail_source_hash():
 
 def measured_traffic(workload, nblk, shape):
     """HBM bytes per launch of the tail kernel from the committed counter
-    summary, if it was taken on the current kernel source with this launch
-    shape; else None."""
+    summary, if it was taken on the current kernel source and holds this
+    launch shape (block count, shape); else None."""
     path = os.path.join(ROOT, "profiles", "k_tail_%s_traffic.txt" % workload)
     if not os.path.exists(path):
         return None
@@ -72,11 +74,10 @@ def measured_traffic(workload, nblk, shape):
             if ":" in line and not line.startswith("#"):
                 k, v = line.split(":", 1)
                 kv[k.strip()] = v.strip()
+    if kv.get("source_sha256") != tail_source_hash():
+        return None
     try:
-        if (kv.get("source_sha256") != tail_source_hash() or int(kv["nblk"]) != nblk
-                or int(kv["shape"]) != int(shape)):
-            return None
-        return float(kv["traffic_bytes_per_launch"])
+        return float(kv["traffic_bytes_per_launch[%d,%d]" % (nblk, int(shape))])
     except (KeyError, ValueError):
         return None
 
@@ -187,8 +188,8 @@ def main():
     bsz = args.batch
     plan = binding.Plan(n, lo, hi, precision="split_bf16", max_batch=bsz, stream=stream, device=dev)
     ntri, nq, nb = plan.n_tri, plan.n_quad, plan.n_bins
-    tuned = plan.autotune() if not args.no_autotune else (None, None)
     d = torch.from_numpy(np.broadcast_to(field, (bsz,) + field.shape).copy()).to(dev)
+    tuned = plan.autotune(d[:1]) if not args.no_autotune else (None, None)
     P = torch.empty(bsz, nb, dtype=torch.float64, device=dev)
     B = torch.empty(bsz, ntri, dtype=torch.float64, device=dev)
     T = torch.empty(bsz, nq, dtype=torch.float64, device=dev)
@@ -266,6 +267,22 @@ def main():
 
     if not args.no_serving:
         out["serving"] = serving_run(args.serving_requests)
+
+    if args.all_tunings:
+        ran = []
+        for shape in (binding.TAIL_DEEP, binding.TAIL_WIDE, binding.TAIL_TWIN):
+            for nblk in (256, 512, 1024, 2048, 4096, 8192, 16384):
+                try:
+                    plan.set_tuning(nblk, shape)
+                except binding.BispecError:
+                    continue
+                for _ in range(3):
+                    step()
+                ran.append([nblk, shape])
+        torch.cuda.synchronize()
+        if tuned[0]:
+            plan.set_tuning(*tuned)
+        out["all_tunings"] = ran
 
     if args.copy_calibration > 0:
         cnt = args.copy_calibration * (1 << 18)

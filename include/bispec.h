@@ -171,16 +171,18 @@ enum {
 };
 
 /* Autotuner: times the fused last-pass + contraction kernel on the attached
- * workspace (zeroed compact rows) for every shape that fits the plan's
+ * workspace, on the compact rows of the map delta (device [N^3] FP32, or
+ * NULL: zero rows; the kernel's speed can depend on the data), for every shape that fits the plan's
  * output tiles and for the default block count per map (one per CU, and
  * enough that no block contracts more than 64 units of 512 points) and two
- * and four times it, within the partial buffer the footprint reserves; keeps
- * the fastest (a candidate after the first must win by 1.5 %: wide, twin,
- * deep, fewer blocks first) and reports it.  Synchronises the stream.
+ * and four times it, within the partial buffer the footprint reserves, each
+ * timed as the median of five launches after a warm-up; keeps the fastest (a
+ * candidate after the first must win by 3 %: wide, twin, deep, fewer blocks
+ * first) and reports it.  Synchronises the stream.
  * bispec_set_tuning restores a stored choice; BISPEC_E_INVALID if nblk is
  * below the 64-unit limit or above the buffer, or the shape is unknown.  A
  * shape that does not fit the tiles of a call runs as wide, else deep. */
-bispec_status bispec_autotune(bispec_plan_t plan, int32_t *nblk_out, int32_t *shape_out);
+bispec_status bispec_autotune(bispec_plan_t plan, const float *delta, int32_t *nblk_out, int32_t *shape_out);
 bispec_status bispec_set_tuning(bispec_plan_t plan, int32_t nblk, int32_t shape);
 
 /* Condition number of each planned triplet's real-space sum,

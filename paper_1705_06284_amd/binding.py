@@ -61,7 +61,7 @@ _SIGS = {
     "polyspec_estimate": [_vp, _vp, _i32, _vp, _vp, _vp],
     "bispec_timing_enable": [_vp, _i32],
     "bispec_graph_enable": [_vp, _i32],
-    "bispec_autotune": [_vp, _ip, _ip],
+    "bispec_autotune": [_vp, _vp, _ip, _ip],
     "bispec_set_tuning": [_vp, _i32, _i32],
     "bispec_plan_condition": [_vp, _dp],
     "bispec_timing_read": [_vp, _dp, _ip],
@@ -228,11 +228,17 @@ class Plan:
             self.workspace = self._torch.empty(sz.value, dtype=self._torch.uint8, device=self.device)
             check(bispec_set_workspace(self.handle, _ptr(self.workspace), sz.value), "bispec_set_workspace")
 
-    def autotune(self):
-        """Time the contraction kernel's launch shapes; returns (blocks, shape),
-        shape one of TAIL_DEEP, TAIL_WIDE, TAIL_TWIN."""
+    def autotune(self, delta=None):
+        """Time the contraction kernel's launch shapes on the map delta (its
+        compact rows; None: zeros); returns (blocks, shape), shape one of
+        TAIL_DEEP, TAIL_WIDE, TAIL_TWIN."""
         nb, sh = ctypes.c_int32(), ctypes.c_int32()
-        check(bispec_autotune(self.handle, ctypes.byref(nb), ctypes.byref(sh)), "bispec_autotune")
+        ptr = None
+        if delta is not None:
+            d = self._input(delta)
+            ptr = _ptr(d[0])
+            self._torch.cuda.synchronize(self.device)     # the map is ready before the plan's stream reads it
+        check(bispec_autotune(self.handle, ptr, ctypes.byref(nb), ctypes.byref(sh)), "bispec_autotune")
         return nb.value, sh.value
 
     def set_tuning(self, nblk, shape):

@@ -937,7 +937,7 @@ bispec_status polyspec_estimate(bispec_plan_t plan, const float *delta, int32_t 
     }
 }
 
-bispec_status bispec_autotune(bispec_plan_t plan, int32_t *nblk_out, int32_t *shape_out) {
+bispec_status bispec_autotune(bispec_plan_t plan, const float *delta, int32_t *nblk_out, int32_t *shape_out) {
     if (!plan) return BISPEC_E_INVALID;
     bispec_plan_s &p = *plan;
     if (!p.ws) return BISPEC_E_NO_WORKSPACE;
@@ -946,8 +946,15 @@ bispec_status bispec_autotune(bispec_plan_t plan, int32_t *nblk_out, int32_t *sh
             const Layout L = make_layout(p, p.max_batch);
             char *ws = (char *)p.ws;
             const int n = p.n;
-            // well-defined operands: zero compact rows
+            // operands: the compact rows of the given map, else zeros
             CK(hipMemsetAsync(ws + L.bc, 0, sizeof(float2) * (size_t)n * n * p.wsum * p.max_batch, p.stream));
+            if (delta) {
+                double *mean = (double *)(ws + L.mean);
+                CK(launch_mean(delta, n, 1, (double *)(ws + L.mean_partial), kMeanParts, mean, p.stream));
+                CK(launch_forward(delta, mean, n, 1, (const float2 *)(ws + L.tw), (float2 *)(ws + L.spec),
+                                  p.stream));
+                CK(run_inverse_zy(p, 1));
+            }
             TailPairs tp{};
             tp.npairs = (int)p.pairs.size();
             for (int q = 0; q < tp.npairs; ++q) {
@@ -962,29 +969,35 @@ bispec_status bispec_autotune(bispec_plan_t plan, int32_t *nblk_out, int32_t *sh
             CK(hipEventCreate(&e1));
             // candidates: the wide, twin and deep shapes (those that fit the
             // tile count) at the default block count and two and four times
-            // it; a later candidate must win by 1.5 % to be kept (the first
-            // ones write and reduce fewer partial tiles)
+            // it, each timed as the median of five launches after one
+            // warm-up; a later candidate must win by 3 % to be kept (the
+            // first ones write and reduce fewer partial tiles)
             float best = 1e30f;
             int best_nblk = p.nblk_pg;
             int best_shape = p.tail_shape;
             const int base = p.nblk_pg;
+            // bring the clocks up before the first candidate is timed
+            for (int rep = 0; rep < 8; ++rep)
+                CK(launch_tail(mode, t, (const float2 *)(ws + L.bc), tp, n, p.nb, 1, (const uchar2 *)(ws + L.pg_pairs),
+                               p.n_mtile, (const float2 *)(ws + L.tw), base, (double *)(ws + L.pg_partial), p.stream,
+                               PG_SHAPE_DEEP));
             for (int sh : {PG_SHAPE_WIDE, PG_SHAPE_TWIN, PG_SHAPE_DEEP}) {
                 if (!tail_shape_fits(n, p.n_mtile, t, sh)) continue;
                 for (int nb : {base, 2 * base, 4 * base}) {
                     if (nb > p.nblk_pg_max) continue;
-                    float tot = 0.0f;
-                    for (int rep = 0; rep < 3; ++rep) {
+                    float ms[6];
+                    for (int rep = 0; rep < 6; ++rep) {
                         CK(hipEventRecord(e0, p.stream));
                         CK(launch_tail(mode, t, (const float2 *)(ws + L.bc), tp, n, p.nb, 1,
                                        (const uchar2 *)(ws + L.pg_pairs), p.n_mtile, (const float2 *)(ws + L.tw),
                                        nb, (double *)(ws + L.pg_partial), p.stream, sh));
                         CK(hipEventRecord(e1, p.stream));
                         CK(hipEventSynchronize(e1));
-                        float ms = 0.0f;
-                        CK(hipEventElapsedTime(&ms, e0, e1));
-                        if (rep) tot += ms;        // first run warms up
+                        CK(hipEventElapsedTime(&ms[rep], e0, e1));
                     }
-                    if (tot < best * 0.985f || best >= 1e30f) {
+                    std::sort(ms + 1, ms + 6);     // ms[0] warms up
+                    const float tot = ms[3];
+                    if (tot < best * 0.97f || best >= 1e30f) {
                         best = tot;
                         best_nblk = nb;
                         best_shape = sh;
