@@ -55,6 +55,7 @@ constexpr int PG_TK_TAIL = 512;           // grid points per LDS tile of the fus
 constexpr int PG_NT_WIDE = 1024, PG_MAXT_WIDE = 1;
 constexpr int PG_NT_DEEP = 512, PG_MAXT_DEEP = 3;
 constexpr int PG_NT_TWIN = 512, PG_MAXT_TWIN = 1, PG_TK_TWIN = 256;
+constexpr bool PG_TWIN_PREFETCH = false;   // the co-resident block hides the loads
 constexpr int PG_FLUSH_POINTS = 4096;     // FP32-mode accumulation span before an FP64 flush
 constexpr int PG_ZERO = PG_ROW_ZERO;      // field row of zeros (padding rows)
 constexpr int PG_ONE = PG_ROW_ONE;        // field row of ones (F_b * 1 rows)
@@ -226,7 +227,7 @@ __device__ __forceinline__ void init_field_tile(float *Ft, int nb) {
 // pair the compact rows Bc[n_z][n_y][m_x + R] are placed at m_x mod N and
 // transformed along x in LDS; the real and imaginary parts are the bin
 // fields F_2q and F_2q+1 at the tile's points, contracted at once.
-template <int MODE, bool WANT_T, int N, int NT, int MAXT, int TKP, int MINW>
+template <int MODE, bool WANT_T, int N, int NT, int MAXT, int TKP, int MINW, bool PREFETCH>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MINW))) void k_tail(const float2 *__restrict__ bc, TailPairs tp, int nb,
                                              const uchar2 *__restrict__ pairs, int n_mtile,
                                              const float2 *__restrict__ tw, int tiles_per_blk, int ksplit,
@@ -291,19 +292,21 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MINW))) void
             }
         }
     };
-    // The loads of tile t + 1 are issued right after tile t is stored and
-    // stay in flight through its transform and contraction.
+    // PREFETCH: the loads of tile t + 1 are issued right after tile t is
+    // stored and stay in flight through its transform and contraction (else
+    // a co-resident block hides their latency).
     int since_flush = 0;
     float2 v[PF];
-    if (t_begin < t_end) fetch(t_begin, v);
+    if (PREFETCH && t_begin < t_end) fetch(t_begin, v);
     for (int64_t tile = t_begin; tile < t_end; ++tile) {
+        if (!PREFETCH) fetch(tile, v);
         __syncthreads();
 #pragma unroll
         for (int k = 0; k < PF; ++k) {
             const int e = tid + k * NT;
             if (e / N < gact) fb[(e / N) * LDP + pad_idx(e % N)] = v[k];
         }
-        if (tile + 1 < t_end) fetch(tile + 1, v);
+        if (PREFETCH && tile + 1 < t_end) fetch(tile + 1, v);
         __syncthreads();
         // The last pass writes the fields straight into the tile: F_2q and
         // F_2q+1 in FP32 and, in split mode, their bf16 halves (which
@@ -430,15 +433,15 @@ hipError_t launch_tail_m(const float2 *bc, const TailPairs &tp, int n, int nb, i
         constexpr int TKW = NN >= PG_TK_TAIL ? NN : PG_TK_TAIL;
         const int per_w = (int)((int64_t)per * PG_TK_TAIL / TKW);
         if (sh == PG_SHAPE_WIDE)
-            hipLaunchKernelGGL((k_tail<MODE, WANT_T, NN, PG_NT_WIDE, PG_MAXT_WIDE, PG_TK_TAIL, 4>), dim3(nblk, batch),
+            hipLaunchKernelGGL((k_tail<MODE, WANT_T, NN, PG_NT_WIDE, PG_MAXT_WIDE, PG_TK_TAIL, 4, true>), dim3(nblk, batch),
                                dim3(PG_NT_WIDE), 0, st, bc, tp, nb, pairs, n_mtile, tw, per_w, ks, partial);
         else if (sh == PG_SHAPE_DEEP)
-            hipLaunchKernelGGL((k_tail<MODE, WANT_T, NN, PG_NT_DEEP, PG_MAXT_DEEP, PG_TK_TAIL, 2>), dim3(nblk, batch),
+            hipLaunchKernelGGL((k_tail<MODE, WANT_T, NN, PG_NT_DEEP, PG_MAXT_DEEP, PG_TK_TAIL, 2, true>), dim3(nblk, batch),
                                dim3(PG_NT_DEEP), 0, st, bc, tp, nb, pairs, n_mtile, tw, per_w, ks, partial);
         else if constexpr (NN <= PG_TK_TWIN) {
             constexpr int TKT = NN >= PG_TK_TWIN ? NN : PG_TK_TWIN;
             const int per_t = (int)((int64_t)per * PG_TK_TAIL / TKT);
-            hipLaunchKernelGGL((k_tail<MODE, WANT_T, NN, PG_NT_TWIN, PG_MAXT_TWIN, PG_TK_TWIN, 4>), dim3(nblk, batch),
+            hipLaunchKernelGGL((k_tail<MODE, WANT_T, NN, PG_NT_TWIN, PG_MAXT_TWIN, PG_TK_TWIN, 4, PG_TWIN_PREFETCH>), dim3(nblk, batch),
                                dim3(PG_NT_TWIN), 0, st, bc, tp, nb, pairs, n_mtile, tw, per_t, ks, partial);
         } else {
             return hipErrorInvalidValue;
