@@ -82,48 +82,55 @@ __device__ __forceinline__ void split8(const float *x, bf16x8 &h, bf16x8 &l) {
     }
 }
 
-// Per-wave state of the product-Gram.  The work items are (output tile,
-// K part) pairs: with ksplit K parts, tile u / ksplit takes the 16-point
-// steps s = kpart (mod ksplit) of every LDS tile, kpart = u mod ksplit.
-// Wave w owns items w + t WAVES (t < MAXT); with several items per wave,
-// WAVES is a multiple of ksplit, so all items of a wave share one K part.  Tiles [0, n_mtile) are pair rows;
-// tile n_mtile (WANT_T) has rows F_a^2 and columns F_b^2.
+// Per-wave state of the product-Gram.  The work items are (pair tile, K
+// part) pairs: with ksplit K parts, tile u / ksplit takes the 16-point steps
+// s = kpart (mod ksplit) of every LDS tile, kpart = u mod ksplit.  Wave w owns
+// items w + t WAVES (t < MAXT); with several items per wave, WAVES is a
+// multiple of ksplit, so all items of a wave share one K part.
+// The p = 4 tile (WANT_T; rows F_a^2, columns F_b^2) rides on pair tile 0,
+// whose lane r < nb holds row (r, r): its A operand at lane r is F_r^2 at the
+// lane's points, which is also what lane r must supply as the B operand of
+// the p = 4 tile.  So the items of tile 0 add three more MFMAs with their own
+// A halves as both operands (entries of rows or columns >= nb are unused).
 template <int MODE, bool WANT_T, int NT, int MAXT>
 struct PgState {
     static constexpr int WAVES = NT / 64;
-    static constexpr int DT = MODE == PG_MODE_F32 ? MAXT : 1;    // FP64 flush registers (FP32 mode)
+    static constexpr int DT = MODE == PG_MODE_F32 ? MAXT + 1 : 1;    // FP64 flush registers (FP32 mode)
     int tile_of[MAXT];
     int kpart, ksplit;
+    bool t_here;                          // WANT_T and one of this wave's items is tile 0
     uchar2 rp[MAXT];
     f32x16 acc[MAXT];
+    f32x16 acct;                          // the p = 4 tile (when t_here)
     double dacc[DT][16];
 
     __device__ __forceinline__ void init(const uchar2 *__restrict__ pairs, int n_mtile, int nb, int wave, int col,
                                          int ks) {
-        const int n_out = n_mtile + (WANT_T ? 1 : 0);
         ksplit = ks;
         kpart = wave % ks;
+        t_here = false;
 #pragma unroll
         for (int t = 0; t < MAXT; ++t) {
             const int u = wave + t * WAVES;
             const int tile = u / ks;
-            tile_of[t] = tile < n_out ? tile : -1;
-            const unsigned char sq = (unsigned char)(col < nb ? col : PG_ZERO);
-            rp[t] = tile < n_mtile ? pairs[tile * 32 + col] : uchar2{sq, sq};
+            tile_of[t] = tile < n_mtile ? tile : -1;
+            t_here = t_here || (WANT_T && tile == 0);
+            rp[t] = tile < n_mtile ? pairs[tile * 32 + col] : uchar2{PG_ZERO, PG_ZERO};
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc[t][r] = 0.0f;
         }
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acct[r] = 0.0f;
 #pragma unroll
         for (int t = 0; t < DT; ++t)
 #pragma unroll
             for (int r = 0; r < 16; ++r) dacc[t][r] = 0.0;
     }
 
-    // Split-mode steps of this wave's K part.  HAS_T: one of the wave's tiles
-    // is the p = 4 tile (its columns come from the rows, not from Bh/Bl).
+    // Split-mode steps of this wave's K part.  HAS_T: t_here.
     template <int TK, int FS, bool HAS_T>
     __device__ __forceinline__ void contract_split(const float *Ft, const __bf16 *bh_row, const __bf16 *bl_row,
-                                                   int n_mtile, int half) {
+                                                   int half) {
 #pragma unroll 1
         for (int s = kpart; s < TK / 16; s += ksplit) {
             const int kp = s * 16 + half * 8;
@@ -140,15 +147,13 @@ struct PgState {
                               i1.x * j1.x, i1.y * j1.y, i1.z * j1.z, i1.w * j1.w};
                 bf16x8 ah, al;
                 split8(a, ah, al);
-                if (HAS_T && tile_of[t] == n_mtile) {
-                    // rows and columns are both F_col^2 at this lane's points
-                    acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, ah, acc[t], 0, 0, 0);
-                    acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, al, acc[t], 0, 0, 0);
-                    acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, ah, acc[t], 0, 0, 0);
-                } else {
-                    acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, acc[t], 0, 0, 0);
-                    acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, acc[t], 0, 0, 0);
-                    acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, acc[t], 0, 0, 0);
+                acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, acc[t], 0, 0, 0);
+                acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, acc[t], 0, 0, 0);
+                acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, acc[t], 0, 0, 0);
+                if (HAS_T && tile_of[t] == 0) {
+                    acct = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, ah, acct, 0, 0, 0);
+                    acct = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, al, acct, 0, 0, 0);
+                    acct = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, ah, acct, 0, 0, 0);
                 }
             }
         }
@@ -157,16 +162,13 @@ struct PgState {
     // Contract TK points of the LDS field tile Ft (row stride FS); in split
     // mode bh_row/bl_row are this lane's column F_col in bf16 halves.
     template <int TK, int FS>
-    __device__ __forceinline__ void contract(const float *Ft, const __bf16 *bh_row, const __bf16 *bl_row,
-                                             int n_mtile, int col, int half) {
+    __device__ __forceinline__ void contract(const float *Ft, const __bf16 *bh_row, const __bf16 *bl_row, int col,
+                                             int half) {
         if constexpr (MODE == PG_MODE_SPLIT) {
-            bool has_t = false;
-#pragma unroll
-            for (int t = 0; t < MAXT; ++t) has_t = has_t || (WANT_T && tile_of[t] == n_mtile);
-            if (has_t)
-                contract_split<TK, FS, WANT_T>(Ft, bh_row, bl_row, n_mtile, half);
+            if (t_here)
+                contract_split<TK, FS, WANT_T>(Ft, bh_row, bl_row, half);
             else
-                contract_split<TK, FS, false>(Ft, bh_row, bl_row, n_mtile, half);
+                contract_split<TK, FS, false>(Ft, bh_row, bl_row, half);
         } else {
 #pragma unroll 1
             for (int s = kpart; s < TK / 2; s += ksplit) {
@@ -176,8 +178,8 @@ struct PgState {
                 for (int t = 0; t < MAXT; ++t) {
                     if (tile_of[t] < 0) continue;
                     const float a = Ft[rp[t].x * FS + k] * Ft[rp[t].y * FS + k];
-                    const float b = (WANT_T && tile_of[t] == n_mtile) ? bk * bk : bk;
-                    acc[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc[t], 0, 0, 0);
+                    acc[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, bk, acc[t], 0, 0, 0);
+                    if (WANT_T && tile_of[t] == 0) acct = __builtin_amdgcn_mfma_f32_32x32x2f32(a, a, acct, 0, 0, 0);
                 }
             }
         }
@@ -193,19 +195,38 @@ struct PgState {
                     acc[t][r] = 0.0f;
                 }
             }
+            if (WANT_T) {
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    dacc[DT - 1][r] += (double)acct[r];
+                    acct[r] = 0.0f;
+                }
+            }
         }
     }
 
-    // Partials of block blk: [ksplit][n_out][32][32].
-    __device__ __forceinline__ void write(double *__restrict__ partial, int64_t blk, int n_out, int col, int half) {
+    // Partials of block blk: [ksplit][n_mtile + WANT_T][32][32]; the p = 4
+    // tile is tile n_mtile.
+    __device__ __forceinline__ void write(double *__restrict__ partial, int64_t blk, int n_mtile, int col,
+                                          int half) {
+        const int n_out = n_mtile + (WANT_T ? 1 : 0);
+        double *base = partial + (blk * ksplit + kpart) * n_out * 1024;
 #pragma unroll
         for (int t = 0; t < MAXT; ++t) {
             if (tile_of[t] < 0) continue;
-            double *out = partial + ((blk * ksplit + kpart) * n_out + tile_of[t]) * 1024;
+            double *out = base + tile_of[t] * 1024;
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
                 const int row = 8 * (r >> 2) + 4 * half + (r & 3);
                 out[row * 32 + col] = (MODE == PG_MODE_F32 ? dacc[t < DT ? t : 0][r] : 0.0) + (double)acc[t][r];
+            }
+        }
+        if (WANT_T && t_here) {
+            double *out = base + n_mtile * 1024;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int row = 8 * (r >> 2) + 4 * half + (r & 3);
+                out[row * 32 + col] = (MODE == PG_MODE_F32 ? dacc[DT - 1][r] : 0.0) + (double)acct[r];
             }
         }
     }
@@ -328,14 +349,14 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MINW))) void
                 }
             }
         });
-        st.template contract<TK, FS>(Ft, bh_row, bl_row, n_mtile, col, half);
+        st.template contract<TK, FS>(Ft, bh_row, bl_row, col, half);
         since_flush += TK;
         if (since_flush >= PG_FLUSH_POINTS) {
             since_flush = 0;
             st.flush();
         }
     }
-    st.write(partial, (int64_t)map * gridDim.x + blockIdx.x, n_mtile + (WANT_T ? 1 : 0), col, half);
+    st.write(partial, (int64_t)map * gridDim.x + blockIdx.x, n_mtile, col, half);
 }
 
 // Fixed-order compensated FP64 sum over blocks of every dense tile entry,
@@ -392,7 +413,8 @@ size_t pgram_partial_doubles(int n_mtile, bool want_t) { return (size_t)(n_mtile
 int64_t tail_units(int n) { return (int64_t)n * n * n / PG_TK_TAIL; }
 
 bool tail_shape_fits(int n, int n_mtile, bool want_t, int shape) {
-    const int n_out = n_mtile + (want_t ? 1 : 0);
+    (void)want_t;                      // the p = 4 tile rides on pair tile 0
+    const int n_out = n_mtile;
     switch (shape) {
         case PG_SHAPE_WIDE: return n_out <= PG_MAXT_WIDE * (PG_NT_WIDE / 64);
         case PG_SHAPE_DEEP: return n_out <= PG_MAXT_DEEP * (PG_NT_DEEP / 64);
@@ -407,7 +429,7 @@ int tail_shape(int n, int n_mtile, bool want_t, int shape) {
 }
 
 int tail_ksplit(int n, int n_mtile, bool want_t, int shape) {
-    const int n_out = n_mtile + (want_t ? 1 : 0);
+    const int n_out = n_mtile;
     const int sh = tail_shape(n, n_mtile, want_t, shape);
     const int nt = sh == PG_SHAPE_WIDE ? PG_NT_WIDE : sh == PG_SHAPE_DEEP ? PG_NT_DEEP : PG_NT_TWIN;
     const int maxt = sh == PG_SHAPE_WIDE ? PG_MAXT_WIDE : sh == PG_SHAPE_DEEP ? PG_MAXT_DEEP : PG_MAXT_TWIN;
