@@ -19,7 +19,8 @@ module serves such a stream on one GPU:
 
 Per-map arithmetic does not depend on the other maps of a batch (every
 kernel indexes maps by grid.y and reduces each map in a fixed order), so a
-result is bitwise the same alone and in any mix.
+result is bitwise the same alone and in any mix (with the same tail launch
+shape; all slots of a size class share the one their first slot tuned).
 
 The scheduling logic talks to a backend with five methods (``footprint``,
 ``make_slot``, ``launch``, ``ready``, ``collect``); ``GpuBackend`` drives the
@@ -76,6 +77,7 @@ class GpuBackend:
         self.device = torch.device(device)
         self.precision = precision
         self.n_bins = n_bins
+        self.tuning = {}          # size class -> (tail blocks, tail shape)
 
     def _plan(self, n, max_batch, stream):
         lo, hi = standard_bins(n, self.n_bins)
@@ -94,6 +96,12 @@ class GpuBackend:
         torch = self.torch
         stream = torch.cuda.Stream(self.device)
         plan = self._plan(n, max_batch, stream)
+        # one tail launch shape per size class, so that a map's result does
+        # not depend on the slot that serves it
+        if n not in self.tuning:
+            self.tuning[n] = plan.autotune()
+        else:
+            plan.set_tuning(*self.tuning[n])
         plan.graph(True)          # the slot's buffers are fixed: replay captured launches
         slot = {
             "n": n, "plan": plan, "stream": stream, "max_batch": max_batch,

@@ -229,7 +229,6 @@ def test_c3_bubbles_256_sampled(binding, prec):
     d = synth.workload_field(wl)
     _say("c3 256^3 sampled %s" % prec)
     plan = binding.Plan(n, lo, hi, precision=prec)
-    P, B, T = plan.polyspec(d)
     trip = plan.triplets
     assert len(trip) == 1522 and plan.n_quad == 300
     sel = _cheap_triplets(n, lo, hi, trip, 2e9)
@@ -237,16 +236,22 @@ def test_c3_bubbles_256_sampled(binding, prec):
     Dk = oracle.dft3(oracle.prepare(d))
     ref = oracle.bispectrum(d, lo, hi, sel, delta_k=Dk)
     assert np.array_equal(plan.counts[idx].astype(np.int64), ref.count)
-    e = _err(B.cpu().numpy()[0][idx], ref)
-    _say("  %d sampled triplets, max err %.2e" % (len(sel), e.max()))
-    assert np.max(e) <= TOL[prec]
     refp, _ = oracle.power_spectrum(d, lo, hi, delta_k=Dk)
-    assert np.max(np.abs(P.cpu().numpy()[0] - refp) / refp) <= TOL[prec]
     quads = plan.quads
     qsel = [q for q in range(len(quads)) if quads[q][2] <= 1]
     reft = oracle.trispectrum(d, lo, hi, quads[qsel], delta_k=Dk)
     assert np.array_equal(plan.quad_counts[qsel].astype(np.int64), reft.count)
-    assert np.max(_err(T.cpu().numpy()[0][qsel], reft)) <= TOL[prec]
+    # every tail launch shape the tuner can pick, at the default block count
+    # (512: no block contracts more than 64 units of 512 points) and the largest
+    for nblk, shape in ((512, binding.TAIL_WIDE), (512, binding.TAIL_TWIN), (2048, binding.TAIL_TWIN),
+                        (512, binding.TAIL_DEEP)):
+        plan.set_tuning(nblk, shape)
+        P, B, T = plan.polyspec(d)
+        e = _err(B.cpu().numpy()[0][idx], ref)
+        _say("  shape %d, %d blocks: %d sampled triplets, max err %.2e" % (shape, nblk, len(sel), e.max()))
+        assert np.max(e) <= TOL[prec]
+        assert np.max(np.abs(P.cpu().numpy()[0] - refp) / refp) <= TOL[prec]
+        assert np.max(_err(T.cpu().numpy()[0][qsel], reft)) <= TOL[prec]
 
 
 def test_empty_shell_is_rejected(binding):

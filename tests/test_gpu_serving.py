@@ -1,5 +1,6 @@
 """The request loop on the GPU: every result of a mixed, batched stream is
-bitwise the result of the same map estimated alone, and matches the oracle."""
+bitwise the result of the same map estimated alone with the same tail launch
+shape, and matches the oracle."""
 import numpy as np
 import pytest
 
@@ -31,6 +32,7 @@ def test_mixed_stream_equals_alone(backend):
     for n in (32, 64):
         lo, hi = serving.standard_bins(n)
         alone[n] = binding.Plan(n, lo, hi, triplets=serving.standard_triplets(), quads=np.zeros((1, 4), np.int32))
+        alone[n].set_tuning(*backend.tuning[n])          # the slots' tail launch shape
     for r in done:
         B, P = alone[r.n].estimate(fields[r.rid])
         assert np.array_equal(B.cpu().numpy()[0], r.result["B"], equal_nan=True)
