@@ -81,7 +81,7 @@ Layout make_layout(const bispec_plan_s &p, int batch) {
     L.ytab = off;         off = align_up(off + sizeof(int2) * p.ytab.size());
     L.mean_partial = off; off = align_up(off + sizeof(double) * kMeanParts * batch);
     L.mean = off;         off = align_up(off + sizeof(double) * batch);
-    L.spec = off;         off = align_up(off + sizeof(float2) * vol * batch);
+    L.spec = off;         off = align_up(off + sizeof(float2) * spec_elems(p.n) * batch);
     L.abox = off;         off = align_up(off + sizeof(float2) * (size_t)p.n * p.absum * batch);
     L.bc = off;           off = align_up(off + sizeof(float2) * (size_t)p.n * p.n * p.wsum * batch);
     L.partial = off;      off = align_up(off + sizeof(double) * (size_t)p.nblk * p.terms.size() * batch);
@@ -644,8 +644,7 @@ hipError_t run_inverse_zy(bispec_plan_s &p, int batch) {
     const Layout L = make_layout(p, p.max_batch);
     char *ws = (char *)p.ws;
     const int n = p.n;
-    const int64_t vol = (int64_t)n * n * n;
-    return launch_inverse_zy((const float2 *)(ws + L.spec), vol, n, batch, (const float2 *)(ws + L.tw),
+    return launch_inverse_zy((const float2 *)(ws + L.spec), spec_elems(n), n, batch, (const float2 *)(ws + L.tw),
                              (const PairDev *)(ws + L.pd), (const int2 *)(ws + L.ztab), (int)p.ztab.size(),
                              (const int2 *)(ws + L.ytab), (int)p.ytab.size(), (const int *)(ws + L.cols),
                              (float2 *)(ws + L.abox), (float2 *)(ws + L.bc), p.stream);

@@ -116,6 +116,11 @@ template <int RADIX, int DIR, typename C> __device__ __forceinline__ void dft_r(
 template <int N> constexpr int pencil_ld() { return N + N / 8 + 1; }
 __device__ __forceinline__ int pad_idx(int i) { return i + (i >> 3); }
 
+// Row length of the half spectrum m_x = 0..N/2 (the other half follows from
+// Hermitian symmetry), rounded up to 16 entries so that rows stay 128-byte
+// aligned and every pencil group of the strided passes stays whole.
+template <int N> constexpr int spec_ld() { return (N / 2 + 1 + 15) / 16 * 16; }
+
 constexpr int ilog8_floor(int n) { return n >= 8 ? 1 + ilog8_floor(n / 8) : 0; }
 constexpr int ipow8(int p) { return p == 0 ? 1 : 8 * ipow8(p - 1); }
 

@@ -2,13 +2,15 @@
 //
 // Pipeline for one map (Watkinson et al. 2017, Section 2):
 //   k_sum_f64 / k_mean_final   FP64 mean of the FP32 input
-//   k_fwd_x, k_fft_strided     forward 3D DFT, Eq. (DeltaFFTtoDelta), FP32
-//   k_inv_z_gather             shell mask of two bins fused into the first
+//   k_fwd_x, k_fft_strided     forward 3D DFT, Eq. (DeltaFFTtoDelta), FP32,
+//                              to the half spectrum m_x >= 0
+//   k_inv_z_prune              shell masks of two bins fused into the first
 //                              inverse pass (Eq. delta_nr): the two real bin
 //                              fields come out as the real and imaginary
 //                              parts of one complex inverse transform
-//   k_fft_strided, k_inv_x_split  remaining inverse passes; split re/im into
-//                              the two bin fields F_b
+//   k_inv_y_prune, k_inv_x_compact  remaining inverse passes (the x pass is
+//                              fused into the contraction on the estimate
+//                              path, mfma.hip)
 //   k_contract_terms           sum_n of products of 2, 3 or 4 bin fields
 //                              (numerators and denominators of Eqs. Jeong_PS,
 //                              Jeong_BI, Jeong_gen), per-block FP64 partials
@@ -73,49 +75,70 @@ __device__ __forceinline__ void load_twiddles(C *tw_s, const C *tw) {
     for (int i = threadIdx.x; i < N; i += 256) tw_s[i] = tw[i];
 }
 
-// Forward pass along x: real input minus the FP64 mean, complex output.
+// Forward pass along x: real input minus the FP64 mean, half-spectrum output
+// [z][y][m_x = 0..N/2] with row length spec_ld<N>() (pad entries zero).  Two
+// real rows a, b share one complex transform Z of a + i b; then
+// A(k) = (Z(k) + conj Z(N-k)) / 2 and B(k) = (Z(k) - conj Z(N-k)) / (2i).
 template <int N>
 __global__ __launch_bounds__(256) void k_fwd_x(const float *__restrict__ delta, const double *__restrict__ mean,
                                                const float2 *__restrict__ tw, float2 *__restrict__ spec) {
-    constexpr int G = pencils_per_block<float, N>();
-    __shared__ float2 s[G * pencil_ld<N>()];
+    constexpr int G0 = pencils_per_block<float, N>();
+    constexpr int G = G0 < N * N / 2 ? G0 : N * N / 2;      // complex pencils = 2G real rows
+    constexpr int HP = spec_ld<N>();
+    constexpr int LD = pencil_ld<N>();
+    constexpr int PER = 2 * G * N / 256;
+    static_assert((2 * G * N) % 256 == 0, "row pairs must divide the block");
+    __shared__ float2 s[G * LD];
     __shared__ float2 tws[N];
     load_twiddles<float2, N>(tws, tw);
     const int64_t vol = (int64_t)N * N * N;
     const int map = blockIdx.y;
     const float *src = delta + map * vol;
-    float2 *dst = spec + map * vol;
+    float2 *dst = spec + map * (int64_t)N * N * HP;
     const double mu = mean[map];
-    const int64_t row0 = (int64_t)blockIdx.x * G;
-    constexpr int LD = pencil_ld<N>();
-    constexpr int PER = G * N / 256;
+    const int64_t row0 = (int64_t)blockIdx.x * 2 * G;
     float x[PER];
 #pragma unroll
     for (int k = 0; k < PER; ++k) x[k] = src[row0 * N + threadIdx.x + k * 256];   // all loads in flight
+    float *sf = reinterpret_cast<float *>(s);
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
         const int e = threadIdx.x + k * 256;
-        s[(e / N) * LD + pad_idx(e % N)] = float2{(float)((double)x[k] - mu), 0.0f};
+        const int r = e / N, i = e % N;          // real row r of the block: pencil r / 2, part r % 2
+        sf[2 * ((r >> 1) * LD + pad_idx(i)) + (r & 1)] = (float)((double)x[k] - mu);
     }
     __syncthreads();
     fft_pencils<float2, N, LD, G, -1>(s, tws);
-    for (int e = threadIdx.x; e < G * N; e += 256) dst[row0 * N + e] = s[(e / N) * LD + pad_idx(e % N)];
+    for (int e = threadIdx.x; e < G * HP; e += 256) {
+        const int p = e / HP, k = e % HP;
+        float2 a = float2{0.0f, 0.0f}, b = float2{0.0f, 0.0f};
+        if (k <= N / 2) {
+            const float2 z = s[p * LD + pad_idx(k)];
+            const float2 zm = s[p * LD + pad_idx((N - k) & (N - 1))];
+            a = float2{0.5f * (z.x + zm.x), 0.5f * (z.y - zm.y)};
+            b = float2{0.5f * (z.y + zm.y), 0.5f * (zm.x - z.x)};
+        }
+        dst[(row0 + 2 * p) * HP + k] = a;
+        dst[(row0 + 2 * p + 1) * HP + k] = b;
+    }
 }
 
-// In-place transform along y (AXIS = 1) or z (AXIS = 2) of a complex volume.
-// A block takes G pencils that are adjacent in x, so every load and store
-// instruction touches contiguous runs of the x-fastest layout.
-template <typename R, int N, int DIR, int AXIS>
+// In-place transform along y (AXIS = 1) or z (AXIS = 2) of a complex volume
+// whose rows hold W entries ([z][y][W]; W = spec_ld<N>() for the half
+// spectrum).  A block takes G pencils that are adjacent in the row, so every
+// load and store instruction touches contiguous runs.
+template <typename R, int N, int DIR, int AXIS, int W>
 __global__ __launch_bounds__(256) void k_fft_strided(cplx<R> *__restrict__ vol_base, const cplx<R> *__restrict__ tw,
                                                      int64_t map_stride) {
     using C = cplx<R>;
     constexpr int G = pencils_per_block<R, N>();
+    static_assert((N * W) % G == 0, "pencil groups must tile the volume");
     __shared__ C s[G * pencil_ld<N>()];
     __shared__ C tws[N];
     load_twiddles<C, N>(tws, tw);
     C *v = vol_base + (int64_t)blockIdx.y * map_stride;
-    const int64_t p0 = (int64_t)blockIdx.x * G;   // first pencil (c * N + x)
-    const int64_t stride = AXIS == 1 ? N : (int64_t)N * N;
+    const int64_t p0 = (int64_t)blockIdx.x * G;   // first pencil (c * W + x)
+    const int64_t stride = AXIS == 1 ? W : (int64_t)N * W;
     constexpr int PER = G * N / 256;
     C x[PER];
 #pragma unroll
@@ -123,8 +146,8 @@ __global__ __launch_bounds__(256) void k_fft_strided(cplx<R> *__restrict__ vol_b
         const int e = threadIdx.x + k * 256;
         const int p = e % G, i = e / G;
         const int64_t pl = p0 + p;
-        const int64_t c = pl / N, xx = pl % N;
-        x[k] = v[AXIS == 1 ? c * N * N + i * stride + xx : (int64_t)i * stride + pl];
+        const int64_t c = pl / W, xx = pl % W;
+        x[k] = v[AXIS == 1 ? c * N * W + i * stride + xx : (int64_t)i * stride + pl];
     }
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
@@ -136,8 +159,8 @@ __global__ __launch_bounds__(256) void k_fft_strided(cplx<R> *__restrict__ vol_b
     for (int e = threadIdx.x; e < G * N; e += 256) {
         const int p = e % G, i = e / G;
         const int64_t pl = p0 + p;
-        const int64_t c = pl / N, x = pl % N;
-        const int64_t addr = AXIS == 1 ? c * N * N + i * stride + x : (int64_t)i * stride + pl;
+        const int64_t c = pl / W, x = pl % W;
+        const int64_t addr = AXIS == 1 ? c * N * W + i * stride + x : (int64_t)i * stride + pl;
         v[addr] = s[p * pencil_ld<N>() + pad_idx(i)];
     }
 }
@@ -187,7 +210,10 @@ __global__ __launch_bounds__(256) void k_inv_z_prune(const cplx<R> *__restrict__
     const bool live = c0 + p < P.ncols;
     const int box = live ? cl[c0 + p] : 0;           // (m_y + R) * Wp + (m_x + R)
     const int my = box / Wp - Rr, mx = box % Wp - Rr;
-    const int64_t col_addr = (int64_t)(my & (N - 1)) * N + (mx & (N - 1));
+    // half spectrum: m_x < 0 is read as conj Delta(-m)
+    constexpr int HP = spec_ld<N>();
+    const bool neg = mx < 0;
+    const int64_t col_addr = neg ? (int64_t)((-my) & (N - 1)) * HP - mx : (int64_t)(my & (N - 1)) * HP + mx;
     C d[PER];
     unsigned in_mask1 = 0, in_mask2 = 0;
 #pragma unroll
@@ -201,8 +227,13 @@ __global__ __launch_bounds__(256) void k_inv_z_prune(const cplx<R> *__restrict__
         in_mask2 |= (unsigned)in2 << k;
         d[k] = C{R(0), R(0)};
         if (in1 || in2) {
-            if constexpr (UNIT) d[k] = C{R(1), R(0)};
-            else d[k] = sp[(int64_t)i * N * N + col_addr];
+            if constexpr (UNIT) {
+                d[k] = C{R(1), R(0)};
+            } else {
+                const int iz = neg ? (N - i) & (N - 1) : i;
+                const C v = sp[(int64_t)iz * N * HP + col_addr];
+                d[k] = neg ? C{v.x, -v.y} : v;
+            }
         }
     }
 #pragma unroll
@@ -462,10 +493,14 @@ hipError_t launch_forward(const float *delta, const double *mean, int n, int bat
     return dispatch_n(n, [&](auto nc) {
         constexpr int NN = decltype(nc)::value;
         constexpr int G = pencils_per_block<float, NN>();
-        const int nblk = NN * NN / G;
-        hipLaunchKernelGGL((k_fwd_x<NN>), dim3(nblk, batch), dim3(256), 0, st, delta, mean, tw, spec);
-        hipLaunchKernelGGL((k_fft_strided<float, NN, -1, 1>), dim3(nblk, batch), dim3(256), 0, st, spec, tw, vol);
-        hipLaunchKernelGGL((k_fft_strided<float, NN, -1, 2>), dim3(nblk, batch), dim3(256), 0, st, spec, tw, vol);
+        constexpr int GX = G < NN * NN / 2 ? G : NN * NN / 2;
+        constexpr int HP = spec_ld<NN>();
+        const int64_t hvol = (int64_t)NN * NN * HP;
+        hipLaunchKernelGGL((k_fwd_x<NN>), dim3(NN * NN / (2 * GX), batch), dim3(256), 0, st, delta, mean, tw, spec);
+        hipLaunchKernelGGL((k_fft_strided<float, NN, -1, 1, HP>), dim3(NN * HP / G, batch), dim3(256), 0, st, spec,
+                           tw, hvol);
+        hipLaunchKernelGGL((k_fft_strided<float, NN, -1, 2, HP>), dim3(NN * HP / G, batch), dim3(256), 0, st, spec,
+                           tw, hvol);
     });
 }
 
@@ -520,6 +555,15 @@ hipError_t launch_inverse_unit_f64(int n, const double2 *tw, const PairDev *pd, 
                                                st);
     if (e != hipSuccess) return e;
     return launch_inverse_x_t<double>(bc, 0, n, 1, tw, g, f1, f2, vol, st);
+}
+
+int64_t spec_elems(int n) {
+    int64_t e = 0;
+    dispatch_n(n, [&](auto nc) {
+        constexpr int NN = decltype(nc)::value;
+        e = (int64_t)NN * NN * spec_ld<NN>();
+    });
+    return e;
 }
 
 int fft_pencils_per_block(int n, bool fp64) {

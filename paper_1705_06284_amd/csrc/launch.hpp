@@ -18,6 +18,8 @@ hipError_t launch_forward(const float *delta, const double *mean, int n, int bat
 // the compact rows land in bc at each pair's boff.  Pass X (launch_inverse_x)
 // reads one pair's compact rows (row stride Wp) and writes F_b1 to f1 and
 // F_b2 to f2 (f2 may be null).
+// Complex entries of one map's half spectrum [N][N][spec_ld<N>()].
+int64_t spec_elems(int n);
 hipError_t launch_inverse_zy(const float2 *spec, int64_t spec_stride, int n, int batch, const float2 *tw,
                              const PairDev *pd, const int2 *ztab, int nz_blk, const int2 *ytab, int ny_blk,
                              const int *cols, float2 *abox, float2 *bc, hipStream_t st);
