@@ -194,12 +194,15 @@ __device__ __forceinline__ void fft_pencils(C *s, const C *tw, int g_act = G) {
 // As fft_pencils, but the last pass hands its outputs (pencil, position in
 // natural order, value) to store instead of writing them back to s; s may be
 // overwritten by store, since every read of the pass precedes it.
-template <typename C, int N, int LD, int G, int DIR, int NT, typename Store>
+// SKIP_FIRST: the caller has already done the first radix-8 pass
+// (first_pass_butterfly); needs N >= 16, so that it is not also the last.
+template <typename C, int N, int LD, int G, int DIR, int NT, bool SKIP_FIRST = false, typename Store>
 __device__ __forceinline__ void fft_pencils_to(C *s, const C *tw, int g_act, Store store) {
     constexpr int P8 = ilog8_floor(N);
     constexpr int RL = N / ipow8(P8);
     constexpr int LAST8 = RL > 1 ? P8 : P8 - 1;     // radix-8 passes written back to s
-    if constexpr (LAST8 >= 1) stockham_pass<C, N, LD, G, DIR, 8, 1, NT>(s, tw, g_act);
+    static_assert(!SKIP_FIRST || N >= 16, "the first pass is the last one");
+    if constexpr (LAST8 >= 1 && !SKIP_FIRST) stockham_pass<C, N, LD, G, DIR, 8, 1, NT>(s, tw, g_act);
     if constexpr (LAST8 >= 2) stockham_pass<C, N, LD, G, DIR, 8, 8, NT>(s, tw, g_act);
     if constexpr (LAST8 >= 3) stockham_pass<C, N, LD, G, DIR, 8, 64, NT>(s, tw, g_act);
     if constexpr (LAST8 >= 4) stockham_pass<C, N, LD, G, DIR, 8, 512, NT>(s, tw, g_act);
@@ -207,6 +210,17 @@ __device__ __forceinline__ void fft_pencils_to(C *s, const C *tw, int g_act, Sto
         stockham_pass_to<C, N, LD, G, DIR, RL, ipow8(P8), NT>(s, tw, g_act, store);
     else
         stockham_pass_to<C, N, LD, G, DIR, 8, ipow8(P8 - 1), NT>(s, tw, g_act, store);
+}
+
+// First radix-8 Stockham pass of one butterfly whose 8 inputs x[jj + t N/8]
+// (t < 8) the caller holds in v: no twiddles (span 1); output u goes to
+// position 8 jj + u of pencil p.  Followed by a barrier and
+// fft_pencils_to<..., SKIP_FIRST = true>.
+template <typename C, int N, int LD, int DIR>
+__device__ __forceinline__ void first_pass_butterfly(C *s, int p, int jj, C *v) {
+    dft8<DIR>(v);
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s[p * LD + pad_idx(8 * jj + u)] = v[u];
 }
 
 // Pencils per block: at least one butterfly task per thread, at most 64 KiB

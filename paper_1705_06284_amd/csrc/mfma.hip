@@ -291,69 +291,124 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MINW))) void
     const __bf16 *bl_row = col < nb ? Bl + col * BS : Bconst + CBS / 2;
 
     // Slot sl = q RT + r holds pair q of tile row r; only the first
-    // npairs RT slots are loaded, transformed and read.  Element k of this
-    // thread's share of a tile is e = tid + k NT: slot e / N at position
-    // i = tid % N (NT is a multiple of N), i.e. at frequency m_x = signed(i).
-    // A wave covers one slot, or 64/N consecutive rows of one pair, so the
-    // pair index is wave-uniform and its parameters are scalar loads.
+    // npairs RT slots are loaded, transformed and read.
     static_assert(NT % N == 0, "block size must be a multiple of the row length");
-    const int mx = signed_freq(tid % N, N);
     const int gact = tp.npairs * RT;
-    auto fetch = [&](int64_t tile, float2 *v) {
-        const int64_t row0 = tile * RT;
-#pragma unroll
-        for (int k = 0; k < PF; ++k) {
-            const int sl = tid / N + k * (NT / N);
-            const int q = __builtin_amdgcn_readfirstlane(sl / RT);
-            const int r = sl % RT;
-            v[k] = float2{0.0f, 0.0f};
-            if (q < tp.npairs) {
-                const int R = tp.R[q];
-                if (mx >= -R && mx <= R) v[k] = bc[tp.off[q] + (map * nrow + row0 + r) * tp.W[q] + mx + R];
+    // The last pass writes the fields straight into the tile: F_2q and
+    // F_2q+1 in FP32 and, in split mode, their bf16 halves (which overwrite
+    // the FFT buffer after the pass has read it).
+    auto store = [&](int sl, int n, float2 f) {
+        const int q = sl / RT, r = sl % RT;
+        const int i = r * N + n;
+        const bool odd = 2 * q + 1 < nb;
+        Ft[(2 * q) * FS + i] = f.x;
+        if (odd) Ft[(2 * q + 1) * FS + i] = f.y;
+        if constexpr (MODE == PG_MODE_SPLIT) {
+            bf16x2 h, l;
+            split2(f.x, f.y, h, l);
+            Bh[(2 * q) * BS + i] = h[0];
+            Bl[(2 * q) * BS + i] = l[0];
+            if (odd) {
+                Bh[(2 * q + 1) * BS + i] = h[1];
+                Bl[(2 * q + 1) * BS + i] = l[1];
             }
         }
     };
-    // PREFETCH: the loads of tile t + 1 are issued right after tile t is
-    // stored and stay in flight through its transform and contraction (else
-    // a co-resident block hides their latency).
     int since_flush = 0;
-    float2 v[PF];
-    if (PREFETCH && t_begin < t_end) fetch(t_begin, v);
-    for (int64_t tile = t_begin; tile < t_end; ++tile) {
-        if (!PREFETCH) fetch(tile, v);
-        __syncthreads();
+    if constexpr (N >= 16) {
+        // The loads feed the first radix-8 pass directly: task (slot p,
+        // butterfly jj) loads x[jj + t N/8], t < 8, from the compact row
+        // (zero where |m_x| > R), so the first pass reads no LDS.  A task's
+        // row base, stride and radius are fixed over the tiles.
+        constexpr int NB1 = N / 8;
+        constexpr int T1 = G * NB1;
+        constexpr int PER1 = T1 < NT ? 1 : T1 / NT;
+        static_assert(T1 % NT == 0 || T1 < NT, "first-pass tasks must fill the block or fit in it");
+        int64_t fbase[PER1];
+        int fw[PER1], fr[PER1];
+        bool fact[PER1];
 #pragma unroll
-        for (int k = 0; k < PF; ++k) {
-            const int e = tid + k * NT;
-            if (e / N < gact) fb[(e / N) * LDP + pad_idx(e % N)] = v[k];
+        for (int k = 0; k < PER1; ++k) {
+            const int task = tid + k * NT;
+            const int p = task / NB1;
+            const int q = p / RT, r = p % RT;
+            fact[k] = (T1 >= NT || tid < T1) && p < gact;
+            fw[k] = fact[k] ? tp.W[q] : 0;
+            fr[k] = fact[k] ? tp.R[q] : -1;
+            fbase[k] = fact[k] ? tp.off[q] + (map * nrow + r) * fw[k] + fr[k] : 0;
         }
-        if (PREFETCH && tile + 1 < t_end) fetch(tile + 1, v);
-        __syncthreads();
-        // The last pass writes the fields straight into the tile: F_2q and
-        // F_2q+1 in FP32 and, in split mode, their bf16 halves (which
-        // overwrite the FFT buffer after the pass has read it).
-        fft_pencils_to<float2, N, LDP, G, +1, NT>(fb, tws, gact, [&](int sl, int n, float2 f) {
-            const int q = sl / RT, r = sl % RT;
-            const int i = r * N + n;
-            const bool odd = 2 * q + 1 < nb;
-            Ft[(2 * q) * FS + i] = f.x;
-            if (odd) Ft[(2 * q + 1) * FS + i] = f.y;
-            if constexpr (MODE == PG_MODE_SPLIT) {
-                bf16x2 h, l;
-                split2(f.x, f.y, h, l);
-                Bh[(2 * q) * BS + i] = h[0];
-                Bl[(2 * q) * BS + i] = l[0];
-                if (odd) {
-                    Bh[(2 * q + 1) * BS + i] = h[1];
-                    Bl[(2 * q + 1) * BS + i] = l[1];
+        auto fetch = [&](int64_t tile, float2 (*v)[8]) {
+#pragma unroll
+            for (int k = 0; k < PER1; ++k) {
+                const int jj = (tid + k * NT) % NB1;
+                const int64_t row = fbase[k] + tile * RT * fw[k];
+#pragma unroll
+                for (int t = 0; t < 8; ++t) {
+                    const int mx = signed_freq(jj + t * NB1, N);
+                    v[k][t] = float2{0.0f, 0.0f};
+                    if (mx >= -fr[k] && mx <= fr[k]) v[k][t] = bc[row + mx];
                 }
             }
-        });
-        st.template contract<TK, FS>(Ft, bh_row, bl_row, col, half);
-        since_flush += TK;
-        if (since_flush >= PG_FLUSH_POINTS) {
-            since_flush = 0;
-            st.flush();
+        };
+        // PREFETCH: the loads of tile t + 1 are issued right after tile t's
+        // first pass and stay in flight through its transform and
+        // contraction (else a co-resident block hides their latency).
+        float2 v[PER1][8];
+        if (PREFETCH && t_begin < t_end) fetch(t_begin, v);
+        for (int64_t tile = t_begin; tile < t_end; ++tile) {
+            if (!PREFETCH) fetch(tile, v);
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < PER1; ++k) {
+                const int task = tid + k * NT;
+                if (fact[k]) first_pass_butterfly<float2, N, LDP, +1>(fb, task / NB1, task % NB1, v[k]);
+            }
+            if (PREFETCH && tile + 1 < t_end) fetch(tile + 1, v);
+            __syncthreads();
+            fft_pencils_to<float2, N, LDP, G, +1, NT, true>(fb, tws, gact, store);
+            st.template contract<TK, FS>(Ft, bh_row, bl_row, col, half);
+            since_flush += TK;
+            if (since_flush >= PG_FLUSH_POINTS) {
+                since_flush = 0;
+                st.flush();
+            }
+        }
+    } else {
+        // N = 8: the one radix-8 pass is also the last.  Element k of this
+        // thread's share of a tile is e = tid + k NT: slot e / N at
+        // position tid % N; a wave covers 64/N consecutive rows of one pair.
+        const int mx = signed_freq(tid % N, N);
+        auto fetch = [&](int64_t tile, float2 *v) {
+            const int64_t row0 = tile * RT;
+#pragma unroll
+            for (int k = 0; k < PF; ++k) {
+                const int sl = tid / N + k * (NT / N);
+                const int q = __builtin_amdgcn_readfirstlane(sl / RT);
+                const int r = sl % RT;
+                v[k] = float2{0.0f, 0.0f};
+                if (q < tp.npairs) {
+                    const int R = tp.R[q];
+                    if (mx >= -R && mx <= R) v[k] = bc[tp.off[q] + (map * nrow + row0 + r) * tp.W[q] + mx + R];
+                }
+            }
+        };
+        float2 v[PF];
+        for (int64_t tile = t_begin; tile < t_end; ++tile) {
+            fetch(tile, v);
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < PF; ++k) {
+                const int e = tid + k * NT;
+                if (e / N < gact) fb[(e / N) * LDP + pad_idx(e % N)] = v[k];
+            }
+            __syncthreads();
+            fft_pencils_to<float2, N, LDP, G, +1, NT>(fb, tws, gact, store);
+            st.template contract<TK, FS>(Ft, bh_row, bl_row, col, half);
+            since_flush += TK;
+            if (since_flush >= PG_FLUSH_POINTS) {
+                since_flush = 0;
+                st.flush();
+            }
         }
     }
     st.write(partial, (int64_t)map * gridDim.x + blockIdx.x, n_mtile, col, half);
