@@ -127,7 +127,11 @@ constexpr int ipow8(int p) { return p == 0 ? 1 : 8 * ipow8(p - 1); }
 // One Stockham pass over the first g_act of the G pencils of the block (NT
 // threads); the others are left untouched.  Output u of a butterfly goes to
 // store(pencil, position, value) once every thread has read its inputs.
-template <typename C, int N, int LD, int G, int DIR, int RADIX, int NS, int NT, typename Store>
+// Task t is butterfly t mod NB of pencil t / NB, or with PFAST butterfly
+// t / G of pencil t mod G (consecutive threads on consecutive pencils, for
+// stores that go straight to memory where pencils are adjacent).
+template <typename C, int N, int LD, int G, int DIR, int RADIX, int NS, int NT, bool PFAST = false,
+          typename Store>
 __device__ __forceinline__ void stockham_pass_to(C *s, const C *tw, int g_act, Store store) {
     constexpr int NB = N / RADIX;          // butterflies per pencil
     constexpr int TASKS = G * NB;
@@ -141,8 +145,9 @@ __device__ __forceinline__ void stockham_pass_to(C *s, const C *tw, int g_act, S
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
         const int task = tid + q * NT;
-        if (task >= act_tasks || (PARTIAL && tid >= TASKS)) break;
-        const int p = task / NB, jj = task % NB;
+        if ((!PFAST && task >= act_tasks) || (PARTIAL && tid >= TASKS)) break;
+        const int p = PFAST ? task % G : task / NB, jj = PFAST ? task / G : task % NB;
+        if (PFAST && p >= g_act) continue;
         const int k = jj % NS;
 #pragma unroll
         for (int t = 0; t < RADIX; ++t) v[q][t] = s[p * LD + pad_idx(jj + t * NB)];
@@ -160,8 +165,9 @@ __device__ __forceinline__ void stockham_pass_to(C *s, const C *tw, int g_act, S
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
         const int task = tid + q * NT;
-        if (task >= act_tasks || (PARTIAL && tid >= TASKS)) break;
-        const int p = task / NB, jj = task % NB;
+        if ((!PFAST && task >= act_tasks) || (PARTIAL && tid >= TASKS)) break;
+        const int p = PFAST ? task % G : task / NB, jj = PFAST ? task / G : task % NB;
+        if (PFAST && p >= g_act) continue;
         const int k = jj % NS;
         const int base = (jj / NS) * NS * RADIX + k;
 #pragma unroll
@@ -170,9 +176,9 @@ __device__ __forceinline__ void stockham_pass_to(C *s, const C *tw, int g_act, S
     __syncthreads();
 }
 
-template <typename C, int N, int LD, int G, int DIR, int RADIX, int NS, int NT>
+template <typename C, int N, int LD, int G, int DIR, int RADIX, int NS, int NT, bool PFAST = false>
 __device__ __forceinline__ void stockham_pass(C *s, const C *tw, int g_act) {
-    stockham_pass_to<C, N, LD, G, DIR, RADIX, NS, NT>(
+    stockham_pass_to<C, N, LD, G, DIR, RADIX, NS, NT, PFAST>(
         s, tw, g_act, [s](int p, int pos, C v) { s[p * LD + pad_idx(pos)] = v; });
 }
 
@@ -196,20 +202,21 @@ __device__ __forceinline__ void fft_pencils(C *s, const C *tw, int g_act = G) {
 // overwritten by store, since every read of the pass precedes it.
 // SKIP_FIRST: the caller has already done the first radix-8 pass
 // (first_pass_butterfly); needs N >= 16, so that it is not also the last.
-template <typename C, int N, int LD, int G, int DIR, int NT, bool SKIP_FIRST = false, typename Store>
+template <typename C, int N, int LD, int G, int DIR, int NT, bool SKIP_FIRST = false, bool PFAST = false,
+          typename Store>
 __device__ __forceinline__ void fft_pencils_to(C *s, const C *tw, int g_act, Store store) {
     constexpr int P8 = ilog8_floor(N);
     constexpr int RL = N / ipow8(P8);
     constexpr int LAST8 = RL > 1 ? P8 : P8 - 1;     // radix-8 passes written back to s
     static_assert(!SKIP_FIRST || N >= 16, "the first pass is the last one");
-    if constexpr (LAST8 >= 1 && !SKIP_FIRST) stockham_pass<C, N, LD, G, DIR, 8, 1, NT>(s, tw, g_act);
-    if constexpr (LAST8 >= 2) stockham_pass<C, N, LD, G, DIR, 8, 8, NT>(s, tw, g_act);
-    if constexpr (LAST8 >= 3) stockham_pass<C, N, LD, G, DIR, 8, 64, NT>(s, tw, g_act);
-    if constexpr (LAST8 >= 4) stockham_pass<C, N, LD, G, DIR, 8, 512, NT>(s, tw, g_act);
+    if constexpr (LAST8 >= 1 && !SKIP_FIRST) stockham_pass<C, N, LD, G, DIR, 8, 1, NT, PFAST>(s, tw, g_act);
+    if constexpr (LAST8 >= 2) stockham_pass<C, N, LD, G, DIR, 8, 8, NT, PFAST>(s, tw, g_act);
+    if constexpr (LAST8 >= 3) stockham_pass<C, N, LD, G, DIR, 8, 64, NT, PFAST>(s, tw, g_act);
+    if constexpr (LAST8 >= 4) stockham_pass<C, N, LD, G, DIR, 8, 512, NT, PFAST>(s, tw, g_act);
     if constexpr (RL > 1)
-        stockham_pass_to<C, N, LD, G, DIR, RL, ipow8(P8), NT>(s, tw, g_act, store);
+        stockham_pass_to<C, N, LD, G, DIR, RL, ipow8(P8), NT, PFAST>(s, tw, g_act, store);
     else
-        stockham_pass_to<C, N, LD, G, DIR, 8, ipow8(P8 - 1), NT>(s, tw, g_act, store);
+        stockham_pass_to<C, N, LD, G, DIR, 8, ipow8(P8 - 1), NT, PFAST>(s, tw, g_act, store);
 }
 
 // First radix-8 Stockham pass of one butterfly whose 8 inputs x[jj + t N/8]

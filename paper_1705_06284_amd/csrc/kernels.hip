@@ -214,40 +214,56 @@ __global__ __launch_bounds__(256) void k_inv_z_prune(const cplx<R> *__restrict__
     constexpr int HP = spec_ld<N>();
     const bool neg = mx < 0;
     const int64_t col_addr = neg ? (int64_t)((-my) & (N - 1)) * HP - mx : (int64_t)(my & (N - 1)) * HP + mx;
-    C d[PER];
-    unsigned in_mask1 = 0, in_mask2 = 0;
-#pragma unroll
-    for (int k = 0; k < PER; ++k) {
-        const int i = (threadIdx.x + k * 256) / G;
+    const int64_t plane = (int64_t)P.g.W * Wp;
+    // the shell masks of the two bins fused into the load: b1 real, b2 imaginary
+    auto masked = [&](int i) {
         const int mz = signed_freq(i, N);
         const int r2 = mz * mz + my * my + mx * mx;
         const bool in1 = live && r2 >= P.g.lo1 && r2 < P.g.hi1;
         const bool in2 = live && r2 >= P.g.lo2 && r2 < P.g.hi2;
-        in_mask1 |= (unsigned)in1 << k;
-        in_mask2 |= (unsigned)in2 << k;
-        d[k] = C{R(0), R(0)};
+        C d = C{R(0), R(0)};
         if (in1 || in2) {
             if constexpr (UNIT) {
-                d[k] = C{R(1), R(0)};
+                d = C{R(1), R(0)};
             } else {
                 const int iz = neg ? (N - i) & (N - 1) : i;
                 const C v = sp[(int64_t)iz * N * HP + col_addr];
-                d[k] = neg ? C{v.x, -v.y} : v;
+                d = neg ? C{v.x, -v.y} : v;
             }
         }
-    }
+        const R a1 = in1 ? R(1) : R(0), a2 = in2 ? R(1) : R(0);
+        return C{d.x * a1 - d.y * a2, d.y * a1 + d.x * a2};
+    };
+    if constexpr (N >= 16) {
+        // The loads feed the first radix-8 pass in registers and the last pass
+        // stores to memory; tasks run pencil-fastest (every task of this
+        // thread is on its column p).
+        constexpr int NB1 = N / 8, PER1 = G * NB1 / 256;
+        static_assert((G * NB1) % 256 == 0, "first-pass tasks must fill the block");
 #pragma unroll
-    for (int k = 0; k < PER; ++k) {
-        const int i = (threadIdx.x + k * 256) / G;
-        const R a1 = (in_mask1 >> k) & 1 ? R(1) : R(0), a2 = (in_mask2 >> k) & 1 ? R(1) : R(0);
-        s[p * pencil_ld<N>() + pad_idx(i)] = C{d[k].x * a1 - d[k].y * a2, d[k].y * a1 + d[k].x * a2};
-    }
-    __syncthreads();
-    fft_pencils<C, N, pencil_ld<N>(), G, +1>(s, tws);
-    const int64_t plane = (int64_t)P.g.W * Wp;
-    for (int e = threadIdx.x; e < G * N; e += 256) {
-        const int p = e % G, i = e / G;
-        if (c0 + p < P.ncols) o[(int64_t)i * plane + cl[c0 + p]] = s[p * pencil_ld<N>() + pad_idx(i)];
+        for (int k = 0; k < PER1; ++k) {
+            const int jj = (threadIdx.x + k * 256) / G;
+            C v[8];
+#pragma unroll
+            for (int t = 0; t < 8; ++t) v[t] = masked(jj + t * NB1);
+            first_pass_butterfly<C, N, pencil_ld<N>(), +1>(s, p, jj, v);
+        }
+        __syncthreads();
+        fft_pencils_to<C, N, pencil_ld<N>(), G, +1, 256, true, true>(s, tws, G, [&](int q, int i, C val) {
+            if (c0 + q < P.ncols) o[(int64_t)i * plane + cl[c0 + q]] = val;
+        });
+    } else {
+        C d[PER];
+#pragma unroll
+        for (int k = 0; k < PER; ++k) d[k] = masked((threadIdx.x + k * 256) / G);
+#pragma unroll
+        for (int k = 0; k < PER; ++k) s[p * pencil_ld<N>() + pad_idx((threadIdx.x + k * 256) / G)] = d[k];
+        __syncthreads();
+        fft_pencils<C, N, pencil_ld<N>(), G, +1>(s, tws);
+        for (int e = threadIdx.x; e < G * N; e += 256) {
+            const int q = e % G, i = e / G;
+            if (c0 + q < P.ncols) o[(int64_t)i * plane + cl[c0 + q]] = s[q * pencil_ld<N>() + pad_idx(i)];
+        }
     }
 }
 
@@ -271,31 +287,63 @@ __global__ __launch_bounds__(256) void k_inv_y_prune(const cplx<R> *__restrict__
     const int W = P.g.W, Wp = P.g.Wp, Rr = P.g.R;
     const int ncols = N * Wp;
     const int64_t plane = (int64_t)W * Wp;
-    constexpr int PER = G * N / 256;
-    {
-        const int p = threadIdx.x % G;               // fixed column of this thread
-        const int c = c0 + p;
-        const int nz = c / Wp, xi = c % Wp;
-        const bool live = c < ncols && xi < W;
-        const int mx = xi - Rr;
-        const C *col = a + (int64_t)nz * plane + xi;
-        C v[PER];
+    if constexpr (N >= 16) {
+        // The loads feed the first radix-8 pass in registers and the last pass
+        // stores to memory; tasks run pencil-fastest, so consecutive threads
+        // touch consecutive columns xi.
+        constexpr int NB1 = N / 8, PER1 = G * NB1 / 256;
+        static_assert((G * NB1) % 256 == 0, "first-pass tasks must fill the block");
 #pragma unroll
-        for (int k = 0; k < PER; ++k) {
-            const int my = signed_freq((threadIdx.x + k * 256) / G, N);
-            v[k] = C{R(0), R(0)};
-            if (live && my >= -Rr && my <= Rr && my * my + mx * mx < P.g.hmax) v[k] = col[(int64_t)(my + Rr) * Wp];
+        for (int k = 0; k < PER1; ++k) {
+            const int task = threadIdx.x + k * 256;
+            const int p = task % G, jj = task / G;
+            const int c = c0 + p;
+            const int nz = c / Wp, xi = c % Wp;
+            const bool live = c < ncols && xi < W;
+            const int mx = xi - Rr;
+            const C *col = a + (int64_t)nz * plane + xi;
+            C v[8];
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                const int my = signed_freq(jj + t * NB1, N);
+                v[t] = C{R(0), R(0)};
+                if (live && my >= -Rr && my <= Rr && my * my + mx * mx < P.g.hmax) v[t] = col[(int64_t)(my + Rr) * Wp];
+            }
+            first_pass_butterfly<C, N, pencil_ld<N>(), +1>(s, p, jj, v);
         }
+        __syncthreads();
+        fft_pencils_to<C, N, pencil_ld<N>(), G, +1, 256, true, true>(s, tws, G, [&](int p, int i, C val) {
+            const int c = c0 + p;
+            const int nz = c / Wp, xi = c % Wp;
+            if (c < ncols && xi < W) o[((int64_t)nz * N + i) * Wp + xi] = val;
+        });
+    } else {
+        constexpr int PER = G * N / 256;
+        {
+            const int p = threadIdx.x % G;               // fixed column of this thread
+            const int c = c0 + p;
+            const int nz = c / Wp, xi = c % Wp;
+            const bool live = c < ncols && xi < W;
+            const int mx = xi - Rr;
+            const C *col = a + (int64_t)nz * plane + xi;
+            C v[PER];
 #pragma unroll
-        for (int k = 0; k < PER; ++k) s[p * pencil_ld<N>() + pad_idx((threadIdx.x + k * 256) / G)] = v[k];
-    }
-    __syncthreads();
-    fft_pencils<C, N, pencil_ld<N>(), G, +1>(s, tws);
-    for (int e = threadIdx.x; e < G * N; e += 256) {
-        const int p = e % G, i = e / G;
-        const int c = c0 + p;
-        const int nz = c / Wp, xi = c % Wp;
-        if (c < ncols && xi < W) o[((int64_t)nz * N + i) * Wp + xi] = s[p * pencil_ld<N>() + pad_idx(i)];
+            for (int k = 0; k < PER; ++k) {
+                const int my = signed_freq((threadIdx.x + k * 256) / G, N);
+                v[k] = C{R(0), R(0)};
+                if (live && my >= -Rr && my <= Rr && my * my + mx * mx < P.g.hmax) v[k] = col[(int64_t)(my + Rr) * Wp];
+            }
+#pragma unroll
+            for (int k = 0; k < PER; ++k) s[p * pencil_ld<N>() + pad_idx((threadIdx.x + k * 256) / G)] = v[k];
+        }
+        __syncthreads();
+        fft_pencils<C, N, pencil_ld<N>(), G, +1>(s, tws);
+        for (int e = threadIdx.x; e < G * N; e += 256) {
+            const int p = e % G, i = e / G;
+            const int c = c0 + p;
+            const int nz = c / Wp, xi = c % Wp;
+            if (c < ncols && xi < W) o[((int64_t)nz * N + i) * Wp + xi] = s[p * pencil_ld<N>() + pad_idx(i)];
+        }
     }
 }
 
@@ -337,6 +385,7 @@ __global__ __launch_bounds__(256) void k_inv_x_compact(const cplx<R> *__restrict
             d2[row0 * N + e] = s[(e / N) * pencil_ld<N>() + pad_idx(e % N)].y;
     }
 }
+
 
 // ---------------------------------------------------------------------------
 // Product sums over the grid: term t multiplies the fields named by the four
@@ -489,7 +538,6 @@ hipError_t launch_mean(const float *x, int n, int batch, double *partial, int np
 
 hipError_t launch_forward(const float *delta, const double *mean, int n, int batch, const float2 *tw,
                           float2 *spec, hipStream_t st) {
-    const int64_t vol = (int64_t)n * n * n;
     return dispatch_n(n, [&](auto nc) {
         constexpr int NN = decltype(nc)::value;
         constexpr int G = pencils_per_block<float, NN>();
