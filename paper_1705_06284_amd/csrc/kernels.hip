@@ -139,29 +139,46 @@ __global__ __launch_bounds__(256) void k_fft_strided(cplx<R> *__restrict__ vol_b
     C *v = vol_base + (int64_t)blockIdx.y * map_stride;
     const int64_t p0 = (int64_t)blockIdx.x * G;   // first pencil (c * W + x)
     const int64_t stride = AXIS == 1 ? W : (int64_t)N * W;
-    constexpr int PER = G * N / 256;
-    C x[PER];
-#pragma unroll
-    for (int k = 0; k < PER; ++k) {
-        const int e = threadIdx.x + k * 256;
-        const int p = e % G, i = e / G;
+    auto addr = [&](int p, int i) {
         const int64_t pl = p0 + p;
-        const int64_t c = pl / W, xx = pl % W;
-        x[k] = v[AXIS == 1 ? c * N * W + i * stride + xx : (int64_t)i * stride + pl];
-    }
+        return AXIS == 1 ? (pl / W) * N * W + i * stride + pl % W : (int64_t)i * stride + pl;
+    };
+    if constexpr (N >= 16) {
+        // loads feed the first radix-8 pass in registers, the last pass stores
+        // to memory; tasks run pencil-fastest
+        constexpr int NB1 = N / 8, PER1 = G * NB1 / 256;
+        static_assert((G * NB1) % 256 == 0, "first-pass tasks must fill the block");
+        C x[PER1][8];
 #pragma unroll
-    for (int k = 0; k < PER; ++k) {
-        const int e = threadIdx.x + k * 256;
-        s[(e % G) * pencil_ld<N>() + pad_idx(e / G)] = x[k];
-    }
-    __syncthreads();
-    fft_pencils<C, N, pencil_ld<N>(), G, DIR>(s, tws);
-    for (int e = threadIdx.x; e < G * N; e += 256) {
-        const int p = e % G, i = e / G;
-        const int64_t pl = p0 + p;
-        const int64_t c = pl / W, x = pl % W;
-        const int64_t addr = AXIS == 1 ? c * N * W + i * stride + x : (int64_t)i * stride + pl;
-        v[addr] = s[p * pencil_ld<N>() + pad_idx(i)];
+        for (int k = 0; k < PER1; ++k) {
+            const int task = threadIdx.x + k * 256;
+#pragma unroll
+            for (int t = 0; t < 8; ++t) x[k][t] = v[addr(task % G, task / G + t * NB1)];
+        }
+#pragma unroll
+        for (int k = 0; k < PER1; ++k) {
+            const int task = threadIdx.x + k * 256;
+            first_pass_butterfly<C, N, pencil_ld<N>(), DIR>(s, task % G, task / G, x[k]);
+        }
+        __syncthreads();
+        fft_pencils_to<C, N, pencil_ld<N>(), G, DIR, 256, true, true>(s, tws, G,
+                                                                      [&](int p, int i, C val) { v[addr(p, i)] = val; });
+    } else {
+        constexpr int PER = G * N / 256;
+        C x[PER];
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int e = threadIdx.x + k * 256;
+            x[k] = v[addr(e % G, e / G)];
+        }
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int e = threadIdx.x + k * 256;
+            s[(e % G) * pencil_ld<N>() + pad_idx(e / G)] = x[k];
+        }
+        __syncthreads();
+        fft_pencils<C, N, pencil_ld<N>(), G, DIR>(s, tws);
+        for (int e = threadIdx.x; e < G * N; e += 256) v[addr(e % G, e / G)] = s[(e % G) * pencil_ld<N>() + pad_idx(e / G)];
     }
 }
 
@@ -240,14 +257,16 @@ __global__ __launch_bounds__(256) void k_inv_z_prune(const cplx<R> *__restrict__
         // thread is on its column p).
         constexpr int NB1 = N / 8, PER1 = G * NB1 / 256;
         static_assert((G * NB1) % 256 == 0, "first-pass tasks must fill the block");
+        C v[PER1][8];
 #pragma unroll
-        for (int k = 0; k < PER1; ++k) {
+        for (int k = 0; k < PER1; ++k) {             // all loads in flight first
             const int jj = (threadIdx.x + k * 256) / G;
-            C v[8];
 #pragma unroll
-            for (int t = 0; t < 8; ++t) v[t] = masked(jj + t * NB1);
-            first_pass_butterfly<C, N, pencil_ld<N>(), +1>(s, p, jj, v);
+            for (int t = 0; t < 8; ++t) v[k][t] = masked(jj + t * NB1);
         }
+#pragma unroll
+        for (int k = 0; k < PER1; ++k)
+            first_pass_butterfly<C, N, pencil_ld<N>(), +1>(s, p, (threadIdx.x + k * 256) / G, v[k]);
         __syncthreads();
         fft_pencils_to<C, N, pencil_ld<N>(), G, +1, 256, true, true>(s, tws, G, [&](int q, int i, C val) {
             if (c0 + q < P.ncols) o[(int64_t)i * plane + cl[c0 + q]] = val;
@@ -293,24 +312,27 @@ __global__ __launch_bounds__(256) void k_inv_y_prune(const cplx<R> *__restrict__
         // touch consecutive columns xi.
         constexpr int NB1 = N / 8, PER1 = G * NB1 / 256;
         static_assert((G * NB1) % 256 == 0, "first-pass tasks must fill the block");
+        // this thread's column p = tid % G is the same for all its tasks
+        const int p = threadIdx.x % G;
+        const int c = c0 + p;
+        const int nz = c / Wp, xi = c % Wp;
+        const bool live = c < ncols && xi < W;
+        const int mx = xi - Rr;
+        const C *col = a + (int64_t)nz * plane + xi;
+        C v[PER1][8];
 #pragma unroll
-        for (int k = 0; k < PER1; ++k) {
-            const int task = threadIdx.x + k * 256;
-            const int p = task % G, jj = task / G;
-            const int c = c0 + p;
-            const int nz = c / Wp, xi = c % Wp;
-            const bool live = c < ncols && xi < W;
-            const int mx = xi - Rr;
-            const C *col = a + (int64_t)nz * plane + xi;
-            C v[8];
+        for (int k = 0; k < PER1; ++k) {             // all loads in flight first
+            const int jj = (threadIdx.x + k * 256) / G;
 #pragma unroll
             for (int t = 0; t < 8; ++t) {
                 const int my = signed_freq(jj + t * NB1, N);
-                v[t] = C{R(0), R(0)};
-                if (live && my >= -Rr && my <= Rr && my * my + mx * mx < P.g.hmax) v[t] = col[(int64_t)(my + Rr) * Wp];
+                v[k][t] = C{R(0), R(0)};
+                if (live && my >= -Rr && my <= Rr && my * my + mx * mx < P.g.hmax) v[k][t] = col[(int64_t)(my + Rr) * Wp];
             }
-            first_pass_butterfly<C, N, pencil_ld<N>(), +1>(s, p, jj, v);
         }
+#pragma unroll
+        for (int k = 0; k < PER1; ++k)
+            first_pass_butterfly<C, N, pencil_ld<N>(), +1>(s, p, (threadIdx.x + k * 256) / G, v[k]);
         __syncthreads();
         fft_pencils_to<C, N, pencil_ld<N>(), G, +1, 256, true, true>(s, tws, G, [&](int p, int i, C val) {
             const int c = c0 + p;
