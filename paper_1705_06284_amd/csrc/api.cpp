@@ -188,9 +188,21 @@ void build_pairs(bispec_plan_s &p) {
         g.Wp = (g.W + 15) / 16 * 16;
         const int q = (int)p.pairs.size();
         p.col_off.push_back((int)p.cols.size());
-        for (int my = -r; my <= r; ++my)
+        // Pass Z columns: the disk m_y^2 + m_x^2 < hmax, each m_y row widened
+        // to whole 16-column groups (128-byte aligned runs of the z-box
+        // rows, so its stores fill whole lines); the extra columns hold no
+        // shell mode and transform to zeros that pass Y never reads.
+        for (int my = -r; my <= r; ++my) {
+            int xa = r + 1, xb = -r - 1;
             for (int mx = -r; mx <= r; ++mx)
-                if (my * my + mx * mx < g.hmax) p.cols.push_back((my + r) * g.Wp + (mx + r));
+                if (my * my + mx * mx < g.hmax) {
+                    xa = std::min(xa, mx);
+                    xb = std::max(xb, mx);
+                }
+            if (xa > xb) continue;
+            const int c0 = (xa + r) / 16 * 16, c1 = (xb + r + 1 + 15) / 16 * 16;
+            for (int xi = c0; xi < c1; ++xi) p.cols.push_back((my + r) * g.Wp + xi);
+        }
         p.col_n.push_back((int)p.cols.size() - p.col_off.back());
         for (int c0 = 0; c0 < p.col_n.back(); c0 += G) p.ztab.push_back(int2{q, c0});
         for (int c0 = 0; c0 < p.n * g.Wp; c0 += G) p.ytab.push_back(int2{q, c0});
