@@ -334,10 +334,12 @@ __global__ __launch_bounds__(256) void k_inv_y_prune(const cplx<R> *__restrict__
         for (int k = 0; k < PER1; ++k)
             first_pass_butterfly<C, N, pencil_ld<N>(), +1>(s, p, (threadIdx.x + k * 256) / G, v[k]);
         __syncthreads();
+        // the row padding xi >= W is written too (zeros: no input there), so
+        // that every store fills whole 128-byte lines
         fft_pencils_to<C, N, pencil_ld<N>(), G, +1, 256, true, true>(s, tws, G, [&](int p, int i, C val) {
             const int c = c0 + p;
             const int nz = c / Wp, xi = c % Wp;
-            if (c < ncols && xi < W) o[((int64_t)nz * N + i) * Wp + xi] = val;
+            if (c < ncols) o[((int64_t)nz * N + i) * Wp + xi] = val;
         });
     } else {
         constexpr int PER = G * N / 256;
