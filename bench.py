@@ -243,6 +243,22 @@ def main():
         out["roofline"] = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                            "frac": ach / HBM_PEAK_GBS, "traffic": None, "kernel": "inverse FFT stage"}
 
+    # tail kernel alone, in triangles/s (the contraction-only rate)
+    out["tail_triangles_per_s"] = ntri * bsz / (stages["contract"] * 1e-3) if stages["contract"] > 0 else None
+
+    # measured HBM copy rate on this machine (device-to-device copy of 512 MiB)
+    src = torch.ones(1 << 27, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    out["hbm_copy_GBps"] = 5 * 2 * src.numel() * 4 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
+
     # the same steps replayed from a captured HIP graph (no stage events)
     plan.set_precision("split_bf16")
     plan.graph(True)

@@ -5,12 +5,15 @@
 //
 //     G[(i,j), k] = sum_n (F_i F_j)(n) F_k(n),
 //
-// a GEMM whose reduction dimension is the grid.  Rows are the pair products
-// (i,j), i <= j < nb, followed by rows (b, ONE) whose product is F_b itself,
-// so that G[(b, ONE), b] = sum_n F_b^2 gives the power-spectrum numerator of
-// Eq. (Jeong_PS).  Columns are the bin fields F_k, k < 32.  An optional extra
-// tile holds the collapsed p = 4 numerators sum_n F_a^2 F_b^2 (rows F_a^2,
-// columns F_b^2).
+// a GEMM whose reduction dimension is the grid.  Rows are pair products
+// (x,y): the (b,b) pairs first (pair tile 0 holds row (r,r) in lane r), then a
+// cover of the requested triplets chosen on the host (each triplet is read
+// from one of its three pairs), then rows (b, ONE) only when nb = 32.
+// Columns are the bin fields F_k, k < 32; column nb < 32 is a field of ones,
+// so G[(b,b), nb] = sum_n F_b^2 is the power-spectrum numerator of
+// Eq. (Jeong_PS).  An optional extra tile holds the collapsed p = 4
+// numerators sum_n F_a^2 F_b^2 (rows F_a^2, columns F_b^2), issued from the A
+// operand of pair tile 0.
 //
 // MODE_SPLIT: each FP32 operand x is split into x_hi = bf16_rne(x) and
 // x_lo = bf16_rne(x - x_hi) (the difference is exact in FP32); the product
@@ -46,16 +49,18 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 constexpr int PG_TK_TAIL = 512;           // grid points per LDS tile of the fused tail
 // Block shapes of the fused tail (threads, output tiles per wave, points per
 // LDS tile; tiles are at least one x-row of N points):
-//   wide: 1024 threads, one tile per wave, 512 points (up to 16 tiles, 4
-//         waves per SIMD);
-//   deep: 512 threads, up to three tiles per wave, 512 points;
+//   wide: 1024 threads, one tile per wave, 512 points (up to 16 pair
+//         tiles, 4 waves per SIMD);
+//   deep: 512 threads, up to three tiles per wave, 512 points, next tile
+//         prefetched into registers;
 //   twin: 512 threads, one tile per wave, 256 points (N <= 256, up to 8
-//         tiles): half the LDS of the others, so two blocks share a CU and
-//         one block's transforms overlap the other's contraction.
+//         pair tiles): half the LDS of the others, so two blocks share a CU
+//         and one block's transforms overlap the other's contraction.
 constexpr int PG_NT_WIDE = 1024, PG_MAXT_WIDE = 1;
 constexpr int PG_NT_DEEP = 512, PG_MAXT_DEEP = 3;
 constexpr int PG_NT_TWIN = 512, PG_MAXT_TWIN = 1, PG_TK_TWIN = 256;
 constexpr bool PG_TWIN_PREFETCH = false;   // the co-resident block hides the loads
+constexpr bool PG_WIDE_PREFETCH = false;   // the prefetch registers cost more (spills) than they hide
 constexpr int PG_FLUSH_POINTS = 4096;     // FP32-mode accumulation span before an FP64 flush
 constexpr int PG_ZERO = PG_ROW_ZERO;      // field row of zeros (padding rows)
 constexpr int PG_ONE = PG_ROW_ONE;        // field row of ones (F_b * 1 rows)
@@ -510,7 +515,7 @@ hipError_t launch_tail_m(const float2 *bc, const TailPairs &tp, int n, int nb, i
         constexpr int TKW = NN >= PG_TK_TAIL ? NN : PG_TK_TAIL;
         const int per_w = (int)((int64_t)per * PG_TK_TAIL / TKW);
         if (sh == PG_SHAPE_WIDE)
-            hipLaunchKernelGGL((k_tail<MODE, WANT_T, NN, PG_NT_WIDE, PG_MAXT_WIDE, PG_TK_TAIL, 4, true>), dim3(nblk, batch),
+            hipLaunchKernelGGL((k_tail<MODE, WANT_T, NN, PG_NT_WIDE, PG_MAXT_WIDE, PG_TK_TAIL, 4, PG_WIDE_PREFETCH>), dim3(nblk, batch),
                                dim3(PG_NT_WIDE), 0, st, bc, tp, nb, pairs, n_mtile, tw, per_w, ks, partial);
         else if (sh == PG_SHAPE_DEEP)
             hipLaunchKernelGGL((k_tail<MODE, WANT_T, NN, PG_NT_DEEP, PG_MAXT_DEEP, PG_TK_TAIL, 2, true>), dim3(nblk, batch),
