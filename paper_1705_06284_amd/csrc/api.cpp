@@ -87,13 +87,7 @@ Layout make_layout(const bispec_plan_s &p, int batch) {
     L.partial = off;      off = align_up(off + sizeof(double) * (size_t)p.nblk * p.terms.size() * batch);
     L.pg_partial = off;
     if (p.mfma_ok) {
-        // the largest partial set over both block shapes, with and without T
-        size_t per_blk = 0;
-        for (int t = 0; t < 2; ++t)
-            for (int sh : {PG_SHAPE_DEEP, PG_SHAPE_WIDE, PG_SHAPE_TWIN})
-                per_blk = std::max(per_blk, pgram_partial_doubles(p.n_mtile, t != 0) *
-                                                (size_t)tail_ksplit(p.n, p.n_mtile, t != 0, sh));
-        off = align_up(off + sizeof(double) * per_blk * p.nblk_pg_max * batch);
+        off = align_up(off + sizeof(double) * pgram_partial_doubles(p.n_mtile, true) * p.nblk_pg_max * batch);
     }
     L.pg_dense = off;
     if (p.mfma_ok) off = align_up(off + sizeof(double) * pgram_partial_doubles(p.n_mtile, true) * batch);
@@ -786,8 +780,7 @@ bispec_status run_estimate_body(bispec_plan_s &p, const float *delta, int batch,
                        (const uchar2 *)(ws + L.pg_pairs), p.n_mtile, tw, p.nblk_pg, pg, p.stream, p.tail_shape));
         const int64_t n_dense = (int64_t)pgram_partial_doubles(p.n_mtile, t_mfma);
         stamp(p, 3);
-        CK(launch_reduce_dense(pg, p.nblk_pg * tail_ksplit(n, p.n_mtile, t_mfma, p.tail_shape), n_dense, batch, dense,
-                               (double *)(ws + L.pg_tmp), p.stream));
+        CK(launch_reduce_dense(pg, p.nblk_pg, n_dense, batch, dense, (double *)(ws + L.pg_tmp), p.stream));
         if (first < last) {
             s = finalize_range(p, true, dense, 1, n_dense, first, last, batch, P, B, T);
             if (s != BISPEC_OK) return s;
@@ -980,9 +973,10 @@ bispec_status bispec_autotune(bispec_plan_t plan, const float *delta, int32_t *n
             CK(hipEventCreate(&e1));
             // candidates: the wide, twin and deep shapes (those that fit the
             // tile count) at the default block count and two and four times
-            // it, each timed as the median of five launches after one
-            // warm-up; a later candidate must win by 3 % to be kept (the
-            // first ones write and reduce fewer partial tiles)
+            // it, each timed (tail kernel plus the reduction of its partials)
+            // as the median of five runs after one warm-up; a later candidate
+            // must win by 3 % to be kept (the first ones write and reduce
+            // fewer partial tiles)
             float best = 1e30f;
             int best_nblk = p.nblk_pg;
             int best_shape = p.tail_shape;
@@ -1002,6 +996,9 @@ bispec_status bispec_autotune(bispec_plan_t plan, const float *delta, int32_t *n
                         CK(launch_tail(mode, t, (const float2 *)(ws + L.bc), tp, n, p.nb, 1,
                                        (const uchar2 *)(ws + L.pg_pairs), p.n_mtile, (const float2 *)(ws + L.tw),
                                        nb, (double *)(ws + L.pg_partial), p.stream, sh));
+                        CK(launch_reduce_dense((const double *)(ws + L.pg_partial), nb,
+                                               (int64_t)pgram_partial_doubles(p.n_mtile, t), 1,
+                                               (double *)(ws + L.pg_dense), (double *)(ws + L.pg_tmp), p.stream));
                         CK(hipEventRecord(e1, p.stream));
                         CK(hipEventSynchronize(e1));
                         CK(hipEventElapsedTime(&ms[rep], e0, e1));

@@ -42,8 +42,7 @@ hipError_t launch_finalize(const double *partial, int nblk, int nterm, int batch
 
 // Product-Gram contraction on MFMA (mfma.hip).  pairs: [n_mtile*32] row
 // factors (field row indices; 32 = zeros, 33 = ones); column nb < 32 is a
-// field of ones.  partial: [batch][nblk * ksplit][n_mtile + want_t][32][32]
-// FP64.
+// field of ones.  partial: [batch][nblk][n_mtile + want_t][32][32] FP64.
 constexpr int PG_MODE_F32 = 0;
 constexpr int PG_MODE_SPLIT = 1;
 constexpr int PG_ROW_ZERO = 32;
@@ -72,8 +71,8 @@ hipError_t launch_tail(int mode, bool want_t, const float2 *bc, const TailPairs 
                        hipStream_t st, int shape);
 bool tail_shape_fits(int n, int n_mtile, bool want_t, int shape);
 int tail_shape(int n, int n_mtile, bool want_t, int shape);
-// K parts per output tile of the launched shape: each block writes
-// tail_ksplit(...) partial sets of n_mtile + want_t tiles.
+// K parts per pair tile of the launched shape (summed inside the block:
+// each block writes one partial set of n_mtile + want_t tiles).
 int tail_ksplit(int n, int n_mtile, bool want_t, int shape);
 // dense[map][e] = sum over the nblk partial sets; tmp holds
 // PG_REDUCE_SEGS * n_dense * batch doubles of segment sums (or null: one pass).

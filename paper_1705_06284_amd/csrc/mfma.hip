@@ -210,28 +210,51 @@ struct PgState {
         }
     }
 
-    // Partials of block blk: [ksplit][n_mtile + WANT_T][32][32]; the p = 4
-    // tile is tile n_mtile.
-    __device__ __forceinline__ void write(double *__restrict__ partial, int64_t blk, int n_mtile, int col,
-                                          int half) {
+    // The K parts of a tile are summed inside the block: parts 1..ksplit-1
+    // leave their sums in scr ([ksplit-1][n_mtile + WANT_T][32][32] FP32,
+    // over the LDS buffers once every tile is done), then part 0 adds them in
+    // order and writes the block's FP64 partials [n_mtile + WANT_T][32][32]
+    // (the p = 4 tile is tile n_mtile).  Called by every thread.
+    __device__ __forceinline__ void write(double *__restrict__ partial, int64_t blk, int n_mtile, int col, int half,
+                                          float *scr) {
         const int n_out = n_mtile + (WANT_T ? 1 : 0);
-        double *base = partial + (blk * ksplit + kpart) * n_out * 1024;
+        auto own = [&](int t, int r) -> double {
+            return (MODE == PG_MODE_F32 ? dacc[t < DT ? t : 0][r] : 0.0) + (double)acc[t][r];
+        };
+        auto own_t = [&](int r) -> double { return (MODE == PG_MODE_F32 ? dacc[DT - 1][r] : 0.0) + (double)acct[r]; };
+        __syncthreads();
+        if (kpart > 0) {
+            float *o = scr + (int64_t)(kpart - 1) * n_out * 1024;
 #pragma unroll
-        for (int t = 0; t < MAXT; ++t) {
-            if (tile_of[t] < 0) continue;
-            double *out = base + tile_of[t] * 1024;
+            for (int t = 0; t < MAXT; ++t) {
+                if (tile_of[t] < 0) continue;
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int row = 8 * (r >> 2) + 4 * half + (r & 3);
-                out[row * 32 + col] = (MODE == PG_MODE_F32 ? dacc[t < DT ? t : 0][r] : 0.0) + (double)acc[t][r];
+                for (int r = 0; r < 16; ++r)
+                    o[tile_of[t] * 1024 + (8 * (r >> 2) + 4 * half + (r & 3)) * 32 + col] = (float)own(t, r);
+            }
+            if (WANT_T && t_here) {
+#pragma unroll
+                for (int r = 0; r < 16; ++r)
+                    o[n_mtile * 1024 + (8 * (r >> 2) + 4 * half + (r & 3)) * 32 + col] = (float)own_t(r);
             }
         }
-        if (WANT_T && t_here) {
-            double *out = base + n_mtile * 1024;
+        __syncthreads();
+        if (kpart == 0) {
+            double *base = partial + blk * n_out * 1024;
+            auto put = [&](int tile, int r, double v) {
+                const int e = tile * 1024 + (8 * (r >> 2) + 4 * half + (r & 3)) * 32 + col;
+                for (int k = 1; k < ksplit; ++k) v += (double)scr[(int64_t)(k - 1) * n_out * 1024 + e];
+                base[e] = v;
+            };
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int row = 8 * (r >> 2) + 4 * half + (r & 3);
-                out[row * 32 + col] = (MODE == PG_MODE_F32 ? dacc[DT - 1][r] : 0.0) + (double)acct[r];
+            for (int t = 0; t < MAXT; ++t) {
+                if (tile_of[t] < 0) continue;
+#pragma unroll
+                for (int r = 0; r < 16; ++r) put(tile_of[t], r, own(t, r));
+            }
+            if (WANT_T && t_here) {
+#pragma unroll
+                for (int r = 0; r < 16; ++r) put(n_mtile, r, own_t(r));
             }
         }
     }
@@ -416,7 +439,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MINW))) void
             }
         }
     }
-    st.write(partial, (int64_t)map * gridDim.x + blockIdx.x, n_mtile, col, half);
+    st.write(partial, (int64_t)map * gridDim.x + blockIdx.x, n_mtile, col, half, reinterpret_cast<float *>(ubuf));
 }
 
 // Fixed-order compensated FP64 sum over blocks of every dense tile entry,
@@ -488,17 +511,32 @@ int tail_shape(int n, int n_mtile, bool want_t, int shape) {
     return tail_shape_fits(n, n_mtile, want_t, PG_SHAPE_WIDE) ? PG_SHAPE_WIDE : PG_SHAPE_DEEP;
 }
 
+// Bytes of the FFT buffer of a shape (the LDS the K-part sums may reuse).
+int tail_fft_bytes(int n, int shape) {
+    const int tkp = shape == PG_SHAPE_TWIN ? PG_TK_TWIN : PG_TK_TAIL;
+    const int tk = n >= tkp ? n : tkp;
+    return 16 * (tk / n) * (n + n / 8 + 1) * 8;
+}
+
 int tail_ksplit(int n, int n_mtile, bool want_t, int shape) {
     const int n_out = n_mtile;
     const int sh = tail_shape(n, n_mtile, want_t, shape);
     const int nt = sh == PG_SHAPE_WIDE ? PG_NT_WIDE : sh == PG_SHAPE_DEEP ? PG_NT_DEEP : PG_NT_TWIN;
     const int maxt = sh == PG_SHAPE_WIDE ? PG_MAXT_WIDE : sh == PG_SHAPE_DEEP ? PG_MAXT_DEEP : PG_MAXT_TWIN;
     const int waves = nt / 64, cap = maxt * waves;
+    // the sums of K parts 1.. must fit the FFT buffer
+    const int scr_tiles = tail_fft_bytes(n, sh) / 4096;
+    const int parts = n_mtile + (want_t ? 1 : 0);
+    auto fits = [&](int k) { return (k - 1) * parts <= scr_tiles; };
     // one item per wave: any count of K parts; several: a power of two that
     // divides the wave count (all items of a wave then share one K part)
-    if (maxt == 1) return std::max(1, std::min(waves / n_out, PG_TK_TAIL / 32));
+    if (maxt == 1) {
+        int k = std::max(1, std::min(waves / n_out, PG_TK_TAIL / 32));
+        while (k > 1 && !fits(k)) --k;
+        return k;
+    }
     int k = 1;
-    while (2 * k <= waves && n_out * 2 * k <= cap) k *= 2;
+    while (2 * k <= waves && n_out * 2 * k <= cap && fits(2 * k)) k *= 2;
     return k;
 }
 
