@@ -246,19 +246,6 @@ def main():
     # tail kernel alone, in triangles/s (the contraction-only rate)
     out["tail_triangles_per_s"] = ntri * bsz / (stages["contract"] * 1e-3) if stages["contract"] > 0 else None
 
-    # measured HBM copy rate on this machine (device-to-device copy of 512 MiB)
-    src = torch.ones(1 << 27, dtype=torch.float32, device=dev)
-    dst = torch.empty_like(src)
-    dst.copy_(src)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(5):
-        dst.copy_(src)
-    e1.record()
-    torch.cuda.synchronize()
-    out["hbm_copy_GBps"] = 5 * 2 * src.numel() * 4 / (e0.elapsed_time(e1) * 1e-3) / 1e9
-    del src, dst
-
     # the same steps replayed from a captured HIP graph (no stage events)
     plan.set_precision("split_bf16")
     plan.graph(True)
@@ -308,6 +295,22 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         out["copy_calibration"] = {"bytes_read": 4 * cnt, "bytes_written": 4 * cnt, "launches": 5}
+        del src, dst
+
+    # measured HBM copy rate on this machine (device-to-device copy of 512 MiB),
+    # after the GPU measurements so that it does not disturb them (not in
+    # counter runs, whose last copies are the calibration)
+    if args.copy_calibration <= 0:
+        src = torch.ones(1 << 27, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(5):
+            dst.copy_(src)
+        e1.record()
+        torch.cuda.synchronize()
+        out["hbm_copy_GBps"] = 5 * 2 * src.numel() * 4 / (e0.elapsed_time(e1) * 1e-3) / 1e9
         del src, dst
 
     if not args.no_cpu_baseline:
