@@ -228,10 +228,8 @@ std::vector<PairDev> pair_devs(const bispec_plan_s &p) {
     return v;
 }
 
-// Rows of the product-Gram: pairs (i,j), i <= j, ordered by j then i; then
-// (b, ONE) rows; padding rows (ZERO, ZERO) up to a multiple of 32.  A term's
-// dense index in a block's tiles is tile*1024 + row_in_tile*32 + column.
-// Rows of the product-Gram.  Every (b,b) row is kept; when nb < 32 column nb
+// Rows of the product-Gram.  Every (b,b) row is kept (rows 0..nb-1, so pair
+// tile 0 holds row (r,r) in lane r, which the p = 4 tile relies on); when nb < 32 column nb
 // is a field of ones, so G[(b,b), nb] is the power-spectrum numerator, else
 // rows (b, ONE) are added for it.  A triplet a <= b <= c can be read from
 // G[(x,y), z] for any of its three pairs (x,y); the pair rows are a greedy
@@ -240,7 +238,8 @@ std::vector<PairDev> pair_devs(const bispec_plan_s &p) {
 // covered by its (b,b) row, and among three distinct bins two share a
 // parity, so the equal-parity pairs (about nb^2/4) always suffice; the
 // greedy cover is smaller (128 rows instead of 156 for 1541 triplets of 24
-// linear bins).
+// linear bins).  Padding rows (ZERO, ZERO) fill the last tile.  A term's
+// dense index in a block's tiles is tile*1024 + row_in_tile*32 + column.
 void build_pgram_tables(bispec_plan_s &p) {
     const int nb = p.nb;
     p.mfma_ok = nb <= 32;
