@@ -230,11 +230,13 @@ __device__ __forceinline__ void first_pass_butterfly(C *s, int p, int jj, C *v) 
     for (int u = 0; u < 8; ++u) s[p * LD + pad_idx(8 * jj + u)] = v[u];
 }
 
-// Pencils per block: at least one butterfly task per thread, at most 64 KiB
-// of LDS for the pencil tile, and no more than the N^2 pencils of one axis.
+// Pencils per block: at least one butterfly task per thread, at most 80 KiB
+// of LDS for the pencil tile (16 FP32 pencils of 512: the pencil-fastest
+// stores of the strided passes then fill whole 128-byte lines), and no more
+// than the N^2 pencils of one axis.
 template <typename R, int N> constexpr int pencils_per_block() {
     constexpr int bytes = (int)sizeof(R) * 2;
-    constexpr int by_lds = 65536 / (pencil_ld<N>() * bytes);
+    constexpr int by_lds = 81920 / (pencil_ld<N>() * bytes);
     constexpr int by_tasks = (2048 + N - 1) / N;
     constexpr int want = by_tasks > 16 ? by_tasks : 16;
     constexpr int gl = want < by_lds ? want : by_lds;
