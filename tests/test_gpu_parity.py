@@ -117,11 +117,14 @@ def test_batch_equals_single_maps(binding):
     lo, hi = synth.linear_bins(n, 5)
     maps = np.stack([synth.lognormal_field(n, 1.5, 1.0, seed=s) for s in (1, 2, 3)])
     _say("batch of 3 vs single")
-    plan = binding.Plan(n, lo, hi, precision="fp32", max_batch=3)
-    P, B, T = plan.polyspec(maps)
-    for i in range(3):
-        p1, b1, t1 = plan.polyspec(maps[i])
-        assert torch.equal(B[i], b1[0]) and torch.equal(P[i], p1[0]) and torch.equal(T[i], t1[0])
+    for prec in ("fp32", "split_bf16"):
+        plan = binding.Plan(n, lo, hi, precision=prec, max_batch=3)
+        for shape in (binding.TAIL_WIDE, binding.TAIL_TWIN, binding.TAIL_DEEP):
+            plan.set_tuning(32, shape)             # 32^3: 64 units of 512 points, 32 blocks
+            P, B, T = plan.polyspec(maps)
+            for i in range(3):
+                p1, b1, t1 = plan.polyspec(maps[i])
+                assert torch.equal(B[i], b1[0]) and torch.equal(P[i], p1[0]) and torch.equal(T[i], t1[0]), (prec, shape)
 
 
 def test_overlapping_bins_and_explicit_zero_count(binding):
