@@ -64,9 +64,11 @@ typedef enum {
 
 /* Arithmetic of the contraction sum_n F_i F_j F_k (and of the P and T sums).
  * The FFTs are FP32 in every mode; cross-block sums and the normalisation are
- * FP64 in every mode.  Modes 0 and 1 evaluate the dense product-Gram
- * G[(i,j),k] = sum_n (F_i F_j) F_k on the matrix cores and need n_bins <= 32;
- * with more bins they run as mode 2. */
+ * FP64 in every mode.  Modes 0 and 1 evaluate the product-Gram
+ * G[(x,y),k] = sum_n (F_x F_y) F_k on the matrix cores, for every column k
+ * and for pair rows (x,y) that cover the requested triplets (each triplet is
+ * read from one of its three pairs); they need n_bins <= 32, and with more
+ * bins they run as mode 2. */
 enum {
     BISPEC_FP32 = 0,        /* product-Gram, FP32 MFMA, FP32 accumulation            */
     BISPEC_SPLIT_BF16 = 1,  /* product-Gram, BF16 MFMA on hi/lo splits (3 products),
