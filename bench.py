@@ -38,6 +38,8 @@ def parse():
     ap.add_argument("--cpu-budget", type=float, default=8e9,
                     help="pair steps of the direct-sum oracle sample")
     ap.add_argument("--no-serving", action="store_true", help="skip the request-stream measurement")
+    ap.add_argument("--no-onepixel", action="store_true",
+                    help="skip the one-pixel-shell measurement with configuration binning")
     ap.add_argument("--serving-requests", type=int, default=2000)
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shape")
     ap.add_argument("--all-tunings", action="store_true",
@@ -95,6 +97,50 @@ def timed_steps(torch, step, steps, stream):
     t1 = time.perf_counter()
     lat = [evs[i].elapsed_time(evs[i + 1]) for i in range(steps)]
     return t1 - t0, lat
+
+
+def onepixel_run(torch, binding, synth, np, dev, stream, steps):
+    """Narrow shells (one k_f, 63 bins at 128^3; more than 32 bins run the
+    vector-ALU contraction) and the table B(theta) at k2 = 2 k1 for k1 = 2..21
+    (20 cos theta bins each) from bispec_rebin."""
+    wl = "onepix_128_lognormal"
+    n = synth.WORKLOADS[wl]["n"]
+    lo, hi = synth.workload_bins(wl)
+    plan = binding.Plan(n, lo, hi, quads=[(0, 0, 0, 0)], stream=stream, device=dev)
+    d = torch.from_numpy(synth.workload_field(wl)).to(dev).unsqueeze(0)
+    B = torch.empty(1, plan.n_tri, dtype=torch.float64, device=dev)
+    groups = []
+    for b1 in range(1, 21):
+        g, _ = plan.theta_groups(b1, 2 * b1 + 1, 20)
+        groups.append(torch.from_numpy(g).to(dev))
+    tab = torch.empty(len(groups), 20, dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+
+    def est():
+        binding.check(binding.polyspec_estimate(plan.handle, binding._ptr(d), 1, None, binding._ptr(B), None),
+                      "polyspec_estimate")
+
+    def rebin():
+        for i, g in enumerate(groups):
+            binding.check(binding.bispec_rebin(plan.handle, binding._ptr(B), 1, binding._ptr(g), 20,
+                                               binding._ptr(tab[i])), "bispec_rebin")
+
+    for _ in range(2):
+        est()
+        rebin()
+    k = max(3, steps // 2)
+    plan.timing_read()
+    plan.timing(True)
+    we, _ = timed_steps(torch, est, k, stream)
+    plan.timing(False)
+    stages, calls = plan.timing_read()
+    wr, _ = timed_steps(torch, rebin, k, stream)
+    return {"workload": wl, "n": n, "bins": plan.n_bins, "triplets": plan.n_tri,
+            "contraction": "FP32 vector ALU (bin fields in HBM)",
+            "ms_per_map": 1e3 * we / k, "triangles_per_s": plan.n_tri * k / we,
+            "stages_ms": {key: v / max(calls, 1) for key, v in stages.items()},
+            "theta_table": {"configs": "k2 = 2 k1, k1 = 2..21 k_f, 20 bins of cos theta",
+                            "ms": 1e3 * wr / k, "groups": int(np.isfinite(tab.cpu().numpy()).sum())}}
 
 
 def percentile(xs, q):
@@ -267,6 +313,9 @@ def main():
         out["split_vs_fp32"] = {"end_to_end": out["fp32_path"]["ms_per_step"] / out["ms_per_step"],
                                 "contraction": st32["contract"] / max(stages["contract"], 1e-9)}
         plan.set_precision("split_bf16")
+
+    if not args.no_onepixel:
+        out["onepixel_128"] = onepixel_run(torch, binding, synth, np, dev, stream, args.steps)
 
     if not args.no_serving:
         out["serving"] = serving_run(args.serving_requests)

@@ -194,6 +194,42 @@ bispec_status bispec_set_tuning(bispec_plan_t plan, int32_t nblk, int32_t shape)
  * of the triangle inequality with few closed triples have large kappa. */
 bispec_status bispec_plan_condition(bispec_plan_t plan, double *kappa_out /*[n_tri]*/);
 
+/* Configuration binning of narrow-shell measurements (Section 3.2 and the
+ * Conclusion: measure B with shells one k_f wide, then bin further).
+ *
+ * bispec_theta_groups assigns the plan's triplets to bins of the angle theta
+ * between the sides k1 and k2 of the triangle, at fixed k1 in bin b1 and k2
+ * in bin b2 (Section 3, Fig. theta_illus: k3 = -k1 - k2 closes the triangle;
+ * Eqs. ratio and alpha fix k2/k1 and the angle).  Triplet t belongs when its
+ * three bins are b1, b2 and one more bin b3 (as a multiset); then, with bin
+ * centres c = (lo + hi) / 2,
+ *     cos theta_t = (c1^2 + c2^2 - c3^2) / (2 c1 c2)      (law of cosines)
+ * and group_out[t] = floor((cos theta_t + 1) n_cos / 2), clamped to n_cos - 1:
+ * n_cos equal bins of cos theta over [-1, 1] (n_cos = 20 gives the paper's
+ * +-0.05).  group_out[t] = -1 when t does not hold b1 and b2, or when the
+ * centres form no triangle (|cos theta| > 1).  cos_out (or NULL) receives
+ * cos theta_t, NaN where t does not hold b1 and b2.  Host only: group_out
+ * and cos_out are host [n_tri] arrays; no workspace is needed.
+ * BISPEC_E_BIN_RANGE for a bin index outside the plan, BISPEC_E_INVALID for
+ * n_cos < 1 or a NULL group_out.
+ *
+ * bispec_rebin averages B over groups of triplets, weighted by the FFT
+ * triangle counts N_t of the plan:
+ *     out[map][g] = sum_{t: group[t] = g} N_t B[map][t] / sum_{t: group[t] = g} N_t
+ * which is the estimator of Eq. Jeong_BI over the union of the groups'
+ * closed triangles (the sums S_t of disjoint triangle sets add).  B: device
+ * [batch][n_tri] FP64 as written by bispec_estimate; group: device [n_tri]
+ * int32 (values outside [0, n_group) join no group); out: device
+ * [batch][n_group] FP64, NaN for a group without a triplet of non-zero
+ * count.  Stream-ordered on the plan's stream; the counts live in the
+ * workspace, so it needs one attached (BISPEC_E_NO_WORKSPACE).  The sums run
+ * in a fixed order (bitwise reproducible).  BISPEC_E_INVALID for NULL
+ * pointers, n_group < 1, or batch outside [1, max_batch]. */
+bispec_status bispec_theta_groups(bispec_plan_t plan, int32_t b1, int32_t b2, int32_t n_cos,
+                                  int32_t *group_out /*[n_tri]*/, double *cos_out /*[n_tri] or NULL*/);
+bispec_status bispec_rebin(bispec_plan_t plan, const double *B, int32_t batch, const int32_t *group,
+                           int32_t n_group, double *out);
+
 /* Graph replay.  While enabled, polyspec_estimate (and bispec_estimate,
  * trispec_estimate) captures its launch sequence on the plan's stream into a
  * HIP graph the first time it sees a (delta, P, B, T, batch, precision)

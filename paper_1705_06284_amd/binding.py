@@ -64,6 +64,8 @@ _SIGS = {
     "bispec_autotune": [_vp, _vp, _ip, _ip],
     "bispec_set_tuning": [_vp, _i32, _i32],
     "bispec_plan_condition": [_vp, _dp],
+    "bispec_theta_groups": [_vp, _i32, _i32, _i32, _ip, _dp],
+    "bispec_rebin": [_vp, _vp, _i32, _vp, _i32, _vp],
     "bispec_timing_read": [_vp, _dp, _ip],
     "bispec_destroy": [_vp],
 }
@@ -94,6 +96,8 @@ bispec_graph_enable = _lib.bispec_graph_enable
 bispec_autotune = _lib.bispec_autotune
 bispec_set_tuning = _lib.bispec_set_tuning
 bispec_plan_condition = _lib.bispec_plan_condition
+bispec_theta_groups = _lib.bispec_theta_groups
+bispec_rebin = _lib.bispec_rebin
 bispec_timing_read = _lib.bispec_timing_read
 bispec_destroy = _lib.bispec_destroy
 N_STAGES = 4
@@ -248,6 +252,33 @@ class Plan:
     def condition(self):
         out = np.zeros(self.n_tri, np.float64)
         check(bispec_plan_condition(self.handle, out.ctypes.data_as(_dp)), "bispec_plan_condition")
+        return out
+
+    def theta_groups(self, b1, b2, n_cos=20):
+        """(group [n_tri] int32, cos theta [n_tri]) for B(theta) at k1 in bin
+        b1 and k2 in bin b2, as in bispec_theta_groups."""
+        group = np.zeros(self.n_tri, np.int32)
+        cos = np.zeros(self.n_tri, np.float64)
+        check(bispec_theta_groups(self.handle, int(b1), int(b2), int(n_cos), group.ctypes.data_as(_ip),
+                                  cos.ctypes.data_as(_dp)), "bispec_theta_groups")
+        return group, cos
+
+    def rebin(self, B, group, n_group):
+        """Count-weighted averages of B ([batch, n_tri] device FP64) over the
+        groups of triplets (host or device [n_tri] int32): [batch, n_group]."""
+        torch = self._torch
+        if B.dim() == 1:
+            B = B.unsqueeze(0)
+        if B.dtype != torch.float64 or not B.is_cuda or tuple(B.shape[1:]) != (self.n_tri,):
+            raise ValueError("expected B as a [batch, %d] float64 tensor on %s" % (self.n_tri, self.device))
+        B = B.contiguous()
+        g = torch.as_tensor(np.asarray(group, dtype=np.int32) if not isinstance(group, torch.Tensor) else group)
+        g = g.to(device=self.device, dtype=torch.int32).contiguous()
+        if g.numel() != self.n_tri:
+            raise ValueError("expected %d group entries" % self.n_tri)
+        out = self._empty(B.shape[0], int(n_group))
+        torch.cuda.synchronize(self.device)      # B and the group table are ready before the plan's stream reads them
+        check(bispec_rebin(self.handle, _ptr(B), B.shape[0], _ptr(g), int(n_group), _ptr(out)), "bispec_rebin")
         return out
 
     def graph(self, on=True):

@@ -73,6 +73,7 @@ Layout make_layout(const bispec_plan_s &p, int batch) {
     L.tw = off;           off = align_up(off + sizeof(float2) * p.n);
     L.terms = off;        off = align_up(off + sizeof(uchar4) * p.terms.size());
     L.scale = off;        off = align_up(off + sizeof(double) * p.scale.size());
+    L.tcount = off;       off = align_up(off + sizeof(double) * p.tri_count.size());
     L.pg_pairs = off;     off = align_up(off + sizeof(uchar2) * p.pg_pairs.size());
     L.pg_idx = off;       off = align_up(off + sizeof(int) * p.pg_idx.size());
     L.cols = off;         off = align_up(off + sizeof(int) * p.cols.size());
@@ -621,6 +622,9 @@ bispec_status upload_tables(bispec_plan_s &p) {
                       p.stream));
     CK(hipMemcpyAsync(ws + L.scale, p.scale.data(), sizeof(double) * p.scale.size(), hipMemcpyHostToDevice,
                       p.stream));
+    if (!p.tri_count.empty())
+        CK(hipMemcpyAsync(ws + L.tcount, p.tri_count.data(), sizeof(double) * p.tri_count.size(),
+                          hipMemcpyHostToDevice, p.stream));
     CK(hipMemcpyAsync(ws + L.cols, p.cols.data(), sizeof(int) * p.cols.size(), hipMemcpyHostToDevice, p.stream));
     const std::vector<PairDev> pd = pair_devs(p);
     CK(hipMemcpyAsync(ws + L.pd, pd.data(), sizeof(PairDev) * pd.size(), hipMemcpyHostToDevice, p.stream));
@@ -1048,6 +1052,58 @@ bispec_status bispec_plan_condition(bispec_plan_t plan, double *kappa_out) {
         const double c = plan->tri_count[t];
         kappa_out[t] = c > 0 ? std::sqrt(m / (npix * c)) : std::numeric_limits<double>::infinity();
     }
+    return BISPEC_OK;
+}
+
+bispec_status bispec_theta_groups(bispec_plan_t plan, int32_t b1, int32_t b2, int32_t n_cos, int32_t *group_out,
+                                  double *cos_out) {
+    if (!plan || !group_out || n_cos < 1) return BISPEC_E_INVALID;
+    if (b1 < 0 || b1 >= plan->nb || b2 < 0 || b2 >= plan->nb) return BISPEC_E_BIN_RANGE;
+    const int nt = (int)plan->tri.size() / 3;
+    auto centre = [&](int b) { return 0.5 * (plan->lo[b] + plan->hi[b]); };
+    const double c1 = centre(b1), c2 = centre(b2);
+    for (int t = 0; t < nt; ++t) {
+        // take one b1 and one b2 out of the triplet's bins; what is left is k3
+        int rest[3] = {plan->tri[3 * t], plan->tri[3 * t + 1], plan->tri[3 * t + 2]};
+        int left = 3;
+        for (int want : {b1, b2}) {
+            int at = -1;
+            for (int i = 0; i < left; ++i)
+                if (rest[i] == want) at = i;
+            if (at < 0) {
+                left = -1;
+                break;
+            }
+            rest[at] = rest[--left];
+        }
+        group_out[t] = -1;
+        if (cos_out) cos_out[t] = std::numeric_limits<double>::quiet_NaN();
+        if (left != 1) continue;
+        const double c3 = centre(rest[0]);
+        // cos theta = num / den; both are exact for half-integer centres
+        const double num = c1 * c1 + c2 * c2 - c3 * c3, den = 2.0 * c1 * c2;
+        if (cos_out) cos_out[t] = num / den;
+        if (!(num >= -den && num <= den)) continue;
+        int g = (int)std::floor((num / den + 1.0) * 0.5 * n_cos);
+        g = std::min(std::max(g, 0), n_cos - 1);
+        // the rounded quotient can land one group off at an exact edge; group
+        // g holds num / den >= -1 + 2 g / n_cos, i.e. n_cos num >= (2 g - n_cos) den
+        while (g + 1 < n_cos && n_cos * num >= (2.0 * (g + 1) - n_cos) * den) ++g;
+        while (g > 0 && n_cos * num < (2.0 * g - n_cos) * den) --g;
+        group_out[t] = g;
+    }
+    return BISPEC_OK;
+}
+
+bispec_status bispec_rebin(bispec_plan_t plan, const double *B, int32_t batch, const int32_t *group,
+                           int32_t n_group, double *out) {
+    if (!plan || !B || !group || !out || n_group < 1) return BISPEC_E_INVALID;
+    if (batch < 1 || batch > plan->max_batch) return BISPEC_E_INVALID;
+    if (!plan->ws) return BISPEC_E_NO_WORKSPACE;
+    const int nt = (int)plan->tri.size() / 3;
+    const Layout L = make_layout(*plan, plan->max_batch);
+    CK(launch_rebin(B, nt, (const double *)((const char *)plan->ws + L.tcount), group, n_group, batch, out,
+                    plan->stream));
     return BISPEC_OK;
 }
 

@@ -16,6 +16,8 @@
 //                              Jeong_BI, Jeong_gen), per-block FP64 partials
 //   k_finalize                 fixed-order FP64 cross-block sum and the
 //                              normalisation H^p / V over the FFT count
+//   k_rebin                    count-weighted averages of B over groups of
+//                              triplets (configuration binning)
 //   k_shell_hist               modes per shell (wave ballot + popcount)
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -511,6 +513,40 @@ __global__ __launch_bounds__(256) void k_finalize(const double *__restrict__ par
     }
 }
 
+// Further binning of B over groups of triplets (Section 3: measure in narrow
+// shells, then bin the configurations): block (g, map) forms
+// sum_{t: group[t] = g} N_t B[map][t] / sum N_t, the estimator of the union of
+// the group's closed triangles.  Each thread sums a fixed strided subset, the
+// wave and block sums run in a fixed order, so the result is deterministic.
+// Triplets with N_t = 0 (B = NaN) contribute nothing; an empty group is NaN.
+__global__ __launch_bounds__(256) void k_rebin(const double *__restrict__ B, int n_tri,
+                                               const double *__restrict__ count, const int *__restrict__ group,
+                                               int n_group, double *__restrict__ out) {
+    const int g = blockIdx.x, map = blockIdx.y;
+    const double *b = B + (int64_t)map * n_tri;
+    double num = 0.0, den = 0.0;
+    for (int t = threadIdx.x; t < n_tri; t += 256) {
+        const double w = count[t];
+        if (group[t] == g && w > 0.0) {
+            num += w * b[t];
+            den += w;
+        }
+    }
+    num = wave_sum(num);
+    den = wave_sum(den);
+    __shared__ double red[2][4];
+    if ((threadIdx.x & 63) == 0) {
+        red[0][threadIdx.x >> 6] = num;
+        red[1][threadIdx.x >> 6] = den;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const double sn = (red[0][0] + red[0][1]) + (red[0][2] + red[0][3]);
+        const double sd = (red[1][0] + red[1][1]) + (red[1][2] + red[1][3]);
+        out[(int64_t)map * n_group + g] = sd > 0.0 ? sn / sd : __builtin_nan("");
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Modes per shell: each thread classifies one grid mode; a wave ballot and a
 // popcount give the wave's count per bin, one integer atomic per wave.
@@ -674,6 +710,12 @@ hipError_t launch_finalize(const double *partial, int nblk, int nterm, int batch
                            int n0, double *o1, int n1, double *o2, int n2, hipStream_t st) {
     hipLaunchKernelGGL(k_finalize, dim3((nterm + 255) / 256, batch), dim3(256), 0, st, partial, nblk, nterm, scale,
                        o0, n0, o1, n1, o2, n2);
+    return hipGetLastError();
+}
+
+hipError_t launch_rebin(const double *B, int n_tri, const double *count, const int *group, int n_group, int batch,
+                        double *out, hipStream_t st) {
+    hipLaunchKernelGGL(k_rebin, dim3(n_group, batch), dim3(256), 0, st, B, n_tri, count, group, n_group, out);
     return hipGetLastError();
 }
 

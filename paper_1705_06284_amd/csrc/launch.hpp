@@ -83,6 +83,10 @@ hipError_t launch_finalize_gather(const double *partial, int nblk, int64_t blk_s
                                   int batch, const double *scale, double *o0, int n0, double *o1, int n1, double *o2,
                                   int n2, hipStream_t st);
 
+// out[map][g] = sum_{group[t] = g} count[t] B[map][t] / sum count[t] (NaN if empty).
+hipError_t launch_rebin(const double *B, int n_tri, const double *count, const int *group, int n_group, int batch,
+                        double *out, hipStream_t st);
+
 hipError_t launch_shell_hist(int n, int nb, const int *lo2, const int *hi2, unsigned long long *counts,
                              hipStream_t st);
 

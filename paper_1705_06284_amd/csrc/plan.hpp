@@ -71,7 +71,7 @@ namespace bispec {
 
 // Byte offsets of the workspace regions (256-byte aligned).
 struct Layout {
-    size_t tw, terms, scale, pg_pairs, pg_idx, cols, pd, ztab, ytab, mean_partial, mean, spec, abox, bc, fields,
+    size_t tw, terms, scale, tcount, pg_pairs, pg_idx, cols, pd, ztab, ytab, mean_partial, mean, spec, abox, bc, fields,
         partial, pg_partial, pg_dense, pg_tmp, total;
 };
 

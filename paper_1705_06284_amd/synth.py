@@ -143,6 +143,9 @@ WORKLOADS = {
                            bins=("linear", 24)),
     "c4_512_lognormal": dict(n=512, kind="lognormal", spectral_index=1.0, sigma=1.5,
                              seed=4, bins=("linear", 32)),
+    # one-pixel shells up to the 64-bin plan limit, for configuration binning
+    "onepix_128_lognormal": dict(n=128, kind="lognormal", spectral_index=1.5, sigma=1.0,
+                                 seed=2, bins=("unit", 1, 63)),
 }
 
 

@@ -1,0 +1,143 @@
+"""GPU parity of configuration binning (bispec_theta_groups, bispec_rebin).
+
+Narrow (one k_f) shells, measured with the HIP path, then grouped by the
+angle between k1 and k2 and averaged with the triangle counts as weights.
+References: the oracle's exact-rational angle groups (bit-exact), its
+count-weighted average of the oracle's B, and its brute force over the mode
+pairs of the two fixed shells.  Error metric as in the estimator's parity
+tests: |X - X_ref| / max(|X_ref|, X_noise), with the group's noise level
+sqrt(sum_t (noise_t N_t)^2) / sum_t N_t; FP32 1e-5, split-BF16 1e-4.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import oracle  # noqa: E402
+from oracle import configs as oc  # noqa: E402
+from paper_1705_06284_amd import synth  # noqa: E402
+
+TOL = {"fp32": 1e-5, "split_bf16": 1e-4}
+
+
+@pytest.fixture(scope="module")
+def binding():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1705_06284_amd import binding as b
+    return b
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def _group_noise(ref, group, n_group):
+    out = np.full(n_group, np.nan)
+    for g in range(n_group):
+        sel = group == g
+        if ref.count[sel].sum() > 0:
+            out[g] = np.sqrt(np.sum((ref.noise[sel] * ref.count[sel]) ** 2)) / ref.count[sel].sum()
+    return out
+
+
+@pytest.mark.parametrize("prec", ["fp32", "split_bf16"])
+def test_theta_rebin_32_against_brute_force(binding, prec):
+    n = 32
+    lo, hi = synth.unit_bins(1, 15)
+    d = synth.lognormal_field(n, 1.5, 1.0, 11)
+    _say("one-pixel 32^3 rebin %s" % prec)
+    plan = binding.Plan(n, lo, hi, precision=prec, quads=[(0, 0, 0, 0)])
+    _, B, _ = plan.polyspec(d, want_p=False, want_t=False)
+    trip = plan.triplets
+    ref = oracle.bispectrum(d, lo, hi, trip)
+    for b1, b2, n_cos in [(1, 4, 20), (3, 3, 20), (2, 9, 10)]:
+        g, cos = plan.theta_groups(b1, b2, n_cos)
+        og, ocos = oc.theta_groups(lo, hi, trip, b1, b2, n_cos)
+        assert np.array_equal(g, og)
+        assert np.allclose(cos, ocos, rtol=0, atol=1e-15, equal_nan=True)
+        out = plan.rebin(B, g, n_cos).cpu().numpy()[0]
+        bd, cd = oc.theta_direct(d, lo, hi, b1, b2, n_cos)
+        cg = np.array([plan.counts[g == k].sum() for k in range(n_cos)])
+        assert np.array_equal(cg.astype(np.int64), cd)
+        ok = cd > 0
+        assert np.array_equal(np.isfinite(out), ok)
+        noise = _group_noise(ref, og, n_cos)
+        e = np.abs(out[ok] - bd[ok]) / np.maximum(np.abs(bd[ok]), noise[ok])
+        _say("  (%d,%d) %d groups, max err %.2e" % (b1, b2, ok.sum(), e.max()))
+        assert e.max() <= TOL[prec]
+        # the rebinning itself is FP64 arithmetic on the GPU's B
+        own = oc.rebin(B.cpu().numpy(), plan.counts, g, n_cos)[0]
+        assert np.allclose(out[ok], own[ok], rtol=1e-13, atol=0)
+
+
+def test_onepixel_128_valu_and_rebin(binding):
+    wl = "onepix_128_lognormal"
+    n = synth.WORKLOADS[wl]["n"]
+    lo, hi = synth.workload_bins(wl)
+    d = synth.workload_field(wl)
+    assert len(lo) == 63
+    _say("one-pixel 128^3, 63 bins")
+    plan = binding.Plan(n, lo, hi, quads=[(0, 0, 0, 0)], max_batch=2)
+    dd = np.stack([d, synth.lognormal_field(n, 1.5, 1.0, 12)])
+    _, B, _ = plan.polyspec(dd, want_p=False, want_t=False)
+    trip = plan.triplets
+    _say("  %d triplets" % len(trip))
+    # the estimator on narrow shells (more than 32 bins: vector-ALU FP32)
+    Dk = oracle.dft3(oracle.prepare(d))
+    cheap = trip[(trip.max(1) <= 12)]
+    idx = [int(np.flatnonzero((trip == t).all(1))[0]) for t in cheap]
+    ref = oracle.bispectrum(d, lo, hi, cheap, delta_k=Dk)
+    assert np.array_equal(plan.counts[idx].astype(np.int64), ref.count)
+    e = np.abs(B.cpu().numpy()[0][idx] - ref.value) / np.maximum(np.abs(ref.value), ref.noise)
+    _say("  %d sampled triplets, max err %.2e" % (len(cheap), e.max()))
+    assert e.max() <= TOL["fp32"]
+    # B(theta) at k1 = 4, k2 = 8 (bins 3, 7): every member has bins <= 11
+    g, _ = plan.theta_groups(3, 7, 20)
+    og, _ = oc.theta_groups(lo, hi, trip, 3, 7, 20)
+    assert np.array_equal(g, og)
+    mem = np.flatnonzero(g >= 0)
+    assert len(mem) > 0 and trip[mem].max() <= 11
+    out = plan.rebin(B, g, 20).cpu().numpy()
+    refm = oracle.bispectrum(d, lo, hi, trip[mem], delta_k=Dk)
+    want = oc.rebin(refm.value, refm.count, g[mem], 20)[0]
+    ok = np.isfinite(want)
+    assert np.array_equal(np.isfinite(out[0]), ok)
+    noise = _group_noise(refm, g[mem], 20)
+    e = np.abs(out[0][ok] - want[ok]) / np.maximum(np.abs(want[ok]), noise[ok])
+    _say("  B(theta) k2 = 2 k1: %d groups, max err %.2e" % (ok.sum(), e.max()))
+    assert e.max() <= TOL["fp32"]
+    # both maps of the batch, against the FP64 rebinning of the GPU's own B
+    own = oc.rebin(B.cpu().numpy(), plan.counts, g, 20)
+    assert np.allclose(out[:, ok], own[:, ok], rtol=1e-13, atol=0)
+    # an exact edge: bins (14, 27, 40) have centres 15, 28, 41, cos = -4/5
+    g2, _ = plan.theta_groups(14, 27, 20)
+    og2, _ = oc.theta_groups(lo, hi, trip, 14, 27, 20)
+    assert np.array_equal(g2, og2)
+    t = np.flatnonzero((trip == (14, 27, 40)).all(1))
+    assert len(t) == 1 and g2[t[0]] == 2
+    # the group sums run in a fixed order
+    again = plan.rebin(B, g, 20).cpu().numpy()
+    assert np.array_equal(np.isnan(again), np.isnan(out))
+    assert np.array_equal(again[np.isfinite(again)], out[np.isfinite(out)])
+
+
+def test_rebin_argument_errors(binding):
+    n = 16
+    lo, hi = synth.unit_bins(1, 7)
+    plan = binding.Plan(n, lo, hi, quads=[(0, 0, 0, 0)])
+    with pytest.raises(binding.BispecError) as ex:
+        plan.theta_groups(0, 7, 20)
+    assert ex.value.code == -3          # BISPEC_E_BIN_RANGE
+    with pytest.raises(binding.BispecError) as ex:
+        plan.theta_groups(0, 1, 0)
+    assert ex.value.code == -1          # BISPEC_E_INVALID
+    _, B, _ = plan.polyspec(synth.lognormal_field(n, 1.5, 1.0, 3), want_p=False, want_t=False)
+    g, _ = plan.theta_groups(0, 1, 4)
+    with pytest.raises(binding.BispecError) as ex:
+        plan.rebin(B, g, 0)
+    assert ex.value.code == -1          # BISPEC_E_INVALID
+    with pytest.raises(binding.BispecError) as ex:
+        plan.rebin(torch.cat([B, B]), g, 4)          # batch above max_batch
+    assert ex.value.code == -1          # BISPEC_E_INVALID
