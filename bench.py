@@ -100,9 +100,10 @@ def timed_steps(torch, step, steps, stream):
 
 
 def onepixel_run(torch, binding, synth, np, dev, stream, steps):
-    """Narrow shells (one k_f, 63 bins at 128^3; more than 32 bins run the
-    vector-ALU contraction) and the table B(theta) at k2 = 2 k1 for k1 = 2..21
-    (20 cos theta bins each) from bispec_rebin."""
+    """Narrow shells (one k_f, 63 bins at 128^3: the bin fields go to HBM and
+    the triplets run on the split-BF16 product-Gram over them, 64 columns),
+    against the same plan on the FP32 vector-ALU terms, and the table B(theta)
+    at k2 = 2 k1 for k1 = 2..21 (20 cos theta bins each) from bispec_rebin."""
     wl = "onepix_128_lognormal"
     n = synth.WORKLOADS[wl]["n"]
     lo, hi = synth.workload_bins(wl)
@@ -135,12 +136,27 @@ def onepixel_run(torch, binding, synth, np, dev, stream, steps):
     plan.timing(False)
     stages, calls = plan.timing_read()
     wr, _ = timed_steps(torch, rebin, k, stream)
-    return {"workload": wl, "n": n, "bins": plan.n_bins, "triplets": plan.n_tri,
-            "contraction": "FP32 vector ALU (bin fields in HBM)",
-            "ms_per_map": 1e3 * we / k, "triangles_per_s": plan.n_tri * k / we,
-            "stages_ms": {key: v / max(calls, 1) for key, v in stages.items()},
-            "theta_table": {"configs": "k2 = 2 k1, k1 = 2..21 k_f, 20 bins of cos theta",
-                            "ms": 1e3 * wr / k, "groups": int(np.isfinite(tab.cpu().numpy()).sum())}}
+    out = {"workload": wl, "n": n, "bins": plan.n_bins, "triplets": plan.n_tri,
+           "contraction": "split-BF16 MFMA product-Gram over the bin fields in HBM (64 columns)",
+           "ms_per_map": 1e3 * we / k, "triangles_per_s": plan.n_tri * k / we,
+           "stages_ms": {key: v / max(calls, 1) for key, v in stages.items()},
+           "theta_table": {"configs": "k2 = 2 k1, k1 = 2..21 k_f, 20 bins of cos theta",
+                           "ms": 1e3 * wr / k, "groups": int(np.isfinite(tab.cpu().numpy()).sum())}}
+    # the fields product-Gram against the peak, algorithmic flops as for the
+    # headline kernel: one product per pair of bins and two flops per triplet
+    npix = float(n) ** 3
+    flops = (2.0 * plan.n_tri + plan.n_bins * (plan.n_bins + 1) / 2) * npix
+    ach = flops / (out["stages_ms"]["contract"] * 1e-3) / 1e12
+    out["roofline"] = {"bound": "mfma", "kernel": "k_pgram_fields + k_reduce_dense", "achieved": ach,
+                       "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": ach / BF16_PEAK_TFLOPS,
+                       "algorithmic_flop": flops}
+    plan.set_precision("fp32")
+    est()
+    kv = max(2, k // 2)
+    wv, _ = timed_steps(torch, est, kv, stream)
+    out["fp32_valu"] = {"ms_per_map": 1e3 * wv / kv, "triangles_per_s": plan.n_tri * kv / wv}
+    out["speedup_vs_fp32_valu"] = out["fp32_valu"]["ms_per_map"] / out["ms_per_map"]
+    return out
 
 
 def percentile(xs, q):

@@ -66,6 +66,9 @@ bool needs_fields(const bispec_plan_s &p) {
     return !p.mfma_ok || !p.quads_collapsed || p.precision == BISPEC_FP32_VALU;
 }
 
+// Dense tile entries of the fields product-Gram (33..64 bins): [n_mtile][32][64].
+size_t wide_dense_doubles(const bispec_plan_s &p) { return (size_t)p.n_mtile * 2048; }
+
 Layout make_layout(const bispec_plan_s &p, int batch) {
     Layout L{};
     const int64_t vol = (int64_t)p.n * p.n * p.n;
@@ -89,12 +92,17 @@ Layout make_layout(const bispec_plan_s &p, int batch) {
     L.pg_partial = off;
     if (p.mfma_ok) {
         off = align_up(off + sizeof(double) * pgram_partial_doubles(p.n_mtile, true) * p.nblk_pg_max * batch);
+    } else if (p.pg_wide) {
+        off = align_up(off + sizeof(double) * wide_dense_doubles(p) * p.nblk_wide * batch);
     }
     L.pg_dense = off;
     if (p.mfma_ok) off = align_up(off + sizeof(double) * pgram_partial_doubles(p.n_mtile, true) * batch);
+    else if (p.pg_wide) off = align_up(off + sizeof(double) * wide_dense_doubles(p) * batch);
     L.pg_tmp = off;
     if (p.mfma_ok)
         off = align_up(off + sizeof(double) * pgram_partial_doubles(p.n_mtile, true) * PG_REDUCE_SEGS * batch);
+    else if (p.pg_wide)
+        off = align_up(off + sizeof(double) * wide_dense_doubles(p) * PG_REDUCE_SEGS * batch);
     // bin fields in HBM: only the vector-ALU contraction and general quads read them
     L.fields = off;
     if (needs_fields(p)) off = align_up(off + sizeof(float) * vol * p.nb * batch);
@@ -244,9 +252,14 @@ std::vector<PairDev> pair_devs(const bispec_plan_s &p) {
 void build_pgram_tables(bispec_plan_s &p) {
     const int nb = p.nb;
     p.mfma_ok = nb <= 32;
+    p.pg_wide = nb > 32 && nb <= 64;
     p.pg_pairs.clear();
     p.pg_idx.clear();
-    if (!p.mfma_ok) return;
+    if (!p.mfma_ok && !p.pg_wide) return;
+    // 33..64 bins: rows are the cover of the triplets alone over 64 columns of
+    // fields in HBM (P and quads take the vector-ALU terms)
+    const bool wide = p.pg_wide;
+    const int row_zero = wide ? PGF_ROW_ZERO : PG_ROW_ZERO;
     std::vector<int> row_of(nb * nb, -1), row_one(nb, -1);
     auto add = [&](int i, int j) {
         if (row_of[i * nb + j] < 0) {
@@ -255,9 +268,10 @@ void build_pgram_tables(bispec_plan_s &p) {
         }
         return row_of[i * nb + j];
     };
-    for (int b = 0; b < nb; ++b) add(b, b);
+    if (!wide)
+        for (int b = 0; b < nb; ++b) add(b, b);
     const bool one_col = nb < 32;
-    if (!one_col)
+    if (!one_col && !wide)
         for (int b = 0; b < nb; ++b) {
             row_one[b] = (int)p.pg_pairs.size();
             p.pg_pairs.push_back(uchar2{(unsigned char)b, (unsigned char)PG_ROW_ONE});
@@ -300,10 +314,19 @@ void build_pgram_tables(bispec_plan_s &p) {
                 tri_col[t] = rest[3 * t + k];
                 break;
             }
-    while (p.pg_pairs.size() % 32) p.pg_pairs.push_back(uchar2{(unsigned char)PG_ROW_ZERO, (unsigned char)PG_ROW_ZERO});
+    if (p.pg_pairs.empty()) p.pg_pairs.push_back(uchar2{(unsigned char)row_zero, (unsigned char)row_zero});
+    while (p.pg_pairs.size() % 32) p.pg_pairs.push_back(uchar2{(unsigned char)row_zero, (unsigned char)row_zero});
     p.n_mtile = (int)p.pg_pairs.size() / 32;
-    auto dense = [](int row, int c) { return (row / 32) * 1024 + (row % 32) * 32 + c; };
+    const int ncol = wide ? 64 : 32;
+    auto dense = [ncol](int row, int c) { return (row / 32) * 32 * ncol + (row % 32) * ncol + c; };
     for (int t = 0; t < ntri; ++t) p.pg_idx.push_back(dense(tri_row[t], tri_col[t]));
+    if (wide) {
+        // blocks of the fields product-Gram: about 16384 points each (at
+        // least 256 blocks, at least one 128-point step per block)
+        const int64_t npix = (int64_t)p.n * p.n * p.n;
+        p.nblk_wide = (int)std::min<int64_t>(std::max<int64_t>(256, npix / 16384), npix / 128);
+        return;
+    }
     for (int b = 0; b < nb; ++b) p.pg_idx.push_back(one_col ? dense(row_of[b * nb + b], nb) : dense(row_one[b], b));
     const int nq = (int)p.quad.size() / 4;
     p.quads_collapsed = true;
@@ -630,7 +653,7 @@ bispec_status upload_tables(bispec_plan_s &p) {
     CK(hipMemcpyAsync(ws + L.pd, pd.data(), sizeof(PairDev) * pd.size(), hipMemcpyHostToDevice, p.stream));
     CK(hipMemcpyAsync(ws + L.ztab, p.ztab.data(), sizeof(int2) * p.ztab.size(), hipMemcpyHostToDevice, p.stream));
     CK(hipMemcpyAsync(ws + L.ytab, p.ytab.data(), sizeof(int2) * p.ytab.size(), hipMemcpyHostToDevice, p.stream));
-    if (p.mfma_ok) {
+    if (p.mfma_ok || p.pg_wide) {
         CK(hipMemcpyAsync(ws + L.pg_pairs, p.pg_pairs.data(), sizeof(uchar2) * p.pg_pairs.size(),
                           hipMemcpyHostToDevice, p.stream));
         CK(hipMemcpyAsync(ws + L.pg_idx, p.pg_idx.data(), sizeof(int) * p.pg_idx.size(), hipMemcpyHostToDevice,
@@ -750,6 +773,20 @@ bispec_status run_estimate_body(bispec_plan_s &p, const float *delta, int batch,
         float *fields = (float *)(ws + L.fields);
         bispec_status s = run_fields(p, delta, batch, fields);
         if (s != BISPEC_OK) return s;
+        if (p.pg_wide && p.precision == BISPEC_SPLIT_BF16 && first == 0 && ntri > 0) {
+            // 33..64 bins in split mode: the triplets on MFMA over the fields
+            // in HBM, P and quads on the vector ALUs below
+            double *pg = (double *)(ws + L.pg_partial);
+            double *dense = (double *)(ws + L.pg_dense);
+            const int64_t n_dense = (int64_t)wide_dense_doubles(p);
+            CK(launch_pgram_fields(fields, n, p.nb, batch, (const uchar2 *)(ws + L.pg_pairs), p.n_mtile,
+                                   p.nblk_wide, pg, p.stream));
+            CK(launch_reduce_dense(pg, p.nblk_wide, n_dense, batch, dense, (double *)(ws + L.pg_tmp), p.stream));
+            s = finalize_range(p, true, dense, 1, n_dense, 0, ntri, batch, P, B, T);
+            if (s != BISPEC_OK) return s;
+            first = ntri;
+            if (first == last && !T) return BISPEC_OK;
+        }
         if (!T) return valu_terms(p, fields, first, last, batch, P, B, T);
         if (first == last) return valu_terms(p, fields, t_first, t_last, batch, P, B, T);
         if (last == t_first) return valu_terms(p, fields, first, t_last, batch, P, B, T);

@@ -74,6 +74,17 @@ int tail_shape(int n, int n_mtile, bool want_t, int shape);
 // K parts per pair tile of the launched shape (summed inside the block:
 // each block writes one partial set of n_mtile + want_t tiles).
 int tail_ksplit(int n, int n_mtile, bool want_t, int shape);
+// Product-Gram over bin fields in HBM (33..64 bins, split-BF16; mfma.hip):
+// fields [batch][nb][N^3] FP32; pairs [n_mtile*32] row factors (field rows
+// 0..63, PGF_ROW_ZERO = zeros); partial [batch][nblk][n_mtile][32][64] FP64,
+// column z < nb the field F_z, the rest zero.  nblk blocks per map, each
+// contracting pgram_fields_chunk(n, nblk) <= PGF_MAX_CHUNK points (else
+// hipErrorInvalidValue).
+constexpr int PGF_ROW_ZERO = 64;
+constexpr int64_t PGF_MAX_CHUNK = 32768;
+int64_t pgram_fields_chunk(int n, int nblk);
+hipError_t launch_pgram_fields(const float *fields, int n, int nb, int batch, const uchar2 *pairs, int n_mtile,
+                               int nblk, double *partial, hipStream_t st);
 // dense[map][e] = sum over the nblk partial sets; tmp holds
 // PG_REDUCE_SEGS * n_dense * batch doubles of segment sums (or null: one pass).
 constexpr int PG_REDUCE_SEGS = 32;

@@ -442,6 +442,111 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MINW))) void
     st.write(partial, (int64_t)map * gridDim.x + blockIdx.x, n_mtile, col, half, reinterpret_cast<float *>(ubuf));
 }
 
+// Product-Gram over bin fields resident in HBM, for plans of 33..64 bins
+// (narrow shells): G[(x,y), z] = sum_n (F_x F_y)(n) F_z(n) in split-BF16,
+// with 64 columns (two 32-column MFMA tiles; columns >= nb are zero).  Block
+// (c, map, g) contracts the points [c chunk, (c+1) chunk) for the pair tiles
+// g PGF_TILES .. (g+1) PGF_TILES - 1; wave w owns the tiles g PGF_TILES + w +
+// r WAVES, r < PGF_MAXR.  Every step stages PGF_TK points of each field in
+// LDS, in FP32 for the row products and as bf16 halves for the columns, so
+// one split of a row product feeds both column tiles.  A chunk is at most
+// 32768 points, the split-mode span of FP32 accumulation; the block writes
+// its FP64 tile partials [n_mtile][32][64] (its own tiles only).
+constexpr int PGF_NT = 512, PGF_MAXR = 4, PGF_TK = 128;
+constexpr int PGF_TILES = PGF_NT / 64 * PGF_MAXR;
+
+__global__ __launch_bounds__(PGF_NT) void k_pgram_fields(const float *__restrict__ fields, int64_t npix, int nb,
+                                                         int64_t map_stride, const uchar2 *__restrict__ pairs,
+                                                         int n_mtile, int64_t chunk, double *__restrict__ partial) {
+    constexpr int TK = PGF_TK, FS = TK + 4, BS = TK + 8, WAVES = PGF_NT / 64, MAXR = PGF_MAXR;
+    __shared__ __attribute__((aligned(16))) float Ft[(PGF_ROW_ZERO + 1) * FS];   // field rows, then a row of zeros
+    __shared__ __attribute__((aligned(16))) __bf16 Bh[64 * BS];
+    __shared__ __attribute__((aligned(16))) __bf16 Bl[64 * BS];
+    const int tid = threadIdx.x, lane = tid & 63, col = lane & 31, half = lane >> 5;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int map = blockIdx.y;
+    // rows nb..63 and the zero row are never loaded: zero them once
+    for (int i = tid; i < (PGF_ROW_ZERO + 1 - nb) * FS; i += PGF_NT) Ft[nb * FS + i] = 0.0f;
+    for (int i = tid; i < (64 - nb) * BS; i += PGF_NT) {
+        Bh[nb * BS + i] = (__bf16)0.0f;
+        Bl[nb * BS + i] = (__bf16)0.0f;
+    }
+    int tile_of[MAXR];
+    uchar2 rp[MAXR];
+    f32x16 acc[MAXR][2];
+#pragma unroll
+    for (int r = 0; r < MAXR; ++r) {
+        const int t = blockIdx.z * PGF_TILES + wave + r * WAVES;
+        tile_of[r] = t < n_mtile ? t : -1;
+        rp[r] = t < n_mtile ? pairs[t * 32 + col] : uchar2{PGF_ROW_ZERO, PGF_ROW_ZERO};
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            acc[r][0][i] = 0.0f;
+            acc[r][1][i] = 0.0f;
+        }
+    }
+    const float *f = fields + (int64_t)map * map_stride;
+    const int64_t p0 = (int64_t)blockIdx.x * chunk;
+    const int64_t p1 = p0 + chunk < npix ? p0 + chunk : npix;
+    for (int64_t p = p0; p < p1; p += TK) {
+        __syncthreads();   // the previous step's reads are done
+        for (int e = tid; e < nb * (TK / 4); e += PGF_NT) {
+            const int b = e / (TK / 4), k = (e % (TK / 4)) * 4;
+            const float4 v = *reinterpret_cast<const float4 *>(f + (int64_t)b * npix + p + k);
+            *reinterpret_cast<float4 *>(&Ft[b * FS + k]) = v;
+            bf16x2 h0, l0, h1, l1;
+            split2(v.x, v.y, h0, l0);
+            split2(v.z, v.w, h1, l1);
+            Bh[b * BS + k] = h0[0];
+            Bh[b * BS + k + 1] = h0[1];
+            Bh[b * BS + k + 2] = h1[0];
+            Bh[b * BS + k + 3] = h1[1];
+            Bl[b * BS + k] = l0[0];
+            Bl[b * BS + k + 1] = l0[1];
+            Bl[b * BS + k + 2] = l1[0];
+            Bl[b * BS + k + 3] = l1[1];
+        }
+        __syncthreads();
+#pragma unroll 1
+        for (int s = 0; s < TK / 16; ++s) {
+            const int kp = s * 16 + half * 8;
+            const bf16x8 bh0 = *reinterpret_cast<const bf16x8 *>(&Bh[col * BS + kp]);
+            const bf16x8 bl0 = *reinterpret_cast<const bf16x8 *>(&Bl[col * BS + kp]);
+            const bf16x8 bh1 = *reinterpret_cast<const bf16x8 *>(&Bh[(32 + col) * BS + kp]);
+            const bf16x8 bl1 = *reinterpret_cast<const bf16x8 *>(&Bl[(32 + col) * BS + kp]);
+#pragma unroll
+            for (int r = 0; r < MAXR; ++r) {
+                if (tile_of[r] < 0) continue;
+                const float4 i0 = *reinterpret_cast<const float4 *>(&Ft[rp[r].x * FS + kp]);
+                const float4 i1 = *reinterpret_cast<const float4 *>(&Ft[rp[r].x * FS + kp + 4]);
+                const float4 j0 = *reinterpret_cast<const float4 *>(&Ft[rp[r].y * FS + kp]);
+                const float4 j1 = *reinterpret_cast<const float4 *>(&Ft[rp[r].y * FS + kp + 4]);
+                float a[8] = {i0.x * j0.x, i0.y * j0.y, i0.z * j0.z, i0.w * j0.w,
+                              i1.x * j1.x, i1.y * j1.y, i1.z * j1.z, i1.w * j1.w};
+                bf16x8 ah, al;
+                split8(a, ah, al);
+                acc[r][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh0, acc[r][0], 0, 0, 0);
+                acc[r][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh1, acc[r][1], 0, 0, 0);
+                acc[r][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl0, acc[r][0], 0, 0, 0);
+                acc[r][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl1, acc[r][1], 0, 0, 0);
+                acc[r][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh0, acc[r][0], 0, 0, 0);
+                acc[r][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh1, acc[r][1], 0, 0, 0);
+            }
+        }
+    }
+    double *base = partial + ((int64_t)map * gridDim.x + blockIdx.x) * ((int64_t)n_mtile * 2048);
+#pragma unroll
+    for (int r = 0; r < MAXR; ++r) {
+        if (tile_of[r] < 0) continue;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int row = 8 * (i >> 2) + 4 * half + (i & 3);
+            base[tile_of[r] * 2048 + row * 64 + col] = (double)acc[r][0][i];
+            base[tile_of[r] * 2048 + row * 64 + 32 + col] = (double)acc[r][1][i];
+        }
+    }
+}
+
 // Fixed-order compensated FP64 sum over blocks of every dense tile entry,
 // in segments: out[map][z][e] = sum_{b in segment z} partial[map][b][e],
 // segment z = [z seg, min((z+1) seg, nblk)) for z = blockIdx.z.  Consecutive
@@ -593,6 +698,24 @@ hipError_t launch_tail(int mode, bool want_t, const float2 *bc, const TailPairs 
                                                      shape)
                   : launch_tail_m<PG_MODE_F32, false>(bc, tp, n, nb, batch, pairs, n_mtile, tw, nblk, partial, st,
                                                       shape);
+}
+
+int64_t pgram_fields_chunk(int n, int nblk) {
+    const int64_t npix = (int64_t)n * n * n;
+    const int64_t c = (npix + nblk - 1) / nblk;
+    return (c + PGF_TK - 1) / PGF_TK * PGF_TK;
+}
+
+hipError_t launch_pgram_fields(const float *fields, int n, int nb, int batch, const uchar2 *pairs, int n_mtile,
+                               int nblk, double *partial, hipStream_t st) {
+    if (nb < 1 || nb > 64 || n_mtile < 1 || nblk < 1 || batch < 1) return hipErrorInvalidValue;
+    const int64_t npix = (int64_t)n * n * n;
+    const int64_t chunk = pgram_fields_chunk(n, nblk);
+    if (npix % PGF_TK != 0 || chunk > PGF_MAX_CHUNK) return hipErrorInvalidValue;
+    const unsigned groups = (unsigned)((n_mtile + PGF_TILES - 1) / PGF_TILES);
+    hipLaunchKernelGGL(k_pgram_fields, dim3(nblk, batch, groups), dim3(PGF_NT), 0, st, fields, npix, nb,
+                       (int64_t)nb * npix, pairs, n_mtile, chunk, partial);
+    return hipGetLastError();
 }
 
 hipError_t launch_reduce_dense(const double *partial, int nblk, int64_t n_dense, int batch, double *dense,

@@ -41,6 +41,8 @@ struct bispec_plan_s {
     // product-Gram (MFMA) contraction
     bool mfma_ok = false;                // n_bins <= 32
     bool quads_collapsed = false;        // every quad is (a,a,b,b) up to order
+    bool pg_wide = false;                // 33..64 bins: product-Gram over the fields in HBM
+    int nblk_wide = 1;                   // blocks per map of that product-Gram
     int n_mtile = 0;                     // 32-row tiles of pair rows
     int nblk_pg = 1;                     // blocks of the product-Gram kernel (tuned)
     int nblk_pg_min = 1;                 // fewest blocks (chunk span limit)

@@ -72,19 +72,21 @@ def test_theta_rebin_32_against_brute_force(binding, prec):
         assert np.allclose(out[ok], own[ok], rtol=1e-13, atol=0)
 
 
-def test_onepixel_128_valu_and_rebin(binding):
+@pytest.mark.parametrize("prec", ["fp32", "split_bf16"])
+def test_onepixel_128_and_rebin(binding, prec):
+    # more than 32 bins: split-BF16 runs the product-Gram over the bin fields
+    # in HBM (64 columns), FP32 the vector-ALU terms
     wl = "onepix_128_lognormal"
     n = synth.WORKLOADS[wl]["n"]
     lo, hi = synth.workload_bins(wl)
     d = synth.workload_field(wl)
     assert len(lo) == 63
-    _say("one-pixel 128^3, 63 bins")
-    plan = binding.Plan(n, lo, hi, quads=[(0, 0, 0, 0)], max_batch=2)
+    _say("one-pixel 128^3, 63 bins, %s" % prec)
+    plan = binding.Plan(n, lo, hi, quads=[(0, 0, 0, 0)], max_batch=2, precision=prec)
     dd = np.stack([d, synth.lognormal_field(n, 1.5, 1.0, 12)])
     _, B, _ = plan.polyspec(dd, want_p=False, want_t=False)
     trip = plan.triplets
     _say("  %d triplets" % len(trip))
-    # the estimator on narrow shells (more than 32 bins: vector-ALU FP32)
     Dk = oracle.dft3(oracle.prepare(d))
     cheap = trip[(trip.max(1) <= 12)]
     idx = [int(np.flatnonzero((trip == t).all(1))[0]) for t in cheap]
@@ -92,7 +94,7 @@ def test_onepixel_128_valu_and_rebin(binding):
     assert np.array_equal(plan.counts[idx].astype(np.int64), ref.count)
     e = np.abs(B.cpu().numpy()[0][idx] - ref.value) / np.maximum(np.abs(ref.value), ref.noise)
     _say("  %d sampled triplets, max err %.2e" % (len(cheap), e.max()))
-    assert e.max() <= TOL["fp32"]
+    assert e.max() <= TOL[prec]
     # B(theta) at k1 = 4, k2 = 8 (bins 3, 7): every member has bins <= 11
     g, _ = plan.theta_groups(3, 7, 20)
     og, _ = oc.theta_groups(lo, hi, trip, 3, 7, 20)
@@ -107,7 +109,7 @@ def test_onepixel_128_valu_and_rebin(binding):
     noise = _group_noise(refm, g[mem], 20)
     e = np.abs(out[0][ok] - want[ok]) / np.maximum(np.abs(want[ok]), noise[ok])
     _say("  B(theta) k2 = 2 k1: %d groups, max err %.2e" % (ok.sum(), e.max()))
-    assert e.max() <= TOL["fp32"]
+    assert e.max() <= TOL[prec]
     # both maps of the batch, against the FP64 rebinning of the GPU's own B
     own = oc.rebin(B.cpu().numpy(), plan.counts, g, 20)
     assert np.allclose(out[:, ok], own[:, ok], rtol=1e-13, atol=0)
@@ -121,6 +123,51 @@ def test_onepixel_128_valu_and_rebin(binding):
     again = plan.rebin(B, g, 20).cpu().numpy()
     assert np.array_equal(np.isnan(again), np.isnan(out))
     assert np.array_equal(again[np.isfinite(again)], out[np.isfinite(out)])
+
+
+def test_wide_bins_64_all_outputs(binding):
+    # 40 shells of width 3/4 at 64^3: B on the fields product-Gram (two
+    # column tiles, several pair-tile groups), P and collapsed T on the
+    # vector ALUs; sampled triplets against the oracle, a batch of two maps
+    n = 64
+    e = 1.0 + 0.75 * np.arange(41)
+    lo, hi = e[:-1], e[1:]
+    d0 = synth.lognormal_field(n, 1.5, 1.0, 21).astype(np.float32)
+    d1 = synth.gaussian_field(n, 2.0, 0.5, 22).astype(np.float32)
+    _say("64^3, 40 bins of 0.75 k_f")
+    plan = binding.Plan(n, lo, hi, max_batch=2)
+    P, B, T = plan.polyspec(np.stack([d0, d1]))
+    trip, quads = plan.triplets, plan.quads
+    _say("  %d triplets, %d quads" % (len(trip), len(quads)))
+    m = oracle.mode_counts(n, lo, hi)
+    for k, d in enumerate((d0, d1)):
+        Dk = oracle.dft3(oracle.prepare(d))
+        key = np.array([sorted(int(b) for b in t)[:2] for t in trip])
+        cost = m[key[:, 0]].astype(float) * m[key[:, 1]]
+        sel = np.flatnonzero(cost <= 2e6)
+        sel = np.concatenate([sel, np.flatnonzero(cost > 2e6)[:: max(1, int(np.sum(cost > 2e6)) // 20)]])
+        ref = oracle.bispectrum(d, lo, hi, trip[sel], delta_k=Dk)
+        assert np.array_equal(plan.counts[sel].astype(np.int64), ref.count)
+        err = np.abs(B.cpu().numpy()[k][sel] - ref.value) / np.maximum(np.abs(ref.value), ref.noise)
+        # shells narrower than k_f leave triplets with little triangle slack:
+        # rounding is amplified by kappa = sqrt(M_i M_j M_k / (N_pix N_t)),
+        # so the bar is TOL up to kappa = 2 and grows with kappa beyond
+        mm = m[trip[sel]].astype(float)
+        kappa = np.sqrt(mm[:, 0] * mm[:, 1] * mm[:, 2] / (float(n) ** 3 * ref.count))
+        w = int(np.argmax(err))
+        _say("  map %d: %d sampled triplets, max err %.2e (kappa %.1f, max kappa %.1f)"
+             % (k, len(sel), err[w], kappa[w], kappa.max()))
+        assert np.all(err <= TOL["split_bf16"] * np.maximum(1.0, kappa / 2.0))
+        assert np.max(err[kappa <= 2.0]) <= TOL["split_bf16"]
+        refp, _ = oracle.power_spectrum(d, lo, hi, delta_k=Dk)
+        assert np.max(np.abs(P.cpu().numpy()[k] - refp) / refp) <= TOL["fp32"]
+        qs = [q for q in range(len(quads)) if max(quads[q]) <= 6]
+        reft = oracle.trispectrum(d, lo, hi, quads[qs], delta_k=Dk)
+        et = np.abs(T.cpu().numpy()[k][qs] - reft.value) / np.maximum(np.abs(reft.value), reft.noise)
+        assert et.max() <= TOL["fp32"]
+    # one map alone gives the same B bit for bit
+    _, B0, _ = plan.polyspec(d0, want_p=False, want_t=False)
+    assert np.array_equal(B0.cpu().numpy()[0], B.cpu().numpy()[0])
 
 
 def test_rebin_argument_errors(binding):
