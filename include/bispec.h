@@ -67,8 +67,12 @@ typedef enum {
  * FP64 in every mode.  Modes 0 and 1 evaluate the product-Gram
  * G[(x,y),k] = sum_n (F_x F_y) F_k on the matrix cores, for every column k
  * and for pair rows (x,y) that cover the requested triplets (each triplet is
- * read from one of its three pairs); they need n_bins <= 32, and with more
- * bins they run as mode 2. */
+ * read from one of its three pairs).  With n_bins <= 32 the product-Gram is
+ * fused with the last inverse pass and also yields P and the collapsed T.
+ * With 33..64 bins (narrow shells; Section 3.2 and the Conclusion advise
+ * shells one k_f wide) mode 1 keeps the bin fields in HBM and runs the
+ * triplets on a 64-column product-Gram over them, P and the quads on the
+ * vector ALUs; mode 0 runs as mode 2 there. */
 enum {
     BISPEC_FP32 = 0,        /* product-Gram, FP32 MFMA, FP32 accumulation            */
     BISPEC_SPLIT_BF16 = 1,  /* product-Gram, BF16 MFMA on hi/lo splits (3 products),

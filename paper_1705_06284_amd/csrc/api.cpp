@@ -696,13 +696,8 @@ bispec_status run_fields(bispec_plan_s &p, const float *delta, int batch, float 
     CK(launch_forward(delta, mean, n, batch, tw, spec, p.stream));
     stamp(p, 1);
     CK(run_inverse_zy(p, batch));
-    for (size_t q = 0; q < p.pairs.size(); ++q) {
-        const int b = 2 * (int)q;
-        const PairGeom &g = p.pairs[q];
-        float2 *bc = (float2 *)(ws + L.bc) + p.bc_off[q] * (int64_t)n * n * p.max_batch;
-        CK(launch_inverse_x(bc, (int64_t)n * n * g.Wp, n, batch, tw, g, fields + (int64_t)b * vol,
-                            b + 1 < p.nb ? fields + (int64_t)(b + 1) * vol : nullptr, (int64_t)p.nb * vol, p.stream));
-    }
+    CK(launch_inverse_x_pairs((const float2 *)(ws + L.bc), n, batch, tw, (const PairDev *)(ws + L.pd),
+                              (int)p.pairs.size(), p.nb, fields, p.stream));
     stamp(p, 2);
     return BISPEC_OK;
 }

@@ -373,21 +373,15 @@ __global__ __launch_bounds__(256) void k_inv_y_prune(const cplx<R> *__restrict__
     }
 }
 
-// Pass X writing the two bin fields (used for bin_fields, the VALU
-// contraction and the FP64 count fields).
+// Pass X over the G rows from row0 of one pair's compact rows src (row
+// stride Wp, radius Rr): the real parts go to d1, the imaginary parts to d2
+// (or nowhere).
 template <typename R, int N>
-__global__ __launch_bounds__(256) void k_inv_x_compact(const cplx<R> *__restrict__ bc, int64_t bc_stride,
-                                                       PairGeom g, const cplx<R> *__restrict__ tw,
-                                                       R *__restrict__ f1, R *__restrict__ f2, int64_t field_stride) {
+__device__ __forceinline__ void inv_x_rows(const cplx<R> *__restrict__ src, int Wp, int Rr, int64_t row0,
+                                           cplx<R> *s, const cplx<R> *tws, R *__restrict__ d1,
+                                           R *__restrict__ d2) {
     using C = cplx<R>;
     constexpr int G = pencils_per_block<R, N>();
-    __shared__ C s[G * pencil_ld<N>()];
-    __shared__ C tws[N];
-    load_twiddles<C, N>(tws, tw);
-    const int map = blockIdx.y;
-    const C *src = bc + map * bc_stride;
-    const int Wp = g.Wp, Rr = g.R;
-    const int64_t row0 = (int64_t)blockIdx.x * G;
     constexpr int PER = G * N / 256;
     C v[PER];
 #pragma unroll
@@ -403,13 +397,44 @@ __global__ __launch_bounds__(256) void k_inv_x_compact(const cplx<R> *__restrict
     }
     __syncthreads();
     fft_pencils<C, N, pencil_ld<N>(), G, +1>(s, tws);
-    R *d1 = f1 + map * field_stride;
     for (int e = threadIdx.x; e < G * N; e += 256) d1[row0 * N + e] = s[(e / N) * pencil_ld<N>() + pad_idx(e % N)].x;
-    if (f2) {
-        R *d2 = f2 + map * field_stride;
+    if (d2)
         for (int e = threadIdx.x; e < G * N; e += 256)
             d2[row0 * N + e] = s[(e / N) * pencil_ld<N>() + pad_idx(e % N)].y;
-    }
+}
+
+// Pass X writing the two bin fields of one pair (the FP64 count fields).
+template <typename R, int N>
+__global__ __launch_bounds__(256) void k_inv_x_compact(const cplx<R> *__restrict__ bc, int64_t bc_stride,
+                                                       PairGeom g, const cplx<R> *__restrict__ tw,
+                                                       R *__restrict__ f1, R *__restrict__ f2, int64_t field_stride) {
+    using C = cplx<R>;
+    constexpr int G = pencils_per_block<R, N>();
+    __shared__ C s[G * pencil_ld<N>()];
+    __shared__ C tws[N];
+    load_twiddles<C, N>(tws, tw);
+    const int map = blockIdx.y;
+    inv_x_rows<R, N>(bc + map * bc_stride, g.Wp, g.R, (int64_t)blockIdx.x * G, s, tws, f1 + map * field_stride,
+                     f2 ? f2 + map * field_stride : nullptr);
+}
+
+// Pass X of every pair in one launch (bin_fields, the vector-ALU terms and
+// the fields product-Gram): block (x, map, q) transforms rows x G .. x G + G - 1
+// of pair q into F_2q and F_2q+1 of fields [batch][nb][N^3].
+template <int N>
+__global__ __launch_bounds__(256) void k_inv_x_pairs(const float2 *__restrict__ bc, const PairDev *__restrict__ pd,
+                                                     const float2 *__restrict__ tw, int nb,
+                                                     float *__restrict__ fields) {
+    constexpr int G = pencils_per_block<float, N>();
+    constexpr int64_t VOL = (int64_t)N * N * N;
+    __shared__ float2 s[G * pencil_ld<N>()];
+    __shared__ float2 tws[N];
+    load_twiddles<float2, N>(tws, tw);
+    const int map = blockIdx.y, q = blockIdx.z;
+    const PairDev P = pd[q];
+    float *f1 = fields + ((int64_t)map * nb + 2 * q) * VOL;
+    inv_x_rows<float, N>(bc + P.boff + map * P.bstride, P.g.Wp, P.g.R, (int64_t)blockIdx.x * G, s, tws, f1,
+                         2 * q + 1 < nb ? f1 + VOL : nullptr);
 }
 
 
@@ -653,6 +678,17 @@ hipError_t launch_inverse_zy(const float2 *spec, int64_t spec_stride, int n, int
 hipError_t launch_inverse_x(const float2 *bc, int64_t bc_stride, int n, int batch, const float2 *tw,
                             const PairGeom &g, float *f1, float *f2, int64_t field_stride, hipStream_t st) {
     return launch_inverse_x_t<float>(bc, bc_stride, n, batch, tw, g, f1, f2, field_stride, st);
+}
+
+hipError_t launch_inverse_x_pairs(const float2 *bc, int n, int batch, const float2 *tw, const PairDev *pd, int npairs,
+                                  int nb, float *fields, hipStream_t st) {
+    if (npairs < 1 || 2 * npairs < nb || 2 * (npairs - 1) >= nb) return hipErrorInvalidValue;
+    return dispatch_n(n, [&](auto nc) {
+        constexpr int NN = decltype(nc)::value;
+        constexpr int G = pencils_per_block<float, NN>();
+        hipLaunchKernelGGL((k_inv_x_pairs<NN>), dim3(NN * NN / G, batch, npairs), dim3(256), 0, st, bc, pd, tw, nb,
+                           fields);
+    });
 }
 
 hipError_t launch_inverse_unit_f64(int n, const double2 *tw, const PairDev *pd, const PairGeom &g,

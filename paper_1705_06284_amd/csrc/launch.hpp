@@ -25,6 +25,11 @@ hipError_t launch_inverse_zy(const float2 *spec, int64_t spec_stride, int n, int
                              const int *cols, float2 *abox, float2 *bc, hipStream_t st);
 hipError_t launch_inverse_x(const float2 *bc, int64_t bc_stride, int n, int batch, const float2 *tw,
                             const PairGeom &g, float *f1, float *f2, int64_t field_stride, hipStream_t st);
+// Pass X of every pair in one launch: pair q (reading its compact rows at
+// pd[q].boff + map pd[q].bstride) writes F_2q and F_2q+1 (if 2q+1 < nb) of
+// fields [batch][nb][N^3].  npairs = ceil(nb / 2).
+hipError_t launch_inverse_x_pairs(const float2 *bc, int n, int batch, const float2 *tw, const PairDev *pd, int npairs,
+                                  int nb, float *fields, hipStream_t st);
 // Unit-amplitude (count) fields I_b of one pair in FP64 (one map).
 hipError_t launch_inverse_unit_f64(int n, const double2 *tw, const PairDev *pd, const PairGeom &g,
                                    const int2 *ztab, int nz_blk, const int2 *ytab, int ny_blk, const int *cols,
