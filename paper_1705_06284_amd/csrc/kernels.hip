@@ -544,30 +544,38 @@ __global__ __launch_bounds__(256) void k_finalize(const double *__restrict__ par
 // the group's closed triangles.  Each thread sums a fixed strided subset, the
 // wave and block sums run in a fixed order, so the result is deterministic.
 // Triplets with N_t = 0 (B = NaN) contribute nothing; an empty group is NaN.
-__global__ __launch_bounds__(256) void k_rebin(const double *__restrict__ B, int n_tri,
-                                               const double *__restrict__ count, const int *__restrict__ group,
-                                               int n_group, double *__restrict__ out) {
+constexpr int RB_NT = 1024;
+
+__global__ __launch_bounds__(RB_NT) void k_rebin(const double *__restrict__ B, int n_tri,
+                                                 const double *__restrict__ count, const int *__restrict__ group,
+                                                 int n_group, double *__restrict__ out) {
     const int g = blockIdx.x, map = blockIdx.y;
     const double *b = B + (int64_t)map * n_tri;
     double num = 0.0, den = 0.0;
-    for (int t = threadIdx.x; t < n_tri; t += 256) {
-        const double w = count[t];
-        if (group[t] == g && w > 0.0) {
-            num += w * b[t];
-            den += w;
+#pragma unroll 4
+    for (int t = threadIdx.x; t < n_tri; t += RB_NT) {
+        if (group[t] == g) {
+            const double w = count[t];
+            if (w > 0.0) {
+                num += w * b[t];
+                den += w;
+            }
         }
     }
     num = wave_sum(num);
     den = wave_sum(den);
-    __shared__ double red[2][4];
+    __shared__ double red[2][RB_NT / 64];
     if ((threadIdx.x & 63) == 0) {
         red[0][threadIdx.x >> 6] = num;
         red[1][threadIdx.x >> 6] = den;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        const double sn = (red[0][0] + red[0][1]) + (red[0][2] + red[0][3]);
-        const double sd = (red[1][0] + red[1][1]) + (red[1][2] + red[1][3]);
+        double sn = 0.0, sd = 0.0;
+        for (int w = 0; w < RB_NT / 64; ++w) {
+            sn += red[0][w];
+            sd += red[1][w];
+        }
         out[(int64_t)map * n_group + g] = sd > 0.0 ? sn / sd : __builtin_nan("");
     }
 }
@@ -751,7 +759,7 @@ hipError_t launch_finalize(const double *partial, int nblk, int nterm, int batch
 
 hipError_t launch_rebin(const double *B, int n_tri, const double *count, const int *group, int n_group, int batch,
                         double *out, hipStream_t st) {
-    hipLaunchKernelGGL(k_rebin, dim3(n_group, batch), dim3(256), 0, st, B, n_tri, count, group, n_group, out);
+    hipLaunchKernelGGL(k_rebin, dim3(n_group, batch), dim3(RB_NT), 0, st, B, n_tri, count, group, n_group, out);
     return hipGetLastError();
 }
 

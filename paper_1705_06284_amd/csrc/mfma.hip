@@ -449,7 +449,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MINW))) void
 // g PGF_TILES .. (g+1) PGF_TILES - 1; wave w owns the tiles g PGF_TILES + w +
 // r WAVES, r < PGF_MAXR.  Every step stages PGF_TK points of each field in
 // LDS, in FP32 for the row products and as bf16 halves for the columns, so
-// one split of a row product feeds both column tiles.  A chunk is at most
+// one split of a row product feeds both column tiles; the next step's
+// loads are in flight during a step's contraction.  A chunk is at most
 // 32768 points, the split-mode span of FP32 accumulation; the block writes
 // its FP64 tile partials [n_mtile][32][64] (its own tiles only).
 constexpr int PGF_NT = 512, PGF_MAXR = 4, PGF_TK = 128;
@@ -488,11 +489,30 @@ __global__ __launch_bounds__(PGF_NT) void k_pgram_fields(const float *__restrict
     const float *f = fields + (int64_t)map * map_stride;
     const int64_t p0 = (int64_t)blockIdx.x * chunk;
     const int64_t p1 = p0 + chunk < npix ? p0 + chunk : npix;
+    // the loads of step p + TK are issued before step p's contraction and
+    // land in registers; after the step they go to LDS
+    constexpr int LPT = 64 * (TK / 4) / PGF_NT;   // float4 per thread at 64 bins
+    static_assert(64 * (TK / 4) % PGF_NT == 0, "field loads must divide the block");
+    float4 pre[LPT];
+    auto fetch = [&](int64_t p) {
+#pragma unroll
+        for (int j = 0; j < LPT; ++j) {
+            const int e = tid + j * PGF_NT;
+            if (e < nb * (TK / 4)) {
+                const int b = e / (TK / 4), k = (e % (TK / 4)) * 4;
+                pre[j] = *reinterpret_cast<const float4 *>(f + (int64_t)b * npix + p + k);
+            }
+        }
+    };
+    if (p0 < p1) fetch(p0);
     for (int64_t p = p0; p < p1; p += TK) {
         __syncthreads();   // the previous step's reads are done
-        for (int e = tid; e < nb * (TK / 4); e += PGF_NT) {
+#pragma unroll
+        for (int j = 0; j < LPT; ++j) {
+            const int e = tid + j * PGF_NT;
+            if (e >= nb * (TK / 4)) continue;
             const int b = e / (TK / 4), k = (e % (TK / 4)) * 4;
-            const float4 v = *reinterpret_cast<const float4 *>(f + (int64_t)b * npix + p + k);
+            const float4 v = pre[j];
             *reinterpret_cast<float4 *>(&Ft[b * FS + k]) = v;
             bf16x2 h0, l0, h1, l1;
             split2(v.x, v.y, h0, l0);
@@ -507,6 +527,7 @@ __global__ __launch_bounds__(PGF_NT) void k_pgram_fields(const float *__restrict
             Bl[b * BS + k + 3] = l1[1];
         }
         __syncthreads();
+        if (p + TK < p1) fetch(p + TK);
 #pragma unroll 1
         for (int s = 0; s < TK / 16; ++s) {
             const int kp = s * 16 + half * 8;
