@@ -100,16 +100,19 @@ def timed_steps(torch, step, steps, stream):
 
 
 def onepixel_run(torch, binding, synth, np, dev, stream, steps):
-    """Narrow shells (one k_f, 63 bins at 128^3: the bin fields go to HBM and
-    the triplets run on the split-BF16 product-Gram over them, 64 columns),
-    against the same plan on the FP32 vector-ALU terms, and the table B(theta)
-    at k2 = 2 k1 for k1 = 2..21 (20 cos theta bins each) from bispec_rebin."""
+    """Narrow shells (one k_f, 63 bins at 128^3: the bin fields go to HBM; the
+    triplets run on the split-BF16 product-Gram over them, 64 columns, P and
+    the 2016 collapsed T on its pass over the squares), against the same plan
+    on the FP32 vector-ALU terms, and the table B(theta) at k2 = 2 k1 for
+    k1 = 2..21 (20 cos theta bins each) from bispec_rebin."""
     wl = "onepix_128_lognormal"
     n = synth.WORKLOADS[wl]["n"]
     lo, hi = synth.workload_bins(wl)
-    plan = binding.Plan(n, lo, hi, quads=[(0, 0, 0, 0)], stream=stream, device=dev)
+    plan = binding.Plan(n, lo, hi, stream=stream, device=dev)
     d = torch.from_numpy(synth.workload_field(wl)).to(dev).unsqueeze(0)
+    P = torch.empty(1, plan.n_bins, dtype=torch.float64, device=dev)
     B = torch.empty(1, plan.n_tri, dtype=torch.float64, device=dev)
+    T = torch.empty(1, plan.n_quad, dtype=torch.float64, device=dev)
     groups = []
     for b1 in range(1, 21):
         g, _ = plan.theta_groups(b1, 2 * b1 + 1, 20)
@@ -118,8 +121,8 @@ def onepixel_run(torch, binding, synth, np, dev, stream, steps):
     torch.cuda.synchronize()
 
     def est():
-        binding.check(binding.polyspec_estimate(plan.handle, binding._ptr(d), 1, None, binding._ptr(B), None),
-                      "polyspec_estimate")
+        binding.check(binding.polyspec_estimate(plan.handle, binding._ptr(d), 1, binding._ptr(P), binding._ptr(B),
+                                                binding._ptr(T)), "polyspec_estimate")
 
     def rebin():
         for i, g in enumerate(groups):
@@ -136,8 +139,10 @@ def onepixel_run(torch, binding, synth, np, dev, stream, steps):
     plan.timing(False)
     stages, calls = plan.timing_read()
     wr, _ = timed_steps(torch, rebin, k, stream)
-    out = {"workload": wl, "n": n, "bins": plan.n_bins, "triplets": plan.n_tri,
-           "contraction": "split-BF16 MFMA product-Gram over the bin fields in HBM (64 columns)",
+    out = {"workload": wl, "n": n, "bins": plan.n_bins, "triplets": plan.n_tri, "quads": plan.n_quad,
+           "outputs": "B, P, T",
+           "contraction": "split-BF16 MFMA product-Gram over the bin fields in HBM (64 columns), "
+                          "P and T from its pass over the squares",
            "ms_per_map": 1e3 * we / k, "triangles_per_s": plan.n_tri * k / we,
            "stages_ms": {key: v / max(calls, 1) for key, v in stages.items()},
            "theta_table": {"configs": "k2 = 2 k1, k1 = 2..21 k_f, 20 bins of cos theta",
@@ -145,9 +150,9 @@ def onepixel_run(torch, binding, synth, np, dev, stream, steps):
     # the fields product-Gram against the peak, algorithmic flops as for the
     # headline kernel: one product per pair of bins and two flops per triplet
     npix = float(n) ** 3
-    flops = (2.0 * plan.n_tri + plan.n_bins * (plan.n_bins + 1) / 2) * npix
+    flops = (2.0 * plan.n_tri + plan.n_bins * (plan.n_bins + 1) / 2) * npix   # B; P and T not counted
     ach = flops / (out["stages_ms"]["contract"] * 1e-3) / 1e12
-    out["roofline"] = {"bound": "mfma", "kernel": "k_pgram_fields + k_reduce_dense", "achieved": ach,
+    out["roofline"] = {"bound": "mfma", "kernel": "k_pgram_fields (triplet pass) + k_reduce_dense", "achieved": ach,
                        "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": ach / BF16_PEAK_TFLOPS,
                        "algorithmic_flop": flops}
     plan.set_precision("fp32")

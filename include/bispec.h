@@ -71,8 +71,10 @@ typedef enum {
  * fused with the last inverse pass and also yields P and the collapsed T.
  * With 33..64 bins (narrow shells; Section 3.2 and the Conclusion advise
  * shells one k_f wide) mode 1 keeps the bin fields in HBM and runs the
- * triplets on a 64-column product-Gram over them, P and the quads on the
- * vector ALUs; mode 0 runs as mode 2 there. */
+ * triplets on a 64-column product-Gram over them, and P and the collapsed
+ * quads on a second pass over the squared fields (rows F_a^2, columns F_b^2
+ * and ones; up to 63 bins); general quads, and P at 64 bins, run on the
+ * vector ALUs.  Mode 0 runs as mode 2 there. */
 enum {
     BISPEC_FP32 = 0,        /* product-Gram, FP32 MFMA, FP32 accumulation            */
     BISPEC_SPLIT_BF16 = 1,  /* product-Gram, BF16 MFMA on hi/lo splits (3 products),

@@ -67,7 +67,7 @@ bool needs_fields(const bispec_plan_s &p) {
 }
 
 // Dense tile entries of the fields product-Gram (33..64 bins): [n_mtile][32][64].
-size_t wide_dense_doubles(const bispec_plan_s &p) { return (size_t)p.n_mtile * 2048; }
+size_t wide_dense_doubles(const bispec_plan_s &p) { return (size_t)std::max(p.n_mtile, p.pg_sq_tiles) * 2048; }
 
 Layout make_layout(const bispec_plan_s &p, int batch) {
     Layout L{};
@@ -325,6 +325,21 @@ void build_pgram_tables(bispec_plan_s &p) {
         // least 256 blocks, at least one 128-point step per block)
         const int64_t npix = (int64_t)p.n * p.n * p.n;
         p.nblk_wide = (int)std::min<int64_t>(std::max<int64_t>(256, npix / 16384), npix / 128);
+        // P and collapsed quads from the product-Gram of the squares
+        // (rows (a,a), columns F_b^2, ones at column nb): -1 leaves a term to
+        // the vector ALUs (P at 64 bins, general quads)
+        p.pg_sq_tiles = (nb + 31) / 32;
+        auto dsq = [](int a, int c) { return (a / 32) * 2048 + (a % 32) * 64 + c; };
+        for (int b = 0; b < nb; ++b) p.pg_idx.push_back(nb < 64 ? dsq(b, nb) : -1);
+        const int nq = (int)p.quad.size() / 4;
+        p.quads_collapsed = true;
+        for (int q = 0; q < nq; ++q) {
+            int a[4] = {p.quad[4 * q], p.quad[4 * q + 1], p.quad[4 * q + 2], p.quad[4 * q + 3]};
+            std::sort(a, a + 4);
+            const bool coll = a[0] == a[1] && a[2] == a[3];
+            p.quads_collapsed = p.quads_collapsed && coll;
+            p.pg_idx.push_back(coll ? dsq(a[0], a[2]) : -1);
+        }
         return;
     }
     for (int b = 0; b < nb; ++b) p.pg_idx.push_back(one_col ? dense(row_of[b * nb + b], nb) : dense(row_one[b], b));
@@ -768,19 +783,36 @@ bispec_status run_estimate_body(bispec_plan_s &p, const float *delta, int batch,
         float *fields = (float *)(ws + L.fields);
         bispec_status s = run_fields(p, delta, batch, fields);
         if (s != BISPEC_OK) return s;
-        if (p.pg_wide && p.precision == BISPEC_SPLIT_BF16 && first == 0 && ntri > 0) {
-            // 33..64 bins in split mode: the triplets on MFMA over the fields
-            // in HBM, P and quads on the vector ALUs below
-            double *pg = (double *)(ws + L.pg_partial);
-            double *dense = (double *)(ws + L.pg_dense);
-            const int64_t n_dense = (int64_t)wide_dense_doubles(p);
+        // 33..64 bins in split mode: the triplets on MFMA over the fields in
+        // HBM; then P and collapsed quads from the product-Gram of the
+        // squares (nb < 64); what is left runs on the vector ALUs below
+        const bool wide = p.pg_wide && p.precision == BISPEC_SPLIT_BF16;
+        // (the partial and dense regions hold the larger of the two passes;
+        // each pass strides its blocks by its own tile count)
+        double *pg = (double *)(ws + L.pg_partial);
+        double *dense = (double *)(ws + L.pg_dense);
+        if (wide && B && ntri > 0) {
+            const int64_t n_dense = (int64_t)p.n_mtile * 2048;
             CK(launch_pgram_fields(fields, n, p.nb, batch, (const uchar2 *)(ws + L.pg_pairs), p.n_mtile,
-                                   p.nblk_wide, pg, p.stream));
+                                   p.nblk_wide, pg, p.stream, false));
             CK(launch_reduce_dense(pg, p.nblk_wide, n_dense, batch, dense, (double *)(ws + L.pg_tmp), p.stream));
             s = finalize_range(p, true, dense, 1, n_dense, 0, ntri, batch, P, B, T);
             if (s != BISPEC_OK) return s;
             first = ntri;
             if (first == last && !T) return BISPEC_OK;
+        }
+        if (wide && p.nb < 64 && (first < last || (T && p.quads_collapsed))) {
+            const int64_t n_dense = (int64_t)p.pg_sq_tiles * 2048;
+            CK(launch_pgram_fields(fields, n, p.nb, batch, nullptr, p.pg_sq_tiles, p.nblk_wide, pg, p.stream, true));
+            CK(launch_reduce_dense(pg, p.nblk_wide, n_dense, batch, dense, (double *)(ws + L.pg_tmp), p.stream));
+            if (first < last) {
+                s = finalize_range(p, true, dense, 1, n_dense, first, last, batch, P, B, T);
+                if (s != BISPEC_OK) return s;
+                first = last;
+            }
+            if (T && p.quads_collapsed) return finalize_range(p, true, dense, 1, n_dense, t_first, t_last, batch, P, B, T);
+            if (!T) return BISPEC_OK;
+            return valu_terms(p, fields, t_first, t_last, batch, P, B, T);
         }
         if (!T) return valu_terms(p, fields, first, last, batch, P, B, T);
         if (first == last) return valu_terms(p, fields, t_first, t_last, batch, P, B, T);

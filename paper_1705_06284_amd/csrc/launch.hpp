@@ -84,12 +84,14 @@ int tail_ksplit(int n, int n_mtile, bool want_t, int shape);
 // 0..63, PGF_ROW_ZERO = zeros); partial [batch][nblk][n_mtile][32][64] FP64,
 // column z < nb the field F_z, the rest zero.  nblk blocks per map, each
 // contracting pgram_fields_chunk(n, nblk) <= PGF_MAX_CHUNK points (else
-// hipErrorInvalidValue).
+// hipErrorInvalidValue).  squares: the product-Gram of the squares (rows
+// (a,a), columns F_b^2 and ones at column nb; nb <= 63, n_mtile =
+// ceil(nb / 32), pairs unused).
 constexpr int PGF_ROW_ZERO = 64;
 constexpr int64_t PGF_MAX_CHUNK = 32768;
 int64_t pgram_fields_chunk(int n, int nblk);
 hipError_t launch_pgram_fields(const float *fields, int n, int nb, int batch, const uchar2 *pairs, int n_mtile,
-                               int nblk, double *partial, hipStream_t st);
+                               int nblk, double *partial, hipStream_t st, bool squares);
 // dense[map][e] = sum over the nblk partial sets; tmp holds
 // PG_REDUCE_SEGS * n_dense * batch doubles of segment sums (or null: one pass).
 constexpr int PG_REDUCE_SEGS = 32;

@@ -453,9 +453,14 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MINW))) void
 // loads are in flight during a step's contraction.  A chunk is at most
 // 32768 points, the split-mode span of FP32 accumulation; the block writes
 // its FP64 tile partials [n_mtile][32][64] (its own tiles only).
+// SQ: the product-Gram of the squares instead, rows (a,a) for a < nb (tile t
+// row r is a = 32 t + r) against the columns F_b^2, b < nb, and a column of
+// ones at b = nb (nb < 64): G[(a,a), b] = sum_n F_a^2 F_b^2 (the collapsed
+// p = 4 numerators) and G[(a,a), nb] = sum_n F_a^2 (the P numerators).
 constexpr int PGF_NT = 512, PGF_MAXR = 4, PGF_TK = 128;
 constexpr int PGF_TILES = PGF_NT / 64 * PGF_MAXR;
 
+template <bool SQ>
 __global__ __launch_bounds__(PGF_NT) void k_pgram_fields(const float *__restrict__ fields, int64_t npix, int nb,
                                                          int64_t map_stride, const uchar2 *__restrict__ pairs,
                                                          int n_mtile, int64_t chunk, double *__restrict__ partial) {
@@ -466,12 +471,20 @@ __global__ __launch_bounds__(PGF_NT) void k_pgram_fields(const float *__restrict
     const int tid = threadIdx.x, lane = tid & 63, col = lane & 31, half = lane >> 5;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int map = blockIdx.y;
-    // rows nb..63 and the zero row are never loaded: zero them once
+    // rows nb..63 and the zero row are never loaded: zero them once (SQ:
+    // column nb is the ones column)
     for (int i = tid; i < (PGF_ROW_ZERO + 1 - nb) * FS; i += PGF_NT) Ft[nb * FS + i] = 0.0f;
-    for (int i = tid; i < (64 - nb) * BS; i += PGF_NT) {
-        Bh[nb * BS + i] = (__bf16)0.0f;
-        Bl[nb * BS + i] = (__bf16)0.0f;
+    const int one_col = SQ && nb < 64 ? nb : -1;
+    const int zr = one_col >= 0 ? nb + 1 : nb;
+    for (int i = tid; i < (64 - zr) * BS; i += PGF_NT) {
+        Bh[zr * BS + i] = (__bf16)0.0f;
+        Bl[zr * BS + i] = (__bf16)0.0f;
     }
+    if (one_col >= 0)
+        for (int i = tid; i < BS; i += PGF_NT) {
+            Bh[one_col * BS + i] = (__bf16)1.0f;
+            Bl[one_col * BS + i] = (__bf16)0.0f;
+        }
     int tile_of[MAXR];
     uchar2 rp[MAXR];
     f32x16 acc[MAXR][2];
@@ -479,7 +492,13 @@ __global__ __launch_bounds__(PGF_NT) void k_pgram_fields(const float *__restrict
     for (int r = 0; r < MAXR; ++r) {
         const int t = blockIdx.z * PGF_TILES + wave + r * WAVES;
         tile_of[r] = t < n_mtile ? t : -1;
-        rp[r] = t < n_mtile ? pairs[t * 32 + col] : uchar2{PGF_ROW_ZERO, PGF_ROW_ZERO};
+        if constexpr (SQ) {
+            const int a = t * 32 + col;
+            rp[r] = t < n_mtile && a < nb ? uchar2{(unsigned char)a, (unsigned char)a}
+                                          : uchar2{PGF_ROW_ZERO, PGF_ROW_ZERO};
+        } else {
+            rp[r] = t < n_mtile ? pairs[t * 32 + col] : uchar2{PGF_ROW_ZERO, PGF_ROW_ZERO};
+        }
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
             acc[r][0][i] = 0.0f;
@@ -514,9 +533,10 @@ __global__ __launch_bounds__(PGF_NT) void k_pgram_fields(const float *__restrict
             const int b = e / (TK / 4), k = (e % (TK / 4)) * 4;
             const float4 v = pre[j];
             *reinterpret_cast<float4 *>(&Ft[b * FS + k]) = v;
+            const float4 w = SQ ? float4{v.x * v.x, v.y * v.y, v.z * v.z, v.w * v.w} : v;
             bf16x2 h0, l0, h1, l1;
-            split2(v.x, v.y, h0, l0);
-            split2(v.z, v.w, h1, l1);
+            split2(w.x, w.y, h0, l0);
+            split2(w.z, w.w, h1, l1);
             Bh[b * BS + k] = h0[0];
             Bh[b * BS + k + 1] = h0[1];
             Bh[b * BS + k + 2] = h1[0];
@@ -728,14 +748,19 @@ int64_t pgram_fields_chunk(int n, int nblk) {
 }
 
 hipError_t launch_pgram_fields(const float *fields, int n, int nb, int batch, const uchar2 *pairs, int n_mtile,
-                               int nblk, double *partial, hipStream_t st) {
+                               int nblk, double *partial, hipStream_t st, bool squares) {
     if (nb < 1 || nb > 64 || n_mtile < 1 || nblk < 1 || batch < 1) return hipErrorInvalidValue;
+    if (squares ? (nb > 63 || n_mtile != (nb + 31) / 32) : !pairs) return hipErrorInvalidValue;
     const int64_t npix = (int64_t)n * n * n;
     const int64_t chunk = pgram_fields_chunk(n, nblk);
     if (npix % PGF_TK != 0 || chunk > PGF_MAX_CHUNK) return hipErrorInvalidValue;
     const unsigned groups = (unsigned)((n_mtile + PGF_TILES - 1) / PGF_TILES);
-    hipLaunchKernelGGL(k_pgram_fields, dim3(nblk, batch, groups), dim3(PGF_NT), 0, st, fields, npix, nb,
-                       (int64_t)nb * npix, pairs, n_mtile, chunk, partial);
+    if (squares)
+        hipLaunchKernelGGL(k_pgram_fields<true>, dim3(nblk, batch, groups), dim3(PGF_NT), 0, st, fields, npix, nb,
+                           (int64_t)nb * npix, pairs, n_mtile, chunk, partial);
+    else
+        hipLaunchKernelGGL(k_pgram_fields<false>, dim3(nblk, batch, groups), dim3(PGF_NT), 0, st, fields, npix, nb,
+                           (int64_t)nb * npix, pairs, n_mtile, chunk, partial);
     return hipGetLastError();
 }
 

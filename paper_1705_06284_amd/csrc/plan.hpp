@@ -43,6 +43,7 @@ struct bispec_plan_s {
     bool quads_collapsed = false;        // every quad is (a,a,b,b) up to order
     bool pg_wide = false;                // 33..64 bins: product-Gram over the fields in HBM
     int nblk_wide = 1;                   // blocks per map of that product-Gram
+    int pg_sq_tiles = 0;                 // row tiles of its squares pass (P, collapsed T)
     int n_mtile = 0;                     // 32-row tiles of pair rows
     int nblk_pg = 1;                     // blocks of the product-Gram kernel (tuned)
     int nblk_pg_min = 1;                 // fewest blocks (chunk span limit)
