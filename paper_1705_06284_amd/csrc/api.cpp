@@ -93,7 +93,10 @@ Layout make_layout(const bispec_plan_s &p, int batch) {
     if (p.mfma_ok) {
         off = align_up(off + sizeof(double) * pgram_partial_doubles(p.n_mtile, true) * p.nblk_pg_max * batch);
     } else if (p.pg_wide) {
-        off = align_up(off + sizeof(double) * wide_dense_doubles(p) * p.nblk_wide * batch);
+        // per block: the triplet pass's tiles, or the K-part sets of the squares pass
+        const size_t sets = std::max((size_t)p.n_mtile,
+                                     (size_t)p.pg_sq_tiles * pgram_fields_kparts(p.pg_sq_tiles, true));
+        off = align_up(off + sizeof(double) * 2048 * sets * p.nblk_wide * batch);
     }
     L.pg_dense = off;
     if (p.mfma_ok) off = align_up(off + sizeof(double) * pgram_partial_doubles(p.n_mtile, true) * batch);
@@ -803,8 +806,9 @@ bispec_status run_estimate_body(bispec_plan_s &p, const float *delta, int batch,
         }
         if (wide && p.nb < 64 && (first < last || (T && p.quads_collapsed))) {
             const int64_t n_dense = (int64_t)p.pg_sq_tiles * 2048;
+            const int sets = p.nblk_wide * pgram_fields_kparts(p.pg_sq_tiles, true);
             CK(launch_pgram_fields(fields, n, p.nb, batch, nullptr, p.pg_sq_tiles, p.nblk_wide, pg, p.stream, true));
-            CK(launch_reduce_dense(pg, p.nblk_wide, n_dense, batch, dense, (double *)(ws + L.pg_tmp), p.stream));
+            CK(launch_reduce_dense(pg, sets, n_dense, batch, dense, (double *)(ws + L.pg_tmp), p.stream));
             if (first < last) {
                 s = finalize_range(p, true, dense, 1, n_dense, first, last, batch, P, B, T);
                 if (s != BISPEC_OK) return s;

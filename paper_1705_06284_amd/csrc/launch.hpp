@@ -86,10 +86,12 @@ int tail_ksplit(int n, int n_mtile, bool want_t, int shape);
 // contracting pgram_fields_chunk(n, nblk) <= PGF_MAX_CHUNK points (else
 // hipErrorInvalidValue).  squares: the product-Gram of the squares (rows
 // (a,a), columns F_b^2 and ones at column nb; nb <= 63, n_mtile =
-// ceil(nb / 32), pairs unused).
+// ceil(nb / 32), pairs unused), with pgram_fields_kparts K parts per block,
+// each its own partial set: partial [batch][nblk * kparts][n_mtile][32][64].
 constexpr int PGF_ROW_ZERO = 64;
 constexpr int64_t PGF_MAX_CHUNK = 32768;
 int64_t pgram_fields_chunk(int n, int nblk);
+int pgram_fields_kparts(int n_mtile, bool squares);
 hipError_t launch_pgram_fields(const float *fields, int n, int nb, int batch, const uchar2 *pairs, int n_mtile,
                                int nblk, double *partial, hipStream_t st, bool squares);
 // dense[map][e] = sum over the nblk partial sets; tmp holds

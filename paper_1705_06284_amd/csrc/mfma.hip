@@ -43,6 +43,7 @@ namespace bispec {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x2 __attribute__((ext_vector_type(2)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
@@ -457,6 +458,11 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MINW))) void
 // row r is a = 32 t + r) against the columns F_b^2, b < nb, and a column of
 // ones at b = nb (nb < 64): G[(a,a), b] = sum_n F_a^2 F_b^2 (the collapsed
 // p = 4 numerators) and G[(a,a), nb] = sum_n F_a^2 (the P numerators).
+// Its one or two row tiles would leave most waves idle, so the waves split
+// the K steps instead: wave w takes tile w % n_mtile and the steps
+// s = w / n_mtile (mod KS), KS = WAVES / n_mtile, and each K part writes its
+// own partial set (partial [batch][nblk][KS][n_mtile][32][64]); the
+// fixed-order reduction over nblk KS sets adds them.
 constexpr int PGF_NT = 512, PGF_MAXR = 4, PGF_TK = 128;
 constexpr int PGF_TILES = PGF_NT / 64 * PGF_MAXR;
 
@@ -468,6 +474,7 @@ __global__ __launch_bounds__(PGF_NT) void k_pgram_fields(const float *__restrict
     __shared__ __attribute__((aligned(16))) float Ft[(PGF_ROW_ZERO + 1) * FS];   // field rows, then a row of zeros
     __shared__ __attribute__((aligned(16))) __bf16 Bh[64 * BS];
     __shared__ __attribute__((aligned(16))) __bf16 Bl[64 * BS];
+    static_assert((BS * 2) % 16 == 0, "bf16 rows must keep 16-byte alignment");
     const int tid = threadIdx.x, lane = tid & 63, col = lane & 31, half = lane >> 5;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int map = blockIdx.y;
@@ -488,15 +495,17 @@ __global__ __launch_bounds__(PGF_NT) void k_pgram_fields(const float *__restrict
     int tile_of[MAXR];
     uchar2 rp[MAXR];
     f32x16 acc[MAXR][2];
+    const int ks = SQ ? WAVES / n_mtile : 1;           // K parts (SQ: n_mtile divides WAVES)
+    const int kpart = SQ ? wave / n_mtile : 0;
 #pragma unroll
     for (int r = 0; r < MAXR; ++r) {
-        const int t = blockIdx.z * PGF_TILES + wave + r * WAVES;
-        tile_of[r] = t < n_mtile ? t : -1;
         if constexpr (SQ) {
-            const int a = t * 32 + col;
-            rp[r] = t < n_mtile && a < nb ? uchar2{(unsigned char)a, (unsigned char)a}
-                                          : uchar2{PGF_ROW_ZERO, PGF_ROW_ZERO};
+            const int t = wave % n_mtile, a = t * 32 + col;
+            tile_of[r] = r == 0 ? t : -1;
+            rp[r] = a < nb ? uchar2{(unsigned char)a, (unsigned char)a} : uchar2{PGF_ROW_ZERO, PGF_ROW_ZERO};
         } else {
+            const int t = blockIdx.z * PGF_TILES + wave + r * WAVES;
+            tile_of[r] = t < n_mtile ? t : -1;
             rp[r] = t < n_mtile ? pairs[t * 32 + col] : uchar2{PGF_ROW_ZERO, PGF_ROW_ZERO};
         }
 #pragma unroll
@@ -537,19 +546,14 @@ __global__ __launch_bounds__(PGF_NT) void k_pgram_fields(const float *__restrict
             bf16x2 h0, l0, h1, l1;
             split2(w.x, w.y, h0, l0);
             split2(w.z, w.w, h1, l1);
-            Bh[b * BS + k] = h0[0];
-            Bh[b * BS + k + 1] = h0[1];
-            Bh[b * BS + k + 2] = h1[0];
-            Bh[b * BS + k + 3] = h1[1];
-            Bl[b * BS + k] = l0[0];
-            Bl[b * BS + k + 1] = l0[1];
-            Bl[b * BS + k + 2] = l1[0];
-            Bl[b * BS + k + 3] = l1[1];
+            // 8-byte stores: (b BS + k) 2 bytes is a multiple of 8 (BS = 136, k = 0 mod 4)
+            *reinterpret_cast<bf16x4 *>(&Bh[b * BS + k]) = bf16x4{h0[0], h0[1], h1[0], h1[1]};
+            *reinterpret_cast<bf16x4 *>(&Bl[b * BS + k]) = bf16x4{l0[0], l0[1], l1[0], l1[1]};
         }
         __syncthreads();
         if (p + TK < p1) fetch(p + TK);
 #pragma unroll 1
-        for (int s = 0; s < TK / 16; ++s) {
+        for (int s = kpart; s < TK / 16; s += ks) {
             const int kp = s * 16 + half * 8;
             const bf16x8 bh0 = *reinterpret_cast<const bf16x8 *>(&Bh[col * BS + kp]);
             const bf16x8 bl0 = *reinterpret_cast<const bf16x8 *>(&Bl[col * BS + kp]);
@@ -575,7 +579,7 @@ __global__ __launch_bounds__(PGF_NT) void k_pgram_fields(const float *__restrict
             }
         }
     }
-    double *base = partial + ((int64_t)map * gridDim.x + blockIdx.x) * ((int64_t)n_mtile * 2048);
+    double *base = partial + (((int64_t)map * gridDim.x + blockIdx.x) * ks + kpart) * ((int64_t)n_mtile * 2048);
 #pragma unroll
     for (int r = 0; r < MAXR; ++r) {
         if (tile_of[r] < 0) continue;
@@ -741,6 +745,8 @@ hipError_t launch_tail(int mode, bool want_t, const float2 *bc, const TailPairs 
                                                       shape);
 }
 
+int pgram_fields_kparts(int n_mtile, bool squares) { return squares ? PGF_NT / 64 / n_mtile : 1; }
+
 int64_t pgram_fields_chunk(int n, int nblk) {
     const int64_t npix = (int64_t)n * n * n;
     const int64_t c = (npix + nblk - 1) / nblk;
@@ -750,11 +756,12 @@ int64_t pgram_fields_chunk(int n, int nblk) {
 hipError_t launch_pgram_fields(const float *fields, int n, int nb, int batch, const uchar2 *pairs, int n_mtile,
                                int nblk, double *partial, hipStream_t st, bool squares) {
     if (nb < 1 || nb > 64 || n_mtile < 1 || nblk < 1 || batch < 1) return hipErrorInvalidValue;
-    if (squares ? (nb > 63 || n_mtile != (nb + 31) / 32) : !pairs) return hipErrorInvalidValue;
+    if (squares ? (nb > 63 || n_mtile != (nb + 31) / 32 || (PGF_NT / 64) % n_mtile != 0) : !pairs)
+        return hipErrorInvalidValue;
     const int64_t npix = (int64_t)n * n * n;
     const int64_t chunk = pgram_fields_chunk(n, nblk);
     if (npix % PGF_TK != 0 || chunk > PGF_MAX_CHUNK) return hipErrorInvalidValue;
-    const unsigned groups = (unsigned)((n_mtile + PGF_TILES - 1) / PGF_TILES);
+    const unsigned groups = squares ? 1u : (unsigned)((n_mtile + PGF_TILES - 1) / PGF_TILES);
     if (squares)
         hipLaunchKernelGGL(k_pgram_fields<true>, dim3(nblk, batch, groups), dim3(PGF_NT), 0, st, fields, npix, nb,
                            (int64_t)nb * npix, pairs, n_mtile, chunk, partial);

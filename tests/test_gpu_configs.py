@@ -182,6 +182,38 @@ def test_wide_bins_64_all_outputs(binding):
     assert np.max(np.abs(P2.cpu().numpy()[0] - P0.cpu().numpy()[0]) / P0.cpu().numpy()[0]) <= TOL["split_bf16"]
 
 
+def test_sixty_four_bins(binding):
+    # the 64-bin limit: no room for the column of ones, so P and the quads
+    # take the FP32 vector-ALU terms while B stays on the fields product-Gram
+    n = 64
+    e = 2.0 + 0.45 * np.arange(65)
+    lo, hi = e[:-1], e[1:]
+    d = synth.lognormal_field(n, 1.5, 1.0, 23).astype(np.float32)
+    _say("64^3, 64 bins of 0.45 k_f")
+    plan = binding.Plan(n, lo, hi)
+    P, B, T = plan.polyspec(d)
+    trip, quads = plan.triplets, plan.quads
+    _say("  %d triplets, %d quads" % (len(trip), len(quads)))
+    m = oracle.mode_counts(n, lo, hi)
+    Dk = oracle.dft3(oracle.prepare(d))
+    key = np.array([sorted(int(b) for b in t)[:2] for t in trip])
+    sel = np.flatnonzero(m[key[:, 0]].astype(float) * m[key[:, 1]] <= 1e6)
+    ref = oracle.bispectrum(d, lo, hi, trip[sel], delta_k=Dk)
+    assert np.array_equal(plan.counts[sel].astype(np.int64), ref.count)
+    err = np.abs(B.cpu().numpy()[0][sel] - ref.value) / np.maximum(np.abs(ref.value), ref.noise)
+    mm = m[trip[sel]].astype(float)
+    kappa = np.sqrt(mm[:, 0] * mm[:, 1] * mm[:, 2] / (float(n) ** 3 * ref.count))
+    _say("  %d sampled triplets, max err %.2e (max kappa %.1f)" % (len(sel), err.max(), kappa.max()))
+    assert np.all(err <= TOL["split_bf16"] * np.maximum(1.0, kappa / 2.0))
+    refp, _ = oracle.power_spectrum(d, lo, hi, delta_k=Dk)
+    assert np.max(np.abs(P.cpu().numpy()[0] - refp) / refp) <= TOL["fp32"]
+    qs = [q for q in range(len(quads)) if max(quads[q]) <= 4]
+    reft = oracle.trispectrum(d, lo, hi, quads[qs], delta_k=Dk)
+    et = np.abs(T.cpu().numpy()[0][qs] - reft.value) / np.maximum(np.abs(reft.value), reft.noise)
+    _say("  %d quads, max err %.2e" % (len(qs), et.max()))
+    assert et.max() <= TOL["fp32"]
+
+
 def test_rebin_argument_errors(binding):
     n = 16
     lo, hi = synth.unit_bins(1, 7)
