@@ -260,7 +260,7 @@ void build_pgram_tables(bispec_plan_s &p) {
     p.pg_idx.clear();
     if (!p.mfma_ok && !p.pg_wide) return;
     // 33..64 bins: rows are the cover of the triplets alone over 64 columns of
-    // fields in HBM (P and quads take the vector-ALU terms)
+    // fields in HBM (P and collapsed quads come from the squares pass)
     const bool wide = p.pg_wide;
     const int row_zero = wide ? PGF_ROW_ZERO : PG_ROW_ZERO;
     std::vector<int> row_of(nb * nb, -1), row_one(nb, -1);

@@ -8,9 +8,12 @@
 //                              inverse pass (Eq. delta_nr): the two real bin
 //                              fields come out as the real and imaginary
 //                              parts of one complex inverse transform
-//   k_inv_y_prune, k_inv_x_compact  remaining inverse passes (the x pass is
-//                              fused into the contraction on the estimate
-//                              path, mfma.hip)
+//   k_inv_y_prune, k_inv_x_pairs, k_inv_x_compact  remaining inverse passes
+//                              (up to 32 bins the x pass is fused into the
+//                              contraction on the estimate path, mfma.hip;
+//                              k_inv_x_pairs writes every bin field to HBM
+//                              in one launch, k_inv_x_compact the FP64
+//                              count fields of one pair)
 //   k_contract_terms           sum_n of products of 2, 3 or 4 bin fields
 //                              (numerators and denominators of Eqs. Jeong_PS,
 //                              Jeong_BI, Jeong_gen), per-block FP64 partials
