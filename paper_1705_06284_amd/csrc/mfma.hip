@@ -463,7 +463,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MINW))) void
 // s = w / n_mtile (mod KS), KS = WAVES / n_mtile, and each K part writes its
 // own partial set (partial [batch][nblk][KS][n_mtile][32][64]); the
 // fixed-order reduction over nblk KS sets adds them.
-constexpr int PGF_NT = 512, PGF_MAXR = 4, PGF_TK = 128;
+constexpr int PGF_NT = 1024, PGF_MAXR = 2, PGF_TK = 128;
 constexpr int PGF_TILES = PGF_NT / 64 * PGF_MAXR;
 
 template <bool SQ>
