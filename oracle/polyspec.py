@@ -343,3 +343,55 @@ def collapsed_quads(n_bins):
     """(a, a, b, b) for a <= b: the collapsed p = 4 configurations."""
     return np.array([(a, a, b, b) for a in range(n_bins) for b in range(a, n_bins)],
                     dtype=np.int32).reshape(-1, 4)
+
+
+def disconnected_sums(delta, k_lo, k_hi, quads, delta_k=None):
+    """S_D per collapsed quad (a, a, b, b): the sum of D(k1) D(k2) D(k3) D(k4)
+    over the closed quadruples (k1, k2 in S_a; k3, k4 in S_b) that split into
+    two pairs k_i = -k_j (the Gaussian pairings of Wick's theorem), each
+    quadruple counted once.  Written out as the union of the three pairing
+    sets, enumerated mode by mode and de-duplicated."""
+    d = prepare(delta)
+    n = d.shape[0]
+    if delta_k is None:
+        delta_k = dft3(d)
+    out = np.zeros(len(quads), dtype=np.complex128)
+    for q, quad in enumerate(np.asarray(quads).reshape(-1, 4)):
+        a, a2, b, b2 = sorted(int(x) for x in quad)
+        if a != a2 or b != b2:
+            raise ValueError("only collapsed quads (a, a, b, b)")
+        sa = [tuple(int(c) for c in m) for m in shell_modes(n, k_lo, k_hi, a)]
+        sb = [tuple(int(c) for c in m) for m in shell_modes(n, k_lo, k_hi, b)]
+        in_a, in_b = set(sa), set(sb)
+        neg = lambda m: (-m[0], -m[1], -m[2])
+        quadset = set()
+        for k1 in sa:
+            for k3 in sb:
+                quadset.add((k1, neg(k1), k3, neg(k3)))           # k2 = -k1, k4 = -k3
+        for k1 in sa:
+            if neg(k1) not in in_b:
+                continue
+            for k2 in sa:
+                if neg(k2) in in_b:
+                    quadset.add((k1, k2, neg(k1), neg(k2)))       # k3 = -k1, k4 = -k2
+                    quadset.add((k1, k2, neg(k2), neg(k1)))       # k4 = -k1, k3 = -k2
+        amp = lambda m: delta_k[m[0] % n, m[1] % n, m[2] % n]
+        out[q] = sum(amp(t[0]) * amp(t[1]) * amp(t[2]) * amp(t[3]) for t in quadset)
+    return out
+
+
+def trispectrum_connected(delta, k_lo, k_hi, quads, box_len=None, delta_k=None):
+    """Collapsed T with the Gaussian pairings removed: (V^3 / N_pix^4)
+    Re(S_q - S_D) / N_q, S_q the closed-quadruple sum of Eq. Jeong_gen and
+    S_D the part of it over paired quadruples (disconnected_sums)."""
+    d = prepare(delta)
+    n = d.shape[0]
+    if delta_k is None:
+        delta_k = dft3(d)
+    full = trispectrum(d, k_lo, k_hi, quads, box_len=box_len, delta_k=delta_k)
+    sd = disconnected_sums(d, k_lo, k_hi, quads, delta_k=delta_k)
+    vol = _volume(n, box_len)
+    npix = float(n) ** 3
+    with np.errstate(invalid="ignore", divide="ignore"):
+        val = vol ** 3 / npix ** 4 * (full.s - sd).real / full.count
+    return val, full, sd
