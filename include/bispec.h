@@ -154,6 +154,25 @@ bispec_status bispec_estimate(bispec_plan_t plan, const float *delta, int32_t ba
 bispec_status trispec_estimate(bispec_plan_t plan, const float *delta, int32_t batch,
                                double *T);
 
+/* Connected collapsed trispectrum: the raw T of Eq. Jeong_gen (p = 4) for
+ * every quad (a,a,b,b), and Tc, the same estimate with the quadruples that
+ * split into two pairs k_i = -k_j removed -- the Gaussian (disconnected)
+ * pairings of Wick's theorem, measured on the map itself:
+ *     Tc = T - V^3 / N_pix^4 * S_D / N_q,
+ *     S_D = X_a X_b              (a != b, disjoint shells)
+ *     S_D = 3 X_a^2 - 3 Y_a      (a = b; inclusion-exclusion over the three
+ *                                 pairings, which share the quadruples
+ *                                 (k,-k,-k,k), (k,-k,k,-k), (k,k,-k,-k))
+ * with X_b = sum_{m in S_b} |Delta(m)|^2 and Y_b = sum |Delta(m)|^4 in FP64
+ * over the FP32 spectrum.  For a Gaussian field Tc has zero mean.  The paper
+ * names the trispectrum but evaluates none (Section 2); this removal of the
+ * disconnected part is a reading of "connected".
+ * T, Tc: device [batch][n_quad] FP64.  BISPEC_E_INVALID if a quad is not
+ * collapsed, if the two shells of a quad (a,a,b,b), a != b, overlap, or for
+ * NULL pointers. */
+bispec_status trispec_connected_estimate(bispec_plan_t plan, const float *delta, int32_t batch,
+                                         double *T, double *Tc);
+
 /* P, B and T from one set of bin fields (lower orders at no extra FFT cost,
  * Section 2 after Eq. Jeong_BI).  Any of P, B, T may be NULL. */
 bispec_status polyspec_estimate(bispec_plan_t plan, const float *delta, int32_t batch,

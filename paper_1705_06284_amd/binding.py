@@ -58,6 +58,7 @@ _SIGS = {
     "bispec_bin_fields": [_vp, _vp, _i32, _vp],
     "bispec_estimate": [_vp, _vp, _i32, _vp, _vp],
     "trispec_estimate": [_vp, _vp, _i32, _vp],
+    "trispec_connected_estimate": [_vp, _vp, _i32, _vp, _vp],
     "polyspec_estimate": [_vp, _vp, _i32, _vp, _vp, _vp],
     "bispec_timing_enable": [_vp, _i32],
     "bispec_graph_enable": [_vp, _i32],
@@ -90,6 +91,7 @@ bispec_plan_mode_counts = _lib.bispec_plan_mode_counts
 bispec_bin_fields = _lib.bispec_bin_fields
 bispec_estimate = _lib.bispec_estimate
 trispec_estimate = _lib.trispec_estimate
+trispec_connected_estimate = _lib.trispec_connected_estimate
 polyspec_estimate = _lib.polyspec_estimate
 bispec_timing_enable = _lib.bispec_timing_enable
 bispec_graph_enable = _lib.bispec_graph_enable
@@ -341,6 +343,16 @@ class Plan:
         T = self._empty(bsz, self.n_quad)
         check(trispec_estimate(self.handle, _ptr(d), bsz, _ptr(T)), "trispec_estimate")
         return T
+
+    def trispec_connected(self, delta):
+        """(T, Tc) as in trispec_connected_estimate: the raw and the connected
+        collapsed trispectrum, device tensors [batch, n_quad]."""
+        d = self._input(delta)
+        bsz = d.shape[0]
+        T = self._empty(bsz, self.n_quad)
+        Tc = self._empty(bsz, self.n_quad)
+        check(trispec_connected_estimate(self.handle, _ptr(d), bsz, _ptr(T), _ptr(Tc)), "trispec_connected_estimate")
+        return T, Tc
 
     def bin_fields(self, delta):
         d = self._input(delta)

@@ -19,6 +19,7 @@
 
 #include "../../include/bispec.h"
 #include "launch.hpp"
+#include "moments.hpp"
 #include "plan.hpp"
 
 using namespace bispec;
@@ -77,6 +78,9 @@ Layout make_layout(const bispec_plan_s &p, int batch) {
     L.terms = off;        off = align_up(off + sizeof(uchar4) * p.terms.size());
     L.scale = off;        off = align_up(off + sizeof(double) * p.scale.size());
     L.tcount = off;       off = align_up(off + sizeof(double) * p.tri_count.size());
+    L.thr = off;          off = align_up(off + sizeof(int) * 2 * p.nb);
+    L.mom_partial = off;  off = align_up(off + sizeof(double) * kMomBlocks * 2 * p.nb * batch);
+    L.mom = off;          off = align_up(off + sizeof(double) * 2 * p.nb * batch);
     L.pg_pairs = off;     off = align_up(off + sizeof(uchar2) * p.pg_pairs.size());
     L.pg_idx = off;       off = align_up(off + sizeof(int) * p.pg_idx.size());
     L.cols = off;         off = align_up(off + sizeof(int) * p.cols.size());
@@ -666,6 +670,9 @@ bispec_status upload_tables(bispec_plan_s &p) {
     if (!p.tri_count.empty())
         CK(hipMemcpyAsync(ws + L.tcount, p.tri_count.data(), sizeof(double) * p.tri_count.size(),
                           hipMemcpyHostToDevice, p.stream));
+    std::vector<int> thr(p.ilo2);
+    thr.insert(thr.end(), p.ihi2.begin(), p.ihi2.end());
+    CK(hipMemcpyAsync(ws + L.thr, thr.data(), sizeof(int) * thr.size(), hipMemcpyHostToDevice, p.stream));
     CK(hipMemcpyAsync(ws + L.cols, p.cols.data(), sizeof(int) * p.cols.size(), hipMemcpyHostToDevice, p.stream));
     const std::vector<PairDev> pd = pair_devs(p);
     CK(hipMemcpyAsync(ws + L.pd, pd.data(), sizeof(PairDev) * pd.size(), hipMemcpyHostToDevice, p.stream));
@@ -1190,6 +1197,34 @@ bispec_status bispec_estimate(bispec_plan_t plan, const float *delta, int32_t ba
 bispec_status trispec_estimate(bispec_plan_t plan, const float *delta, int32_t batch, double *T) {
     if (!T) return BISPEC_E_INVALID;
     return polyspec_estimate(plan, delta, batch, nullptr, nullptr, T);
+}
+
+bispec_status trispec_connected_estimate(bispec_plan_t plan, const float *delta, int32_t batch, double *T,
+                                        double *Tc) {
+    if (!T || !Tc) return BISPEC_E_INVALID;
+    bispec_status s = check_call(plan, delta, batch);
+    if (s != BISPEC_OK) return s;
+    bispec_plan_s &p = *plan;
+    const int nq = (int)p.quad.size() / 4, ntri = (int)p.tri.size() / 3;
+    for (int q = 0; q < nq; ++q) {
+        int a[4] = {p.quad[4 * q], p.quad[4 * q + 1], p.quad[4 * q + 2], p.quad[4 * q + 3]};
+        std::sort(a, a + 4);
+        if (a[0] != a[1] || a[2] != a[3]) return BISPEC_E_INVALID;                 // collapsed quads only
+        const int x = a[0], y = a[2];
+        if (x != y && p.ilo2[x] < p.ihi2[y] && p.ilo2[y] < p.ihi2[x]) return BISPEC_E_INVALID;   // shells overlap
+    }
+    s = polyspec_estimate(plan, delta, batch, nullptr, nullptr, T);
+    if (s != BISPEC_OK) return s;
+    const Layout L = make_layout(p, p.max_batch);
+    char *ws = (char *)p.ws;
+    const double npix = (double)p.n * p.n * p.n;
+    CK(launch_shell_moments((const float2 *)(ws + L.spec), spec_elems(p.n), p.n, p.nb, batch,
+                            (const int *)(ws + L.thr), kMomBlocks, (double *)(ws + L.mom_partial), p.stream));
+    CK(launch_reduce_dense((const double *)(ws + L.mom_partial), kMomBlocks, 2 * p.nb, batch,
+                           (double *)(ws + L.mom), nullptr, p.stream));
+    CK(launch_trispec_connected(T, (const double *)(ws + L.mom), (const uchar4 *)(ws + L.terms) + ntri + p.nb,
+                                (const double *)(ws + L.scale) + ntri + p.nb, npix, nq, p.nb, batch, Tc, p.stream));
+    return BISPEC_OK;
 }
 
 bispec_status bispec_timing_enable(bispec_plan_t plan, int32_t on) {

@@ -22,6 +22,9 @@
 //   k_rebin                    count-weighted averages of B over groups of
 //                              triplets (configuration binning)
 //   k_shell_hist               modes per shell (wave ballot + popcount)
+//   k_shell_moments, k_trispec_connected  per-shell sums of |Delta|^2 and
+//                              |Delta|^4, and the collapsed T with its
+//                              Gaussian pairings removed
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -29,6 +32,7 @@
 
 #include "fft_core.hpp"
 #include "launch.hpp"
+#include "moments.hpp"
 
 namespace bispec {
 
@@ -583,6 +587,88 @@ __global__ __launch_bounds__(RB_NT) void k_rebin(const double *__restrict__ B, i
     }
 }
 
+// Per-shell moments of the half spectrum: X_b = sum_{m in S_b} |D(m)|^2 and
+// Y_b = sum_{m in S_b} |D(m)|^4 over the full spectrum (an entry with
+// m_x > 0 stands for m and -m, which have the same modulus; the m_x = 0
+// plane holds both of each pair).  Each step the block's 256 entries go to
+// LDS, and thread b < nb adds those of shell b in index order; block
+// partials partial[map][block][b][2] are summed in a fixed order afterwards.
+__global__ __launch_bounds__(256) void k_shell_moments(const float2 *__restrict__ spec, int64_t spec_stride, int n,
+                                                       int hp, int nb, const int *__restrict__ thr,
+                                                       double *__restrict__ partial) {
+    __shared__ int r2s[256];
+    __shared__ double v2s[256], v4s[256];
+    const int map = blockIdx.y, tid = threadIdx.x;
+    const int xw = n / 2 + 1;
+    const int64_t total = (int64_t)n * n * xw;
+    const float2 *sp = spec + (int64_t)map * spec_stride;
+    const int lo2 = tid < nb ? thr[tid] : 0, hi2 = tid < nb ? thr[nb + tid] : 0;
+    double ax = 0.0, ay = 0.0;
+    for (int64_t base = (int64_t)blockIdx.x * 256; base < total; base += (int64_t)gridDim.x * 256) {
+        const int64_t e = base + tid;
+        int r2 = -1;
+        double v2 = 0.0, v4 = 0.0;
+        if (e < total) {
+            const int x = (int)(e % xw);
+            const int64_t row = e / xw;
+            const int y = (int)(row % n), z = (int)(row / n);
+            const int mz = signed_freq(z, n), my = signed_freq(y, n);
+            r2 = mz * mz + my * my + x * x;
+            const float2 v = sp[row * hp + x];
+            const double a = (double)v.x * v.x + (double)v.y * v.y;
+            const double w = x == 0 ? 1.0 : 2.0;
+            v2 = w * a;
+            v4 = w * a * a;
+        }
+        r2s[tid] = r2;
+        v2s[tid] = v2;
+        v4s[tid] = v4;
+        __syncthreads();
+        if (tid < nb)
+            for (int i = 0; i < 256; ++i) {
+                const int q = r2s[i];
+                if (q > 0 && q >= lo2 && q < hi2) {
+                    ax += v2s[i];
+                    ay += v4s[i];
+                }
+            }
+        __syncthreads();
+    }
+    if (tid < nb) {
+        double *o = partial + (((int64_t)map * gridDim.x + blockIdx.x) * nb + tid) * 2;
+        o[0] = ax;
+        o[1] = ay;
+    }
+}
+
+// Connected collapsed T: Tc = T - scale N_pix S_D for the quad (a,a,b,b),
+// S_D = X_a X_b, plus 2 X_a^2 - 3 Y_a when a = b (the three Gaussian
+// pairings of k1..k4, inclusion-exclusion over their common quadruples
+// (k,-k,-k,k) and the like; for disjoint shells a != b only k2 = -k1,
+// k4 = -k3 pairs).  mom [map][nb][2] = (X, Y); scale is the raw T's
+// normalisation per quad, V^3 / N_pix^4 / (N_pix N_q).
+__global__ __launch_bounds__(256) void k_trispec_connected(const double *__restrict__ T,
+                                                           const double *__restrict__ mom,
+                                                           const uchar4 *__restrict__ quads,
+                                                           const double *__restrict__ scale, double npix, int nq,
+                                                           int nb, double *__restrict__ Tc) {
+    const int q = blockIdx.x * 256 + threadIdx.x, map = blockIdx.y;
+    if (q >= nq) return;
+    const uchar4 t = quads[q];
+    int s[4] = {t.x, t.y, t.z, t.w};
+    for (int i = 1; i < 4; ++i)
+        for (int j = i; j > 0 && s[j] < s[j - 1]; --j) {
+            const int u = s[j];
+            s[j] = s[j - 1];
+            s[j - 1] = u;
+        }
+    const int a = s[0], b = s[2];
+    const double *m = mom + (int64_t)map * nb * 2;
+    const double xa = m[2 * a], xb = m[2 * b], ya = m[2 * a + 1];
+    const double sd = xa * xb + (a == b ? 2.0 * xa * xa - 3.0 * ya : 0.0);
+    Tc[(int64_t)map * nq + q] = T[(int64_t)map * nq + q] - scale[q] * npix * sd;
+}
+
 // ---------------------------------------------------------------------------
 // Modes per shell: each thread classifies one grid mode; a wave ballot and a
 // popcount give the wave's count per bin, one integer atomic per wave.
@@ -763,6 +849,23 @@ hipError_t launch_finalize(const double *partial, int nblk, int nterm, int batch
 hipError_t launch_rebin(const double *B, int n_tri, const double *count, const int *group, int n_group, int batch,
                         double *out, hipStream_t st) {
     hipLaunchKernelGGL(k_rebin, dim3(n_group, batch), dim3(RB_NT), 0, st, B, n_tri, count, group, n_group, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_shell_moments(const float2 *spec, int64_t spec_stride, int n, int nb, int batch, const int *thr,
+                                int nblk, double *partial, hipStream_t st) {
+    if (nb < 1 || nb > 256 || nblk < 1) return hipErrorInvalidValue;
+    const int hp = (int)(spec_elems(n) / ((int64_t)n * n));
+    hipLaunchKernelGGL(k_shell_moments, dim3(nblk, batch), dim3(256), 0, st, spec, spec_stride, n, hp, nb, thr,
+                       partial);
+    return hipGetLastError();
+}
+
+hipError_t launch_trispec_connected(const double *T, const double *mom, const uchar4 *quads, const double *scale,
+                                    double npix, int nq, int nb, int batch, double *Tc, hipStream_t st) {
+    if (nq < 1) return hipSuccess;
+    hipLaunchKernelGGL(k_trispec_connected, dim3((nq + 255) / 256, batch), dim3(256), 0, st, T, mom, quads, scale,
+                       npix, nq, nb, Tc);
     return hipGetLastError();
 }
 

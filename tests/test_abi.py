@@ -82,5 +82,6 @@ def test_null_arguments(b):
     assert b.bispec_bin_fields(None, None, 1, None) == -1
     assert b.bispec_theta_groups(None, 0, 0, 20, None, None) == -1
     assert b.bispec_rebin(None, None, 1, None, 1, None) == -1
+    assert b.trispec_connected_estimate(None, None, 1, None, None) == -1
     sz = ctypes.c_size_t()
     assert b.bispec_plan_footprint(None, 1, ctypes.byref(sz)) == -1

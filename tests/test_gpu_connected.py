@@ -1,0 +1,78 @@
+"""GPU parity of the connected collapsed trispectrum (trispec_connected_estimate).
+
+Reference: oracle.polyspec.trispectrum_connected (direct closed-quadruple sums
+minus the paired quadruples, enumerated mode by mode).  Bar per quad:
+|Tc - Tc_ref| <= TOL max(|T_ref|, T_noise) + 2e-6 |T_ref - Tc_ref|.  Tc is T
+minus the disconnected part, so it carries the raw T's absolute error, whose
+bound is TOL max(|T_ref|, T_noise) (FP32 1e-5, split-BF16 1e-4), plus the
+error of the subtracted part, which the library sums in FP64 from the FP32
+spectrum (relative error of each |Delta|^2 about 1e-6).  For collapsed
+quads |T_ref| is far above the noise level (the disconnected part
+dominates), so Tc is known to a fixed fraction of T, not of itself.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import oracle  # noqa: E402
+from oracle import polyspec  # noqa: E402
+from paper_1705_06284_amd import synth  # noqa: E402
+
+TOL = {"fp32": 1e-5, "split_bf16": 1e-4}
+
+
+@pytest.fixture(scope="module")
+def binding():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1705_06284_amd import binding as b
+    return b
+
+
+@pytest.mark.parametrize("prec", ["fp32", "split_bf16"])
+def test_connected_trispectrum_32(binding, prec):
+    n = 32
+    lo, hi = synth.unit_bins(1, 8)
+    d0 = synth.lognormal_field(n, 1.5, 1.0, 41).astype(np.float32)
+    d1 = synth.gaussian_field(n, 1.0, 1.0, 42).astype(np.float32)
+    print("connected T 32^3 %s" % prec, flush=True)
+    plan = binding.Plan(n, lo, hi, precision=prec, max_batch=2)
+    T, Tc = plan.trispec_connected(np.stack([d0, d1]))
+    quads = plan.quads
+    sel = [q for q in range(len(quads)) if max(quads[q]) <= 4]
+    for k, d in enumerate((d0, d1)):
+        val, full, sd = polyspec.trispectrum_connected(d, lo, hi, quads[sel])
+        t = T.cpu().numpy()[k][sel]
+        tc = Tc.cpu().numpy()[k][sel]
+        et = np.abs(t - full.value) / np.maximum(np.abs(full.value), full.noise)
+        bar = TOL[prec] * np.maximum(np.abs(full.value), full.noise) + 2e-6 * np.abs(full.value - val)
+        ec = np.abs(tc - val) / bar
+        print("  map %d: %d quads, raw T max err %.2e, connected max err / bar %.2f, |T_disc| / noise up to %.1f"
+              % (k, len(sel), et.max(), ec.max(), np.max(np.abs(full.value - val) / full.noise)), flush=True)
+        assert et.max() <= TOL[prec]
+        assert ec.max() <= 1.0
+    # one map alone gives the same result bit for bit
+    T0, Tc0 = plan.trispec_connected(d0)
+    assert np.array_equal(Tc0.cpu().numpy()[0], Tc.cpu().numpy()[0])
+
+
+def test_connected_trispectrum_rejects_general_and_overlapping(binding):
+    n = 16
+    lo, hi = synth.unit_bins(1, 4)
+    d = synth.lognormal_field(n, 1.5, 1.0, 43).astype(np.float32)
+    plan = binding.Plan(n, lo, hi, quads=[(0, 1, 2, 3)], precision="fp32")
+    with pytest.raises(binding.BispecError) as ex:
+        plan.trispec_connected(d)
+    assert ex.value.code == -1          # BISPEC_E_INVALID: not a collapsed quad
+    lo2, hi2 = np.array([1.0, 1.5]), np.array([2.5, 3.0])
+    plan2 = binding.Plan(n, lo2, hi2, quads=[(0, 0, 1, 1)], precision="fp32")
+    with pytest.raises(binding.BispecError) as ex:
+        plan2.trispec_connected(d)
+    assert ex.value.code == -1          # BISPEC_E_INVALID: the two shells overlap
+    plan3 = binding.Plan(n, lo2, hi2, quads=[(1, 1, 1, 1)], precision="fp32")
+    T, Tc = plan3.trispec_connected(d)   # one shell with itself is fine
+    val, full, _ = polyspec.trispectrum_connected(d, lo2, hi2, np.array([(1, 1, 1, 1)]))
+    assert abs(Tc.cpu().numpy()[0][0] - val[0]) <= (1e-5 * max(abs(full.value[0]), full.noise[0])
+                                                    + 2e-6 * abs(full.value[0] - val[0]))
