@@ -324,6 +324,24 @@ def main():
                            "latency_ms": {"p50": percentile(latg, 50), "p99": percentile(latg, 99)}}
 
     if not args.no_compare:
+        # comparisons: the connected collapsed T (Gaussian pairings removed)
+        # against the raw T alone, same plan and map; then the FP32 paths
+        Tc = torch.empty_like(T)
+
+        def t_only():
+            binding.check(binding.polyspec_estimate(plan.handle, binding._ptr(d), bsz, None, None, binding._ptr(T)),
+                          "polyspec_estimate")
+
+        def t_conn():
+            binding.check(binding.trispec_connected_estimate(plan.handle, binding._ptr(d), bsz, binding._ptr(T),
+                                                             binding._ptr(Tc)), "trispec_connected_estimate")
+
+        t_only()
+        t_conn()
+        w_t, _ = timed_steps(torch, t_only, args.steps, stream)
+        w_c, _ = timed_steps(torch, t_conn, args.steps, stream)
+        out["connected_T"] = {"quads": nq, "ms_per_map_raw_T": 1e3 * w_t / (args.steps * bsz),
+                              "ms_per_map_connected": 1e3 * w_c / (args.steps * bsz)}
         w32, lat32, st32 = run("fp32", args.steps, 2, timing=True)
         wv, latv, stv = run("fp32_valu", max(3, args.steps // 4), 1, timing=True)
         kv = max(3, args.steps // 4)
