@@ -80,6 +80,7 @@ Layout make_layout(const bispec_plan_s &p, int batch) {
     L.tcount = off;       off = align_up(off + sizeof(double) * p.tri_count.size());
     L.thr = off;          off = align_up(off + sizeof(int) * 2 * p.nb);
     L.mom_partial = off;  off = align_up(off + sizeof(double) * kMomBlocks * 2 * p.nb * batch);
+    L.mom_tmp = off;      off = align_up(off + sizeof(double) * PG_REDUCE_SEGS * 2 * p.nb * batch);
     L.mom = off;          off = align_up(off + sizeof(double) * 2 * p.nb * batch);
     L.pg_pairs = off;     off = align_up(off + sizeof(uchar2) * p.pg_pairs.size());
     L.pg_idx = off;       off = align_up(off + sizeof(int) * p.pg_idx.size());
@@ -1221,7 +1222,7 @@ bispec_status trispec_connected_estimate(bispec_plan_t plan, const float *delta,
     CK(launch_shell_moments((const float2 *)(ws + L.spec), spec_elems(p.n), p.n, p.nb, batch,
                             (const int *)(ws + L.thr), kMomBlocks, (double *)(ws + L.mom_partial), p.stream));
     CK(launch_reduce_dense((const double *)(ws + L.mom_partial), kMomBlocks, 2 * p.nb, batch,
-                           (double *)(ws + L.mom), nullptr, p.stream));
+                           (double *)(ws + L.mom), (double *)(ws + L.mom_tmp), p.stream));
     CK(launch_trispec_connected(T, (const double *)(ws + L.mom), (const uchar4 *)(ws + L.terms) + ntri + p.nb,
                                 (const double *)(ws + L.scale) + ntri + p.nb, npix, nq, p.nb, batch, Tc, p.stream));
     return BISPEC_OK;

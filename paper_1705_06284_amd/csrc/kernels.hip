@@ -590,20 +590,31 @@ __global__ __launch_bounds__(RB_NT) void k_rebin(const double *__restrict__ B, i
 // Per-shell moments of the half spectrum: X_b = sum_{m in S_b} |D(m)|^2 and
 // Y_b = sum_{m in S_b} |D(m)|^4 over the full spectrum (an entry with
 // m_x > 0 stands for m and -m, which have the same modulus; the m_x = 0
-// plane holds both of each pair).  Each step the block's 256 entries go to
-// LDS, and thread b < nb adds those of shell b in index order; block
-// partials partial[map][block][b][2] are summed in a fixed order afterwards.
+// plane holds both of each pair).  Each step covers 256 entries: the block
+// finds their |m|^2 range, and for every shell that meets it sums the
+// members' values with wave shuffles and a fixed-order combination of the
+// four wave sums into an LDS accumulator of the shell.  Block partials
+// partial[map][block][b][2] are summed in a fixed order afterwards.
+constexpr int SM_MAXB = 64;
+
 __global__ __launch_bounds__(256) void k_shell_moments(const float2 *__restrict__ spec, int64_t spec_stride, int n,
                                                        int hp, int nb, const int *__restrict__ thr,
                                                        double *__restrict__ partial) {
-    __shared__ int r2s[256];
-    __shared__ double v2s[256], v4s[256];
-    const int map = blockIdx.y, tid = threadIdx.x;
+    __shared__ int lo2s[SM_MAXB], hi2s[SM_MAXB];
+    __shared__ double acc[2][SM_MAXB];
+    __shared__ double red[2][4];
+    __shared__ int rng[2][4];
+    const int map = blockIdx.y, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int xw = n / 2 + 1;
     const int64_t total = (int64_t)n * n * xw;
     const float2 *sp = spec + (int64_t)map * spec_stride;
-    const int lo2 = tid < nb ? thr[tid] : 0, hi2 = tid < nb ? thr[nb + tid] : 0;
-    double ax = 0.0, ay = 0.0;
+    if (tid < nb) {
+        lo2s[tid] = thr[tid];
+        hi2s[tid] = thr[nb + tid];
+        acc[0][tid] = 0.0;
+        acc[1][tid] = 0.0;
+    }
+    __syncthreads();
     for (int64_t base = (int64_t)blockIdx.x * 256; base < total; base += (int64_t)gridDim.x * 256) {
         const int64_t e = base + tid;
         int r2 = -1;
@@ -620,24 +631,42 @@ __global__ __launch_bounds__(256) void k_shell_moments(const float2 *__restrict_
             v2 = w * a;
             v4 = w * a * a;
         }
-        r2s[tid] = r2;
-        v2s[tid] = v2;
-        v4s[tid] = v4;
+        // |m|^2 range of the step's entries (the mean mode and padding excluded)
+        int rmin = r2 > 0 ? r2 : INT32_MAX, rmax = r2 > 0 ? r2 : -1;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            rmin = min(rmin, __shfl_xor(rmin, o, 64));
+            rmax = max(rmax, __shfl_xor(rmax, o, 64));
+        }
+        if (lane == 0) {
+            rng[0][wave] = rmin;
+            rng[1][wave] = rmax;
+        }
         __syncthreads();
-        if (tid < nb)
-            for (int i = 0; i < 256; ++i) {
-                const int q = r2s[i];
-                if (q > 0 && q >= lo2 && q < hi2) {
-                    ax += v2s[i];
-                    ay += v4s[i];
-                }
+        rmin = min(min(rng[0][0], rng[0][1]), min(rng[0][2], rng[0][3]));
+        rmax = max(max(rng[1][0], rng[1][1]), max(rng[1][2], rng[1][3]));
+        for (int b = 0; b < nb; ++b) {
+            const int lo = lo2s[b], hi = hi2s[b];
+            if (hi <= rmin || lo > rmax) continue;          // block-uniform
+            const bool in = r2 > 0 && r2 >= lo && r2 < hi;
+            double x2 = wave_sum(in ? v2 : 0.0), x4 = wave_sum(in ? v4 : 0.0);
+            if (lane == 0) {
+                red[0][wave] = x2;
+                red[1][wave] = x4;
             }
-        __syncthreads();
+            __syncthreads();
+            if (tid == 0) {
+                acc[0][b] += (red[0][0] + red[0][1]) + (red[0][2] + red[0][3]);
+                acc[1][b] += (red[1][0] + red[1][1]) + (red[1][2] + red[1][3]);
+            }
+            __syncthreads();
+        }
+        __syncthreads();   // rng is rewritten by the next step
     }
     if (tid < nb) {
         double *o = partial + (((int64_t)map * gridDim.x + blockIdx.x) * nb + tid) * 2;
-        o[0] = ax;
-        o[1] = ay;
+        o[0] = acc[0][tid];
+        o[1] = acc[1][tid];
     }
 }
 
@@ -854,7 +883,7 @@ hipError_t launch_rebin(const double *B, int n_tri, const double *count, const i
 
 hipError_t launch_shell_moments(const float2 *spec, int64_t spec_stride, int n, int nb, int batch, const int *thr,
                                 int nblk, double *partial, hipStream_t st) {
-    if (nb < 1 || nb > 256 || nblk < 1) return hipErrorInvalidValue;
+    if (nb < 1 || nb > SM_MAXB || nblk < 1) return hipErrorInvalidValue;
     const int hp = (int)(spec_elems(n) / ((int64_t)n * n));
     hipLaunchKernelGGL(k_shell_moments, dim3(nblk, batch), dim3(256), 0, st, spec, spec_stride, n, hp, nb, thr,
                        partial);

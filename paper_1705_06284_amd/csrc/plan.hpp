@@ -73,11 +73,11 @@ struct bispec_plan_s {
 namespace bispec {
 
 // Blocks of the per-shell spectral moments (connected trispectrum).
-constexpr int kMomBlocks = 256;
+constexpr int kMomBlocks = 2048;
 
 // Byte offsets of the workspace regions (256-byte aligned).
 struct Layout {
-    size_t tw, terms, scale, tcount, thr, mom_partial, mom, pg_pairs, pg_idx, cols, pd, ztab, ytab, mean_partial, mean, spec, abox, bc, fields,
+    size_t tw, terms, scale, tcount, thr, mom_partial, mom_tmp, mom, pg_pairs, pg_idx, cols, pd, ztab, ytab, mean_partial, mean, spec, abox, bc, fields,
         partial, pg_partial, pg_dense, pg_tmp, total;
 };
 
