@@ -315,6 +315,27 @@ class Plan:
     def _empty(self, *shape):
         return self._torch.empty(*shape, dtype=self._torch.float64, device=self.device)
 
+    def _enter(self):
+        """The plan's stream waits for the work queued so far on the current
+        stream (the staging of the input, the allocation of the outputs)."""
+        torch = self._torch
+        cur = torch.cuda.current_stream(self.device)
+        if cur.cuda_stream != self.stream.cuda_stream:
+            self.stream.wait_stream(cur)
+
+    def _leave(self, *tensors):
+        """Tensors the library reads or writes on the plan's stream stay
+        allocated until that stream's work is done, even if the caller drops
+        them (the caching allocator otherwise reuses their blocks on the
+        current stream)."""
+        torch = self._torch
+        cur = torch.cuda.current_stream(self.device)
+        if cur.cuda_stream == self.stream.cuda_stream:
+            return
+        for t in tensors:
+            if t is not None:
+                t.record_stream(self.stream)
+
     def polyspec(self, delta, want_p=True, want_b=True, want_t=True, out=None):
         """(P, B, T) device tensors [batch, ...]; entries not wanted are None."""
         d = self._input(delta)
@@ -325,7 +346,9 @@ class Plan:
             T = self._empty(bsz, self.n_quad) if want_t else None
         else:
             P, B, T = out
+        self._enter()
         check(polyspec_estimate(self.handle, _ptr(d), bsz, _ptr(P), _ptr(B), _ptr(T)), "polyspec_estimate")
+        self._leave(d, P, B, T)
         return P, B, T
 
     def estimate(self, delta, want_p=True):
@@ -334,14 +357,18 @@ class Plan:
         bsz = d.shape[0]
         B = self._empty(bsz, self.n_tri)
         P = self._empty(bsz, self.n_bins) if want_p else None
+        self._enter()
         check(bispec_estimate(self.handle, _ptr(d), bsz, _ptr(B), _ptr(P)), "bispec_estimate")
+        self._leave(d, B, P)
         return B, P
 
     def trispec(self, delta):
         d = self._input(delta)
         bsz = d.shape[0]
         T = self._empty(bsz, self.n_quad)
+        self._enter()
         check(trispec_estimate(self.handle, _ptr(d), bsz, _ptr(T)), "trispec_estimate")
+        self._leave(d, T)
         return T
 
     def trispec_connected(self, delta):
@@ -351,7 +378,9 @@ class Plan:
         bsz = d.shape[0]
         T = self._empty(bsz, self.n_quad)
         Tc = self._empty(bsz, self.n_quad)
+        self._enter()
         check(trispec_connected_estimate(self.handle, _ptr(d), bsz, _ptr(T), _ptr(Tc)), "trispec_connected_estimate")
+        self._leave(d, T, Tc)
         return T, Tc
 
     def bin_fields(self, delta):
@@ -359,7 +388,9 @@ class Plan:
         bsz = d.shape[0]
         f = self._torch.empty(bsz, self.n_bins, self.n, self.n, self.n, dtype=self._torch.float32,
                               device=self.device)
+        self._enter()
         check(bispec_bin_fields(self.handle, _ptr(d), bsz, _ptr(f)), "bispec_bin_fields")
+        self._leave(d, f)
         return f
 
     def close(self):

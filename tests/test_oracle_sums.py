@@ -37,8 +37,9 @@ def _wrap(c, n):
     return ((c + n // 2) % n) - n // 2
 
 
-def brute_bispectrum_sums(delta64, lo, hi):
-    """S[i,j,k] (ordered slots, mod-N closure) and strict S by full enumeration."""
+def brute_bispectrum_sums(delta64, lo, hi, want_sq=False):
+    """S[i,j,k] (ordered slots, mod-N closure) and strict S by full enumeration;
+    with want_sq also Q[i,j,k] = sum |D1 D2 D3|^2 over the same closed triples."""
     n = delta64.shape[0]
     D = np.fft.fftn(delta64)                  # library FFT, not the oracle's DFT
     m = _grid_modes(n, max(hi))
@@ -49,6 +50,7 @@ def brute_bispectrum_sums(delta64, lo, hi):
     Ss = np.zeros((nb, nb, nb), complex)
     C = np.zeros((nb, nb, nb))
     Cs = np.zeros((nb, nb, nb))
+    Q = np.zeros((nb, nb, nb))
     chunk = 64
     for a0 in range(0, len(m), chunk):
         m1 = m[a0:a0 + chunk]
@@ -63,6 +65,10 @@ def brute_bispectrum_sums(delta64, lo, hi):
         C += np.einsum("ai,bj,abk->ijk", m1m, mem, m3)
         Ss += np.einsum("ai,bj,abk,ab->ijk", m1m, mem, m3, prod * strict)
         Cs += np.einsum("ai,bj,abk,ab->ijk", m1m, mem, m3, strict.astype(float))
+        if want_sq:
+            Q += np.einsum("ai,bj,abk,ab->ijk", m1m, mem, m3, np.abs(prod) ** 2)
+    if want_sq:
+        return S, C, Ss, Cs, Q
     return S, C, Ss, Cs
 
 
@@ -81,6 +87,55 @@ def test_counts_and_sums_match_bruteforce_8():
         assert abs(res.s_strict[t] - Ss[i, j, k]) <= 1e-9 * (1 + np.abs(S).max())
     # 8^3 with hi = N/2 = 4 aliases: at least one triplet has count != strict
     assert np.any(res.count != res.count_strict)
+
+
+def test_noise_level_matches_bruteforce_8():
+    """The noise level of every parity bar, norm sqrt(sum |D1 D2 D3|^2) / N_t
+    (the random-phase spread of the mean over closed triples), against the
+    full-grid enumeration of the closed triples and their squared products."""
+    rng = np.random.default_rng(6)
+    n = 8
+    d = rng.standard_normal((n, n, n)).astype(np.float32)
+    lo, hi = np.array([0.5, 1.5, 2.5]), np.array([1.5, 2.5, 4.0])
+    trip = np.array(list(itertools.combinations_with_replacement(range(3), 3)))
+    L = 5.0
+    res = oracle.bispectrum(d, lo, hi, trip, box_len=L)
+    S, C, _, _, Q = brute_bispectrum_sums(oracle.prepare(d), lo, hi, want_sq=True)
+    norm = (L ** 3) ** 2 / float(n) ** 9
+    for t, (i, j, k) in enumerate(trip):
+        want = norm * np.sqrt(Q[i, j, k]) / C[i, j, k]
+        assert np.isclose(res.noise[t], want, rtol=1e-10), (t, res.noise[t], want)
+        # and B itself, with the box length entering as V^2
+        assert np.isclose(res.value[t], norm * S[i, j, k].real / C[i, j, k], rtol=1e-9,
+                          atol=1e-9 * norm * np.sqrt(Q[i, j, k]) / C[i, j, k])
+
+
+def test_candidate_filter_keeps_every_closed_triplet():
+    """Every bin triplet with a non-zero brute-force count (closure modulo N,
+    aliasing included) passes the candidate filter, and the filter drops
+    some triplets on a layout with a gap between shells."""
+    n = 8
+    lo, hi = np.array([0.5, 1.2, 2.0, 3.0]), np.array([1.2, 2.0, 3.0, 4.0])
+    _, C, _, Cs = brute_bispectrum_sums(np.ones((n, n, n)), lo, hi)
+    assert np.any(np.round(C) != np.round(Cs))          # aliased closures occur
+    cand = {tuple(t) for t in oracle.candidate_triplets(lo, hi)}
+    full = list(itertools.combinations_with_replacement(range(4), 3))
+    assert len(cand) < len(full)
+    for t in full:
+        if round(C[t]) > 0:
+            assert t in cand, t
+    closed, cnt = oracle.closed_triplets(n, lo, hi)
+    assert {tuple(t) for t in closed} == {t for t in full if round(C[t]) > 0}
+    assert all(c == round(C[tuple(t)]) for t, c in zip(closed, cnt))
+    # a gapped layout: (0, 0, 2) fails the triangle test and has no closure
+    n = 16
+    lo, hi = np.array([1.0, 2.0, 6.0]), np.array([2.0, 3.0, 7.5])
+    _, C, _, _ = brute_bispectrum_sums(np.ones((n, n, n)), lo, hi)
+    cand = {tuple(t) for t in oracle.candidate_triplets(lo, hi)}
+    assert (0, 0, 2) not in cand and round(C[0, 0, 2]) == 0
+    for t in itertools.combinations_with_replacement(range(3), 3):
+        if round(C[t]) > 0:
+            assert t in cand, t
 
 
 def test_counts_match_bruteforce_16_linear_bins():
@@ -135,6 +190,10 @@ def test_planewave_three_shells_closed_form():
     V = float(n) ** 3
     want = V ** 2 * A ** 3 * np.cos(ph.sum()) / (4 * res.count[0])
     assert np.isclose(res.value[0], want, rtol=2e-6)    # FP32 input rounding
+    # noise level: of the N_t closed triples only (m1, m2, m3) and its
+    # negative carry amplitude, each |product| = (A N_pix / 2)^3
+    assert res.count[0] > 2
+    assert np.isclose(res.noise[0], V ** 2 * A ** 3 * np.sqrt(2.0) / (8 * res.count[0]), rtol=2e-6)
     # B(alpha delta) = alpha^3 B
     res2 = oracle.bispectrum((2.0 * d).astype(np.float32), lo, hi, [(0, 1, 2)])
     assert np.isclose(res2.value[0], 8 * res.value[0], rtol=1e-12)
