@@ -35,8 +35,12 @@ def parse():
     ap.add_argument("--batch", type=int, default=1, help="maps per step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the FP32 comparison paths")
-    ap.add_argument("--cpu-budget", type=float, default=8e9,
+    ap.add_argument("--cpu-budget", type=float, default=2e9,
                     help="pair steps of the direct-sum oracle sample")
+    ap.add_argument("--cpu-bins", type=int, default=8,
+                    help="bins of the FP64 FFT-form sample of the CPU baseline")
+    ap.add_argument("--inverse-batch", type=int, default=4,
+                    help="maps per call of the inverse-stage measurement (0: skip)")
     ap.add_argument("--no-serving", action="store_true", help="skip the request-stream measurement")
     ap.add_argument("--no-onepixel", action="store_true",
                     help="skip the one-pixel-shell measurement with configuration binning")
@@ -52,15 +56,34 @@ def parse():
 
 TAIL_SOURCES = ("paper_1705_06284_amd/csrc/mfma.hip", "paper_1705_06284_amd/csrc/fft_core.hpp",
                 "paper_1705_06284_amd/csrc/launch.hpp")
+FFT_SOURCES = ("paper_1705_06284_amd/csrc/kernels.hip", "paper_1705_06284_amd/csrc/fft_core.hpp",
+               "paper_1705_06284_amd/csrc/launch.hpp", "paper_1705_06284_amd/csrc/api.cpp")
 
 
-def tail_source_hash():
+def tail_source_hash(sources=TAIL_SOURCES):
     import hashlib
     h = hashlib.sha256()
-    for f in TAIL_SOURCES:
+    for f in sources:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
+
+
+def profile_values(name, sources):
+    """key: value lines of a committed counter summary, if it was taken on the
+    current sources; else None."""
+    path = os.path.join(ROOT, "profiles", name)
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("source_sha256") != tail_source_hash(sources):
+        return None
+    return kv
 
 
 def measured_traffic(workload, nblk, shape):
@@ -159,8 +182,8 @@ def onepixel_run(torch, binding, synth, np, dev, stream, steps):
     est()
     kv = max(2, k // 2)
     wv, _ = timed_steps(torch, est, kv, stream)
-    out["fp32_valu"] = {"ms_per_map": 1e3 * wv / kv, "triangles_per_s": plan.n_tri * kv / wv}
-    out["speedup_vs_fp32_valu"] = out["fp32_valu"]["ms_per_map"] / out["ms_per_map"]
+    out["fp32_valu"] = {"ms_per_map": 1e3 * wv / kv, "triangles_per_s": plan.n_tri * kv / wv,
+                        "kind": "simple vector-ALU kernel, not tuned (a reference point, not a competitor)"}
     return out
 
 
@@ -169,10 +192,28 @@ def percentile(xs, q):
     return float(np.percentile(np.asarray(xs), q))
 
 
-def cpu_baseline(field, lo, hi, trip, budget):
-    """The FP64 oracle on a bounded sample of the same map: its DFT plus the
-    direct sums of the triplets whose loops are cheapest (up to `budget` pair
-    steps in total)."""
+def cpu_baseline(field, lo, hi, trip, n_bins_sample=8):
+    """The FP64 FFT form of the estimator (oracle/fftref.py: the paper's own
+    method, Section 2, on the CPU) on a bounded sample of the same map: the
+    forward FFT, the bin fields of the first n_bins_sample bins and every
+    closed triplet among them."""
+    import numpy as np
+    from oracle import fftref
+    sel = trip[np.max(trip, axis=1) < n_bins_sample]
+    t0 = time.perf_counter()
+    R = fftref.FFTReference(field, lo, hi)
+    R.bispectrum(sel)
+    dt = time.perf_counter() - t0
+    threads = fftref._workers()
+    return {"value": len(sel) / dt, "unit": "triangles/s", "cores": threads, "kind": "oracle",
+            "sample": "FP64 FFT form of the estimator (oracle/fftref.py, scipy.fft on %d threads) on the same "
+                      "%d^3 map: forward FFT, bin and count fields of bins 0..%d and their %d closed triplets "
+                      "(of %d), %.1f s" % (threads, field.shape[0], n_bins_sample - 1, len(sel), len(trip), dt)}
+
+
+def cpu_direct_sum(field, lo, hi, trip, budget):
+    """The FP64 direct-sum oracle on the triplets whose closed-pair loops are
+    cheapest (up to `budget` pair steps in total)."""
     import numpy as np
     import oracle
     m = oracle.mode_counts(field.shape[0], lo, hi)
@@ -190,49 +231,93 @@ def cpu_baseline(field, lo, hi, trip, budget):
     oracle.bispectrum(field, lo, hi, sel, delta_k=dk)
     dt = time.perf_counter() - t0
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": len(sel) / dt, "unit": "triangles/s", "cores": threads, "kind": "oracle",
-            "sample": "FP64 direct-sum oracle on the same %d^3 map: its separable DFT plus the %d of %d "
-                      "closed triplets with the cheapest closed-pair loops (%.2e pair steps), %.1f s"
-                      % (field.shape[0], len(sel), len(trip), used, dt)}
+    return {"value": len(sel) / dt, "unit": "triangles/s", "cores": threads,
+            "sample": "FP64 direct sums: separable DFT plus the %d of %d closed triplets with the cheapest "
+                      "closed-pair loops (%.2e pair steps), %.1f s" % (len(sel), len(trip), used, dt)}
 
 
 def serving_run(n_requests, warmup=200, load=0.7, seed=5):
     """Poisson stream of 64^3/128^3/256^3 lognormal maps (4:2:1) on one GPU:
-    saturation throughput from a burst, then p50/p99 latency at `load` times
-    that rate.  Each request asks for 12 equilateral + 12 squeezed triplets
-    and P at 12 bins.  Maps come from a pool of 8/4/2 seeded fields per size
-    (seed 5000 + i), pinned in host memory before the run."""
+    saturation throughput from a burst, then p50/p99 latency (overall and per
+    size) at `load` times that rate.  Each request asks for 12 equilateral +
+    12 squeezed triplets and P at 12 bins.  Request i carries its own map,
+    drawn on the device before the run from seed 5000 + i."""
     import numpy as np
+    import torch
     from paper_1705_06284_amd import serving, synth
     sizes = (64, 128, 256)
     be = serving.GpuBackend()
-    pool = {n: [be.pinned(synth.lognormal_field(n, 1.5, 1.0, 5000 + i)) for i in range(k)]
-            for n, k in zip(sizes, (8, 4, 2))}
-    ns = serving.mixed_sizes(n_requests + warmup, seed)
+    total = n_requests + warmup
+    ns = serving.mixed_sizes(total, seed)
+    maps = [synth.lognormal_field_device(int(n), 1.5, 1.0, 5000 + i, device=be.device) for i, n in enumerate(ns)]
+    torch.cuda.synchronize()
 
-    def reqs(offset):
-        return [serving.Request(rid=i, n=int(n), field=pool[int(n)][i % len(pool[int(n)])])
-                for i, n in enumerate(ns[offset:], start=offset)]
+    def reqs():
+        return [serving.Request(rid=i, n=int(n), field=maps[i]) for i, n in enumerate(ns)]
 
     srv = serving.Server(be, sizes=sizes, slots_per_size=2, max_batch=4)
-    burst = reqs(0)
+    burst = reqs()
     t0 = time.perf_counter()
     srv.run(burst, [0.0] * len(burst))
     sat = len(burst) / (time.perf_counter() - t0)
     srv.finished.clear()
     rate = load * sat
-    arr = serving.poisson_arrivals(rate, n_requests + warmup, seed)
-    stream = reqs(0)
+    arr = serving.poisson_arrivals(rate, total, seed)
     t0 = time.perf_counter()
-    done = srv.run(stream, list(arr))
+    done = srv.run(reqs(), list(arr))
     wall = time.perf_counter() - t0
     measured = [r for r in done if r.rid >= warmup]
     summ = serving.latency_summary(measured)
     ntri = 24
     summ.update({"rate_maps_per_s": rate, "saturation_maps_per_s": sat, "maps_per_s": len(done) / wall,
                  "triangles_per_s": len(done) * ntri / wall, "requests": len(measured), "warmup": warmup,
-                 "mix": "64^3:128^3:256^3 = 4:2:1, 12 equilateral + 12 squeezed + P, slots 2/size, batch <= 4"})
+                 "mix": "64^3:128^3:256^3 = 4:2:1, one map per request (seed 5000 + id), 12 equilateral + "
+                        "12 squeezed + P, slots 2/size, batch <= 4"})
+    del maps
     return summ
+
+
+def inverse_stage(torch, binding, plan_args, field, dev, stream, batch, steps):
+    """The shell-masked inverse passes Z and Y of every bin pair on `batch`
+    copies of the map (batch 4 at 256^3 puts 4 x 1.2 GB through HBM, far past
+    the 256 MB Infinity Cache): stage time per call, and bytes per second
+    from the committed counter summary when it was taken on these sources."""
+    import numpy as np
+    n, lo, hi = plan_args
+    plan = binding.Plan(n, lo, hi, precision="split_bf16", max_batch=batch, stream=stream, device=dev)
+    d = torch.from_numpy(np.broadcast_to(field, (batch,) + field.shape).copy()).to(dev)
+    P = torch.empty(batch, plan.n_bins, dtype=torch.float64, device=dev)
+    B = torch.empty(batch, plan.n_tri, dtype=torch.float64, device=dev)
+    T = torch.empty(batch, plan.n_quad, dtype=torch.float64, device=dev)
+
+    def step():
+        binding.check(binding.polyspec_estimate(plan.handle, binding._ptr(d), batch, binding._ptr(P),
+                                                binding._ptr(B), binding._ptr(T)), "polyspec_estimate")
+    for _ in range(3):
+        step()
+    torch.cuda.synchronize()
+    plan.timing_read()
+    plan.timing(True)
+    timed_steps(torch, step, steps, stream)
+    plan.timing(False)
+    st, calls = plan.timing_read()
+    ms = st["inverse"] / max(calls, 1)
+    npix = float(n) ** 3
+    modes = plan.mode_counts.astype(np.float64)
+    algo = float(np.sum(modes) * 8 + plan.n_bins * npix * 4) * batch
+    out = {"batch": batch, "kernels": "k_inv_z_prune + k_inv_y_prune", "stage_ms": ms,
+           "algorithmic_bytes": algo, "peak": HBM_PEAK_GBS, "unit": "GB/s"}
+    kv = profile_values("fft_%dcube_traffic.txt" % n, FFT_SOURCES)
+    if kv is not None and kv.get("batch") == str(batch):
+        try:
+            byts = float(kv["inverse_zy_bytes_per_call"])
+            out["traffic"] = byts
+            out["achieved"] = byts / (ms * 1e-3) / 1e9
+            out["frac"] = out["achieved"] / HBM_PEAK_GBS
+        except (KeyError, ValueError):
+            pass
+    plan.close()
+    return out
 
 
 def main():
@@ -348,10 +433,16 @@ def main():
         out["fp32_path"] = {"value": ntri * bsz * args.steps / w32, "ms_per_step": 1e3 * w32 / args.steps,
                             "contract_ms": st32["contract"], "kind": "same product-Gram on FP32 MFMA"}
         out["fp32_valu_path"] = {"value": ntri * bsz * kv / wv, "ms_per_step": 1e3 * wv / kv,
-                                 "contract_ms": stv["contract"], "kind": "requested sums only, FP32 VALU"}
+                                 "contract_ms": stv["contract"],
+                                 "kind": "requested sums only, FP32 vector ALU (simple kernel, not tuned: "
+                                         "a reference point, not a competitor)"}
         out["split_vs_fp32"] = {"end_to_end": out["fp32_path"]["ms_per_step"] / out["ms_per_step"],
                                 "contraction": st32["contract"] / max(stages["contract"], 1e-9)}
         plan.set_precision("split_bf16")
+
+    if args.inverse_batch > 0 and bsz == 1:
+        out["roofline_inverse"] = inverse_stage(torch, binding, (n, lo, hi), field, dev, stream,
+                                                args.inverse_batch, max(5, args.steps // 2))
 
     if not args.no_onepixel:
         out["onepixel_128"] = onepixel_run(torch, binding, synth, np, dev, stream, args.steps)
@@ -417,7 +508,8 @@ def main():
         del a, b
 
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(field, lo, hi, plan.triplets, args.cpu_budget)
+        out["cpu_baseline"] = cpu_baseline(field, lo, hi, plan.triplets, args.cpu_bins)
+        out["cpu_direct_sum"] = cpu_direct_sum(field, lo, hi, plan.triplets, args.cpu_budget)
     print(json.dumps(out), flush=True)
 
 

@@ -247,5 +247,10 @@ def latency_summary(finished: List[Request]) -> dict:
     lat = np.array([r.latency for r in finished]) * 1e3
     if lat.size == 0:
         return {"p50_ms": None, "p99_ms": None, "count": 0}
-    return {"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
-            "mean_ms": float(lat.mean()), "count": int(lat.size)}
+    out = {"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+           "mean_ms": float(lat.mean()), "count": int(lat.size), "by_size": {}}
+    for n in sorted({r.n for r in finished}):
+        ln = np.array([r.latency for r in finished if r.n == n]) * 1e3
+        out["by_size"][str(n)] = {"p50_ms": float(np.percentile(ln, 50)), "p99_ms": float(np.percentile(ln, 99)),
+                                  "count": int(ln.size)}
+    return out

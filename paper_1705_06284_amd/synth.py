@@ -50,6 +50,26 @@ def lognormal_field(n: int, spectral_index: float, sigma: float, seed: int) -> n
     return (np.exp(g - 0.5 * sigma * sigma) - 1.0).astype(np.float32)
 
 
+def lognormal_field_device(n: int, spectral_index: float, sigma: float, seed: int, device="cuda"):
+    """The lognormal recipe of ``lognormal_field`` drawn on a GPU with torch
+    (its own seeded generator and FFTs, FP64), for request streams that need
+    a fresh map per request: an FP32 [N, N, N] device tensor.  Not bit-equal
+    to ``lognormal_field`` for the same seed."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    white = torch.randn((n, n, n), generator=g, dtype=torch.float64, device=device)
+    wk = torch.fft.rfftn(white)
+    f = torch.fft.fftfreq(n, d=1.0 / n, device=device, dtype=torch.float64)
+    fr = torch.fft.rfftfreq(n, d=1.0 / n, device=device, dtype=torch.float64)
+    k2 = f[:, None, None] ** 2 + f[None, :, None] ** 2 + fr[None, None, :] ** 2
+    amp = torch.where(k2 > 0, k2.clamp_min(1.0) ** (-spectral_index / 4.0), torch.zeros_like(k2))
+    gf = torch.fft.irfftn(wk * amp, s=(n, n, n))
+    gf = gf - gf.mean()
+    gf = gf * (sigma / torch.sqrt(torch.mean(gf * gf)))
+    return (torch.exp(gf - 0.5 * sigma * sigma) - 1.0).to(torch.float32)
+
+
 def local_quadratic_field(n: int, spectral_index: float, sigma_g: float, f_nl: float,
                           seed: int, dtype=np.float32) -> np.ndarray:
     """delta = g + f (g^2 - <g^2>) with <g^2> the realisation mean."""

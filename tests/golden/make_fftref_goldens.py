@@ -1,0 +1,123 @@
+#!/usr/bin/env python3
+"""Write the FP64 reference values of the large parity workloads.
+
+Calls only ``oracle/`` (the FP64 FFT form of the estimator, pinned to the
+direct sums in tests/test_oracle_fftref.py) and the seeded input generators
+of ``paper_1705_06284_amd/synth.py``.  Nothing here touches the HIP path.
+Each workload's values go to ``tests/golden/<workload>.fftref.npz`` together
+with a digest of the input map (FP64 moments and a strided sample), which
+the GPU tests compare with the map they generate before they use the values.
+
+Configuration sets (Eq. Jeong_BI, Eq. Jeong_PS, Eq. Jeong_gen with p = 4):
+
+* c2_128_lognormal, c3_256_bubbles: every closed triplet (the candidates of
+  the triangle test whose FFT count is non-zero), every bin's P and every
+  collapsed quad (a,a,b,b).
+* onepix_128_lognormal (63 one-k_f shells): every closed triplet and P.
+* c4_512_lognormal (32 bins): a stratified sample that touches every bin --
+  every equilateral (b,b,b), one seeded triplet per bin, the triangle-edge
+  triplets k = i + j + 1 with k >= 29 (the worst-conditioned ones), 16 more
+  seeded triplets -- and the quads (b,b,b,b) plus 32 seeded (a,a,b,b).
+
+Usage: python tests/golden/make_fftref_goldens.py [workload ...]
+"""
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path.insert(0, ROOT)
+
+import oracle  # noqa: E402
+from oracle import fftref  # noqa: E402
+from paper_1705_06284_amd import synth  # noqa: E402
+
+WORKLOADS = ("c2_128_lognormal", "c3_256_bubbles", "onepix_128_lognormal", "c4_512_lognormal")
+
+
+def c4_sample(nb, cand, seed=4):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    cs = {tuple(int(x) for x in t) for t in cand}
+    pick = []
+    for b in range(nb):
+        if (b, b, b) in cs:
+            pick.append((b, b, b))
+    for b in range(nb):
+        mem = sorted(t for t in cs if b in t)
+        pick.append(mem[int(rng.integers(len(mem)))])
+    for k in (29, 30, 31):
+        for i in range(0, k):
+            j = k - 1 - i
+            if i <= j and (i, j, k) in cs:
+                pick.append((i, j, k))
+    allc = sorted(cs)
+    for _ in range(16):
+        pick.append(allc[int(rng.integers(len(allc)))])
+    out = []
+    for t in pick:
+        if t not in out:
+            out.append(t)
+    quads = [(b, b, b, b) for b in range(nb)]
+    while len(quads) < nb + 32:
+        a, b = sorted(int(x) for x in rng.integers(nb, size=2))
+        if a != b and (a, a, b, b) not in quads:
+            quads.append((a, a, b, b))
+    return np.array(out, np.int32), np.array(quads, np.int32)
+
+
+def make(wl, cache_bytes):
+    n = synth.WORKLOADS[wl]["n"]
+    lo, hi = synth.workload_bins(wl)
+    nb = len(lo)
+    t0 = time.time()
+    d = synth.workload_field(wl)
+    dig = fftref.field_digest(d)
+    R = fftref.FFTReference(d, lo, hi, cache_bytes=cache_bytes)
+    cand = oracle.candidate_triplets(lo, hi)
+    if wl == "c4_512_lognormal":
+        trip, quads = c4_sample(nb, cand)
+    else:
+        trip = cand
+        quads = oracle.collapsed_quads(nb) if wl != "onepix_128_lognormal" else np.zeros((0, 4), np.int32)
+    print("%s: %d triplets, %d quads" % (wl, len(trip), len(quads)), flush=True)
+    fb = R.bispectrum(trip)
+    keep = fb.count > 0
+    print("  B done (%.0f s), %d closed" % (time.time() - t0, int(keep.sum())), flush=True)
+    p, m = R.power_spectrum()
+    out = dict(triplets=trip[keep], B=fb.value[keep], B_noise=fb.noise[keep], B_count=fb.count[keep],
+               B_count_frac=fb.count_frac[keep], kappa=R.condition(trip[keep], fb.count[keep]),
+               P=p, M=m, k_lo=lo, k_hi=hi, n=np.int64(n),
+               digest_moments=np.array([dig["size"], dig["sum"], dig["sum2"], dig["sum3"]], np.float64),
+               digest_sample=np.array(dig["sample"], np.float64))
+    if len(quads):
+        ft = R.trispectrum(quads)
+        out.update(quads=quads, T=ft.value, T_noise=ft.noise, T_count=ft.count, T_count_frac=ft.count_frac)
+    else:
+        out.update(quads=quads, T=np.zeros(0), T_noise=np.zeros(0), T_count=np.zeros(0, np.int64),
+                   T_count_frac=np.zeros(0))
+    assert R.max_imag < 1e-10, R.max_imag
+    # triangle counts resolve to single units; p = 4 counts outgrow the FP64
+    # unit resolution of N_pix N_q and are held to a relative 1e-9
+    assert out["B_count_frac"].max() < 0.01, out["B_count_frac"].max()
+    assert not len(quads) or np.max(out["T_count_frac"] / np.maximum(out["T_count"], 1)) < 1e-9
+    path = os.path.join(HERE, "%s.fftref.npz" % wl)
+    np.savez_compressed(path, **out)
+    print("  wrote %s (%.0f s; max count distance %.1e, max kappa %.2f)"
+          % (path, time.time() - t0, out["B_count_frac"].max(), out["kappa"].max()), flush=True)
+
+
+def load(wl):
+    """The stored values of a workload and a check of the map they belong to."""
+    z = np.load(os.path.join(HERE, "%s.fftref.npz" % wl))
+    dm = z["digest_moments"]
+    dig = {"size": int(dm[0]), "sum": dm[1], "sum2": dm[2], "sum3": dm[3], "sample": list(z["digest_sample"])}
+    return z, dig
+
+
+if __name__ == "__main__":
+    todo = sys.argv[1:] or list(WORKLOADS)
+    for wl in todo:
+        make(wl, cache_bytes=(34 << 30) if wl.startswith("c4") else (16 << 30))
