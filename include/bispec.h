@@ -178,6 +178,23 @@ bispec_status trispec_connected_estimate(bispec_plan_t plan, const float *delta,
 bispec_status polyspec_estimate(bispec_plan_t plan, const float *delta, int32_t batch,
                                 double *P, double *B, double *T);
 
+/* polyspec_estimate without any device allocation and without the plan's
+ * workspace, for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Same arguments, kernels and results as polyspec_estimate.  The kernels run
+ * on a static scratch that the library keeps on every device it runs on
+ * (64 MiB each, held until the process ends); the call needs the device that
+ * is current at the call to be the plan's device.  BISPEC_E_NO_WORKSPACE
+ * when the plan's workspace at its max_batch (bispec_plan_footprint) is
+ * larger than the scratch (a 64^3 plan of a few bins fits; 128^3 does not).
+ * The first call of a plan after another plan used the scratch copies the
+ * plan's small tables into it and synchronises the plan's stream.  Every call
+ * on one device shares that device's scratch, which keeps the last call's
+ * contents: calls that overlap on one device race and give undefined
+ * results.  No graph capture or replay happens in this call. */
+bispec_status polyspec_estimate_noalloc(bispec_plan_t plan, const float *delta, int32_t batch,
+                                        double *P, double *B, double *T);
+
 /* Stage timing (diagnostics).  While enabled, every estimate or bin-field
  * call records HIP events on the plan's stream at its stage boundaries:
  * [0] FP64 mean + forward FFT, [1] shell-masked inverse FFTs (all bins),

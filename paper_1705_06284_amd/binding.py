@@ -60,6 +60,7 @@ _SIGS = {
     "trispec_estimate": [_vp, _vp, _i32, _vp],
     "trispec_connected_estimate": [_vp, _vp, _i32, _vp, _vp],
     "polyspec_estimate": [_vp, _vp, _i32, _vp, _vp, _vp],
+    "polyspec_estimate_noalloc": [_vp, _vp, _i32, _vp, _vp, _vp],
     "bispec_timing_enable": [_vp, _i32],
     "bispec_graph_enable": [_vp, _i32],
     "bispec_autotune": [_vp, _vp, _ip, _ip],
@@ -93,6 +94,7 @@ bispec_estimate = _lib.bispec_estimate
 trispec_estimate = _lib.trispec_estimate
 trispec_connected_estimate = _lib.trispec_connected_estimate
 polyspec_estimate = _lib.polyspec_estimate
+polyspec_estimate_noalloc = _lib.polyspec_estimate_noalloc
 bispec_timing_enable = _lib.bispec_timing_enable
 bispec_graph_enable = _lib.bispec_graph_enable
 bispec_autotune = _lib.bispec_autotune

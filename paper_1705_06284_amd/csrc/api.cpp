@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdint>
 #include <cstdio>
@@ -20,6 +21,7 @@
 #include "../../include/bispec.h"
 #include "launch.hpp"
 #include "moments.hpp"
+#include "noalloc.hpp"
 #include "plan.hpp"
 
 using namespace bispec;
@@ -546,7 +548,9 @@ bispec_status plan_impl(const bispec_plan_desc *d, bispec_plan_t *out) {
     for (int t = 0; t < 4 * d->n_quad; ++t)
         if (d->quad[t] < 0 || d->quad[t] >= nb) return BISPEC_E_INVALID;
 
+    static std::atomic<unsigned long long> next_uid{1};
     bispec_plan_s *p = new bispec_plan_s();
+    p->uid = next_uid++;
     p->n = n;
     p->box_len = d->box_len > 0 ? d->box_len : (double)n;
     p->nb = nb;
@@ -1016,6 +1020,53 @@ bispec_status polyspec_estimate(bispec_plan_t plan, const float *delta, int32_t 
         CK(hipGraphLaunch(exec, p.stream));
         return BISPEC_OK;
     } catch (...) {
+        return BISPEC_E_HIP;
+    }
+}
+
+bispec_status polyspec_estimate_noalloc(bispec_plan_t plan, const float *delta, int32_t batch, double *P, double *B,
+                                        double *T) {
+    if (!plan || !delta) return BISPEC_E_INVALID;
+    if (batch < 1 || batch > plan->max_batch) return BISPEC_E_INVALID;
+    bispec_plan_s &p = *plan;
+    int dev = 0;
+    CK(hipGetDevice(&dev));
+    void *scr = nullptr;
+    CK(scratch_address(dev, &scr));
+    const size_t need = make_layout(p, p.max_batch).total;
+    if (need > kScratchBytes) {
+        std::snprintf(g_last_error, sizeof(g_last_error),
+                      "the plan's workspace of %zu bytes exceeds the static scratch of %zu bytes", need,
+                      kScratchBytes);
+        return BISPEC_E_NO_WORKSPACE;
+    }
+    // The plan's own workspace is set aside for the call and restored after.
+    struct Swap {
+        bispec_plan_s &p;
+        void *ws;
+        size_t bytes;
+        bool fields;
+        ~Swap() {
+            p.ws = ws;
+            p.ws_bytes = bytes;
+            p.ws_fields = fields;
+        }
+    } swap{p, p.ws, p.ws_bytes, p.ws_fields};
+    p.ws = scr;
+    p.ws_bytes = kScratchBytes;
+    p.ws_fields = needs_fields(p);
+    try {
+        if (!scratch_claim(dev, p.uid)) {
+            // another plan (or none) used the scratch last: this plan's tables
+            bispec_status s = upload_tables(p);
+            if (s != BISPEC_OK) {
+                scratch_release(dev);
+                return s;
+            }
+        }
+        return run_estimate(p, delta, batch, P, B, T);
+    } catch (...) {
+        scratch_release(dev);
         return BISPEC_E_HIP;
     }
 }

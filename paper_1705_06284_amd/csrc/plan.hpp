@@ -9,6 +9,7 @@
 #include "fft_core.hpp"
 
 struct bispec_plan_s {
+    unsigned long long uid = 0;  // unique per plan in the process (never reused)
     int n = 0;                 // grid side N
     double box_len = 0;        // L (V = L^3)
     int nb = 0;                // bins
