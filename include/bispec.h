@@ -74,7 +74,14 @@ typedef enum {
  * triplets on a 64-column product-Gram over them, and P and the collapsed
  * quads on a second pass over the squared fields (rows F_a^2, columns F_b^2
  * and ones; up to 63 bins); general quads, and P at 64 bins, run on the
- * vector ALUs.  Mode 0 runs as mode 2 there. */
+ * vector ALUs.  Mode 0 runs as mode 2 there.
+ * In modes 0 and 1, triplets whose condition number
+ * kappa_t = sqrt(M_i M_j M_k / (N_pix N_t)) exceeds 4 (shells narrower than
+ * k_f near the edge of the triangle inequality; bispec_plan_condition) are
+ * read instead from product-Gram rows of their own on the FP64 matrix cores,
+ * over the bin fields in HBM, so their error stays at the level of the FP32
+ * FFTs (about 2.5e-7 kappa relative to the noise level of B).  Such plans
+ * keep the bin fields in the workspace (bispec_plan_footprint). */
 enum {
     BISPEC_FP32 = 0,        /* product-Gram, FP32 MFMA, FP32 accumulation            */
     BISPEC_SPLIT_BF16 = 1,  /* product-Gram, BF16 MFMA on hi/lo splits (3 products),

@@ -66,8 +66,10 @@ int ceil_int(double x) { return (int)std::ceil(x); }
 namespace bispec {
 
 bool needs_fields(const bispec_plan_s &p) {
-    return !p.mfma_ok || !p.quads_collapsed || p.precision == BISPEC_FP32_VALU;
+    return !p.mfma_ok || !p.quads_collapsed || p.precision == BISPEC_FP32_VALU || p.n_mtile_r > 0;
 }
+
+size_t refine_dense_doubles(const bispec_plan_s &p) { return (size_t)p.n_mtile_r * 2048; }
 
 // Dense tile entries of the fields product-Gram (33..64 bins): [n_mtile][32][64].
 size_t wide_dense_doubles(const bispec_plan_s &p) { return (size_t)std::max(p.n_mtile, p.pg_sq_tiles) * 2048; }
@@ -86,6 +88,7 @@ Layout make_layout(const bispec_plan_s &p, int batch) {
     L.mom = off;          off = align_up(off + sizeof(double) * 2 * p.nb * batch);
     L.pg_pairs = off;     off = align_up(off + sizeof(uchar2) * p.pg_pairs.size());
     L.pg_idx = off;       off = align_up(off + sizeof(int) * p.pg_idx.size());
+    L.pg_pairs_r = off;   off = align_up(off + sizeof(uchar2) * p.pg_pairs_r.size());
     L.cols = off;         off = align_up(off + sizeof(int) * p.cols.size());
     L.pd = off;           off = align_up(off + sizeof(PairDev) * p.pairs.size());
     L.ztab = off;         off = align_up(off + sizeof(int2) * p.ztab.size());
@@ -113,6 +116,12 @@ Layout make_layout(const bispec_plan_s &p, int batch) {
         off = align_up(off + sizeof(double) * pgram_partial_doubles(p.n_mtile, true) * PG_REDUCE_SEGS * batch);
     else if (p.pg_wide)
         off = align_up(off + sizeof(double) * wide_dense_doubles(p) * PG_REDUCE_SEGS * batch);
+    // refinement pass: FP64 partials of its blocks, their reduction
+    const size_t rd = refine_dense_doubles(p);
+    const size_t rblk = (size_t)p.nblk_r;
+    L.pg_partial_r = off; off = align_up(off + sizeof(double) * rd * rblk * batch);
+    L.pg_dense_r = off;   off = align_up(off + sizeof(double) * rd * batch);
+    L.pg_tmp_r = off;     off = align_up(off + sizeof(double) * rd * PG_REDUCE_SEGS * batch);
     // bin fields in HBM: only the vector-ALU contraction and general quads read them
     L.fields = off;
     if (needs_fields(p)) off = align_up(off + sizeof(float) * vol * p.nb * batch);
@@ -247,36 +256,73 @@ std::vector<PairDev> pair_devs(const bispec_plan_s &p) {
     return v;
 }
 
+// Greedy set cover of triplets by pair rows: repeatedly the pair (x <= y,
+// index x*nb + y) that reads the most not-yet-covered triplets (lowest pair
+// index on ties).  row_of holds the rows already present (-1: none) and is
+// extended; add(x, y) appends a row.  A triplet a <= b <= c can be read from
+// G[(x,y), z] for any of its three pairs, a repeated bin from its (b,b) row,
+// and among three distinct bins two share a parity, so the equal-parity pairs
+// (about nb^2/4) always suffice; the greedy cover is smaller.
+template <class Add>
+void greedy_cover(int nb, const std::vector<int> &tp, const std::vector<int> &tris, std::vector<int> &row_of,
+                  Add add) {
+    auto covered = [&](int t) {
+        return row_of[tp[3 * t]] >= 0 || row_of[tp[3 * t + 1]] >= 0 || row_of[tp[3 * t + 2]] >= 0;
+    };
+    std::vector<int> open;
+    for (int t : tris)
+        if (!covered(t)) open.push_back(t);
+    std::vector<int> cnt(nb * nb);
+    while (!open.empty()) {
+        std::fill(cnt.begin(), cnt.end(), 0);
+        for (int t : open)
+            for (int k = 0; k < 3; ++k) ++cnt[tp[3 * t + k]];
+        const int best = (int)(std::max_element(cnt.begin(), cnt.end()) - cnt.begin());
+        add(best / nb, best % nb);
+        std::vector<int> left;
+        for (int t : open)
+            if (!covered(t)) left.push_back(t);
+        open.swap(left);
+    }
+}
+
 // Rows of the product-Gram.  Every (b,b) row is kept (rows 0..nb-1, so pair
 // tile 0 holds row (r,r) in lane r, which the p = 4 tile relies on); when nb < 32 column nb
 // is a field of ones, so G[(b,b), nb] is the power-spectrum numerator, else
-// rows (b, ONE) are added for it.  A triplet a <= b <= c can be read from
-// G[(x,y), z] for any of its three pairs (x,y); the pair rows are a greedy
-// set cover of the requested triplets: repeatedly the pair in the most
-// not-yet-covered triplets (lowest pair index on ties).  A repeated bin is
-// covered by its (b,b) row, and among three distinct bins two share a
-// parity, so the equal-parity pairs (about nb^2/4) always suffice; the
-// greedy cover is smaller (128 rows instead of 156 for 1541 triplets of 24
-// linear bins).  Padding rows (ZERO, ZERO) fill the last tile.  A term's
-// dense index in a block's tiles is tile*1024 + row_in_tile*32 + column.
+// rows (b, ONE) are added for it.  The other rows are a greedy cover of the
+// well-conditioned triplets; the ill-conditioned ones (kappa above
+// kRefineKappa) get a cover of their own, the refinement rows, which run in
+// FP32 mode.  Padding rows (ZERO, ZERO) fill the last tile of each table.  A
+// term's dense index in a block's tiles is tile*32*ncol + row_in_tile*ncol +
+// column (ncol = 32, or 64 with more than 32 bins), with PG_IDX_ALT set for
+// the refinement tiles.
 void build_pgram_tables(bispec_plan_s &p) {
     const int nb = p.nb;
     p.mfma_ok = nb <= 32;
     p.pg_wide = nb > 32 && nb <= 64;
     p.pg_pairs.clear();
     p.pg_idx.clear();
+    p.pg_pairs_r.clear();
+    p.n_mtile_r = 0;
     if (!p.mfma_ok && !p.pg_wide) return;
     // 33..64 bins: rows are the cover of the triplets alone over 64 columns of
     // fields in HBM (P and collapsed quads come from the squares pass)
     const bool wide = p.pg_wide;
     const int row_zero = wide ? PGF_ROW_ZERO : PG_ROW_ZERO;
-    std::vector<int> row_of(nb * nb, -1), row_one(nb, -1);
+    std::vector<int> row_of(nb * nb, -1), row_one(nb, -1), row_of_r(nb * nb, -1);
     auto add = [&](int i, int j) {
         if (row_of[i * nb + j] < 0) {
             row_of[i * nb + j] = (int)p.pg_pairs.size();
             p.pg_pairs.push_back(uchar2{(unsigned char)i, (unsigned char)j});
         }
         return row_of[i * nb + j];
+    };
+    auto add_r = [&](int i, int j) {
+        if (row_of_r[i * nb + j] < 0) {
+            row_of_r[i * nb + j] = (int)p.pg_pairs_r.size();
+            p.pg_pairs_r.push_back(uchar2{(unsigned char)i, (unsigned char)j});
+        }
+        return row_of_r[i * nb + j];
     };
     if (!wide)
         for (int b = 0; b < nb; ++b) add(b, b);
@@ -298,43 +344,51 @@ void build_pgram_tables(bispec_plan_s &p) {
             rest[3 * t + k] = c[k][2];
         }
     }
-    auto covered = [&](int t) {
-        return row_of[tp[3 * t]] >= 0 || row_of[tp[3 * t + 1]] >= 0 || row_of[tp[3 * t + 2]] >= 0;
-    };
-    std::vector<int> open;
-    for (int t = 0; t < ntri; ++t)
-        if (!covered(t)) open.push_back(t);
-    std::vector<int> cnt(nb * nb);
-    while (!open.empty()) {
-        std::fill(cnt.begin(), cnt.end(), 0);
-        for (int t : open)
-            for (int k = 0; k < 3; ++k) ++cnt[tp[3 * t + k]];
-        const int best = (int)(std::max_element(cnt.begin(), cnt.end()) - cnt.begin());
-        add(best / nb, best % nb);
-        std::vector<int> left;
-        for (int t : open)
-            if (!covered(t)) left.push_back(t);
-        open.swap(left);
+    // condition numbers decide which cover reads a triplet
+    const double npix = (double)p.n * p.n * p.n;
+    p.refine.assign(ntri, 0);
+    std::vector<int> main_t, ref_t;
+    for (int t = 0; t < ntri; ++t) {
+        const double m = (double)p.modes[p.tri[3 * t]] * (double)p.modes[p.tri[3 * t + 1]] *
+                         (double)p.modes[p.tri[3 * t + 2]];
+        const double c = p.tri_count.empty() ? 0.0 : p.tri_count[t];
+        if (c > 0 && std::sqrt(m / (npix * c)) > kRefineKappa) {
+            p.refine[t] = 1;
+            ref_t.push_back(t);
+        } else {
+            main_t.push_back(t);
+        }
     }
+    greedy_cover(nb, tp, main_t, row_of, add);
+    greedy_cover(nb, tp, ref_t, row_of_r, add_r);
     std::vector<int> tri_row(ntri), tri_col(ntri);
-    for (int t = 0; t < ntri; ++t)
+    for (int t = 0; t < ntri; ++t) {
+        const std::vector<int> &ro = p.refine[t] ? row_of_r : row_of;
         for (int k = 0; k < 3; ++k)
-            if (row_of[tp[3 * t + k]] >= 0) {
-                tri_row[t] = row_of[tp[3 * t + k]];
+            if (ro[tp[3 * t + k]] >= 0) {
+                tri_row[t] = ro[tp[3 * t + k]];
                 tri_col[t] = rest[3 * t + k];
                 break;
             }
+    }
     if (p.pg_pairs.empty()) p.pg_pairs.push_back(uchar2{(unsigned char)row_zero, (unsigned char)row_zero});
     while (p.pg_pairs.size() % 32) p.pg_pairs.push_back(uchar2{(unsigned char)row_zero, (unsigned char)row_zero});
     p.n_mtile = (int)p.pg_pairs.size() / 32;
+    while (p.pg_pairs_r.size() % 32) p.pg_pairs_r.push_back(uchar2{(unsigned char)row_zero, (unsigned char)row_zero});
+    p.n_mtile_r = (int)p.pg_pairs_r.size() / 32;
     const int ncol = wide ? 64 : 32;
     auto dense = [ncol](int row, int c) { return (row / 32) * 32 * ncol + (row % 32) * ncol + c; };
-    for (int t = 0; t < ntri; ++t) p.pg_idx.push_back(dense(tri_row[t], tri_col[t]));
+    // the refinement rows run on the 64-column FP64 product-Gram over fields in HBM
+    auto dense_r = [](int row, int c) { return (row / 32) * 2048 + (row % 32) * 64 + c; };
+    for (int t = 0; t < ntri; ++t)
+        p.pg_idx.push_back(p.refine[t] ? (dense_r(tri_row[t], tri_col[t]) | PG_IDX_ALT)
+                                       : dense(tri_row[t], tri_col[t]));
+    // blocks of the product-Gram kernels over fields in HBM: about 16384
+    // points each (at least 256 blocks, at least one 128-point step per block)
+    const int64_t npix_i = (int64_t)p.n * p.n * p.n;
+    p.nblk_r = (int)std::min<int64_t>(std::max<int64_t>(256, npix_i / 16384), npix_i / 128);
     if (wide) {
-        // blocks of the fields product-Gram: about 16384 points each (at
-        // least 256 blocks, at least one 128-point step per block)
-        const int64_t npix = (int64_t)p.n * p.n * p.n;
-        p.nblk_wide = (int)std::min<int64_t>(std::max<int64_t>(256, npix / 16384), npix / 128);
+        p.nblk_wide = p.nblk_r;
         // P and collapsed quads from the product-Gram of the squares
         // (rows (a,a), columns F_b^2, ones at column nb): -1 leaves a term to
         // the vector ALUs (P at 64 bins, general quads)
@@ -688,6 +742,9 @@ bispec_status upload_tables(bispec_plan_s &p) {
                           hipMemcpyHostToDevice, p.stream));
         CK(hipMemcpyAsync(ws + L.pg_idx, p.pg_idx.data(), sizeof(int) * p.pg_idx.size(), hipMemcpyHostToDevice,
                           p.stream));
+        if (p.n_mtile_r > 0)
+            CK(hipMemcpyAsync(ws + L.pg_pairs_r, p.pg_pairs_r.data(), sizeof(uchar2) * p.pg_pairs_r.size(),
+                              hipMemcpyHostToDevice, p.stream));
     }
     CK(hipStreamSynchronize(p.stream));
     return BISPEC_OK;
@@ -760,8 +817,9 @@ bispec_status finalize_range(bispec_plan_s &p, bool gather, const double *partia
     if (p.timing && !p.ev_cur[3]) stamp(p, 3);
     if (gather) {
         const int *idx = (const int *)(ws + L.pg_idx) + first;
-        CK(launch_finalize_gather(partial, nblk, blk_stride, idx, nterm, batch, scale, oo[0], nn[0], oo[1], nn[1],
-                                  oo[2], nn[2], p.stream));
+        CK(launch_finalize_gather(partial, nblk, blk_stride, (const double *)(ws + L.pg_dense_r),
+                                  (int64_t)refine_dense_doubles(p), idx, nterm, batch, scale, oo[0], nn[0], oo[1],
+                                  nn[1], oo[2], nn[2], p.stream));
     } else {
         CK(launch_finalize(partial, nblk, nterm, batch, scale, oo[0], nn[0], oo[1], nn[1], oo[2], nn[2], p.stream));
     }
@@ -793,7 +851,7 @@ bispec_status run_estimate_body(bispec_plan_s &p, const float *delta, int batch,
     int first = B ? 0 : ntri, last = P ? ntri + p.nb : ntri;
     if (!B && !P) first = last = 0;
     const bool mfma = p.mfma_ok && p.precision != BISPEC_FP32_VALU;
-    if ((!mfma || (T && !p.quads_collapsed)) && !p.ws_fields) return BISPEC_E_NO_WORKSPACE;
+    if ((!mfma || (T && !p.quads_collapsed) || (B && p.n_mtile_r > 0)) && !p.ws_fields) return BISPEC_E_NO_WORKSPACE;
     if (!mfma) {
         float *fields = (float *)(ws + L.fields);
         bispec_status s = run_fields(p, delta, batch, fields);
@@ -811,6 +869,14 @@ bispec_status run_estimate_body(bispec_plan_s &p, const float *delta, int batch,
             CK(launch_pgram_fields(fields, n, p.nb, batch, (const uchar2 *)(ws + L.pg_pairs), p.n_mtile,
                                    p.nblk_wide, pg, p.stream, false));
             CK(launch_reduce_dense(pg, p.nblk_wide, n_dense, batch, dense, (double *)(ws + L.pg_tmp), p.stream));
+            if (p.n_mtile_r > 0) {
+                // ill-conditioned triplets: FP64 product-Gram rows of their own
+                double *pr = (double *)(ws + L.pg_partial_r);
+                CK(launch_pgram_fields_f64(fields, n, p.nb, batch, (const uchar2 *)(ws + L.pg_pairs_r), p.n_mtile_r,
+                                           p.nblk_r, pr, p.stream));
+                CK(launch_reduce_dense(pr, p.nblk_r, (int64_t)refine_dense_doubles(p), batch,
+                                       (double *)(ws + L.pg_dense_r), (double *)(ws + L.pg_tmp_r), p.stream));
+            }
             s = finalize_range(p, true, dense, 1, n_dense, 0, ntri, batch, P, B, T);
             if (s != BISPEC_OK) return s;
             first = ntri;
@@ -862,8 +928,22 @@ bispec_status run_estimate_body(bispec_plan_s &p, const float *delta, int batch,
         CK(launch_tail(mode, t_mfma, (const float2 *)(ws + L.bc), tp, n, p.nb, batch,
                        (const uchar2 *)(ws + L.pg_pairs), p.n_mtile, tw, p.nblk_pg, pg, p.stream, p.tail_shape));
         const int64_t n_dense = (int64_t)pgram_partial_doubles(p.n_mtile, t_mfma);
+        const bool refine = first < ntri && p.n_mtile_r > 0;
+        if (refine) {
+            // ill-conditioned triplets: the bin fields from the compact rows
+            // (still in place), then FP64 product-Gram rows of their own
+            float *fields = (float *)(ws + L.fields);
+            CK(launch_inverse_x_pairs((const float2 *)(ws + L.bc), n, batch, tw, (const PairDev *)(ws + L.pd),
+                                      (int)p.pairs.size(), p.nb, fields, p.stream));
+            CK(launch_pgram_fields_f64(fields, n, p.nb, batch, (const uchar2 *)(ws + L.pg_pairs_r), p.n_mtile_r,
+                                       p.nblk_r, (double *)(ws + L.pg_partial_r), p.stream));
+        }
         stamp(p, 3);
         CK(launch_reduce_dense(pg, p.nblk_pg, n_dense, batch, dense, (double *)(ws + L.pg_tmp), p.stream));
+        if (refine)
+            CK(launch_reduce_dense((const double *)(ws + L.pg_partial_r), p.nblk_r,
+                                   (int64_t)refine_dense_doubles(p), batch, (double *)(ws + L.pg_dense_r),
+                                   (double *)(ws + L.pg_tmp_r), p.stream));
         if (first < last) {
             s = finalize_range(p, true, dense, 1, n_dense, first, last, batch, P, B, T);
             if (s != BISPEC_OK) return s;

@@ -99,9 +99,18 @@ hipError_t launch_pgram_fields(const float *fields, int n, int nb, int batch, co
 constexpr int PG_REDUCE_SEGS = 32;
 hipError_t launch_reduce_dense(const double *partial, int nblk, int64_t n_dense, int batch, double *dense,
                                double *tmp, hipStream_t st);
-hipError_t launch_finalize_gather(const double *partial, int nblk, int64_t blk_stride, const int *idx, int nterm,
-                                  int batch, const double *scale, double *o0, int n0, double *o1, int n1, double *o2,
-                                  int n2, hipStream_t st);
+// Terms whose idx carries PG_IDX_ALT read alt (block stride alt_stride) at
+// idx & ~PG_IDX_ALT instead of partial: the refinement pass's dense tiles.
+constexpr int PG_IDX_ALT = 1 << 30;
+hipError_t launch_finalize_gather(const double *partial, int nblk, int64_t blk_stride, const double *alt,
+                                  int64_t alt_stride, const int *idx, int nterm, int batch, const double *scale,
+                                  double *o0, int n0, double *o1, int n1, double *o2, int n2, hipStream_t st);
+// FP64 product-Gram over bin fields in HBM (the refinement rows of
+// ill-conditioned triplets, any plan of up to 64 bins): same tables and
+// partial layout as launch_pgram_fields, one pair tile per wave, nblk blocks
+// of pgram_fields_chunk(n, nblk) points.
+hipError_t launch_pgram_fields_f64(const float *fields, int n, int nb, int batch, const uchar2 *pairs, int n_mtile,
+                                   int nblk, double *partial, hipStream_t st);
 
 // out[map][g] = sum_{group[t] = g} count[t] B[map][t] / sum count[t] (NaN if empty).
 hipError_t launch_rebin(const double *B, int n_tri, const double *count, const int *group, int n_group, int batch,

@@ -24,7 +24,9 @@
 // (k_reduce_dense).  A chunk is at most 2048 split-mode MFMA steps, so the
 // FP32 accumulators of split mode are converted only at the end of a chunk;
 // FP32 mode (two points per step) adds its accumulators into FP64 registers
-// every 4096 points.
+// every 32 MFMAs.  Triplets whose sums cancel strongly (ill-conditioned ones)
+// are not read from these tiles but from an FP64 product-Gram over the bin
+// fields (k_pgram_fields_f64).
 //
 // Lane layouts (checked on the device): for the 32x32x16 bf16 operation lane
 // l holds A[l%32][8(l/32)+j] and B[8(l/32)+j][l%32], j < 8; for 32x32x2 f32
@@ -62,7 +64,8 @@ constexpr int PG_NT_DEEP = 512, PG_MAXT_DEEP = 3;
 constexpr int PG_NT_TWIN = 512, PG_MAXT_TWIN = 1, PG_TK_TWIN = 256;
 constexpr bool PG_TWIN_PREFETCH = false;   // the co-resident block hides the loads
 constexpr bool PG_WIDE_PREFETCH = false;   // the prefetch registers cost more (spills) than they hide
-constexpr int PG_FLUSH_POINTS = 4096;     // FP32-mode accumulation span before an FP64 flush
+constexpr int PG_FLUSH_POINTS = 4096;     // FP32 mode: flush at least this often (whole tiles)
+constexpr int PG_F32_FLUSH_STEPS = 32;    // FP32 mode: MFMAs (of 2 points) per FP32 accumulation span
 constexpr int PG_ZERO = PG_ROW_ZERO;      // field row of zeros (padding rows)
 constexpr int PG_ONE = PG_ROW_ONE;        // field row of ones (F_b * 1 rows)
 constexpr int PG_FROWS = 34;
@@ -176,6 +179,10 @@ struct PgState {
             else
                 contract_split<TK, FS, false>(Ft, bh_row, bl_row, half);
         } else {
+            // every PG_F32_FLUSH_STEPS MFMAs (2 points each) the FP32
+            // accumulators move into the FP64 ones, so each FP32 sum spans at
+            // most 64 points of its K part
+            int steps = 0;
 #pragma unroll 1
             for (int s = kpart; s < TK / 2; s += ksplit) {
                 const int k = 2 * s + half;
@@ -186,6 +193,10 @@ struct PgState {
                     const float a = Ft[rp[t].x * FS + k] * Ft[rp[t].y * FS + k];
                     acc[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, bk, acc[t], 0, 0, 0);
                     if (WANT_T && tile_of[t] == 0) acct = __builtin_amdgcn_mfma_f32_32x32x2f32(a, a, acct, 0, 0, 0);
+                }
+                if (++steps == PG_F32_FLUSH_STEPS) {
+                    steps = 0;
+                    flush();
                 }
             }
         }
@@ -592,6 +603,91 @@ __global__ __launch_bounds__(PGF_NT) void k_pgram_fields(const float *__restrict
     }
 }
 
+// The same product-Gram on the FP64 matrix cores (v_mfma_f64_16x16x4f64),
+// for the rows of ill-conditioned triplets, whose sums cancel so strongly
+// that FP32 (or split-BF16) rounding of the products and their accumulation
+// would show: the pair product of two FP32 fields is exact in FP64, and so
+// are the products with the column fields up to FP64 rounding.  64 columns
+// (columns >= nb are zero).  Block (c, map, g) contracts the points
+// [c chunk, (c+1) chunk) for the 32-row pair tile g WAVES + w of wave w.
+// Each step stages PGF64_TK points of every field in LDS; one K step (4
+// points) is 8 MFMAs 16x16x4: row halves (lanes l % 16 and 16 + l % 16) times
+// the four 16-column quarters.  Lane layout (checked on the device): lane l
+// feeds A[l % 16][l / 16] and B[l / 16][l % 16], and holds
+// C[4 r + l / 16][l % 16] in accumulator register r.  Partials
+// [batch][nblk][n_mtile][32][64] FP64, as the split kernel writes them.
+constexpr int PGF64_NT = 256, PGF64_TK = 128;
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(PGF64_NT) void k_pgram_fields_f64(const float *__restrict__ fields, int64_t npix,
+                                                               int nb, int64_t map_stride,
+                                                               const uchar2 *__restrict__ pairs, int n_mtile,
+                                                               int64_t chunk, double *__restrict__ partial) {
+    constexpr int TK = PGF64_TK, FS = TK + 4, WAVES = PGF64_NT / 64;
+    __shared__ __attribute__((aligned(16))) float Ft[(PGF_ROW_ZERO + 1) * FS];
+    const int tid = threadIdx.x, lane = tid & 63, r16 = lane & 15, kq = lane >> 4;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int map = blockIdx.y;
+    for (int i = tid; i < (PGF_ROW_ZERO + 1 - nb) * FS; i += PGF64_NT) Ft[nb * FS + i] = 0.0f;
+    const int tile = blockIdx.z * WAVES + wave;
+    const bool live = tile < n_mtile;
+    const uchar2 zero = uchar2{PGF_ROW_ZERO, PGF_ROW_ZERO};
+    const uchar2 rp0 = live ? pairs[tile * 32 + r16] : zero;
+    const uchar2 rp1 = live ? pairs[tile * 32 + 16 + r16] : zero;
+    f64x4 c[2][4];
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) c[h][q] = f64x4{0.0, 0.0, 0.0, 0.0};
+    const float *f = fields + (int64_t)map * map_stride;
+    const int64_t p0 = (int64_t)blockIdx.x * chunk;
+    const int64_t p1 = p0 + chunk < npix ? p0 + chunk : npix;
+    constexpr int LPT = 64 * (TK / 4) / PGF64_NT;   // float4 per thread at 64 bins
+    static_assert(64 * (TK / 4) % PGF64_NT == 0, "field loads must divide the block");
+    for (int64_t p = p0; p < p1; p += TK) {
+        float4 v[LPT];
+#pragma unroll
+        for (int j = 0; j < LPT; ++j) {
+            const int e = tid + j * PGF64_NT;
+            if (e < nb * (TK / 4)) {
+                const int b = e / (TK / 4), k = (e % (TK / 4)) * 4;
+                v[j] = *reinterpret_cast<const float4 *>(f + (int64_t)b * npix + p + k);
+            }
+        }
+        __syncthreads();   // the previous step's reads are done
+#pragma unroll
+        for (int j = 0; j < LPT; ++j) {
+            const int e = tid + j * PGF64_NT;
+            if (e < nb * (TK / 4)) {
+                const int b = e / (TK / 4), k = (e % (TK / 4)) * 4;
+                *reinterpret_cast<float4 *>(&Ft[b * FS + k]) = v[j];
+            }
+        }
+        __syncthreads();
+        if (!live) continue;
+#pragma unroll 2
+        for (int s = 0; s < TK / 4; ++s) {
+            const int k = 4 * s + kq;
+            const double a0 = (double)Ft[rp0.x * FS + k] * (double)Ft[rp0.y * FS + k];
+            const double a1 = (double)Ft[rp1.x * FS + k] * (double)Ft[rp1.y * FS + k];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const double b = (double)Ft[(16 * q + r16) * FS + k];
+                c[0][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b, c[0][q], 0, 0, 0);
+                c[1][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b, c[1][q], 0, 0, 0);
+            }
+        }
+    }
+    if (!live) return;
+    double *base = partial + ((int64_t)map * gridDim.x + blockIdx.x) * ((int64_t)n_mtile * 2048) + tile * 2048;
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) base[(16 * h + 4 * r + kq) * 64 + 16 * q + r16] = c[h][q][r];
+}
+
 // Fixed-order compensated FP64 sum over blocks of every dense tile entry,
 // in segments: out[map][z][e] = sum_{b in segment z} partial[map][b][e],
 // segment z = [z seg, min((z+1) seg, nblk)) for z = blockIdx.z.  Consecutive
@@ -617,13 +713,19 @@ __global__ __launch_bounds__(256) void k_reduce_dense(const double *__restrict__
 // Fixed-order FP64 sum over blocks of the dense tile partials, gathered at
 // idx[t] and scaled: segment layout as in k_finalize.
 __global__ __launch_bounds__(256) void k_finalize_gather(const double *__restrict__ partial, int nblk,
-                                                         int64_t blk_stride, const int *__restrict__ idx, int nterm,
+                                                         int64_t blk_stride, const double *__restrict__ alt,
+                                                         int64_t alt_stride, const int *__restrict__ idx, int nterm,
                                                          const double *__restrict__ scale, double *o0, int n0,
                                                          double *o1, int n1, double *o2, int n2) {
     const int t = blockIdx.x * 256 + threadIdx.x;
     const int map = blockIdx.y;
     if (t >= nterm) return;
-    const double *p = partial + (int64_t)map * nblk * blk_stride + idx[t];
+    // entries flagged PG_IDX_ALT live in the refinement pass's dense tiles
+    const int it = idx[t];
+    const bool in_alt = (it & PG_IDX_ALT) != 0;
+    if (in_alt) blk_stride = alt_stride;
+    const double *p = in_alt ? alt + (int64_t)map * nblk * alt_stride + (it & ~PG_IDX_ALT)
+                             : partial + (int64_t)map * nblk * blk_stride + it;
     double acc = 0.0, comp = 0.0;
     for (int b = 0; b < nblk; ++b) {
         const double x = p[(int64_t)b * blk_stride];
@@ -787,11 +889,23 @@ hipError_t launch_reduce_dense(const double *partial, int nblk, int64_t n_dense,
     return hipGetLastError();
 }
 
-hipError_t launch_finalize_gather(const double *partial, int nblk, int64_t blk_stride, const int *idx, int nterm,
-                                  int batch, const double *scale, double *o0, int n0, double *o1, int n1, double *o2,
-                                  int n2, hipStream_t st) {
+hipError_t launch_finalize_gather(const double *partial, int nblk, int64_t blk_stride, const double *alt,
+                                  int64_t alt_stride, const int *idx, int nterm, int batch, const double *scale,
+                                  double *o0, int n0, double *o1, int n1, double *o2, int n2, hipStream_t st) {
     hipLaunchKernelGGL(k_finalize_gather, dim3((nterm + 255) / 256, batch), dim3(256), 0, st, partial, nblk,
-                       blk_stride, idx, nterm, scale, o0, n0, o1, n1, o2, n2);
+                       blk_stride, alt, alt_stride, idx, nterm, scale, o0, n0, o1, n1, o2, n2);
+    return hipGetLastError();
+}
+
+hipError_t launch_pgram_fields_f64(const float *fields, int n, int nb, int batch, const uchar2 *pairs, int n_mtile,
+                                   int nblk, double *partial, hipStream_t st) {
+    if (nb < 1 || nb > 64 || n_mtile < 1 || nblk < 1 || batch < 1 || !pairs) return hipErrorInvalidValue;
+    const int64_t npix = (int64_t)n * n * n;
+    const int64_t chunk = pgram_fields_chunk(n, nblk);
+    if (npix % PGF64_TK != 0 || chunk % PGF64_TK != 0) return hipErrorInvalidValue;
+    const unsigned groups = (unsigned)((n_mtile + PGF64_NT / 64 - 1) / (PGF64_NT / 64));
+    hipLaunchKernelGGL(k_pgram_fields_f64, dim3(nblk, batch, groups), dim3(PGF64_NT), 0, st, fields, npix, nb,
+                       (int64_t)nb * npix, pairs, n_mtile, chunk, partial);
     return hipGetLastError();
 }
 

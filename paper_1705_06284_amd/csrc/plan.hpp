@@ -52,6 +52,13 @@ struct bispec_plan_s {
     int tail_shape = 1;                  // tail block shape, PG_SHAPE_* (tuned; 1 = wide)
     std::vector<uchar2> pg_pairs;        // [n_mtile*32] row factors
     std::vector<int> pg_idx;             // per term: index into a block's dense tiles
+                                         // (| PG_IDX_ALT: into the refinement tiles)
+    // refinement rows: triplets whose condition number exceeds kRefineKappa
+    // run on FP32-mode product-Gram rows of their own in every precision
+    std::vector<unsigned char> refine;   // per triplet: 1 = read from the refinement tiles
+    std::vector<uchar2> pg_pairs_r;      // [n_mtile_r*32] row factors of those rows
+    int n_mtile_r = 0;                   // 32-row tiles of refinement rows (0: none)
+    int nblk_r = 1;                      // blocks per map of the refinement pass
     // stage timing: one event per stage boundary per call
     bool timing = false;
     std::vector<hipEvent_t> ev_pool;     // free events
@@ -78,9 +85,18 @@ constexpr int kMomBlocks = 2048;
 
 // Byte offsets of the workspace regions (256-byte aligned).
 struct Layout {
-    size_t tw, terms, scale, tcount, thr, mom_partial, mom_tmp, mom, pg_pairs, pg_idx, cols, pd, ztab, ytab, mean_partial, mean, spec, abox, bc, fields,
-        partial, pg_partial, pg_dense, pg_tmp, total;
+    size_t tw, terms, scale, tcount, thr, mom_partial, mom_tmp, mom, pg_pairs, pg_idx, pg_pairs_r, cols, pd, ztab,
+        ytab, mean_partial, mean, spec, abox, bc, fields, partial, pg_partial, pg_dense, pg_tmp, pg_partial_r,
+        pg_dense_r, pg_tmp_r, total;
 };
+
+// Triplets with a condition number sqrt(M_i M_j M_k / (N_pix N_t)) above
+// this run on the FP32-mode refinement rows (split-BF16 rounding, about
+// 1.5e-5 kappa relative to the noise level, would pass 1e-4 beyond it).
+constexpr double kRefineKappa = 4.0;
+
+// Doubles of the refinement pass's dense tiles per map.
+size_t refine_dense_doubles(const bispec_plan_s &p);
 
 Layout make_layout(const bispec_plan_s &p, int batch);
 bool needs_fields(const bispec_plan_s &p);

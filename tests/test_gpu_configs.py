@@ -150,16 +150,15 @@ def test_wide_bins_64_all_outputs(binding):
         ref = oracle.bispectrum(d, lo, hi, trip[sel], delta_k=Dk)
         assert np.array_equal(plan.counts[sel].astype(np.int64), ref.count)
         err = np.abs(B.cpu().numpy()[k][sel] - ref.value) / np.maximum(np.abs(ref.value), ref.noise)
-        # shells narrower than k_f leave triplets with little triangle slack:
-        # rounding is amplified by kappa = sqrt(M_i M_j M_k / (N_pix N_t)),
-        # so the bar is TOL up to kappa = 2 and grows with kappa beyond
+        # shells narrower than k_f leave triplets with little triangle slack
+        # (condition number kappa = sqrt(M_i M_j M_k / (N_pix N_t)) up to ~43
+        # here); those above 4 run on the FP64 refinement rows
         mm = m[trip[sel]].astype(float)
         kappa = np.sqrt(mm[:, 0] * mm[:, 1] * mm[:, 2] / (float(n) ** 3 * ref.count))
         w = int(np.argmax(err))
         _say("  map %d: %d sampled triplets, max err %.2e (kappa %.1f, max kappa %.1f)"
              % (k, len(sel), err[w], kappa[w], kappa.max()))
-        assert np.all(err <= TOL["split_bf16"] * np.maximum(1.0, kappa / 2.0))
-        assert np.max(err[kappa <= 2.0]) <= TOL["split_bf16"]
+        assert np.all(err <= TOL["split_bf16"])
         refp, _ = oracle.power_spectrum(d, lo, hi, delta_k=Dk)
         ep = np.abs(P.cpu().numpy()[k] - refp) / refp
         qs = [q for q in range(len(quads)) if max(quads[q]) <= 6]
@@ -204,7 +203,7 @@ def test_sixty_four_bins(binding):
     mm = m[trip[sel]].astype(float)
     kappa = np.sqrt(mm[:, 0] * mm[:, 1] * mm[:, 2] / (float(n) ** 3 * ref.count))
     _say("  %d sampled triplets, max err %.2e (max kappa %.1f)" % (len(sel), err.max(), kappa.max()))
-    assert np.all(err <= TOL["split_bf16"] * np.maximum(1.0, kappa / 2.0))
+    assert np.all(err <= TOL["split_bf16"])
     refp, _ = oracle.power_spectrum(d, lo, hi, delta_k=Dk)
     assert np.max(np.abs(P.cpu().numpy()[0] - refp) / refp) <= TOL["fp32"]
     qs = [q for q in range(len(quads)) if max(quads[q]) <= 4]
