@@ -21,12 +21,15 @@
  * the grid's fundamental cell, i.e. k1+k2+k3 = 0 holds in Z^3 and not only
  * modulo N (the aliasing discussion of Section 3, Eq. delta_sefusatti).
  *
- * Delta is the full complex DFT on the N^3 grid, layout [z][y][x], entry
- * (m mod N).  Passing re == NULL makes every amplitude 1, which turns the
- * sums into the polygon counts of the denominator of Eq. gen_Nspec3.
+ * Delta is the full complex DFT on the nz x ny x nx grid, layout [z][y][x],
+ * entry (m mod N) per axis.  Passing re == NULL makes every amplitude 1, which
+ * turns the sums into the polygon counts of the denominator of Eq. gen_Nspec3.
  *
- * Bin membership comes from a per-|m|^2 bit mask built by the caller:
- * bit b of mask[r2] is set when mode vectors with |m|^2 = r2 belong to bin b.
+ * Bin membership comes from a bit mask indexed by the integer
+ * q = (sz mz)^2 + (sy my)^2 + (sx mx)^2 built by the caller (sz, sy, sx = 1
+ * on a cubic grid, where q = |m|^2; on a grid of cubic cells q is |k|^2 in
+ * units of 2 pi / (lcm of the sides) cells): bit b of mask[q] is set when mode
+ * vectors of that q belong to bin b.
  *
  * Output layout per bin b (ORC_NACC doubles):
  *   [0] Re S   [1] Im S   [2] count   [3] Re S_strict   [4] Im S_strict
@@ -41,18 +44,24 @@
 
 #define ORC_NACC 7
 
+/* Reduce c modulo n into [-n/2, n/2) (odd n: [-(n-1)/2, (n-1)/2]). */
 static inline int wrap_c(int c, int n) {
-    int h = n / 2;
-    if (c >= h) return c - n;
-    if (c < -h) return c + n;
-    return c;
+    int r = ((c % n) + n) % n;
+    return r >= n - n / 2 ? r - n : r;
 }
 
-static inline int64_t grid_index(int mz, int my, int mx, int n) {
-    int z = mz < 0 ? mz + n : mz;
-    int y = my < 0 ? my + n : my;
-    int x = mx < 0 ? mx + n : mx;
-    return ((int64_t)z * n + y) * n + x;
+typedef struct { int nz, ny, nx, sz, sy, sx; } grid_t;
+
+static inline int64_t grid_index(int mz, int my, int mx, const grid_t *g) {
+    int z = mz < 0 ? mz + g->nz : mz;
+    int y = my < 0 ? my + g->ny : my;
+    int x = mx < 0 ? mx + g->nx : mx;
+    return ((int64_t)z * g->ny + y) * g->nx + x;
+}
+
+static inline int64_t grid_q(int mz, int my, int mx, const grid_t *g) {
+    int64_t a = (int64_t)g->sz * mz, b = (int64_t)g->sy * my, c = (int64_t)g->sx * mx;
+    return a * a + b * b + c * c;
 }
 
 static inline void amp(const double *re, const double *im, int64_t g,
@@ -83,11 +92,13 @@ static inline void accumulate(double *acc, uint64_t bits, double pr, double pi,
 }
 
 /* p = 3: ordered pairs (m1 in A, m2 in B) closed by m3 = -(m1+m2) mod N. */
-int orc_pair_sums(int n, const double *re, const double *im,
+int orc_pair_sums(int nz, int ny, int nx, int sz, int sy, int sx, const double *re, const double *im,
                   int na, const int32_t *ma, int nb_modes, const int32_t *mb,
                   const uint64_t *mask, int64_t mask_len, uint64_t want,
                   int n_bins, double *out) {
-    if (n <= 0 || n_bins <= 0 || n_bins > 64) return -1;
+    if (nz <= 0 || ny <= 0 || nx <= 0 || n_bins <= 0 || n_bins > 64) return -1;
+    const grid_t G = {nz, ny, nx, sz, sy, sx};
+    const grid_t *g = &G;
     int nt = omp_get_max_threads();
     double *part = (double *)calloc((size_t)nt * n_bins * ORC_NACC, sizeof(double));
     if (!part) return -2;
@@ -98,19 +109,19 @@ int orc_pair_sums(int n, const double *re, const double *im,
         for (int a = 0; a < na; ++a) {
             int z1 = ma[3 * a], y1 = ma[3 * a + 1], x1 = ma[3 * a + 2];
             double r1, i1;
-            amp(re, im, grid_index(z1, y1, x1, n), &r1, &i1);
+            amp(re, im, grid_index(z1, y1, x1, g), &r1, &i1);
             for (int b = 0; b < nb_modes; ++b) {
                 int z2 = mb[3 * b], y2 = mb[3 * b + 1], x2 = mb[3 * b + 2];
                 int uz = -(z1 + z2), uy = -(y1 + y2), ux = -(x1 + x2);
-                int z3 = wrap_c(uz, n), y3 = wrap_c(uy, n), x3 = wrap_c(ux, n);
-                int64_t r2 = (int64_t)z3 * z3 + (int64_t)y3 * y3 + (int64_t)x3 * x3;
-                if (r2 >= mask_len) continue;
-                uint64_t bits = mask[r2] & want;
+                int z3 = wrap_c(uz, nz), y3 = wrap_c(uy, ny), x3 = wrap_c(ux, nx);
+                int64_t q = grid_q(z3, y3, x3, g);
+                if (q >= mask_len) continue;
+                uint64_t bits = mask[q] & want;
                 if (!bits) continue;
                 int strict = (z3 == uz) && (y3 == uy) && (x3 == ux);
                 double r2a, i2a, r3a, i3a;
-                amp(re, im, grid_index(z2, y2, x2, n), &r2a, &i2a);
-                amp(re, im, grid_index(z3, y3, x3, n), &r3a, &i3a);
+                amp(re, im, grid_index(z2, y2, x2, g), &r2a, &i2a);
+                amp(re, im, grid_index(z3, y3, x3, g), &r3a, &i3a);
                 double pr = r1 * r2a - i1 * i2a;
                 double pi = r1 * i2a + i1 * r2a;
                 double qr = pr * r3a - pi * i3a;
@@ -126,12 +137,14 @@ int orc_pair_sums(int n, const double *re, const double *im,
 
 /* p = 4: ordered triples (m1 in A, m2 in B, m3 in C) closed by
  * m4 = -(m1+m2+m3) mod N. */
-int orc_triple_sums(int n, const double *re, const double *im,
+int orc_triple_sums(int nz, int ny, int nx, int sz, int sy, int sx, const double *re, const double *im,
                     int na, const int32_t *ma, int nb_modes, const int32_t *mb,
                     int nc, const int32_t *mc,
                     const uint64_t *mask, int64_t mask_len, uint64_t want,
                     int n_bins, double *out) {
-    if (n <= 0 || n_bins <= 0 || n_bins > 64) return -1;
+    if (nz <= 0 || ny <= 0 || nx <= 0 || n_bins <= 0 || n_bins > 64) return -1;
+    const grid_t G = {nz, ny, nx, sz, sy, sx};
+    const grid_t *g = &G;
     int nt = omp_get_max_threads();
     double *part = (double *)calloc((size_t)nt * n_bins * ORC_NACC, sizeof(double));
     if (!part) return -2;
@@ -142,28 +155,25 @@ int orc_triple_sums(int n, const double *re, const double *im,
         for (int a = 0; a < na; ++a) {
             int z1 = ma[3 * a], y1 = ma[3 * a + 1], x1 = ma[3 * a + 2];
             double r1, i1;
-            amp(re, im, grid_index(z1, y1, x1, n), &r1, &i1);
+            amp(re, im, grid_index(z1, y1, x1, g), &r1, &i1);
             for (int b = 0; b < nb_modes; ++b) {
                 int z2 = mb[3 * b], y2 = mb[3 * b + 1], x2 = mb[3 * b + 2];
                 double r2a, i2a;
-                amp(re, im, grid_index(z2, y2, x2, n), &r2a, &i2a);
+                amp(re, im, grid_index(z2, y2, x2, g), &r2a, &i2a);
                 double pr = r1 * r2a - i1 * i2a;
                 double pi = r1 * i2a + i1 * r2a;
                 for (int c = 0; c < nc; ++c) {
                     int z3 = mc[3 * c], y3 = mc[3 * c + 1], x3 = mc[3 * c + 2];
                     int uz = -(z1 + z2 + z3), uy = -(y1 + y2 + y3), ux = -(x1 + x2 + x3);
-                    /* three shell components each lie in (-N/2, N/2), so one
-                     * reduction step may not suffice: reduce fully. */
-                    int z4 = ((uz % n) + n) % n, y4 = ((uy % n) + n) % n, x4 = ((ux % n) + n) % n;
-                    z4 = wrap_c(z4, n); y4 = wrap_c(y4, n); x4 = wrap_c(x4, n);
-                    int64_t r2 = (int64_t)z4 * z4 + (int64_t)y4 * y4 + (int64_t)x4 * x4;
-                    if (r2 >= mask_len) continue;
-                    uint64_t bits = mask[r2] & want;
+                    int z4 = wrap_c(uz, nz), y4 = wrap_c(uy, ny), x4 = wrap_c(ux, nx);
+                    int64_t q = grid_q(z4, y4, x4, g);
+                    if (q >= mask_len) continue;
+                    uint64_t bits = mask[q] & want;
                     if (!bits) continue;
                     int strict = (z4 == uz) && (y4 == uy) && (x4 == ux);
                     double r3a, i3a, r4a, i4a;
-                    amp(re, im, grid_index(z3, y3, x3, n), &r3a, &i3a);
-                    amp(re, im, grid_index(z4, y4, x4, n), &r4a, &i4a);
+                    amp(re, im, grid_index(z3, y3, x3, g), &r3a, &i3a);
+                    amp(re, im, grid_index(z4, y4, x4, g), &r4a, &i4a);
                     double qr = pr * r3a - pi * i3a;
                     double qi = pr * i3a + pi * r3a;
                     double sr = qr * r4a - qi * i4a;

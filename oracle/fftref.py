@@ -20,7 +20,8 @@ order of steps:
 
 The shells are the same as the direct-sum oracle's (``polyspec``): mode m
 (signed integer components in [-N/2, N/2)) is in bin b iff
-lo_b^2 <= |m|^2 < hi_b^2 and m != 0, with the squared edges formed in FP64.
+lo_b^2 <= |m|^2 < hi_b^2 and m != 0, with the squared edges formed in FP64;
+on a non-cubic grid of cubic cells |m|^2 is the integer q of ``polyspec``.
 
 For the parity bar the module also forms the random-phase noise level of
 each estimate, norm * sqrt(sum over closed tuples of prod |Delta|^2) / count.
@@ -83,17 +84,16 @@ class FFTReference:
 
     def __init__(self, delta, k_lo, k_hi, box_len=None, cache_bytes=16 << 30):
         d = polyspec.prepare(delta)
-        n = d.shape[0]
-        assert d.shape == (n, n, n)
-        self.n = n
-        self.npix = float(n) ** 3
-        L = float(n) if (box_len is None or box_len <= 0) else float(box_len)
-        self.volume = L ** 3
-        self.lo2, self.hi2 = polyspec.squared_edges(k_lo, k_hi)
+        shape = d.shape
+        self.shape = shape
+        self.npix = float(np.prod(shape))
+        self.volume = polyspec._volume(shape, box_len)
+        self.lo2, self.hi2 = polyspec.squared_edges(k_lo, k_hi, shape)
         self.n_bins = len(self.lo2)
         self.delta_k = _fftn(d)                              # step 1
-        f = polyspec.freq(n).astype(np.int64)
-        self.r2 = f[:, None, None] ** 2 + f[None, :, None] ** 2 + f[None, None, :] ** 2
+        sc = polyspec.q_scales(shape)
+        fz, fy, fx = (sc[a] * polyspec.freq(shape[a]).astype(np.int64) for a in range(3))
+        self.r2 = fz[:, None, None] ** 2 + fy[None, :, None] ** 2 + fx[None, None, :] ** 2
         self._cache = OrderedDict()
         self._cache_bytes = int(cache_bytes)
         self.max_imag = 0.0                                  # largest |Im| / max |Re| seen

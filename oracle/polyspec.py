@@ -11,7 +11,12 @@ What it computes (Watkinson et al. 2017, arXiv:1705.06284, Section 2):
 * Shells: bin b holds the modes with lo_b^2 <= |m|^2 < hi_b^2, m != 0, every
   component in [-N/2, N/2) (the spherical-shell reading of the bin rule of
   Eq. gen_Nspec3; Nyquist modes never qualify because hi_b <= N/2,
-  Eq. nyqvist).
+  Eq. nyqvist).  Non-cubic grids N_z x N_y x N_x (footnote to the pixel
+  coordinates, Section 2: one fundamental per axis) have cubic cells, so
+  L_i = L_x N_i / N_x; with P the lcm of the sides and s_i = P / N_i,
+  q = sum_i (s_i m_i)^2 is |k|^2 in units of (2 pi / (P cells))^2 and the
+  shells, with edges in units of the x-axis fundamental 2 pi / L_x, are
+  (lo_b s_x)^2 <= q < (hi_b s_x)^2.  On a cubic grid q = |m|^2.
 * The bispectrum of Eq. (Jeong_BI) equals the direct sum over ordered closed
   triples (Kronecker delta taken modulo N, the phase-sum identity before
   Eq. gen_Nspec4):
@@ -60,12 +65,13 @@ def _load():
         dp = ctypes.POINTER(ctypes.c_double)
         ip = ctypes.POINTER(ctypes.c_int32)
         up = ctypes.POINTER(ctypes.c_uint64)
-        lib.orc_pair_sums.argtypes = [ctypes.c_int, dp, dp, ctypes.c_int, ip, ctypes.c_int, ip,
-                                      up, ctypes.c_int64, ctypes.c_uint64, ctypes.c_int, dp]
+        six = [ctypes.c_int] * 6
+        lib.orc_pair_sums.argtypes = six + [dp, dp, ctypes.c_int, ip, ctypes.c_int, ip,
+                                            up, ctypes.c_int64, ctypes.c_uint64, ctypes.c_int, dp]
         lib.orc_pair_sums.restype = ctypes.c_int
-        lib.orc_triple_sums.argtypes = [ctypes.c_int, dp, dp, ctypes.c_int, ip, ctypes.c_int, ip,
-                                        ctypes.c_int, ip, up, ctypes.c_int64, ctypes.c_uint64,
-                                        ctypes.c_int, dp]
+        lib.orc_triple_sums.argtypes = six + [dp, dp, ctypes.c_int, ip, ctypes.c_int, ip,
+                                              ctypes.c_int, ip, up, ctypes.c_int64, ctypes.c_uint64,
+                                              ctypes.c_int, dp]
         lib.orc_triple_sums.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -81,49 +87,76 @@ def _ptr(a, ctype):
 # Bins and shells (Eq. gen_Nspec3 with the spherical-shell reading)
 # ----------------------------------------------------------------------------
 
-def squared_edges(k_lo, k_hi):
-    """FP64 squared bin edges, in units of the fundamental mode k_f."""
+def grid_shape(n):
+    """(N_z, N_y, N_x) of a grid given by its side N (cubic) or its shape."""
+    if np.ndim(n) == 0:
+        return (int(n),) * 3
+    t = tuple(int(x) for x in n)
+    assert len(t) == 3
+    return t
+
+
+def q_scales(n):
+    """(s_z, s_y, s_x) = P / N_i with P the lcm of the sides (1, 1, 1 on a cube)."""
+    nz, ny, nx = grid_shape(n)
+    P = int(np.lcm.reduce([nz, ny, nx]))
+    return P // nz, P // ny, P // nx
+
+
+def squared_edges(k_lo, k_hi, n=None):
+    """FP64 squared bin edges in q units: (lo s_x)^2 and (hi s_x)^2, formed as
+    (lo * lo) * (s_x * s_x); on a cubic grid lo^2 and hi^2, in units of k_f."""
     lo = np.asarray(k_lo, dtype=np.float64)
     hi = np.asarray(k_hi, dtype=np.float64)
-    return lo * lo, hi * hi
+    sx2 = float(q_scales(n)[2] ** 2) if n is not None else 1.0
+    return (lo * lo) * sx2, (hi * hi) * sx2
 
 
 def freq(n: int) -> np.ndarray:
-    """Signed integer frequency of each DFT index: 0..N/2-1, -N/2..-1."""
+    """Signed integer frequency of each DFT index: 0..ceil(N/2)-1, then
+    -floor(N/2)..-1 (for even N: -N/2..N/2-1)."""
     i = np.arange(n)
-    return np.where(i < n // 2, i, i - n)
+    return np.where(i < n - n // 2, i, i - n)
 
 
-def bin_mask_table(n: int, k_lo, k_hi) -> np.ndarray:
-    """uint64 bit mask per integer |m|^2: bit b set iff lo_b^2 <= |m|^2 < hi_b^2.
+def _q_of(mz, my, mx, s):
+    return ((s[0] * np.asarray(mz, np.int64)) ** 2 + (s[1] * np.asarray(my, np.int64)) ** 2
+            + (s[2] * np.asarray(mx, np.int64)) ** 2)
 
-    |m|^2 = 0 (the mean) belongs to no bin.
-    """
-    lo2, hi2 = squared_edges(k_lo, k_hi)
+
+def bin_mask_table(n, k_lo, k_hi) -> np.ndarray:
+    """uint64 bit mask per integer q: bit b set iff the modes with that q are
+    in bin b (q = |m|^2 on a cubic grid).  q = 0 (the mean) is in no bin."""
+    shape, s = grid_shape(n), q_scales(n)
+    lo2, hi2 = squared_edges(k_lo, k_hi, n)
     assert len(lo2) <= 64
-    r2max = 3 * (n // 2) ** 2
-    r2 = np.arange(r2max + 1, dtype=np.float64)
-    mask = np.zeros(r2max + 1, dtype=np.uint64)
+    qmax = int(_q_of(shape[0] // 2, shape[1] // 2, shape[2] // 2, s))
+    q = np.arange(qmax + 1, dtype=np.float64)
+    mask = np.zeros(qmax + 1, dtype=np.uint64)
     for b in range(len(lo2)):
-        sel = (r2 >= lo2[b]) & (r2 < hi2[b])
+        sel = (q >= lo2[b]) & (q < hi2[b])
         sel[0] = False
         mask[sel] |= np.uint64(1) << np.uint64(b)
     return mask
 
 
-def shell_modes(n: int, k_lo, k_hi, b: int) -> np.ndarray:
+def shell_modes(n, k_lo, k_hi, b: int) -> np.ndarray:
     """All mode vectors (mz, my, mx) of bin b as an int32 array [M_b, 3]."""
-    lo2, hi2 = squared_edges(k_lo, k_hi)
-    h = min(int(np.ceil(np.sqrt(hi2[b]))) + 1, n // 2)
-    f = np.arange(-h, h + 1) if h < n // 2 else freq(n)
-    f = f[(f >= -(n // 2)) & (f < n // 2)]
-    mz, my, mx = np.meshgrid(f, f, f, indexing="ij")
-    r2 = (mz.astype(np.int64) ** 2 + my.astype(np.int64) ** 2 + mx.astype(np.int64) ** 2)
-    sel = (r2 > 0) & (r2.astype(np.float64) >= lo2[b]) & (r2.astype(np.float64) < hi2[b])
+    shape, s = grid_shape(n), q_scales(n)
+    lo2, hi2 = squared_edges(k_lo, k_hi, n)
+    axes = []
+    for ax in range(3):
+        f = freq(shape[ax])
+        h = int(np.ceil(np.sqrt(hi2[b]) / s[ax])) + 1
+        axes.append(np.sort(f[np.abs(f) <= h]))
+    mz, my, mx = np.meshgrid(*axes, indexing="ij")
+    q = _q_of(mz, my, mx, s)
+    qf = q.astype(np.float64)
+    sel = (q > 0) & (qf >= lo2[b]) & (qf < hi2[b])
     return np.ascontiguousarray(np.stack([mz[sel], my[sel], mx[sel]], axis=1).astype(np.int32))
 
 
-def mode_counts(n: int, k_lo, k_hi) -> np.ndarray:
+def mode_counts(n, k_lo, k_hi) -> np.ndarray:
     """M_b: number of modes in each shell."""
     return np.array([len(shell_modes(n, k_lo, k_hi, b)) for b in range(len(k_lo))], dtype=np.int64)
 
@@ -143,12 +176,10 @@ def dft_matrix(n: int) -> np.ndarray:
 def dft3(delta: np.ndarray) -> np.ndarray:
     """Unnormalised 3D DFT of a real [z][y][x] grid, as three matrix products."""
     d = np.asarray(delta, dtype=np.float64)
-    n = d.shape[0]
-    assert d.shape == (n, n, n)
-    w = dft_matrix(n)
-    a = d @ w.T                                   # x axis
-    a = np.matmul(w, a)                           # y axis (batched over z)
-    a = (w @ a.reshape(n, n * n)).reshape(n, n, n)  # z axis
+    nz, ny, nx = d.shape
+    a = d @ dft_matrix(nx).T                                    # x axis
+    a = np.matmul(dft_matrix(ny), a)                            # y axis (batched over z)
+    a = (dft_matrix(nz) @ a.reshape(nz, ny * nx)).reshape(nz, ny, nx)  # z axis
     return a
 
 
@@ -173,9 +204,12 @@ class Spectrum:
     noise: np.ndarray        # norm * sqrt(sum |product|^2) / count
 
 
-def _volume(n: int, box_len):
-    L = float(n) if (box_len is None or box_len <= 0) else float(box_len)
-    return L ** 3
+def _volume(n, box_len):
+    """V = L_x L_y L_z with cubic cells: L_i = L_x N_i / N_x (L_x = N_x cells
+    when box_len is not given)."""
+    nz, ny, nx = grid_shape(n)
+    L = float(nx) if (box_len is None or box_len <= 0) else float(box_len)
+    return L ** 3 * (nz / nx) * (ny / nx)
 
 
 def _grid_parts(delta_k):
@@ -189,7 +223,7 @@ def _grid_parts(delta_k):
 def _pair_sums(n, re, im, ma, mb, mask, want_bits, n_bins):
     lib = _load()
     out = np.zeros((n_bins, _NACC), dtype=np.float64)
-    rc = lib.orc_pair_sums(n, _ptr(re, ctypes.c_double), _ptr(im, ctypes.c_double),
+    rc = lib.orc_pair_sums(*grid_shape(n), *q_scales(n), _ptr(re, ctypes.c_double), _ptr(im, ctypes.c_double),
                            len(ma), _ptr(ma, ctypes.c_int32), len(mb), _ptr(mb, ctypes.c_int32),
                            _ptr(mask, ctypes.c_uint64), len(mask), ctypes.c_uint64(want_bits),
                            n_bins, _ptr(out, ctypes.c_double))
@@ -200,7 +234,7 @@ def _pair_sums(n, re, im, ma, mb, mask, want_bits, n_bins):
 def _triple_sums(n, re, im, ma, mb, mc, mask, want_bits, n_bins):
     lib = _load()
     out = np.zeros((n_bins, _NACC), dtype=np.float64)
-    rc = lib.orc_triple_sums(n, _ptr(re, ctypes.c_double), _ptr(im, ctypes.c_double),
+    rc = lib.orc_triple_sums(*grid_shape(n), *q_scales(n), _ptr(re, ctypes.c_double), _ptr(im, ctypes.c_double),
                              len(ma), _ptr(ma, ctypes.c_int32), len(mb), _ptr(mb, ctypes.c_int32),
                              len(mc), _ptr(mc, ctypes.c_int32),
                              _ptr(mask, ctypes.c_uint64), len(mask), ctypes.c_uint64(want_bits),
@@ -263,24 +297,24 @@ def _finish(acc, norm):
 def bispectrum(delta, k_lo, k_hi, triplets, box_len=None, delta_k=None) -> Spectrum:
     """Direct-sum bispectrum of Eq. (Jeong_BI) for each triplet of bin indices."""
     d = prepare(delta)
-    n = d.shape[0]
+    n = d.shape
     if delta_k is None:
         delta_k = dft3(d)
     acc = _tuple_sums(n, delta_k, k_lo, k_hi, triplets, 3)
     vol = _volume(n, box_len)
-    npix = float(n) ** 3
+    npix = float(np.prod(n))
     return _finish(acc, vol ** 2 / npix ** 3)
 
 
 def trispectrum(delta, k_lo, k_hi, quads, box_len=None, delta_k=None) -> Spectrum:
     """Direct-sum p = 4 polyspectrum of Eq. (Jeong_gen) for each quad of bins."""
     d = prepare(delta)
-    n = d.shape[0]
+    n = d.shape
     if delta_k is None:
         delta_k = dft3(d)
     acc = _tuple_sums(n, delta_k, k_lo, k_hi, quads, 4)
     vol = _volume(n, box_len)
-    npix = float(n) ** 3
+    npix = float(np.prod(n))
     return _finish(acc, vol ** 3 / npix ** 4)
 
 
@@ -298,16 +332,16 @@ def quad_counts(n, k_lo, k_hi, quads):
 def power_spectrum(delta, k_lo, k_hi, box_len=None, delta_k=None):
     """P_b of Eq. (Jeong_PS) as the shell average of |Delta|^2 (Parseval)."""
     d = prepare(delta)
-    n = d.shape[0]
+    n = d.shape
     if delta_k is None:
         delta_k = dft3(d)
     vol = _volume(n, box_len)
-    npix = float(n) ** 3
+    npix = float(np.prod(n))
     out = np.zeros(len(k_lo))
     m = np.zeros(len(k_lo), dtype=np.int64)
     for b in range(len(k_lo)):
         md = shell_modes(n, k_lo, k_hi, b)
-        v = delta_k[md[:, 0] % n, md[:, 1] % n, md[:, 2] % n]
+        v = delta_k[md[:, 0] % n[0], md[:, 1] % n[1], md[:, 2] % n[2]]
         m[b] = len(md)
         out[b] = vol / npix ** 2 * np.sum(np.abs(v) ** 2) / len(md) if len(md) else np.nan
     return out, m

@@ -99,9 +99,13 @@ def make(wl, cache_bytes):
         out.update(quads=quads, T=np.zeros(0), T_noise=np.zeros(0), T_count=np.zeros(0, np.int64),
                    T_count_frac=np.zeros(0))
     assert R.max_imag < 1e-10, R.max_imag
-    # triangle counts resolve to single units; p = 4 counts outgrow the FP64
-    # unit resolution of N_pix N_q and are held to a relative 1e-9
-    assert out["B_count_frac"].max() < 0.01, out["B_count_frac"].max()
+    # triangle counts resolve to single units up to 256^3; at 512^3 the FP64
+    # rounding of the count fields moves sum I I I / N_pix by a few 1e-2 for
+    # counts near 1e12 (2e-14 relative), so they are held to a relative 1e-13
+    # there; p = 4 counts outgrow the unit resolution of N_pix N_q and are held
+    # to a relative 1e-9
+    fr, ct = out["B_count_frac"], np.maximum(out["B_count"], 1)
+    assert np.all((fr < 0.01) | (fr < 1e-13 * ct)), np.max(fr)
     assert not len(quads) or np.max(out["T_count_frac"] / np.maximum(out["T_count"], 1)) < 1e-9
     path = os.path.join(HERE, "%s.fftref.npz" % wl)
     np.savez_compressed(path, **out)
