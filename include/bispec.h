@@ -53,7 +53,8 @@ typedef struct bispec_plan_s *bispec_plan_t;   /* opaque, owned by the library *
 typedef enum {
     BISPEC_OK = 0,
     BISPEC_E_INVALID = -1,        /* null pointer, bad index, batch out of range  */
-    BISPEC_E_UNSUPPORTED_N = -2,  /* n_side not a power of two in [8, 512]       */
+    BISPEC_E_UNSUPPORTED_N = -2,  /* a side outside [2, 1024], or a prime factor
+                                     other than 2, 3, 5 and one prime <= 127     */
     BISPEC_E_BIN_RANGE = -3,      /* need 0 <= k_lo < k_hi <= N/2, finite         */
     BISPEC_E_EMPTY_BIN = -4,      /* a shell holds no mode                        */
     BISPEC_E_NO_WORKSPACE = -5,   /* workspace missing or smaller than footprint  */
@@ -89,9 +90,22 @@ enum {
     BISPEC_FP32_VALU = 2    /* only the requested sums, FP32 vector ALU               */
 };
 
+/* Grids.  A cubic grid of side N = 2^k, 8 <= N <= 512 (the paper advises 2^n
+ * grids, Section 2) runs the pruned transforms fused with the contraction.
+ * Any other grid N_z x N_y x N_x (n_side, n_y, n_x), each side in [2, 1024]
+ * and a product of 2, 3, 5 and at most one other prime <= 127 (the paper's
+ * 600^3 toy boxes, Section 3.3; its 536^3 = 8 x 67 N-body grid, Section 3.2),
+ * runs mixed-radix Stockham transforms, keeps the bin fields in HBM and
+ * contracts them on the fields product-Gram (up to 63 bins).  Non-cubic grids
+ * have cubic cells (the footnote on pixel coordinates, Section 2: one
+ * fundamental 2 pi / L_i per axis): box_len is L_x, L_i = L_x N_i / N_x,
+ * V = L_x L_y L_z, and shell edges are in units of the x-axis fundamental
+ * 2 pi / L_x, |k| / k_f = sqrt(sum_i (m_i N_x / N_i)^2).  Membership is exact:
+ * with P the lcm of the sides and s_i = P / N_i, q = sum_i (s_i m_i)^2 is
+ * compared with (lo s_x)^2 and (hi s_x)^2 formed in FP64 as (lo lo)(s_x s_x). */
 typedef struct {
-    int32_t n_side;        /* N, a power of two, 8..512 (Section 2: 2^n grids)       */
-    double box_len;        /* L; <= 0 means L = N (grid units, H = V/N_pix = 1)      */
+    int32_t n_side;        /* N (cubic) or N_z                                        */
+    double box_len;        /* L (L_x); <= 0 means L_x = N_x (grid units, H = 1)       */
     int32_t n_bins;        /* 1..64                                                   */
     const double *k_lo;    /* [n_bins] lower shell edges in k_f units (inclusive)     */
     const double *k_hi;    /* [n_bins] upper shell edges in k_f units (exclusive)     */
@@ -102,6 +116,8 @@ typedef struct {
     int32_t precision;     /* BISPEC_FP32, BISPEC_SPLIT_BF16 or BISPEC_FP32_VALU      */
     int32_t max_batch;     /* largest batch any later call will pass, >= 1            */
     void *stream;          /* hipStream_t for all work of this plan (NULL = default) */
+    int32_t n_y;           /* N_y; 0 = n_side                                         */
+    int32_t n_x;           /* N_x; 0 = n_side (edges: 0 <= k_lo < k_hi <= N_x / 2)    */
 } bispec_plan_desc;
 
 /* Build a plan: validate the descriptor, tabulate the shells, evaluate the
@@ -161,7 +177,8 @@ bispec_status bispec_estimate(bispec_plan_t plan, const float *delta, int32_t ba
 bispec_status trispec_estimate(bispec_plan_t plan, const float *delta, int32_t batch,
                                double *T);
 
-/* Connected collapsed trispectrum: the raw T of Eq. Jeong_gen (p = 4) for
+/* Connected collapsed trispectrum (cubic power-of-two grids;
+ * BISPEC_E_UNSUPPORTED_N on other grids): the raw T of Eq. Jeong_gen (p = 4) for
  * every quad (a,a,b,b), and Tc, the same estimate with the quadruples that
  * split into two pairs k_i = -k_j removed -- the Gaussian (disconnected)
  * pairings of Wick's theorem, measured on the map itself:

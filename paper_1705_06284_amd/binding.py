@@ -39,7 +39,8 @@ class PlanDesc(ctypes.Structure):
                 ("k_lo", ctypes.POINTER(ctypes.c_double)), ("k_hi", ctypes.POINTER(ctypes.c_double)),
                 ("n_tri", ctypes.c_int32), ("tri", ctypes.POINTER(ctypes.c_int32)),
                 ("n_quad", ctypes.c_int32), ("quad", ctypes.POINTER(ctypes.c_int32)),
-                ("precision", ctypes.c_int32), ("max_batch", ctypes.c_int32), ("stream", ctypes.c_void_p)]
+                ("precision", ctypes.c_int32), ("max_batch", ctypes.c_int32), ("stream", ctypes.c_void_p),
+                ("n_y", ctypes.c_int32), ("n_x", ctypes.c_int32)]
 
 
 _vp = ctypes.c_void_p
@@ -140,8 +141,10 @@ def _ptr(t):
 class Plan:
     """One estimator plan with a workspace allocated from torch on ``device``.
 
-    k_lo, k_hi: shell edges in units of k_f; triplets: [n, 3] bin indices or
-    None for every closed triplet; quads: [n, 4] or None for every (a,a,b,b).
+    n: the side N of a cubic grid, or its shape (N_z, N_y, N_x); k_lo, k_hi:
+    shell edges in units of k_f (of the x axis); triplets: [n, 3] bin indices
+    or None for every closed triplet; quads: [n, 4] or None for every
+    (a,a,b,b).
     """
 
     def __init__(self, n, k_lo, k_hi, triplets=None, quads=None, box_len=None,
@@ -153,7 +156,11 @@ class Plan:
             raise ValueError("the estimator runs on a GPU device only")
         torch.cuda.init()
         torch.empty(1, device=self.device)        # HIP context current before the library's first call
-        self.n = int(n)
+        shape = (int(n),) * 3 if np.ndim(n) == 0 else tuple(int(x) for x in n)
+        if len(shape) != 3:
+            raise ValueError("n: a side or a shape (N_z, N_y, N_x)")
+        self.shape = shape
+        self.n = shape[0]
         self.k_lo = _arr(k_lo, np.float64)
         self.k_hi = _arr(k_hi, np.float64)
         self.n_bins = len(self.k_lo)
@@ -166,7 +173,9 @@ class Plan:
             stream = torch.cuda.current_stream(self.device)
         self.stream = stream
         d = PlanDesc()
-        d.n_side = self.n
+        d.n_side = shape[0]
+        d.n_y = shape[1]
+        d.n_x = shape[2]
         d.box_len = -1.0 if box_len is None else float(box_len)
         d.n_bins = self.n_bins
         d.k_lo = self.k_lo.ctypes.data_as(_dp)
@@ -310,8 +319,8 @@ class Plan:
         delta = delta.to(device=self.device, dtype=torch.float32).contiguous()
         if delta.dim() == 3:
             delta = delta.unsqueeze(0)
-        if tuple(delta.shape[1:]) != (self.n, self.n, self.n):
-            raise ValueError("expected [batch, N, N, N] with N = %d" % self.n)
+        if tuple(delta.shape[1:]) != self.shape:
+            raise ValueError("expected [batch, %d, %d, %d]" % self.shape)
         return delta
 
     def _empty(self, *shape):
@@ -388,8 +397,7 @@ class Plan:
     def bin_fields(self, delta):
         d = self._input(delta)
         bsz = d.shape[0]
-        f = self._torch.empty(bsz, self.n_bins, self.n, self.n, self.n, dtype=self._torch.float32,
-                              device=self.device)
+        f = self._torch.empty((bsz, self.n_bins) + self.shape, dtype=self._torch.float32, device=self.device)
         self._enter()
         check(bispec_bin_fields(self.handle, _ptr(d), bsz, _ptr(f)), "bispec_bin_fields")
         self._leave(d, f)

@@ -16,9 +16,11 @@
 #include <cstring>
 #include <limits>
 #include <new>
+#include <numeric>
 #include <vector>
 
 #include "../../include/bispec.h"
+#include "general.hpp"
 #include "launch.hpp"
 #include "moments.hpp"
 #include "noalloc.hpp"
@@ -65,8 +67,10 @@ int ceil_int(double x) { return (int)std::ceil(x); }
 
 namespace bispec {
 
+int64_t field_len(const bispec_plan_s &p) { return p.general ? p.fstride : (int64_t)p.n * p.n * p.n; }
+
 bool needs_fields(const bispec_plan_s &p) {
-    return !p.mfma_ok || !p.quads_collapsed || p.precision == BISPEC_FP32_VALU || p.n_mtile_r > 0;
+    return p.general || !p.mfma_ok || !p.quads_collapsed || p.precision == BISPEC_FP32_VALU || p.n_mtile_r > 0;
 }
 
 size_t refine_dense_doubles(const bispec_plan_s &p) { return (size_t)p.n_mtile_r * 2048; }
@@ -76,9 +80,10 @@ size_t wide_dense_doubles(const bispec_plan_s &p) { return (size_t)std::max(p.n_
 
 Layout make_layout(const bispec_plan_s &p, int batch) {
     Layout L{};
-    const int64_t vol = (int64_t)p.n * p.n * p.n;
+    const int64_t vol = field_len(p);
     size_t off = 0;
-    L.tw = off;           off = align_up(off + sizeof(float2) * p.n);
+    const int ntw = p.general ? p.gg.nz + p.gg.ny + p.gg.nx : p.n;
+    L.tw = off;           off = align_up(off + sizeof(float2) * ntw);
     L.terms = off;        off = align_up(off + sizeof(uchar4) * p.terms.size());
     L.scale = off;        off = align_up(off + sizeof(double) * p.scale.size());
     L.tcount = off;       off = align_up(off + sizeof(double) * p.tri_count.size());
@@ -95,9 +100,16 @@ Layout make_layout(const bispec_plan_s &p, int batch) {
     L.ytab = off;         off = align_up(off + sizeof(int2) * p.ytab.size());
     L.mean_partial = off; off = align_up(off + sizeof(double) * kMeanParts * batch);
     L.mean = off;         off = align_up(off + sizeof(double) * batch);
-    L.spec = off;         off = align_up(off + sizeof(float2) * spec_elems(p.n) * batch);
-    L.abox = off;         off = align_up(off + sizeof(float2) * (size_t)p.n * p.absum * batch);
-    L.bc = off;           off = align_up(off + sizeof(float2) * (size_t)p.n * p.n * p.wsum * batch);
+    if (p.general) {
+        // full complex spectrum, and one pair's inverse transform at a time
+        L.spec = off;     off = align_up(off + sizeof(float2) * (size_t)p.npix * batch);
+        L.abox = off;     off = align_up(off + sizeof(float2) * (size_t)p.npix * batch);
+        L.bc = off;
+    } else {
+        L.spec = off;     off = align_up(off + sizeof(float2) * spec_elems(p.n) * batch);
+        L.abox = off;     off = align_up(off + sizeof(float2) * (size_t)p.n * p.absum * batch);
+        L.bc = off;       off = align_up(off + sizeof(float2) * (size_t)p.n * p.n * p.wsum * batch);
+    }
     L.partial = off;      off = align_up(off + sizeof(double) * (size_t)p.nblk * p.terms.size() * batch);
     L.pg_partial = off;
     if (p.mfma_ok) {
@@ -122,6 +134,7 @@ Layout make_layout(const bispec_plan_s &p, int batch) {
     L.pg_partial_r = off; off = align_up(off + sizeof(double) * rd * rblk * batch);
     L.pg_dense_r = off;   off = align_up(off + sizeof(double) * rd * batch);
     L.pg_tmp_r = off;     off = align_up(off + sizeof(double) * rd * PG_REDUCE_SEGS * batch);
+    L.refine_t = off;     off = align_up(off + sizeof(int) * p.refine_t.size());
     // bin fields in HBM: only the vector-ALU contraction and general quads read them
     L.fields = off;
     if (needs_fields(p)) off = align_up(off + sizeof(float) * vol * p.nb * batch);
@@ -298,8 +311,8 @@ void greedy_cover(int nb, const std::vector<int> &tp, const std::vector<int> &tr
 // the refinement tiles.
 void build_pgram_tables(bispec_plan_s &p) {
     const int nb = p.nb;
-    p.mfma_ok = nb <= 32;
-    p.pg_wide = nb > 32 && nb <= 64;
+    p.mfma_ok = !p.general && nb <= 32;
+    p.pg_wide = p.general ? nb <= 63 : (nb > 32 && nb <= 64);
     p.pg_pairs.clear();
     p.pg_idx.clear();
     p.pg_pairs_r.clear();
@@ -345,8 +358,9 @@ void build_pgram_tables(bispec_plan_s &p) {
         }
     }
     // condition numbers decide which cover reads a triplet
-    const double npix = (double)p.n * p.n * p.n;
+    const double npix = (double)p.npix;
     p.refine.assign(ntri, 0);
+    p.refine_t.clear();
     std::vector<int> main_t, ref_t;
     for (int t = 0; t < ntri; ++t) {
         const double m = (double)p.modes[p.tri[3 * t]] * (double)p.modes[p.tri[3 * t + 1]] *
@@ -355,6 +369,7 @@ void build_pgram_tables(bispec_plan_s &p) {
         if (c > 0 && std::sqrt(m / (npix * c)) > kRefineKappa) {
             p.refine[t] = 1;
             ref_t.push_back(t);
+            p.refine_t.push_back(t);
         } else {
             main_t.push_back(t);
         }
@@ -385,7 +400,7 @@ void build_pgram_tables(bispec_plan_s &p) {
                                        : dense(tri_row[t], tri_col[t]));
     // blocks of the product-Gram kernels over fields in HBM: about 16384
     // points each (at least 256 blocks, at least one 128-point step per block)
-    const int64_t npix_i = (int64_t)p.n * p.n * p.n;
+    const int64_t npix_i = field_len(p);
     p.nblk_r = (int)std::min<int64_t>(std::max<int64_t>(256, npix_i / 16384), npix_i / 128);
     if (wide) {
         p.nblk_wide = p.nblk_r;
@@ -424,8 +439,10 @@ void build_pgram_tables(bispec_plan_s &p) {
 void build_terms(bispec_plan_s &p) {
     p.terms.clear();
     p.scale.clear();
-    const double npix = (double)p.n * p.n * p.n;
-    const double V = p.box_len * p.box_len * p.box_len;
+    const double npix = (double)p.npix;
+    // cubic cells: L_i = L_x N_i / N_x on a non-cubic grid
+    const double V = p.box_len * p.box_len * p.box_len *
+                     (p.general ? ((double)p.gg.nz / p.gg.nx) * ((double)p.gg.ny / p.gg.nx) : 1.0);
     const double nan = std::numeric_limits<double>::quiet_NaN();
     const int ntri = (int)p.tri.size() / 3;
     for (int t = 0; t < ntri; ++t) {
@@ -452,6 +469,123 @@ void build_terms(bispec_plan_s &p) {
 // other two upper edges (necessary for a triangle closed in Z^3).
 bool admits_triangle(const bispec_plan_s &p, int i, int j, int k) {
     return p.lo[k] < p.hi[i] + p.hi[j] && p.lo[j] < p.hi[i] + p.hi[k] && p.lo[i] < p.hi[j] + p.hi[k];
+}
+
+// Integer tuple counts from the FP64 grid sums sum_n I...I of the count
+// fields (terms: triplets, then (b,b) per bin, then quads), divided by N_pix.
+bispec_status counts_from_sums(const bispec_plan_s &p, const std::vector<double> &sums, int ntri, double npix,
+                               std::vector<double> &tri_cnt, std::vector<double> &quad_cnt) {
+    const int nb = p.nb, nq = (int)p.quad.size() / 4;
+    auto to_count = [&](double s, double *out) -> bool {
+        const double c = s / npix;
+        const double r = std::nearbyint(c);
+        *out = r;
+        return std::fabs(c - r) <= 0.01;
+    };
+    tri_cnt.assign(ntri, 0.0);
+    for (int t = 0; t < ntri; ++t)
+        if (!to_count(sums[t], &tri_cnt[t])) return BISPEC_E_NUMERIC;
+    for (int b = 0; b < nb; ++b) {
+        double m;
+        if (!to_count(sums[ntri + b], &m) || m != (double)p.modes[b]) return BISPEC_E_NUMERIC;
+    }
+    // p = 4 counts grow like M^3 and outrun what an FP64 sum resolves to one
+    // unit once N_pix N_q passes ~2^53 ulp-scale: they are rounded to the
+    // nearest integer and checked to a relative 1e-9.
+    quad_cnt.assign(nq, 0.0);
+    for (int q = 0; q < nq; ++q) {
+        const double c = sums[ntri + nb + q] / npix;
+        quad_cnt[q] = std::nearbyint(c);
+        if (std::fabs(c - quad_cnt[q]) > std::max(0.01, 1e-9 * std::fabs(c))) return BISPEC_E_NUMERIC;
+    }
+    return BISPEC_OK;
+}
+
+// Count terms: candidate triplets, (b,b) per bin (the mode-count check), quads.
+std::vector<uchar4> count_terms(const bispec_plan_s &p, const std::vector<int> &cand_tri) {
+    std::vector<uchar4> terms;
+    const int ntri = (int)cand_tri.size() / 3;
+    for (int t = 0; t < ntri; ++t)
+        terms.push_back(uchar4{(unsigned char)cand_tri[3 * t], (unsigned char)cand_tri[3 * t + 1],
+                               (unsigned char)cand_tri[3 * t + 2], 0xFF});
+    for (int b = 0; b < p.nb; ++b) terms.push_back(uchar4{(unsigned char)b, (unsigned char)b, 0xFF, 0xFF});
+    const int nq = (int)p.quad.size() / 4;
+    for (int q = 0; q < nq; ++q)
+        terms.push_back(uchar4{(unsigned char)p.quad[4 * q], (unsigned char)p.quad[4 * q + 1],
+                               (unsigned char)p.quad[4 * q + 2], (unsigned char)p.quad[4 * q + 3]});
+    return terms;
+}
+
+// Twiddle tables W_n^j = exp(-2 pi i j / n), j < n, of the axes z, y, x of a
+// general grid (at each axis's tw_off), from the exactly reduced argument.
+template <typename C, typename R> std::vector<C> gen_twiddles(const GenGrid &g) {
+    std::vector<C> tw;
+    for (int a = 0; a < 3; ++a) {
+        const int n = g.ax[a].n;
+        for (int j = 0; j < n; ++j) {
+            const double ang = 2.0 * M_PI * (double)j / (double)n;
+            tw.push_back(C{(R)std::cos(ang), (R)-std::sin(ang)});
+        }
+    }
+    return tw;
+}
+
+// Pair (b, b + 1) of a general grid's shells.
+GenPair gen_pair(const bispec_plan_s &p, int b) {
+    const bool two = b + 1 < p.nb;
+    return GenPair{p.qlo[b], p.qhi[b], two ? p.qlo[b + 1] : 0, two ? p.qhi[b + 1] : 0};
+}
+
+// Count fields and sums of a general grid: unit-amplitude fields of every
+// bin in FP64 by the mixed-radix transforms, then the compensated FP64 term sums.
+bispec_status compute_counts_general(bispec_plan_s &p, std::vector<int> &cand_tri, std::vector<double> &tri_cnt,
+                                     std::vector<double> &quad_cnt) {
+    const int nb = p.nb;
+    hipStream_t st = p.stream;
+    const std::vector<uchar4> terms = count_terms(p, cand_tri);
+    const int nterm = (int)terms.size(), ntri = (int)cand_tri.size() / 3;
+    const int64_t fs = p.fstride;
+    const int nblk = contract_blocks(fs);
+    const std::vector<double2> tw = gen_twiddles<double2, double>(p.gg);
+    size_t off = 0;
+    const size_t o_tw = off;      off = align_up(off + sizeof(double2) * tw.size());
+    const size_t o_terms = off;   off = align_up(off + sizeof(uchar4) * nterm);
+    const size_t o_ones = off;    off = align_up(off + sizeof(double) * nterm);
+    const size_t o_sums = off;    off = align_up(off + sizeof(double) * nterm);
+    const size_t o_partial = off; off = align_up(off + sizeof(double) * (size_t)nblk * nterm);
+    const size_t o_work = off;    off = align_up(off + sizeof(double2) * (size_t)p.npix);
+    const size_t o_fields = off;  off = align_up(off + sizeof(double) * (size_t)fs * nb);
+    char *mem = nullptr;
+    {
+        const hipError_t e = hipMalloc((void **)&mem, off);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            char what[128];
+            std::snprintf(what, sizeof(what), "hipMalloc of %zu bytes for the count fields", off);
+            return record(BISPEC_E_OOM, what, e);
+        }
+    }
+    struct Free {
+        char *m;
+        ~Free() { (void)hipFree(m); }
+    } guard{mem};
+    std::vector<double> ones(nterm, 1.0);
+    CK(hipMemcpyAsync(mem + o_tw, tw.data(), sizeof(double2) * tw.size(), hipMemcpyHostToDevice, st));
+    CK(hipMemcpyAsync(mem + o_terms, terms.data(), sizeof(uchar4) * nterm, hipMemcpyHostToDevice, st));
+    CK(hipMemcpyAsync(mem + o_ones, ones.data(), sizeof(double) * nterm, hipMemcpyHostToDevice, st));
+    double *fields = (double *)(mem + o_fields);
+    for (int b = 0; b < nb; b += 2)
+        CK(gen_inverse_unit_f64((double2 *)(mem + o_work), p.gg, gen_pair(p, b), (const double2 *)(mem + o_tw),
+                                fields + (int64_t)b * fs, b + 1 < nb ? fields + (int64_t)(b + 1) * fs : nullptr, st));
+    CK(gen_zero_pads_f64(fields, p.npix, fs, nb, st));
+    CK(launch_contract_terms_f64(fields, fs, nb, (const uchar4 *)(mem + o_terms), nterm, nblk,
+                                 (double *)(mem + o_partial), st));
+    CK(launch_finalize((const double *)(mem + o_partial), nblk, nterm, 1, (const double *)(mem + o_ones),
+                       (double *)(mem + o_sums), nterm, nullptr, 0, nullptr, 0, st));
+    std::vector<double> sums(nterm);
+    CK(hipMemcpyAsync(sums.data(), mem + o_sums, sizeof(double) * nterm, hipMemcpyDeviceToHost, st));
+    CK(hipStreamSynchronize(st));
+    return counts_from_sums(p, sums, ntri, (double)p.npix, tri_cnt, quad_cnt);
 }
 
 // FP64 count fields I_b and their product sums, evaluated on the device.
@@ -557,44 +691,46 @@ bispec_status compute_counts(bispec_plan_s &p, std::vector<int> &cand_tri, std::
     std::vector<double> sums(nterm);
     CK(hipMemcpyAsync(sums.data(), mem + o_sums, sizeof(double) * nterm, hipMemcpyDeviceToHost, st));
     CK(hipStreamSynchronize(st));
-
-    auto to_count = [&](double s, double *out) -> bool {
-        const double c = s / (double)vol;
-        const double r = std::nearbyint(c);
-        *out = r;
-        return std::fabs(c - r) <= 0.01;
-    };
-    tri_cnt.assign(ntri, 0.0);
-    for (int t = 0; t < ntri; ++t)
-        if (!to_count(sums[t], &tri_cnt[t])) return BISPEC_E_NUMERIC;
-    for (int b = 0; b < nb; ++b) {
-        double m;
-        if (!to_count(sums[ntri + b], &m) || m != (double)p.modes[b]) return BISPEC_E_NUMERIC;
-    }
-    // p = 4 counts grow like M^3 and outrun what an FP64 sum resolves to one
-    // unit once N_pix N_q passes ~2^53 ulp-scale: they are rounded to the
-    // nearest integer and checked to a relative 1e-9.
-    quad_cnt.assign(nq, 0.0);
-    for (int q = 0; q < nq; ++q) {
-        const double c = sums[ntri + nb + q] / (double)vol;
-        quad_cnt[q] = std::nearbyint(c);
-        if (std::fabs(c - quad_cnt[q]) > std::max(0.01, 1e-9 * std::fabs(c))) return BISPEC_E_NUMERIC;
-    }
-    return BISPEC_OK;
+    return counts_from_sums(p, sums, ntri, (double)vol, tri_cnt, quad_cnt);
 }
 
 bispec_status plan_impl(const bispec_plan_desc *d, bispec_plan_t *out) {
     if (!d || !out) return BISPEC_E_INVALID;
-    if (!is_pow2_in_range(d->n_side)) return BISPEC_E_UNSUPPORTED_N;
+    // grid: N_z = n_side, N_y and N_x default to it; a cubic power of two in
+    // [8, 512] takes the pruned path, any other grid the mixed-radix one
+    const int nz = d->n_side, ny = d->n_y > 0 ? d->n_y : d->n_side, nx = d->n_x > 0 ? d->n_x : d->n_side;
+    if (d->n_y < 0 || d->n_x < 0) return BISPEC_E_INVALID;
+    const bool general = !(nz == ny && ny == nx && is_pow2_in_range(nz));
+    GenGrid gg{};
+    if (general) {
+        const int sides[3] = {nz, ny, nx};
+        int off = 0;
+        for (int a = 0; a < 3; ++a) {
+            if (sides[a] < 2 || sides[a] > 1024 || !gen_factor(sides[a], gg.ax[a])) return BISPEC_E_UNSUPPORTED_N;
+            gg.ax[a].tw_off = off;
+            off += sides[a];
+        }
+        const long long P = std::lcm(std::lcm((long long)nz, (long long)ny), (long long)nx);
+        gg.nz = nz;
+        gg.ny = ny;
+        gg.nx = nx;
+        gg.sz = P / nz;
+        gg.sy = P / ny;
+        gg.sx = P / nx;
+        gg.npix = (long long)nz * ny * nx;
+        if (d->n_bins > 63) return BISPEC_E_INVALID;
+    }
     if (d->n_bins < 1 || d->n_bins > 64 || !d->k_lo || !d->k_hi) return BISPEC_E_INVALID;
     if (d->precision < BISPEC_FP32 || d->precision > BISPEC_FP32_VALU) return BISPEC_E_INVALID;
     if (d->max_batch < 1) return BISPEC_E_INVALID;
     if (d->n_tri < 0 || (d->n_tri > 0 && !d->tri)) return BISPEC_E_INVALID;
     if (d->n_quad < 0 || (d->n_quad > 0 && !d->quad)) return BISPEC_E_INVALID;
     const int n = d->n_side, nb = d->n_bins;
+    // edges in units of the x-axis fundamental; k below the Nyquist wave
+    // number pi / cell keeps every component below N_i / 2
     for (int b = 0; b < nb; ++b) {
         const double lo = d->k_lo[b], hi = d->k_hi[b];
-        if (!std::isfinite(lo) || !std::isfinite(hi) || lo < 0.0 || lo >= hi || hi > 0.5 * n)
+        if (!std::isfinite(lo) || !std::isfinite(hi) || lo < 0.0 || lo >= hi || hi > 0.5 * nx)
             return BISPEC_E_BIN_RANGE;
     }
     for (int t = 0; t < 3 * d->n_tri; ++t)
@@ -606,7 +742,11 @@ bispec_status plan_impl(const bispec_plan_desc *d, bispec_plan_t *out) {
     bispec_plan_s *p = new bispec_plan_s();
     p->uid = next_uid++;
     p->n = n;
-    p->box_len = d->box_len > 0 ? d->box_len : (double)n;
+    p->general = general;
+    p->gg = gg;
+    p->npix = (int64_t)nz * ny * nx;
+    p->fstride = (p->npix + 127) / 128 * 128;
+    p->box_len = d->box_len > 0 ? d->box_len : (double)nx;
     p->nb = nb;
     p->lo.assign(d->k_lo, d->k_lo + nb);
     p->hi.assign(d->k_hi, d->k_hi + nb);
@@ -614,8 +754,17 @@ bispec_status plan_impl(const bispec_plan_desc *d, bispec_plan_t *out) {
     p->max_batch = d->max_batch;
     p->stream = (hipStream_t)d->stream;
     for (int b = 0; b < nb; ++b) {
-        p->ilo2.push_back(std::max(1, ceil_int(p->lo[b] * p->lo[b])));
-        p->ihi2.push_back(ceil_int(p->hi[b] * p->hi[b]));
+        if (general) {
+            // q = sum (s_i m_i)^2 against (lo s_x)^2 and (hi s_x)^2, formed as (lo lo)(s_x s_x)
+            const double sx2 = (double)(gg.sx * gg.sx);
+            p->qlo.push_back(std::max(1LL, (long long)std::ceil((p->lo[b] * p->lo[b]) * sx2)));
+            p->qhi.push_back((long long)std::ceil((p->hi[b] * p->hi[b]) * sx2));
+            p->ilo2.push_back(0);
+            p->ihi2.push_back(0);
+        } else {
+            p->ilo2.push_back(std::max(1, ceil_int(p->lo[b] * p->lo[b])));
+            p->ihi2.push_back(ceil_int(p->hi[b] * p->hi[b]));
+        }
     }
     struct Owner {
         bispec_plan_s *p;
@@ -624,7 +773,34 @@ bispec_status plan_impl(const bispec_plan_desc *d, bispec_plan_t *out) {
     } own{p};
 
     // modes per shell
-    {
+    if (general) {
+        long long *thr = nullptr;
+        unsigned long long *cnt = nullptr;
+        hipError_t e = hipMalloc((void **)&thr, sizeof(long long) * 2 * nb);
+        if (e == hipSuccess) e = hipMalloc((void **)&cnt, sizeof(unsigned long long) * nb);
+        if (e != hipSuccess) {
+            (void)hipFree(thr);
+            (void)hipGetLastError();
+            return record(BISPEC_E_OOM, "hipMalloc of the shell tables", e);
+        }
+        std::vector<long long> th(p->qlo);
+        th.insert(th.end(), p->qhi.begin(), p->qhi.end());
+        std::vector<unsigned long long> hc(nb, 0);
+        bool ok = hipMemcpyAsync(thr, th.data(), sizeof(long long) * 2 * nb, hipMemcpyHostToDevice, p->stream) ==
+                      hipSuccess &&
+                  hipMemsetAsync(cnt, 0, sizeof(unsigned long long) * nb, p->stream) == hipSuccess &&
+                  gen_shell_hist(gg, nb, thr, thr + nb, cnt, p->stream) == hipSuccess &&
+                  hipMemcpyAsync(hc.data(), cnt, sizeof(unsigned long long) * nb, hipMemcpyDeviceToHost,
+                                 p->stream) == hipSuccess &&
+                  hipStreamSynchronize(p->stream) == hipSuccess;
+        (void)hipFree(thr);
+        (void)hipFree(cnt);
+        if (!ok) return record(BISPEC_E_HIP, "modes-per-shell pass", hipGetLastError());
+        for (int b = 0; b < nb; ++b) {
+            p->modes.push_back((int64_t)hc[b]);
+            if (hc[b] == 0) return BISPEC_E_EMPTY_BIN;
+        }
+    } else {
         int *thr = nullptr;
         unsigned long long *cnt = nullptr;
         hipError_t e = hipMalloc((void **)&thr, sizeof(int) * 2 * nb);
@@ -679,9 +855,10 @@ bispec_status plan_impl(const bispec_plan_desc *d, bispec_plan_t *out) {
         p->quad.assign(d->quad, d->quad + 4 * d->n_quad);
     }
 
-    build_pairs(*p);
+    if (!general) build_pairs(*p);
     std::vector<double> tri_cnt, quad_cnt;
-    bispec_status s = compute_counts(*p, cand, tri_cnt, quad_cnt);
+    bispec_status s = general ? compute_counts_general(*p, cand, tri_cnt, quad_cnt)
+                              : compute_counts(*p, cand, tri_cnt, quad_cnt);
     if (s != BISPEC_OK) return s;
     if (auto_tri) {
         for (size_t t = 0; t < tri_cnt.size(); ++t)
@@ -694,8 +871,8 @@ bispec_status plan_impl(const bispec_plan_desc *d, bispec_plan_t *out) {
         p->tri_count = tri_cnt;
     }
     p->quad_count = quad_cnt;
-    p->nblk = contract_blocks((int64_t)n * n * n);
-    {
+    p->nblk = contract_blocks(field_len(*p));
+    if (!general) {
         // Tail blocks: every block contracts at most PG_CHUNK_TILES tiles
         // (its FP32 accumulation span), and there are at least 256 blocks
         // (one per CU) when the map has that many tiles.  The tuner may take
@@ -716,12 +893,17 @@ bispec_status plan_impl(const bispec_plan_desc *d, bispec_plan_t *out) {
 bispec_status upload_tables(bispec_plan_s &p) {
     const Layout L = make_layout(p, p.max_batch);
     char *ws = (char *)p.ws;
-    std::vector<float2> tw(p.n);
-    for (int i = 0; i < p.n; ++i) {
-        const double a = 2.0 * M_PI * (double)i / (double)p.n;
-        tw[i] = float2{(float)std::cos(a), (float)-std::sin(a)};
+    std::vector<float2> tw;
+    if (p.general) {
+        tw = gen_twiddles<float2, float>(p.gg);
+    } else {
+        tw.resize(p.n);
+        for (int i = 0; i < p.n; ++i) {
+            const double a = 2.0 * M_PI * (double)i / (double)p.n;
+            tw[i] = float2{(float)std::cos(a), (float)-std::sin(a)};
+        }
     }
-    CK(hipMemcpyAsync(ws + L.tw, tw.data(), sizeof(float2) * p.n, hipMemcpyHostToDevice, p.stream));
+    CK(hipMemcpyAsync(ws + L.tw, tw.data(), sizeof(float2) * tw.size(), hipMemcpyHostToDevice, p.stream));
     CK(hipMemcpyAsync(ws + L.terms, p.terms.data(), sizeof(uchar4) * p.terms.size(), hipMemcpyHostToDevice,
                       p.stream));
     CK(hipMemcpyAsync(ws + L.scale, p.scale.data(), sizeof(double) * p.scale.size(), hipMemcpyHostToDevice,
@@ -742,9 +924,12 @@ bispec_status upload_tables(bispec_plan_s &p) {
                           hipMemcpyHostToDevice, p.stream));
         CK(hipMemcpyAsync(ws + L.pg_idx, p.pg_idx.data(), sizeof(int) * p.pg_idx.size(), hipMemcpyHostToDevice,
                           p.stream));
-        if (p.n_mtile_r > 0)
+        if (p.n_mtile_r > 0) {
             CK(hipMemcpyAsync(ws + L.pg_pairs_r, p.pg_pairs_r.data(), sizeof(uchar2) * p.pg_pairs_r.size(),
                               hipMemcpyHostToDevice, p.stream));
+            CK(hipMemcpyAsync(ws + L.refine_t, p.refine_t.data(), sizeof(int) * p.refine_t.size(),
+                              hipMemcpyHostToDevice, p.stream));
+        }
     }
     CK(hipStreamSynchronize(p.stream));
     return BISPEC_OK;
@@ -769,10 +954,29 @@ hipError_t run_inverse_zy(bispec_plan_s &p, int batch) {
                              (float2 *)(ws + L.abox), (float2 *)(ws + L.bc), p.stream);
 }
 
-// mean, forward transform, and all bin fields into `fields` ([batch][nb][N^3]).
-bispec_status run_fields(bispec_plan_s &p, const float *delta, int batch, float *fields) {
+// mean, forward transform, and all bin fields into `fields` ([batch][nb][stride];
+// on a general grid stride is the field length given, and entries from the
+// end of the grid to it are zeroed when pad is set).
+bispec_status run_fields(bispec_plan_s &p, const float *delta, int batch, float *fields, int64_t stride,
+                         bool pad) {
     const Layout L = make_layout(p, p.max_batch);
     char *ws = (char *)p.ws;
+    if (p.general) {
+        const float2 *tw = (const float2 *)(ws + L.tw);
+        double *mean = (double *)(ws + L.mean);
+        float2 *spec = (float2 *)(ws + L.spec);
+        stamp(p, 0);
+        CK(gen_mean(delta, p.gg, batch, (double *)(ws + L.mean_partial), kMeanParts, mean, p.stream));
+        CK(gen_forward(delta, mean, p.gg, batch, tw, spec, p.stream));
+        stamp(p, 1);
+        for (int b = 0; b < p.nb; b += 2)
+            CK(gen_inverse_pair(spec, (float2 *)(ws + L.abox), p.gg, gen_pair(p, b), batch, tw,
+                                fields + (int64_t)b * stride, b + 1 < p.nb ? fields + (int64_t)(b + 1) * stride : nullptr,
+                                (int64_t)p.nb * stride, p.stream));
+        if (pad) CK(gen_zero_pads_f32(fields, p.npix, stride, batch * p.nb, p.stream));
+        stamp(p, 2);
+        return BISPEC_OK;
+    }
     const int n = p.n;
     const int64_t vol = (int64_t)n * n * n;
     const float2 *tw = (const float2 *)(ws + L.tw);
@@ -831,7 +1035,7 @@ bispec_status valu_terms(bispec_plan_s &p, const float *fields, int first, int l
                          double *T) {
     const Layout L = make_layout(p, p.max_batch);
     char *ws = (char *)p.ws;
-    const int64_t vol = (int64_t)p.n * p.n * p.n;
+    const int64_t vol = field_len(p);
     const int nterm = last - first;
     if (nterm <= 0) return BISPEC_OK;
     double *partial = (double *)(ws + L.partial);
@@ -854,7 +1058,8 @@ bispec_status run_estimate_body(bispec_plan_s &p, const float *delta, int batch,
     if ((!mfma || (T && !p.quads_collapsed) || (B && p.n_mtile_r > 0)) && !p.ws_fields) return BISPEC_E_NO_WORKSPACE;
     if (!mfma) {
         float *fields = (float *)(ws + L.fields);
-        bispec_status s = run_fields(p, delta, batch, fields);
+        const int64_t fl = field_len(p);
+        bispec_status s = run_fields(p, delta, batch, fields, fl, true);
         if (s != BISPEC_OK) return s;
         // 33..64 bins in split mode: the triplets on MFMA over the fields in
         // HBM; then P and collapsed quads from the product-Gram of the
@@ -866,13 +1071,13 @@ bispec_status run_estimate_body(bispec_plan_s &p, const float *delta, int batch,
         double *dense = (double *)(ws + L.pg_dense);
         if (wide && B && ntri > 0) {
             const int64_t n_dense = (int64_t)p.n_mtile * 2048;
-            CK(launch_pgram_fields(fields, n, p.nb, batch, (const uchar2 *)(ws + L.pg_pairs), p.n_mtile,
+            CK(launch_pgram_fields(fields, fl, p.nb, batch, (const uchar2 *)(ws + L.pg_pairs), p.n_mtile,
                                    p.nblk_wide, pg, p.stream, false));
             CK(launch_reduce_dense(pg, p.nblk_wide, n_dense, batch, dense, (double *)(ws + L.pg_tmp), p.stream));
             if (p.n_mtile_r > 0) {
                 // ill-conditioned triplets: FP64 product-Gram rows of their own
                 double *pr = (double *)(ws + L.pg_partial_r);
-                CK(launch_pgram_fields_f64(fields, n, p.nb, batch, (const uchar2 *)(ws + L.pg_pairs_r), p.n_mtile_r,
+                CK(launch_pgram_fields_f64(fields, fl, p.nb, batch, (const uchar2 *)(ws + L.pg_pairs_r), p.n_mtile_r,
                                            p.nblk_r, pr, p.stream));
                 CK(launch_reduce_dense(pr, p.nblk_r, (int64_t)refine_dense_doubles(p), batch,
                                        (double *)(ws + L.pg_dense_r), (double *)(ws + L.pg_tmp_r), p.stream));
@@ -885,7 +1090,7 @@ bispec_status run_estimate_body(bispec_plan_s &p, const float *delta, int batch,
         if (wide && p.nb < 64 && (first < last || (T && p.quads_collapsed))) {
             const int64_t n_dense = (int64_t)p.pg_sq_tiles * 2048;
             const int sets = p.nblk_wide * pgram_fields_kparts(p.pg_sq_tiles, true);
-            CK(launch_pgram_fields(fields, n, p.nb, batch, nullptr, p.pg_sq_tiles, p.nblk_wide, pg, p.stream, true));
+            CK(launch_pgram_fields(fields, fl, p.nb, batch, nullptr, p.pg_sq_tiles, p.nblk_wide, pg, p.stream, true));
             CK(launch_reduce_dense(pg, sets, n_dense, batch, dense, (double *)(ws + L.pg_tmp), p.stream));
             if (first < last) {
                 s = finalize_range(p, true, dense, 1, n_dense, first, last, batch, P, B, T);
@@ -896,12 +1101,27 @@ bispec_status run_estimate_body(bispec_plan_s &p, const float *delta, int batch,
             if (!T) return BISPEC_OK;
             return valu_terms(p, fields, t_first, t_last, batch, P, B, T);
         }
-        if (!T) return valu_terms(p, fields, first, last, batch, P, B, T);
-        if (first == last) return valu_terms(p, fields, t_first, t_last, batch, P, B, T);
-        if (last == t_first) return valu_terms(p, fields, first, t_last, batch, P, B, T);
-        s = valu_terms(p, fields, first, last, batch, P, B, T);
+        if (!T) s = valu_terms(p, fields, first, last, batch, P, B, T);
+        else if (first == last) s = valu_terms(p, fields, t_first, t_last, batch, P, B, T);
+        else if (last == t_first) s = valu_terms(p, fields, first, t_last, batch, P, B, T);
+        else {
+            s = valu_terms(p, fields, first, last, batch, P, B, T);
+            if (s == BISPEC_OK) s = valu_terms(p, fields, t_first, t_last, batch, P, B, T);
+        }
         if (s != BISPEC_OK) return s;
-        return valu_terms(p, fields, t_first, t_last, batch, P, B, T);
+        // ill-conditioned triplets of the vector-ALU route (FP32 mode): the
+        // FP64 refinement rows, written over the vector-ALU values
+        if (B && first == 0 && ntri > 0 && p.n_mtile_r > 0 && p.precision != BISPEC_FP32_VALU) {
+            double *pr = (double *)(ws + L.pg_partial_r);
+            CK(launch_pgram_fields_f64(fields, fl, p.nb, batch, (const uchar2 *)(ws + L.pg_pairs_r), p.n_mtile_r,
+                                       p.nblk_r, pr, p.stream));
+            CK(launch_reduce_dense(pr, p.nblk_r, (int64_t)refine_dense_doubles(p), batch,
+                                   (double *)(ws + L.pg_dense_r), (double *)(ws + L.pg_tmp_r), p.stream));
+            CK(launch_scatter_alt((const double *)(ws + L.pg_dense_r), (int64_t)refine_dense_doubles(p),
+                                  (const int *)(ws + L.pg_idx), (const double *)(ws + L.scale),
+                                  (const int *)(ws + L.refine_t), (int)p.refine_t.size(), batch, B, ntri, p.stream));
+        }
+        return BISPEC_OK;
     }
     // FFT-domain part, then the fused last pass + product-Gram
     const float2 *tw = (const float2 *)(ws + L.tw);
@@ -935,8 +1155,8 @@ bispec_status run_estimate_body(bispec_plan_s &p, const float *delta, int batch,
             float *fields = (float *)(ws + L.fields);
             CK(launch_inverse_x_pairs((const float2 *)(ws + L.bc), n, batch, tw, (const PairDev *)(ws + L.pd),
                                       (int)p.pairs.size(), p.nb, fields, p.stream));
-            CK(launch_pgram_fields_f64(fields, n, p.nb, batch, (const uchar2 *)(ws + L.pg_pairs_r), p.n_mtile_r,
-                                       p.nblk_r, (double *)(ws + L.pg_partial_r), p.stream));
+            CK(launch_pgram_fields_f64(fields, (int64_t)n * n * n, p.nb, batch, (const uchar2 *)(ws + L.pg_pairs_r),
+                                       p.n_mtile_r, p.nblk_r, (double *)(ws + L.pg_partial_r), p.stream));
         }
         stamp(p, 3);
         CK(launch_reduce_dense(pg, p.nblk_pg, n_dense, batch, dense, (double *)(ws + L.pg_tmp), p.stream));
@@ -1059,7 +1279,8 @@ bispec_status bispec_bin_fields(bispec_plan_t plan, const float *delta, int32_t 
     if (s != BISPEC_OK) return s;
     if (!fields) return BISPEC_E_INVALID;
     try {
-        bispec_status st = run_fields(*plan, delta, batch, fields);
+        const int64_t len = plan->general ? plan->npix : (int64_t)plan->n * plan->n * plan->n;
+        bispec_status st = run_fields(*plan, delta, batch, fields, len, false);
         stamp_rest(*plan, 3);
         return st;
     } catch (...) {
@@ -1251,7 +1472,7 @@ bispec_status bispec_set_tuning(bispec_plan_t plan, int32_t nblk, int32_t shape)
 
 bispec_status bispec_plan_condition(bispec_plan_t plan, double *kappa_out) {
     if (!plan || !kappa_out) return BISPEC_E_INVALID;
-    const double npix = (double)plan->n * plan->n * plan->n;
+    const double npix = (double)plan->npix;
     const int nt = (int)plan->tri.size() / 3;
     for (int t = 0; t < nt; ++t) {
         const double m = (double)plan->modes[plan->tri[3 * t]] * (double)plan->modes[plan->tri[3 * t + 1]] *
@@ -1337,6 +1558,7 @@ bispec_status trispec_connected_estimate(bispec_plan_t plan, const float *delta,
     bispec_status s = check_call(plan, delta, batch);
     if (s != BISPEC_OK) return s;
     bispec_plan_s &p = *plan;
+    if (p.general) return BISPEC_E_UNSUPPORTED_N;   // the spectral moments run on the half spectrum of a cube
     const int nq = (int)p.quad.size() / 4, ntri = (int)p.tri.size() / 3;
     for (int q = 0; q < nq; ++q) {
         int a[4] = {p.quad[4 * q], p.quad[4 * q + 1], p.quad[4 * q + 2], p.quad[4 * q + 3]};

@@ -80,7 +80,8 @@ int tail_shape(int n, int n_mtile, bool want_t, int shape);
 // each block writes one partial set of n_mtile + want_t tiles).
 int tail_ksplit(int n, int n_mtile, bool want_t, int shape);
 // Product-Gram over bin fields in HBM (33..64 bins, split-BF16; mfma.hip):
-// fields [batch][nb][N^3] FP32; pairs [n_mtile*32] row factors (field rows
+// fields [batch][nb][npix] FP32 (npix: the field stride, a multiple of 128;
+// entries beyond the grid are zero); pairs [n_mtile*32] row factors (field rows
 // 0..63, PGF_ROW_ZERO = zeros); partial [batch][nblk][n_mtile][32][64] FP64,
 // column z < nb the field F_z, the rest zero.  nblk blocks per map, each
 // contracting pgram_fields_chunk(n, nblk) <= PGF_MAX_CHUNK points (else
@@ -90,9 +91,9 @@ int tail_ksplit(int n, int n_mtile, bool want_t, int shape);
 // each its own partial set: partial [batch][nblk * kparts][n_mtile][32][64].
 constexpr int PGF_ROW_ZERO = 64;
 constexpr int64_t PGF_MAX_CHUNK = 32768;
-int64_t pgram_fields_chunk(int n, int nblk);
+int64_t pgram_fields_chunk(int64_t npix, int nblk);
 int pgram_fields_kparts(int n_mtile, bool squares);
-hipError_t launch_pgram_fields(const float *fields, int n, int nb, int batch, const uchar2 *pairs, int n_mtile,
+hipError_t launch_pgram_fields(const float *fields, int64_t npix, int nb, int batch, const uchar2 *pairs, int n_mtile,
                                int nblk, double *partial, hipStream_t st, bool squares);
 // dense[map][e] = sum over the nblk partial sets; tmp holds
 // PG_REDUCE_SEGS * n_dense * batch doubles of segment sums (or null: one pass).
@@ -105,12 +106,16 @@ constexpr int PG_IDX_ALT = 1 << 30;
 hipError_t launch_finalize_gather(const double *partial, int nblk, int64_t blk_stride, const double *alt,
                                   int64_t alt_stride, const int *idx, int nterm, int batch, const double *scale,
                                   double *o0, int n0, double *o1, int n1, double *o2, int n2, hipStream_t st);
+// out[map][list[i]] = scale[t] * alt[map][idx[t] & ~PG_IDX_ALT], t = list[i]
+// (the refined triplets of the vector-ALU route, written over its values).
+hipError_t launch_scatter_alt(const double *alt, int64_t alt_stride, const int *idx, const double *scale,
+                              const int *list, int nlist, int batch, double *out, int nout, hipStream_t st);
 // FP64 product-Gram over bin fields in HBM (the refinement rows of
 // ill-conditioned triplets, any plan of up to 64 bins): same tables and
 // partial layout as launch_pgram_fields, one pair tile per wave, nblk blocks
 // of pgram_fields_chunk(n, nblk) points.
-hipError_t launch_pgram_fields_f64(const float *fields, int n, int nb, int batch, const uchar2 *pairs, int n_mtile,
-                                   int nblk, double *partial, hipStream_t st);
+hipError_t launch_pgram_fields_f64(const float *fields, int64_t npix, int nb, int batch, const uchar2 *pairs,
+                                   int n_mtile, int nblk, double *partial, hipStream_t st);
 
 // out[map][g] = sum_{group[t] = g} count[t] B[map][t] / sum count[t] (NaN if empty).
 hipError_t launch_rebin(const double *B, int n_tri, const double *count, const int *group, int n_group, int batch,

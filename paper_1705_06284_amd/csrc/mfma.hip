@@ -849,19 +849,17 @@ hipError_t launch_tail(int mode, bool want_t, const float2 *bc, const TailPairs 
 
 int pgram_fields_kparts(int n_mtile, bool squares) { return squares ? PGF_NT / 64 / n_mtile : 1; }
 
-int64_t pgram_fields_chunk(int n, int nblk) {
-    const int64_t npix = (int64_t)n * n * n;
+int64_t pgram_fields_chunk(int64_t npix, int nblk) {
     const int64_t c = (npix + nblk - 1) / nblk;
     return (c + PGF_TK - 1) / PGF_TK * PGF_TK;
 }
 
-hipError_t launch_pgram_fields(const float *fields, int n, int nb, int batch, const uchar2 *pairs, int n_mtile,
+hipError_t launch_pgram_fields(const float *fields, int64_t npix, int nb, int batch, const uchar2 *pairs, int n_mtile,
                                int nblk, double *partial, hipStream_t st, bool squares) {
     if (nb < 1 || nb > 64 || n_mtile < 1 || nblk < 1 || batch < 1) return hipErrorInvalidValue;
     if (squares ? (nb > 63 || n_mtile != (nb + 31) / 32 || (PGF_NT / 64) % n_mtile != 0) : !pairs)
         return hipErrorInvalidValue;
-    const int64_t npix = (int64_t)n * n * n;
-    const int64_t chunk = pgram_fields_chunk(n, nblk);
+    const int64_t chunk = pgram_fields_chunk(npix, nblk);
     if (npix % PGF_TK != 0 || chunk > PGF_MAX_CHUNK) return hipErrorInvalidValue;
     const unsigned groups = squares ? 1u : (unsigned)((n_mtile + PGF_TILES - 1) / PGF_TILES);
     if (squares)
@@ -897,11 +895,29 @@ hipError_t launch_finalize_gather(const double *partial, int nblk, int64_t blk_s
     return hipGetLastError();
 }
 
-hipError_t launch_pgram_fields_f64(const float *fields, int n, int nb, int batch, const uchar2 *pairs, int n_mtile,
-                                   int nblk, double *partial, hipStream_t st) {
+// out[map][t] = scale[t] * alt[map][idx[t] & ~PG_IDX_ALT] for the listed t.
+__global__ __launch_bounds__(256) void k_scatter_alt(const double *__restrict__ alt, int64_t alt_stride,
+                                                     const int *__restrict__ idx, const double *__restrict__ scale,
+                                                     const int *__restrict__ list, int nlist,
+                                                     double *__restrict__ out, int nout) {
+    const int i = blockIdx.x * 256 + threadIdx.x, map = blockIdx.y;
+    if (i >= nlist) return;
+    const int t = list[i];
+    out[(int64_t)map * nout + t] = scale[t] * alt[(int64_t)map * alt_stride + (idx[t] & ~PG_IDX_ALT)];
+}
+
+hipError_t launch_scatter_alt(const double *alt, int64_t alt_stride, const int *idx, const double *scale,
+                              const int *list, int nlist, int batch, double *out, int nout, hipStream_t st) {
+    if (nlist < 1) return hipSuccess;
+    hipLaunchKernelGGL(k_scatter_alt, dim3((nlist + 255) / 256, batch), dim3(256), 0, st, alt, alt_stride, idx, scale,
+                       list, nlist, out, nout);
+    return hipGetLastError();
+}
+
+hipError_t launch_pgram_fields_f64(const float *fields, int64_t npix, int nb, int batch, const uchar2 *pairs,
+                                   int n_mtile, int nblk, double *partial, hipStream_t st) {
     if (nb < 1 || nb > 64 || n_mtile < 1 || nblk < 1 || batch < 1 || !pairs) return hipErrorInvalidValue;
-    const int64_t npix = (int64_t)n * n * n;
-    const int64_t chunk = pgram_fields_chunk(n, nblk);
+    const int64_t chunk = pgram_fields_chunk(npix, nblk);
     if (npix % PGF64_TK != 0 || chunk % PGF64_TK != 0) return hipErrorInvalidValue;
     const unsigned groups = (unsigned)((n_mtile + PGF64_NT / 64 - 1) / (PGF64_NT / 64));
     hipLaunchKernelGGL(k_pgram_fields_f64, dim3(nblk, batch, groups), dim3(PGF64_NT), 0, st, fields, npix, nb,

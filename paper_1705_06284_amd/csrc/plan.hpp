@@ -7,11 +7,19 @@
 #include <vector>
 
 #include "fft_core.hpp"
+#include "general.hpp"
 
 struct bispec_plan_s {
     unsigned long long uid = 0;  // unique per plan in the process (never reused)
-    int n = 0;                 // grid side N
-    double box_len = 0;        // L (V = L^3)
+    int n = 0;                 // grid side N (cubic grids; N_z otherwise)
+    double box_len = 0;        // L (V = L^3); L_x on a non-cubic grid
+    // grids that are not cubic powers of two: sides N_z x N_y x N_x of cubic
+    // cells, mixed-radix transforms (general.hip), bin fields in HBM
+    bool general = false;
+    bispec::GenGrid gg{};
+    std::vector<long long> qlo, qhi;     // member iff qlo <= q < qhi (general grids)
+    int64_t npix = 0;                    // N_z N_y N_x
+    int64_t fstride = 0;                 // stride of one bin field in HBM (padded to 128)
     int nb = 0;                // bins
     std::vector<double> lo, hi;          // edges in k_f units
     std::vector<int> ilo2, ihi2;         // member iff ilo2 <= |m|^2 < ihi2 (integers)
@@ -56,6 +64,7 @@ struct bispec_plan_s {
     // refinement rows: triplets whose condition number exceeds kRefineKappa
     // run on FP32-mode product-Gram rows of their own in every precision
     std::vector<unsigned char> refine;   // per triplet: 1 = read from the refinement tiles
+    std::vector<int> refine_t;           // the indices of those triplets
     std::vector<uchar2> pg_pairs_r;      // [n_mtile_r*32] row factors of those rows
     int n_mtile_r = 0;                   // 32-row tiles of refinement rows (0: none)
     int nblk_r = 1;                      // blocks per map of the refinement pass
@@ -87,7 +96,7 @@ constexpr int kMomBlocks = 2048;
 struct Layout {
     size_t tw, terms, scale, tcount, thr, mom_partial, mom_tmp, mom, pg_pairs, pg_idx, pg_pairs_r, cols, pd, ztab,
         ytab, mean_partial, mean, spec, abox, bc, fields, partial, pg_partial, pg_dense, pg_tmp, pg_partial_r,
-        pg_dense_r, pg_tmp_r, total;
+        pg_dense_r, pg_tmp_r, refine_t, total;
 };
 
 // Triplets with a condition number sqrt(M_i M_j M_k / (N_pix N_t)) above

@@ -62,7 +62,7 @@ def _desc(b, n=32, lo=(1.0,), hi=(4.0,), prec=0, batch=1, tri=None):
 
 
 @pytest.mark.parametrize("kw,code", [
-    (dict(n=48), -2), (dict(n=4), -2), (dict(n=1024), -2),
+    (dict(n=1), -2), (dict(n=2048), -2), (dict(n=49), -2), (dict(n=131), -2), (dict(n=143), -2),
     (dict(lo=(1.0,), hi=(17.0,)), -3), (dict(lo=(5.0,), hi=(5.0,)), -3), (dict(lo=(-1.0,), hi=(2.0,)), -3),
     (dict(lo=(float("nan"),), hi=(2.0,)), -3),
     (dict(prec=7), -1), (dict(batch=0), -1), (dict(tri=[(0, 0, 3)]), -1),
