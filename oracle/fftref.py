@@ -70,7 +70,8 @@ class FFTSpectrum:
     """Estimates of one configuration list from the FFT form."""
     value: np.ndarray        # B, T or P in the paper's normalisation
     s: np.ndarray            # closed-tuple sum of prod Delta: sum_n prod F / N_pix
-    count: np.ndarray        # closed tuples (ordered, closure modulo N), rounded
+    count: np.ndarray        # closed tuples (ordered, closure modulo N), rounded, FP64
+                             # (p = 4 counts pass 2^63 on large grids)
     count_frac: np.ndarray   # |sum_n prod I / N_pix - count|: distance to an integer
     noise: np.ndarray        # norm * sqrt(sum_closed prod |Delta|^2) / count
 
@@ -84,13 +85,24 @@ class FFTReference:
 
     def __init__(self, delta, k_lo, k_hi, box_len=None, cache_bytes=16 << 30):
         d = polyspec.prepare(delta)
-        shape = d.shape
+        self._setup(d.shape, k_lo, k_hi, box_len, cache_bytes, _fftn(d))     # step 1
+
+    @classmethod
+    def from_spectrum(cls, delta_k, k_lo, k_hi, box_len=None, cache_bytes=16 << 30):
+        """The same sums for a given full complex spectrum on the grid
+        (Hermitian: real fields), e.g. a model spectrum whose averages over
+        the closed tuples of each configuration are wanted."""
+        self = cls.__new__(cls)
+        self._setup(delta_k.shape, k_lo, k_hi, box_len, cache_bytes, np.asarray(delta_k, np.complex128))
+        return self
+
+    def _setup(self, shape, k_lo, k_hi, box_len, cache_bytes, delta_k):
         self.shape = shape
         self.npix = float(np.prod(shape))
         self.volume = polyspec._volume(shape, box_len)
         self.lo2, self.hi2 = polyspec.squared_edges(k_lo, k_hi, shape)
         self.n_bins = len(self.lo2)
-        self.delta_k = _fftn(d)                              # step 1
+        self.delta_k = delta_k
         sc = polyspec.q_scales(shape)
         fz, fy, fx = (sc[a] * polyspec.freq(shape[a]).astype(np.int64) for a in range(3))
         self.r2 = fz[:, None, None] ** 2 + fy[None, :, None] ** 2 + fx[None, None, :] ** 2
@@ -154,8 +166,7 @@ class FFTReference:
         with np.errstate(invalid="ignore", divide="ignore"):
             val = norm * out["S"] / cnt
             noise = norm * np.sqrt(np.maximum(out["Q"], 0.0)) / cnt
-        return FFTSpectrum(value=val, s=out["S"], count=cnt.astype(np.int64),
-                           count_frac=np.abs(out["C"] - cnt), noise=noise)
+        return FFTSpectrum(value=val, s=out["S"], count=cnt, count_frac=np.abs(out["C"] - cnt), noise=noise)
 
     def bispectrum(self, triplets):
         """Eq. (Jeong_BI): B = V^2 / N_pix^3 sum F F F / sum I I I."""

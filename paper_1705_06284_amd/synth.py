@@ -92,7 +92,8 @@ def toy_bubbles(n: int, radius: float, ionized_target: float, seed: int,
 
     Each sphere first tries up to ``max_tries`` uniform lattice centres for a
     spot whose periodic distance to every earlier centre is >= 2 R (no
-    overlap); if none is free it takes an overlapping one.  Spheres are the
+    overlap); if none is free it takes an overlapping one (``max_tries = 0``:
+    every centre uniform, overlap allowed).  Spheres are the
     lattice cells within periodic distance R of the centre.  Placement stops
     once the ionised cell fraction reaches ``ionized_target``.  Returns the
     mean-subtracted FP32 x_HI field (and placement statistics on request).
@@ -166,6 +167,13 @@ WORKLOADS = {
     # one-pixel shells up to the 64-bin plan limit, for configuration binning
     "onepix_128_lognormal": dict(n=128, kind="lognormal", spectral_index=1.5, sigma=1.0,
                                  seed=2, bins=("unit", 1, 63)),
+    # the toy reionisation boxes of Section 3.3: 600^3 cells of 1 Mpc, spheres
+    # of radius 10 Mpc at uniform random centres (overlap allowed, as in the
+    # paper's boxes), neutral fractions 0.99 and 0.88; 61 shells of 2 k_f
+    "toy600_xhi099": dict(n=600, kind="bubbles", radius=10.0, target=0.01, seed=6, bins=("width", 1.0, 2.0, 61),
+                          box_len=600.0, max_tries=0),
+    "toy600_xhi088": dict(n=600, kind="bubbles", radius=10.0, target=0.12, seed=7, bins=("width", 1.0, 2.0, 61),
+                          box_len=600.0, max_tries=0),
 }
 
 
@@ -174,6 +182,9 @@ def workload_bins(name: str):
     b = w["bins"]
     if b[0] == "unit":
         return unit_bins(b[1], b[2])
+    if b[0] == "width":               # nb bins of width w from lo: [lo + i w, lo + (i + 1) w)
+        e = b[1] + b[2] * np.arange(b[3] + 1, dtype=np.float64)
+        return e[:-1].copy(), e[1:].copy()
     return linear_bins(w["n"], b[1])
 
 
@@ -185,5 +196,5 @@ def workload_field(name: str, seed=None) -> np.ndarray:
     if w["kind"] == "lognormal":
         return lognormal_field(w["n"], w["spectral_index"], w["sigma"], s)
     if w["kind"] == "bubbles":
-        return toy_bubbles(w["n"], w["radius"], w["target"], s)
+        return toy_bubbles(w["n"], w["radius"], w["target"], s, max_tries=w.get("max_tries", 1000))
     raise KeyError(name)
