@@ -70,12 +70,13 @@ typedef enum {
  * and for pair rows (x,y) that cover the requested triplets (each triplet is
  * read from one of its three pairs).  With n_bins <= 32 the product-Gram is
  * fused with the last inverse pass and also yields P and the collapsed T.
- * With 33..64 bins (narrow shells; Section 3.2 and the Conclusion advise
- * shells one k_f wide) mode 1 keeps the bin fields in HBM and runs the
- * triplets on a 64-column product-Gram over them, and P and the collapsed
- * quads on a second pass over the squared fields (rows F_a^2, columns F_b^2
- * and ones; up to 63 bins); general quads, and P at 64 bins, run on the
- * vector ALUs.  Mode 0 runs as mode 2 there.
+ * With 33..128 bins (narrow shells; Section 3.2 and the Conclusion advise
+ * shells one k_f wide, e.g. 127 one-pixel shells at 256^3) mode 1 keeps the
+ * bin fields in HBM and runs the triplets on a product-Gram over them, one
+ * pass per group of 64 columns with pair rows chosen per group, and P and the
+ * collapsed quads on a pass over the squared fields (rows F_a^2, columns
+ * F_b^2 and ones); general quads, and P and T when n_bins is 64 or 128, run
+ * on the vector ALUs.  Mode 0 runs as mode 2 there.
  * In modes 0 and 1, triplets whose condition number
  * kappa_t = sqrt(M_i M_j M_k / (N_pix N_t)) exceeds 4 (shells narrower than
  * k_f near the edge of the triangle inequality; bispec_plan_condition) are
@@ -96,7 +97,7 @@ enum {
  * and a product of 2, 3, 5 and at most one other prime <= 127 (the paper's
  * 600^3 toy boxes, Section 3.3; its 536^3 = 8 x 67 N-body grid, Section 3.2),
  * runs mixed-radix Stockham transforms, keeps the bin fields in HBM and
- * contracts them on the fields product-Gram (up to 63 bins).  Non-cubic grids
+ * contracts them on the fields product-Gram.  Non-cubic grids
  * have cubic cells (the footnote on pixel coordinates, Section 2: one
  * fundamental 2 pi / L_i per axis): box_len is L_x, L_i = L_x N_i / N_x,
  * V = L_x L_y L_z, and shell edges are in units of the x-axis fundamental
@@ -106,7 +107,7 @@ enum {
 typedef struct {
     int32_t n_side;        /* N (cubic) or N_z                                        */
     double box_len;        /* L (L_x); <= 0 means L_x = N_x (grid units, H = 1)       */
-    int32_t n_bins;        /* 1..64                                                   */
+    int32_t n_bins;        /* 1..128                                                  */
     const double *k_lo;    /* [n_bins] lower shell edges in k_f units (inclusive)     */
     const double *k_hi;    /* [n_bins] upper shell edges in k_f units (exclusive)     */
     int32_t n_tri;         /* number of triplets; 0 = every closed triplet i<=j<=k    */

@@ -96,7 +96,7 @@ def theta_direct(delta, k_lo, k_hi, b1, b2, n_cos, box_len=None):
     d = _ps.prepare(delta)
     n = d.shape[0]
     dk = _ps.dft3(d)
-    mask = _ps.bin_mask_table(n, k_lo, k_hi)
+    lo2, hi2 = _ps.squared_edges(k_lo, k_hi, n)
     nb = len(k_lo)
     c1, c2 = _centre(k_lo, k_hi, b1), _centre(k_lo, k_hi, b2)
     grp = [cos_group(c1, c2, _centre(k_lo, k_hi, b3), n_cos)[1] for b3 in range(nb)]
@@ -107,8 +107,7 @@ def theta_direct(delta, k_lo, k_hi, b1, b2, n_cos, box_len=None):
     C = np.zeros(n_cos, dtype=np.int64)
     for m1 in s1:
         m3 = (-(m1[None, :] + s2) + h) % n - h                # wrapped closing modes
-        r2 = (m3 * m3).sum(axis=1)
-        bits = mask[r2]
+        r2 = (m3 * m3).sum(axis=1).astype(np.float64)
         idx = m3 % n
         d1 = dk[m1[0] % n, m1[1] % n, m1[2] % n]
         prod = d1 * dk[s2[:, 0] % n, s2[:, 1] % n, s2[:, 2] % n] * dk[idx[:, 0], idx[:, 1], idx[:, 2]]
@@ -116,7 +115,7 @@ def theta_direct(delta, k_lo, k_hi, b1, b2, n_cos, box_len=None):
             g = grp[b3]
             if g < 0:
                 continue
-            sel = (bits >> np.uint64(b3)) & np.uint64(1) == 1
+            sel = (r2 > 0) & (r2 >= lo2[b3]) & (r2 < hi2[b3])
             if sel.any():
                 S[g] += prod[sel].sum()
                 C[g] += int(sel.sum())

@@ -35,7 +35,8 @@
  *   [0] Re S   [1] Im S   [2] count   [3] Re S_strict   [4] Im S_strict
  *   [5] strict count      [6] sum |product|^2
  * Per-thread partials are merged in thread order, so a fixed thread count
- * gives a fixed result.
+ * gives a fixed result.  Small loops run on fewer threads (one per 2^18
+ * tuples), which keeps the many short calls of narrow-shell plans cheap.
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -70,6 +71,12 @@ static inline void amp(const double *re, const double *im, int64_t g,
     else    { *ar = 1.0;   *ai = 0.0;   }
 }
 
+static int threads_for(double work) {
+    int nt = omp_get_max_threads();
+    const double want = 1.0 + work / 262144.0;
+    return want < (double)nt ? (int)want : nt;
+}
+
 static void merge(double *out, double *part, int nthreads, int nb) {
     memset(out, 0, sizeof(double) * (size_t)nb * ORC_NACC);
     for (int t = 0; t < nthreads; ++t)
@@ -99,7 +106,7 @@ int orc_pair_sums(int nz, int ny, int nx, int sz, int sy, int sx, const double *
     if (nz <= 0 || ny <= 0 || nx <= 0 || n_bins <= 0 || n_bins > 64) return -1;
     const grid_t G = {nz, ny, nx, sz, sy, sx};
     const grid_t *g = &G;
-    int nt = omp_get_max_threads();
+    int nt = threads_for((double)na * nb_modes);
     double *part = (double *)calloc((size_t)nt * n_bins * ORC_NACC, sizeof(double));
     if (!part) return -2;
 #pragma omp parallel num_threads(nt)
@@ -145,7 +152,7 @@ int orc_triple_sums(int nz, int ny, int nx, int sz, int sy, int sx, const double
     if (nz <= 0 || ny <= 0 || nx <= 0 || n_bins <= 0 || n_bins > 64) return -1;
     const grid_t G = {nz, ny, nx, sz, sy, sx};
     const grid_t *g = &G;
-    int nt = omp_get_max_threads();
+    int nt = threads_for((double)na * nb_modes * nc);
     double *part = (double *)calloc((size_t)nt * n_bins * ORC_NACC, sizeof(double));
     if (!part) return -2;
 #pragma omp parallel num_threads(nt)

@@ -124,19 +124,21 @@ def _q_of(mz, my, mx, s):
             + (s[2] * np.asarray(mx, np.int64)) ** 2)
 
 
-def bin_mask_table(n, k_lo, k_hi) -> np.ndarray:
-    """uint64 bit mask per integer q: bit b set iff the modes with that q are
-    in bin b (q = |m|^2 on a cubic grid).  q = 0 (the mean) is in no bin."""
+def bin_mask_table(n, k_lo, k_hi, bins=None) -> np.ndarray:
+    """uint64 bit mask per integer q: bit i set iff the modes with that q are
+    in bin bins[i] (q = |m|^2 on a cubic grid; bins: at most 64 bin indices,
+    default all bins).  q = 0 (the mean) is in no bin."""
     shape, s = grid_shape(n), q_scales(n)
     lo2, hi2 = squared_edges(k_lo, k_hi, n)
-    assert len(lo2) <= 64
+    bins = list(range(len(lo2))) if bins is None else list(bins)
+    assert len(bins) <= 64
     qmax = int(_q_of(shape[0] // 2, shape[1] // 2, shape[2] // 2, s))
     q = np.arange(qmax + 1, dtype=np.float64)
     mask = np.zeros(qmax + 1, dtype=np.uint64)
-    for b in range(len(lo2)):
+    for i, b in enumerate(bins):
         sel = (q >= lo2[b]) & (q < hi2[b])
         sel[0] = False
-        mask[sel] |= np.uint64(1) << np.uint64(b)
+        mask[sel] |= np.uint64(1) << np.uint64(i)
     return mask
 
 
@@ -252,7 +254,9 @@ def _tuple_sums(n, delta_k, k_lo, k_hi, tuples, order):
     """
     tuples = np.asarray(tuples, dtype=np.int64).reshape(-1, order)
     n_bins = len(k_lo)
-    mask = bin_mask_table(n, k_lo, k_hi)
+    # the bit masks hold 64 bins: beyond that, each group of tuples gets a
+    # table of its own closing bins
+    full = bin_mask_table(n, k_lo, k_hi) if n_bins <= 64 else None
     modes = {}
 
     def sh(b):
@@ -270,15 +274,23 @@ def _tuple_sums(n, delta_k, k_lo, k_hi, tuples, order):
         groups.setdefault(key, []).append((t, srt[-1]))
     acc = np.zeros((len(tuples), _NACC))
     for key, items in groups.items():
-        want = 0
-        for _, last in items:
-            want |= 1 << last
-        if order == 3:
-            out = _pair_sums(n, re, im, sh(key[0]), sh(key[1]), mask, want, n_bins)
-        else:
-            out = _triple_sums(n, re, im, sh(key[0]), sh(key[1]), sh(key[2]), mask, want, n_bins)
-        for t, last in items:
-            acc[t] = out[last]
+        lasts = sorted({last for _, last in items})
+        for c0 in range(0, len(lasts), 64):
+            part = lasts[c0:c0 + 64]
+            if full is not None:
+                mask, slot, nslot = full, {b: b for b in part}, n_bins
+            else:
+                mask, slot, nslot = bin_mask_table(n, k_lo, k_hi, part), {b: i for i, b in enumerate(part)}, len(part)
+            want = 0
+            for b in part:
+                want |= 1 << slot[b]
+            if order == 3:
+                out = _pair_sums(n, re, im, sh(key[0]), sh(key[1]), mask, want, nslot)
+            else:
+                out = _triple_sums(n, re, im, sh(key[0]), sh(key[1]), sh(key[2]), mask, want, nslot)
+            for t, last in items:
+                if last in slot:
+                    acc[t] = out[slot[last]]
     return acc
 
 

@@ -69,14 +69,19 @@ namespace bispec {
 
 int64_t field_len(const bispec_plan_s &p) { return p.general ? p.fstride : (int64_t)p.n * p.n * p.n; }
 
+double spec_scale(const bispec_plan_s &p) { return std::ldexp(1.0, -p.spec_shift); }
+
 bool needs_fields(const bispec_plan_s &p) {
     return p.general || !p.mfma_ok || !p.quads_collapsed || p.precision == BISPEC_FP32_VALU || p.n_mtile_r > 0;
 }
 
 size_t refine_dense_doubles(const bispec_plan_s &p) { return (size_t)p.n_mtile_r * 2048; }
 
-// Dense tile entries of the fields product-Gram (33..64 bins): [n_mtile][32][64].
-size_t wide_dense_doubles(const bispec_plan_s &p) { return (size_t)std::max(p.n_mtile, p.pg_sq_tiles) * 2048; }
+// Dense tile entries of the fields product-Gram (33..128 bins, general
+// grids): [n_mtile][32][64], or the squares pass's [n_cgroup*sq_tiles][32][64].
+size_t wide_dense_doubles(const bispec_plan_s &p) {
+    return (size_t)std::max(p.n_mtile, p.n_cgroup * p.pg_sq_tiles) * 2048;
+}
 
 Layout make_layout(const bispec_plan_s &p, int batch) {
     Layout L{};
@@ -116,8 +121,8 @@ Layout make_layout(const bispec_plan_s &p, int batch) {
         off = align_up(off + sizeof(double) * pgram_partial_doubles(p.n_mtile, true) * p.nblk_pg_max * batch);
     } else if (p.pg_wide) {
         // per block: the triplet pass's tiles, or the K-part sets of the squares pass
-        const size_t sets = std::max((size_t)p.n_mtile,
-                                     (size_t)p.pg_sq_tiles * pgram_fields_kparts(p.pg_sq_tiles, true));
+        const size_t sets = std::max((size_t)p.n_mtile, (size_t)p.n_cgroup * p.pg_sq_tiles *
+                                                            pgram_fields_kparts(p.pg_sq_tiles, true));
         off = align_up(off + sizeof(double) * 2048 * sets * p.nblk_wide * batch);
     }
     L.pg_dense = off;
@@ -277,7 +282,7 @@ std::vector<PairDev> pair_devs(const bispec_plan_s &p) {
 // and among three distinct bins two share a parity, so the equal-parity pairs
 // (about nb^2/4) always suffice; the greedy cover is smaller.
 template <class Add>
-void greedy_cover(int nb, const std::vector<int> &tp, const std::vector<int> &tris, std::vector<int> &row_of,
+void greedy_cover(int nitem, const std::vector<int> &tp, const std::vector<int> &tris, std::vector<int> &row_of,
                   Add add) {
     auto covered = [&](int t) {
         return row_of[tp[3 * t]] >= 0 || row_of[tp[3 * t + 1]] >= 0 || row_of[tp[3 * t + 2]] >= 0;
@@ -285,13 +290,13 @@ void greedy_cover(int nb, const std::vector<int> &tp, const std::vector<int> &tr
     std::vector<int> open;
     for (int t : tris)
         if (!covered(t)) open.push_back(t);
-    std::vector<int> cnt(nb * nb);
+    std::vector<int> cnt(nitem);
     while (!open.empty()) {
         std::fill(cnt.begin(), cnt.end(), 0);
         for (int t : open)
             for (int k = 0; k < 3; ++k) ++cnt[tp[3 * t + k]];
         const int best = (int)(std::max_element(cnt.begin(), cnt.end()) - cnt.begin());
-        add(best / nb, best % nb);
+        add(best);
         std::vector<int> left;
         for (int t : open)
             if (!covered(t)) left.push_back(t);
@@ -299,46 +304,59 @@ void greedy_cover(int nb, const std::vector<int> &tp, const std::vector<int> &tr
     }
 }
 
-// Rows of the product-Gram.  Every (b,b) row is kept (rows 0..nb-1, so pair
-// tile 0 holds row (r,r) in lane r, which the p = 4 tile relies on); when nb < 32 column nb
-// is a field of ones, so G[(b,b), nb] is the power-spectrum numerator, else
-// rows (b, ONE) are added for it.  The other rows are a greedy cover of the
-// well-conditioned triplets; the ill-conditioned ones (kappa above
-// kRefineKappa) get a cover of their own, the refinement rows, which run in
-// FP32 mode.  Padding rows (ZERO, ZERO) fill the last tile of each table.  A
+// Rows of the product-Gram.  Fused tail (up to 32 bins): every (b,b) row is
+// kept (rows 0..nb-1, so pair tile 0 holds row (r,r) in lane r, which the
+// p = 4 tile relies on); when nb < 32 column nb is a field of ones, so
+// G[(b,b), nb] is the power-spectrum numerator, else rows (b, ONE) are added
+// for it.  The other rows are a greedy cover of the well-conditioned
+// triplets; the ill-conditioned ones (kappa above kRefineKappa) get a cover of
+// their own, the refinement rows, which run on the FP64 product-Gram over the
+// bin fields.  Over fields in HBM (33..128 bins, or any general grid) the
+// columns come in groups of 64 and a cover item is a pair read against one
+// group; each group's rows fill whole tiles of their own (ZERO padding).  A
 // term's dense index in a block's tiles is tile*32*ncol + row_in_tile*ncol +
-// column (ncol = 32, or 64 with more than 32 bins), with PG_IDX_ALT set for
-// the refinement tiles.
+// column within the group (ncol = 32 for the tail, else 64), with PG_IDX_ALT
+// set for the refinement tiles.
 void build_pgram_tables(bispec_plan_s &p) {
     const int nb = p.nb;
     p.mfma_ok = !p.general && nb <= 32;
-    p.pg_wide = p.general ? nb <= 63 : (nb > 32 && nb <= 64);
+    p.pg_wide = p.general ? nb <= PGF_MAX_BINS : (nb > 32 && nb <= PGF_MAX_BINS);
     p.pg_pairs.clear();
     p.pg_idx.clear();
     p.pg_pairs_r.clear();
+    p.pg_gtile.assign(1, 0);
+    p.pg_gtile_r.assign(1, 0);
     p.n_mtile_r = 0;
     if (!p.mfma_ok && !p.pg_wide) return;
-    // 33..64 bins: rows are the cover of the triplets alone over 64 columns of
-    // fields in HBM (P and collapsed quads come from the squares pass)
+    // over fields in HBM the rows are the cover of the triplets alone (P and
+    // collapsed quads come from the squares pass)
     const bool wide = p.pg_wide;
-    const int row_zero = wide ? PGF_ROW_ZERO : PG_ROW_ZERO;
-    std::vector<int> row_of(nb * nb, -1), row_one(nb, -1), row_of_r(nb * nb, -1);
-    auto add = [&](int i, int j) {
-        if (row_of[i * nb + j] < 0) {
-            row_of[i * nb + j] = (int)p.pg_pairs.size();
-            p.pg_pairs.push_back(uchar2{(unsigned char)i, (unsigned char)j});
+    const int G = wide ? (nb + 63) / 64 : 1;                // column groups of the main rows
+    const int Gr = (nb + 63) / 64;                          // and of the refinement rows
+    p.n_cgroup = G;
+    const int row_zero = wide ? pgf_row_zero(nb) : PG_ROW_ZERO;
+    const uchar2 zero2{(unsigned char)row_zero, (unsigned char)row_zero};
+    const uchar2 zero2r{(unsigned char)pgf_row_zero(nb), (unsigned char)pgf_row_zero(nb)};
+    // cover item of pair x*nb + y (x <= y) against column group g: (x*nb + y)*G + g
+    std::vector<int> row_of(nb * nb * G, -1), row_one(nb, -1), row_of_r(nb * nb * Gr, -1);
+    std::vector<std::vector<int>> grp(G), grp_r(Gr);       // items per group, in the order chosen
+    auto add = [&](int item) {
+        if (row_of[item] >= 0) return;
+        if (wide) {
+            row_of[item] = 0;                               // row numbers follow the group layout
+            grp[item % G].push_back(item);
+        } else {
+            row_of[item] = (int)p.pg_pairs.size();
+            p.pg_pairs.push_back(uchar2{(unsigned char)(item / nb), (unsigned char)(item % nb)});
         }
-        return row_of[i * nb + j];
     };
-    auto add_r = [&](int i, int j) {
-        if (row_of_r[i * nb + j] < 0) {
-            row_of_r[i * nb + j] = (int)p.pg_pairs_r.size();
-            p.pg_pairs_r.push_back(uchar2{(unsigned char)i, (unsigned char)j});
-        }
-        return row_of_r[i * nb + j];
+    auto add_r = [&](int item) {
+        if (row_of_r[item] >= 0) return;
+        row_of_r[item] = 0;
+        grp_r[item % Gr].push_back(item);
     };
     if (!wide)
-        for (int b = 0; b < nb; ++b) add(b, b);
+        for (int b = 0; b < nb; ++b) add(b * nb + b);
     const bool one_col = nb < 32;
     if (!one_col && !wide)
         for (int b = 0; b < nb; ++b) {
@@ -346,15 +364,17 @@ void build_pgram_tables(bispec_plan_s &p) {
             p.pg_pairs.push_back(uchar2{(unsigned char)b, (unsigned char)PG_ROW_ONE});
         }
     const int ntri = (int)p.tri.size() / 3;
-    // pair index x*nb + y (x <= y) of the three pairs of each sorted triplet
-    std::vector<int> tp(3 * ntri), rest(3 * ntri);
+    // the three (pair, column) readings of each sorted triplet
+    std::vector<int> tpair(3 * ntri), rest(3 * ntri), tp(3 * ntri), tp_r(3 * ntri);
     for (int t = 0; t < ntri; ++t) {
         int a[3] = {p.tri[3 * t], p.tri[3 * t + 1], p.tri[3 * t + 2]};
         std::sort(a, a + 3);
         const int c[3][3] = {{a[0], a[1], a[2]}, {a[0], a[2], a[1]}, {a[1], a[2], a[0]}};
         for (int k = 0; k < 3; ++k) {
-            tp[3 * t + k] = c[k][0] * nb + c[k][1];
+            tpair[3 * t + k] = c[k][0] * nb + c[k][1];
             rest[3 * t + k] = c[k][2];
+            tp[3 * t + k] = tpair[3 * t + k] * G + (G > 1 ? c[k][2] / 64 : 0);
+            tp_r[3 * t + k] = tpair[3 * t + k] * Gr + (Gr > 1 ? c[k][2] / 64 : 0);
         }
     }
     // condition numbers decide which cover reads a triplet
@@ -374,42 +394,71 @@ void build_pgram_tables(bispec_plan_s &p) {
             main_t.push_back(t);
         }
     }
-    greedy_cover(nb, tp, main_t, row_of, add);
-    greedy_cover(nb, tp, ref_t, row_of_r, add_r);
-    std::vector<int> tri_row(ntri), tri_col(ntri);
-    for (int t = 0; t < ntri; ++t) {
-        const std::vector<int> &ro = p.refine[t] ? row_of_r : row_of;
-        for (int k = 0; k < 3; ++k)
-            if (ro[tp[3 * t + k]] >= 0) {
-                tri_row[t] = ro[tp[3 * t + k]];
-                tri_col[t] = rest[3 * t + k];
-                break;
+    greedy_cover(nb * nb * G, tp, main_t, row_of, add);
+    greedy_cover(nb * nb * Gr, tp_r, ref_t, row_of_r, add_r);
+    // group layouts: each group's rows in whole tiles, tiles in group order
+    auto lay_out = [&](std::vector<std::vector<int>> &gr, int ng, std::vector<int> &rof, std::vector<uchar2> &rows,
+                       std::vector<int> &gtile, const uchar2 &z) {
+        gtile.assign(1, 0);
+        for (int g = 0; g < ng; ++g) {
+            for (int item : gr[g]) {
+                rof[item] = (int)rows.size();
+                const int pr = item / ng;
+                rows.push_back(uchar2{(unsigned char)(pr / nb), (unsigned char)(pr % nb)});
             }
+            while (rows.size() % 32) rows.push_back(z);
+            gtile.push_back((int)rows.size() / 32);
+        }
+    };
+    if (wide) {
+        lay_out(grp, G, row_of, p.pg_pairs, p.pg_gtile, zero2);
+        if (p.pg_pairs.empty()) {
+            // no triplet rows: one tile of zeros in group 0
+            p.pg_pairs.assign(32, zero2);
+            for (int g = 1; g <= G; ++g) p.pg_gtile[g] = 1;
+        }
+    } else {
+        if (p.pg_pairs.empty()) p.pg_pairs.push_back(zero2);
+        while (p.pg_pairs.size() % 32) p.pg_pairs.push_back(zero2);
+        p.pg_gtile = {0, (int)p.pg_pairs.size() / 32};
     }
-    if (p.pg_pairs.empty()) p.pg_pairs.push_back(uchar2{(unsigned char)row_zero, (unsigned char)row_zero});
-    while (p.pg_pairs.size() % 32) p.pg_pairs.push_back(uchar2{(unsigned char)row_zero, (unsigned char)row_zero});
     p.n_mtile = (int)p.pg_pairs.size() / 32;
-    while (p.pg_pairs_r.size() % 32) p.pg_pairs_r.push_back(uchar2{(unsigned char)row_zero, (unsigned char)row_zero});
+    lay_out(grp_r, Gr, row_of_r, p.pg_pairs_r, p.pg_gtile_r, zero2r);
     p.n_mtile_r = (int)p.pg_pairs_r.size() / 32;
     const int ncol = wide ? 64 : 32;
     auto dense = [ncol](int row, int c) { return (row / 32) * 32 * ncol + (row % 32) * ncol + c; };
-    // the refinement rows run on the 64-column FP64 product-Gram over fields in HBM
-    auto dense_r = [](int row, int c) { return (row / 32) * 2048 + (row % 32) * 64 + c; };
-    for (int t = 0; t < ntri; ++t)
-        p.pg_idx.push_back(p.refine[t] ? (dense_r(tri_row[t], tri_col[t]) | PG_IDX_ALT)
-                                       : dense(tri_row[t], tri_col[t]));
+    for (int t = 0; t < ntri; ++t) {
+        const bool r = p.refine[t];
+        const std::vector<int> &ro = r ? row_of_r : row_of;
+        const std::vector<int> &it = r ? tp_r : tp;
+        int idx = -1;
+        for (int k = 0; k < 3 && idx < 0; ++k)
+            if (ro[it[3 * t + k]] >= 0) {
+                const int row = ro[it[3 * t + k]], c = rest[3 * t + k];
+                // refinement rows: 64-column tiles over the fields
+                idx = r ? ((row / 32) * 2048 + (row % 32) * 64 + c % 64) | PG_IDX_ALT
+                        : (wide ? dense(row, c % 64) : dense(row, c));
+            }
+        p.pg_idx.push_back(idx);
+    }
     // blocks of the product-Gram kernels over fields in HBM: about 16384
     // points each (at least 256 blocks, at least one 128-point step per block)
     const int64_t npix_i = field_len(p);
     p.nblk_r = (int)std::min<int64_t>(std::max<int64_t>(256, npix_i / 16384), npix_i / 128);
     if (wide) {
-        p.nblk_wide = p.nblk_r;
-        // P and collapsed quads from the product-Gram of the squares
-        // (rows (a,a), columns F_b^2, ones at column nb): -1 leaves a term to
-        // the vector ALUs (P at 64 bins, general quads)
-        p.pg_sq_tiles = (nb + 31) / 32;
-        auto dsq = [](int a, int c) { return (a / 32) * 2048 + (a % 32) * 64 + c; };
-        for (int b = 0; b < nb; ++b) p.pg_idx.push_back(nb < 64 ? dsq(b, nb) : -1);
+        // with many row tiles the launch already has blocks to spare: fewer,
+        // longer chunks (within the FP32 accumulation span) keep the
+        // partials small
+        const int64_t need = (npix_i + PGF_MAX_CHUNK - 1) / PGF_MAX_CHUNK;
+        p.nblk_wide = p.n_mtile > 64 ? (int)std::max<int64_t>(need, std::min<int64_t>(p.nblk_r, 256)) : p.nblk_r;
+        // P and collapsed quads from the product-Gram of the squares (rows
+        // (a,a), columns F_b^2 of each group, ones at column nb): -1 leaves a
+        // term to the vector ALUs (when nb is a multiple of 64, or general quads)
+        p.pg_sq_tiles = pgf_sq_tiles(nb);
+        p.pg_sq_ok = nb % 64 != 0;
+        const int S = p.pg_sq_tiles;
+        auto dsq = [S](int a, int c) { return ((c / 64) * S + a / 32) * 2048 + (a % 32) * 64 + c % 64; };
+        for (int b = 0; b < nb; ++b) p.pg_idx.push_back(p.pg_sq_ok ? dsq(b, nb) : -1);
         const int nq = (int)p.quad.size() / 4;
         p.quads_collapsed = true;
         for (int q = 0; q < nq; ++q) {
@@ -417,11 +466,12 @@ void build_pgram_tables(bispec_plan_s &p) {
             std::sort(a, a + 4);
             const bool coll = a[0] == a[1] && a[2] == a[3];
             p.quads_collapsed = p.quads_collapsed && coll;
-            p.pg_idx.push_back(coll ? dsq(a[0], a[2]) : -1);
+            p.pg_idx.push_back(coll && p.pg_sq_ok ? dsq(a[0], a[2]) : -1);
         }
         return;
     }
-    for (int b = 0; b < nb; ++b) p.pg_idx.push_back(one_col ? dense(row_of[b * nb + b], nb) : dense(row_one[b], b));
+    for (int b = 0; b < nb; ++b)
+        p.pg_idx.push_back(one_col ? dense(row_of[b * nb + b], nb) : dense(row_one[b], b));
     const int nq = (int)p.quad.size() / 4;
     p.quads_collapsed = true;
     for (int q = 0; q < nq; ++q) {
@@ -444,23 +494,26 @@ void build_terms(bispec_plan_s &p) {
     const double V = p.box_len * p.box_len * p.box_len *
                      (p.general ? ((double)p.gg.nz / p.gg.nx) * ((double)p.gg.ny / p.gg.nx) : 1.0);
     const double nan = std::numeric_limits<double>::quiet_NaN();
+    // the bin fields carry 2^-spec_shift: a product of p of them 2^(-p spec_shift)
+    const double u2 = std::ldexp(1.0, 2 * p.spec_shift), u3 = std::ldexp(1.0, 3 * p.spec_shift),
+                 u4 = std::ldexp(1.0, 4 * p.spec_shift);
     const int ntri = (int)p.tri.size() / 3;
     for (int t = 0; t < ntri; ++t) {
         p.terms.push_back(uchar4{(unsigned char)p.tri[3 * t], (unsigned char)p.tri[3 * t + 1],
                                  (unsigned char)p.tri[3 * t + 2], 0xFF});
         const double c = p.tri_count.empty() ? 0.0 : p.tri_count[t];
-        p.scale.push_back(c > 0 ? V * V / (npix * npix * npix) / (npix * c) : nan);
+        p.scale.push_back(c > 0 ? V * V / (npix * npix * npix) / (npix * c) * u3 : nan);
     }
     for (int b = 0; b < p.nb; ++b) {
         p.terms.push_back(uchar4{(unsigned char)b, (unsigned char)b, 0xFF, 0xFF});
-        p.scale.push_back(V / (npix * npix) / (npix * (double)p.modes[b]));
+        p.scale.push_back(V / (npix * npix) / (npix * (double)p.modes[b]) * u2);
     }
     const int nq = (int)p.quad.size() / 4;
     for (int q = 0; q < nq; ++q) {
         p.terms.push_back(uchar4{(unsigned char)p.quad[4 * q], (unsigned char)p.quad[4 * q + 1],
                                  (unsigned char)p.quad[4 * q + 2], (unsigned char)p.quad[4 * q + 3]});
         const double c = p.quad_count.empty() ? 0.0 : p.quad_count[q];
-        p.scale.push_back(c > 0 ? V * V * V / (npix * npix * npix * npix) / (npix * c) : nan);
+        p.scale.push_back(c > 0 ? V * V * V / (npix * npix * npix * npix) / (npix * c) * u4 : nan);
     }
     build_pgram_tables(p);
 }
@@ -718,9 +771,8 @@ bispec_status plan_impl(const bispec_plan_desc *d, bispec_plan_t *out) {
         gg.sy = P / ny;
         gg.sx = P / nx;
         gg.npix = (long long)nz * ny * nx;
-        if (d->n_bins > 63) return BISPEC_E_INVALID;
     }
-    if (d->n_bins < 1 || d->n_bins > 64 || !d->k_lo || !d->k_hi) return BISPEC_E_INVALID;
+    if (d->n_bins < 1 || d->n_bins > PGF_MAX_BINS || !d->k_lo || !d->k_hi) return BISPEC_E_INVALID;
     if (d->precision < BISPEC_FP32 || d->precision > BISPEC_FP32_VALU) return BISPEC_E_INVALID;
     if (d->max_batch < 1) return BISPEC_E_INVALID;
     if (d->n_tri < 0 || (d->n_tri > 0 && !d->tri)) return BISPEC_E_INVALID;
@@ -746,6 +798,7 @@ bispec_status plan_impl(const bispec_plan_desc *d, bispec_plan_t *out) {
     p->gg = gg;
     p->npix = (int64_t)nz * ny * nx;
     p->fstride = (p->npix + 127) / 128 * 128;
+    p->spec_shift = std::ilogb((double)p->npix);
     p->box_len = d->box_len > 0 ? d->box_len : (double)nx;
     p->nb = nb;
     p->lo.assign(d->k_lo, d->k_lo + nb);
@@ -958,7 +1011,7 @@ hipError_t run_inverse_zy(bispec_plan_s &p, int batch) {
 // on a general grid stride is the field length given, and entries from the
 // end of the grid to it are zeroed when pad is set).
 bispec_status run_fields(bispec_plan_s &p, const float *delta, int batch, float *fields, int64_t stride,
-                         bool pad) {
+                         bool pad, double scale) {
     const Layout L = make_layout(p, p.max_batch);
     char *ws = (char *)p.ws;
     if (p.general) {
@@ -967,7 +1020,7 @@ bispec_status run_fields(bispec_plan_s &p, const float *delta, int batch, float 
         float2 *spec = (float2 *)(ws + L.spec);
         stamp(p, 0);
         CK(gen_mean(delta, p.gg, batch, (double *)(ws + L.mean_partial), kMeanParts, mean, p.stream));
-        CK(gen_forward(delta, mean, p.gg, batch, tw, spec, p.stream));
+        CK(gen_forward(delta, mean, p.gg, batch, tw, spec, p.stream, scale));
         stamp(p, 1);
         for (int b = 0; b < p.nb; b += 2)
             CK(gen_inverse_pair(spec, (float2 *)(ws + L.abox), p.gg, gen_pair(p, b), batch, tw,
@@ -984,13 +1037,44 @@ bispec_status run_fields(bispec_plan_s &p, const float *delta, int batch, float 
     float2 *spec = (float2 *)(ws + L.spec);
     stamp(p, 0);
     CK(launch_mean(delta, n, batch, (double *)(ws + L.mean_partial), kMeanParts, mean, p.stream));
-    CK(launch_forward(delta, mean, n, batch, tw, spec, p.stream));
+    CK(launch_forward(delta, mean, n, batch, tw, spec, p.stream, scale));
     stamp(p, 1);
     CK(run_inverse_zy(p, batch));
     CK(launch_inverse_x_pairs((const float2 *)(ws + L.bc), n, batch, tw, (const PairDev *)(ws + L.pd),
                               (int)p.pairs.size(), p.nb, fields, p.stream));
     stamp(p, 2);
     return BISPEC_OK;
+}
+
+// The product-Gram over bin fields in HBM, one launch per group of 64
+// columns: rows pairs[32 gtile[g] ..] against fields 64 g .. 64 g + 63,
+// partial tiles gtile[g] .. gtile[g+1] - 1 of every block's set.
+hipError_t pgram_groups(const bispec_plan_s &p, const float *fields, int64_t fl, int batch, const uchar2 *pairs,
+                        const std::vector<int> &gtile, bool f64, int nblk, double *partial) {
+    const int tiles = gtile.back();
+    for (size_t g = 0; g + 1 < gtile.size(); ++g) {
+        const int nt = gtile[g + 1] - gtile[g];
+        if (nt == 0) continue;
+        const uchar2 *pg = pairs + 32 * (int64_t)gtile[g];
+        const hipError_t e =
+            f64 ? launch_pgram_fields_f64(fields, fl, p.nb, batch, pg, nt, 64 * (int)g, gtile[g], tiles, nblk,
+                                          partial, p.stream)
+                : launch_pgram_fields(fields, fl, p.nb, batch, pg, nt, 64 * (int)g, gtile[g], tiles, nblk, partial,
+                                      p.stream, false);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+// The product-Gram of the squares, one launch per column group.
+hipError_t pgram_squares(const bispec_plan_s &p, const float *fields, int64_t fl, int batch, double *partial) {
+    const int S = p.pg_sq_tiles;
+    for (int g = 0; g < p.n_cgroup; ++g) {
+        const hipError_t e = launch_pgram_fields(fields, fl, p.nb, batch, nullptr, S, 64 * g, g * S,
+                                                 p.n_cgroup * S, p.nblk_wide, partial, p.stream, true);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 // Final FP64 reduction of terms [first, last) into B ([0,ntri)), P
@@ -1059,11 +1143,12 @@ bispec_status run_estimate_body(bispec_plan_s &p, const float *delta, int batch,
     if (!mfma) {
         float *fields = (float *)(ws + L.fields);
         const int64_t fl = field_len(p);
-        bispec_status s = run_fields(p, delta, batch, fields, fl, true);
+        bispec_status s = run_fields(p, delta, batch, fields, fl, true, spec_scale(p));
         if (s != BISPEC_OK) return s;
-        // 33..64 bins in split mode: the triplets on MFMA over the fields in
-        // HBM; then P and collapsed quads from the product-Gram of the
-        // squares (nb < 64); what is left runs on the vector ALUs below
+        // split mode over the fields in HBM (33..128 bins, general grids):
+        // the triplets on MFMA; then P and collapsed quads from the
+        // product-Gram of the squares (nb not a multiple of 64); what is left
+        // runs on the vector ALUs below
         const bool wide = p.pg_wide && p.precision == BISPEC_SPLIT_BF16;
         // (the partial and dense regions hold the larger of the two passes;
         // each pass strides its blocks by its own tile count)
@@ -1071,14 +1156,14 @@ bispec_status run_estimate_body(bispec_plan_s &p, const float *delta, int batch,
         double *dense = (double *)(ws + L.pg_dense);
         if (wide && B && ntri > 0) {
             const int64_t n_dense = (int64_t)p.n_mtile * 2048;
-            CK(launch_pgram_fields(fields, fl, p.nb, batch, (const uchar2 *)(ws + L.pg_pairs), p.n_mtile,
-                                   p.nblk_wide, pg, p.stream, false));
+            CK(pgram_groups(p, fields, fl, batch, (const uchar2 *)(ws + L.pg_pairs), p.pg_gtile, false, p.nblk_wide,
+                            pg));
             CK(launch_reduce_dense(pg, p.nblk_wide, n_dense, batch, dense, (double *)(ws + L.pg_tmp), p.stream));
             if (p.n_mtile_r > 0) {
                 // ill-conditioned triplets: FP64 product-Gram rows of their own
                 double *pr = (double *)(ws + L.pg_partial_r);
-                CK(launch_pgram_fields_f64(fields, fl, p.nb, batch, (const uchar2 *)(ws + L.pg_pairs_r), p.n_mtile_r,
-                                           p.nblk_r, pr, p.stream));
+                CK(pgram_groups(p, fields, fl, batch, (const uchar2 *)(ws + L.pg_pairs_r), p.pg_gtile_r, true,
+                                p.nblk_r, pr));
                 CK(launch_reduce_dense(pr, p.nblk_r, (int64_t)refine_dense_doubles(p), batch,
                                        (double *)(ws + L.pg_dense_r), (double *)(ws + L.pg_tmp_r), p.stream));
             }
@@ -1087,10 +1172,10 @@ bispec_status run_estimate_body(bispec_plan_s &p, const float *delta, int batch,
             first = ntri;
             if (first == last && !T) return BISPEC_OK;
         }
-        if (wide && p.nb < 64 && (first < last || (T && p.quads_collapsed))) {
-            const int64_t n_dense = (int64_t)p.pg_sq_tiles * 2048;
+        if (wide && p.pg_sq_ok && (first < last || (T && p.quads_collapsed))) {
+            const int64_t n_dense = (int64_t)p.n_cgroup * p.pg_sq_tiles * 2048;
             const int sets = p.nblk_wide * pgram_fields_kparts(p.pg_sq_tiles, true);
-            CK(launch_pgram_fields(fields, fl, p.nb, batch, nullptr, p.pg_sq_tiles, p.nblk_wide, pg, p.stream, true));
+            CK(pgram_squares(p, fields, fl, batch, pg));
             CK(launch_reduce_dense(pg, sets, n_dense, batch, dense, (double *)(ws + L.pg_tmp), p.stream));
             if (first < last) {
                 s = finalize_range(p, true, dense, 1, n_dense, first, last, batch, P, B, T);
@@ -1113,8 +1198,8 @@ bispec_status run_estimate_body(bispec_plan_s &p, const float *delta, int batch,
         // FP64 refinement rows, written over the vector-ALU values
         if (B && first == 0 && ntri > 0 && p.n_mtile_r > 0 && p.precision != BISPEC_FP32_VALU) {
             double *pr = (double *)(ws + L.pg_partial_r);
-            CK(launch_pgram_fields_f64(fields, fl, p.nb, batch, (const uchar2 *)(ws + L.pg_pairs_r), p.n_mtile_r,
-                                       p.nblk_r, pr, p.stream));
+            CK(pgram_groups(p, fields, fl, batch, (const uchar2 *)(ws + L.pg_pairs_r), p.pg_gtile_r, true, p.nblk_r,
+                            pr));
             CK(launch_reduce_dense(pr, p.nblk_r, (int64_t)refine_dense_doubles(p), batch,
                                    (double *)(ws + L.pg_dense_r), (double *)(ws + L.pg_tmp_r), p.stream));
             CK(launch_scatter_alt((const double *)(ws + L.pg_dense_r), (int64_t)refine_dense_doubles(p),
@@ -1128,7 +1213,7 @@ bispec_status run_estimate_body(bispec_plan_s &p, const float *delta, int batch,
     double *mean = (double *)(ws + L.mean);
     stamp(p, 0);
     CK(launch_mean(delta, n, batch, (double *)(ws + L.mean_partial), kMeanParts, mean, p.stream));
-    CK(launch_forward(delta, mean, n, batch, tw, (float2 *)(ws + L.spec), p.stream));
+    CK(launch_forward(delta, mean, n, batch, tw, (float2 *)(ws + L.spec), p.stream, spec_scale(p)));
     stamp(p, 1);
     CK(run_inverse_zy(p, batch));
     stamp(p, 2);
@@ -1155,8 +1240,8 @@ bispec_status run_estimate_body(bispec_plan_s &p, const float *delta, int batch,
             float *fields = (float *)(ws + L.fields);
             CK(launch_inverse_x_pairs((const float2 *)(ws + L.bc), n, batch, tw, (const PairDev *)(ws + L.pd),
                                       (int)p.pairs.size(), p.nb, fields, p.stream));
-            CK(launch_pgram_fields_f64(fields, (int64_t)n * n * n, p.nb, batch, (const uchar2 *)(ws + L.pg_pairs_r),
-                                       p.n_mtile_r, p.nblk_r, (double *)(ws + L.pg_partial_r), p.stream));
+            CK(pgram_groups(p, fields, (int64_t)n * n * n, batch, (const uchar2 *)(ws + L.pg_pairs_r), p.pg_gtile_r,
+                            true, p.nblk_r, (double *)(ws + L.pg_partial_r)));
         }
         stamp(p, 3);
         CK(launch_reduce_dense(pg, p.nblk_pg, n_dense, batch, dense, (double *)(ws + L.pg_tmp), p.stream));
@@ -1280,7 +1365,7 @@ bispec_status bispec_bin_fields(bispec_plan_t plan, const float *delta, int32_t 
     if (!fields) return BISPEC_E_INVALID;
     try {
         const int64_t len = plan->general ? plan->npix : (int64_t)plan->n * plan->n * plan->n;
-        bispec_status st = run_fields(*plan, delta, batch, fields, len, false);
+        bispec_status st = run_fields(*plan, delta, batch, fields, len, false, 1.0);   // the fields as defined
         stamp_rest(*plan, 3);
         return st;
     } catch (...) {
@@ -1387,7 +1472,7 @@ bispec_status bispec_autotune(bispec_plan_t plan, const float *delta, int32_t *n
                 double *mean = (double *)(ws + L.mean);
                 CK(launch_mean(delta, n, 1, (double *)(ws + L.mean_partial), kMeanParts, mean, p.stream));
                 CK(launch_forward(delta, mean, n, 1, (const float2 *)(ws + L.tw), (float2 *)(ws + L.spec),
-                                  p.stream));
+                                  p.stream, spec_scale(p)));
                 CK(run_inverse_zy(p, 1));
             }
             TailPairs tp{};

@@ -151,7 +151,8 @@ __device__ C *gen_fft(C *a, C *b, const C *tw, const GenAxis &ax, int G) {
 // the full spectrum; block (x, map) holds rows x G .. x G + G - 1.
 __global__ __launch_bounds__(GEN_NT) void k_gen_fwd_x(const float *__restrict__ delta,
                                                       const double *__restrict__ mean, float2 *__restrict__ spec,
-                                                      const float2 *__restrict__ tw, GenGrid g, int G) {
+                                                      const float2 *__restrict__ tw, GenGrid g, int G,
+                                                      double scale) {
     extern __shared__ __attribute__((aligned(16))) float2 gsm[];
     const GenAxis &ax = g.ax[2];
     const int n = ax.n;
@@ -163,7 +164,8 @@ __global__ __launch_bounds__(GEN_NT) void k_gen_fwd_x(const float *__restrict__ 
     const double mu = mean[map];
     for (int e = threadIdx.x; e < G * n; e += GEN_NT) {
         const int p = e / n, i = e % n;
-        a[e] = r0 + p < rows ? float2{(float)((double)src[(r0 + p) * n + i] - mu), 0.0f} : float2{0.0f, 0.0f};
+        a[e] = r0 + p < rows ? float2{(float)(((double)src[(r0 + p) * n + i] - mu) * scale), 0.0f}
+                             : float2{0.0f, 0.0f};
     }
     __syncthreads();
     const float2 *res = gen_fft<-1>(a, b, tw + ax.tw_off, ax, G);
@@ -385,11 +387,11 @@ hipError_t gen_mean(const float *x, const GenGrid &g, int batch, double *part, i
 }
 
 hipError_t gen_forward(const float *delta, const double *mean, const GenGrid &g, int batch, const float2 *tw,
-                       float2 *spec, hipStream_t st) {
+                       float2 *spec, hipStream_t st, double scale) {
     const int Gx = gen_pencils(g.nx, sizeof(float2));
     const int64_t rows = (int64_t)g.nz * g.ny;
     hipLaunchKernelGGL(k_gen_fwd_x, dim3((unsigned)((rows + Gx - 1) / Gx), batch), dim3(GEN_NT),
-                       gen_smem<float2>(g.nx, Gx), st, delta, mean, spec, tw, g, Gx);
+                       gen_smem<float2>(g.nx, Gx), st, delta, mean, spec, tw, g, Gx, scale);
     const int Gy = gen_pencils(g.ny, sizeof(float2));
     hipLaunchKernelGGL((k_gen_axis<float2, -1, 1>), dim3((unsigned)(g.nz * ((g.nx + Gy - 1) / Gy)), batch),
                        dim3(GEN_NT), gen_smem<float2>(g.ny, Gy), st, spec, tw, g, Gy);

@@ -42,10 +42,11 @@ int gen_pencils(int n, size_t elem_bytes);
 
 hipError_t gen_mean(const float *x, const GenGrid &g, int batch, double *part, int nparts, double *mean,
                     hipStream_t st);
-// Forward transform of batch maps [batch][npix] (mean subtracted) into the
-// full complex spectra [batch][npix]; tw: the three axis tables.
+// Forward transform of batch maps [batch][npix] (mean subtracted, then
+// multiplied by scale, a power of two) into the full complex spectra
+// [batch][npix]; tw: the three axis tables.
 hipError_t gen_forward(const float *delta, const double *mean, const GenGrid &g, int batch, const float2 *tw,
-                       float2 *spec, hipStream_t st);
+                       float2 *spec, hipStream_t st, double scale);
 // Inverse transform of one shell pair: work [batch][npix] complex scratch;
 // fields F_b1 to f1 and F_b2 to f2 (may be null), map m at m * map_stride.
 hipError_t gen_inverse_pair(const float2 *spec, float2 *work, const GenGrid &g, const GenPair &pr, int batch,

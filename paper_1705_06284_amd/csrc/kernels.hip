@@ -90,7 +90,8 @@ __device__ __forceinline__ void load_twiddles(C *tw_s, const C *tw) {
 // A(k) = (Z(k) + conj Z(N-k)) / 2 and B(k) = (Z(k) - conj Z(N-k)) / (2i).
 template <int N>
 __global__ __launch_bounds__(256) void k_fwd_x(const float *__restrict__ delta, const double *__restrict__ mean,
-                                               const float2 *__restrict__ tw, float2 *__restrict__ spec) {
+                                               const float2 *__restrict__ tw, float2 *__restrict__ spec,
+                                               double scale) {
     constexpr int G0 = pencils_per_block<float, N>();
     constexpr int G = G0 < N * N / 2 ? G0 : N * N / 2;      // complex pencils = 2G real rows
     constexpr int HP = spec_ld<N>();
@@ -114,7 +115,7 @@ __global__ __launch_bounds__(256) void k_fwd_x(const float *__restrict__ delta, 
     for (int k = 0; k < PER; ++k) {
         const int e = threadIdx.x + k * 256;
         const int r = e / N, i = e % N;          // real row r of the block: pencil r / 2, part r % 2
-        sf[2 * ((r >> 1) * LD + pad_idx(i)) + (r & 1)] = (float)((double)x[k] - mu);
+        sf[2 * ((r >> 1) * LD + pad_idx(i)) + (r & 1)] = (float)(((double)x[k] - mu) * scale);
     }
     __syncthreads();
     fft_pencils<float2, N, LD, G, -1>(s, tws);
@@ -595,7 +596,7 @@ __global__ __launch_bounds__(RB_NT) void k_rebin(const double *__restrict__ B, i
 // members' values with wave shuffles and a fixed-order combination of the
 // four wave sums into an LDS accumulator of the shell.  Block partials
 // partial[map][block][b][2] are summed in a fixed order afterwards.
-constexpr int SM_MAXB = 64;
+constexpr int SM_MAXB = 128;
 
 __global__ __launch_bounds__(256) void k_shell_moments(const float2 *__restrict__ spec, int64_t spec_stride, int n,
                                                        int hp, int nb, const int *__restrict__ thr,
@@ -748,14 +749,15 @@ hipError_t launch_mean(const float *x, int n, int batch, double *partial, int np
 }
 
 hipError_t launch_forward(const float *delta, const double *mean, int n, int batch, const float2 *tw,
-                          float2 *spec, hipStream_t st) {
+                          float2 *spec, hipStream_t st, double scale) {
     return dispatch_n(n, [&](auto nc) {
         constexpr int NN = decltype(nc)::value;
         constexpr int G = pencils_per_block<float, NN>();
         constexpr int GX = G < NN * NN / 2 ? G : NN * NN / 2;
         constexpr int HP = spec_ld<NN>();
         const int64_t hvol = (int64_t)NN * NN * HP;
-        hipLaunchKernelGGL((k_fwd_x<NN>), dim3(NN * NN / (2 * GX), batch), dim3(256), 0, st, delta, mean, tw, spec);
+        hipLaunchKernelGGL((k_fwd_x<NN>), dim3(NN * NN / (2 * GX), batch), dim3(256), 0, st, delta, mean, tw, spec,
+                           scale);
         hipLaunchKernelGGL((k_fft_strided<float, NN, -1, 1, HP>), dim3(NN * HP / G, batch), dim3(256), 0, st, spec,
                            tw, hvol);
         hipLaunchKernelGGL((k_fft_strided<float, NN, -1, 2, HP>), dim3(NN * HP / G, batch), dim3(256), 0, st, spec,

@@ -9,9 +9,10 @@ namespace bispec {
 
 hipError_t launch_mean(const float *x, int n, int batch, double *partial, int nparts, double *mean, hipStream_t st);
 
-// Forward 3D DFT of batch maps (mean subtracted on load) into full complex spectra.
+// Forward 3D DFT of batch maps (mean subtracted on load, then multiplied by
+// scale, a power of two) into the half spectra.
 hipError_t launch_forward(const float *delta, const double *mean, int n, int batch, const float2 *tw,
-                          float2 *spec, hipStream_t st);
+                          float2 *spec, hipStream_t st, double scale);
 
 // Pruned inverse transform (see k_inv_z_prune): passes Z and Y of every pair
 // in pd, one launch each, block tables (pair, first column) in ztab / ytab;
@@ -79,22 +80,31 @@ int tail_shape(int n, int n_mtile, bool want_t, int shape);
 // K parts per pair tile of the launched shape (summed inside the block:
 // each block writes one partial set of n_mtile + want_t tiles).
 int tail_ksplit(int n, int n_mtile, bool want_t, int shape);
-// Product-Gram over bin fields in HBM (33..64 bins, split-BF16; mfma.hip):
-// fields [batch][nb][npix] FP32 (npix: the field stride, a multiple of 128;
-// entries beyond the grid are zero); pairs [n_mtile*32] row factors (field rows
-// 0..63, PGF_ROW_ZERO = zeros); partial [batch][nblk][n_mtile][32][64] FP64,
-// column z < nb the field F_z, the rest zero.  nblk blocks per map, each
+// Product-Gram over bin fields in HBM (33..128 bins, split-BF16; mfma.hip),
+// one group of 64 columns per launch: fields [batch][nb][npix] FP32 (npix:
+// the field stride, a multiple of 128; entries beyond the grid are zero);
+// columns c < 64 are the fields col0 + c (zero at or beyond nb; col0 a
+// multiple of 64 below nb); pairs [n_mtile*32] row factors of the group (field
+// rows 0..nb-1, pgf_row_zero(nb) = zeros); partial
+// [batch][nblk][tiles_total][32][64] FP64, the launch writing tiles tile0 ..
+// tile0 + n_mtile - 1 of every block's set.  nblk blocks per map, each
 // contracting pgram_fields_chunk(n, nblk) <= PGF_MAX_CHUNK points (else
 // hipErrorInvalidValue).  squares: the product-Gram of the squares (rows
-// (a,a), columns F_b^2 and ones at column nb; nb <= 63, n_mtile =
-// ceil(nb / 32), pairs unused), with pgram_fields_kparts K parts per block,
-// each its own partial set: partial [batch][nblk * kparts][n_mtile][32][64].
-constexpr int PGF_ROW_ZERO = 64;
+// (a,a), a < nb, n_mtile = pgf_sq_tiles(nb), pairs unused; columns F_b^2 of
+// the group and ones at column nb - col0 when that is below 64), with
+// pgram_fields_kparts K parts per block, each its own partial set: partial
+// [batch][nblk * kparts][tiles_total][32][64].
+constexpr int PGF_ROW_ZERO = 64;        // zero row of plans of up to 64 bins
+constexpr int PGF_ROW_ZERO_XL = 128;    // and of 65..128 bins
+constexpr int PGF_MAX_BINS = 128;
+inline int pgf_row_zero(int nb) { return nb <= PGF_ROW_ZERO ? PGF_ROW_ZERO : PGF_ROW_ZERO_XL; }
 constexpr int64_t PGF_MAX_CHUNK = 32768;
 int64_t pgram_fields_chunk(int64_t npix, int nblk);
 int pgram_fields_kparts(int n_mtile, bool squares);
+int pgf_sq_tiles(int nb);               // 1, 2 or 4 row tiles of (a,a)
 hipError_t launch_pgram_fields(const float *fields, int64_t npix, int nb, int batch, const uchar2 *pairs, int n_mtile,
-                               int nblk, double *partial, hipStream_t st, bool squares);
+                               int col0, int tile0, int tiles_total, int nblk, double *partial, hipStream_t st,
+                               bool squares);
 // dense[map][e] = sum over the nblk partial sets; tmp holds
 // PG_REDUCE_SEGS * n_dense * batch doubles of segment sums (or null: one pass).
 constexpr int PG_REDUCE_SEGS = 32;
@@ -111,11 +121,12 @@ hipError_t launch_finalize_gather(const double *partial, int nblk, int64_t blk_s
 hipError_t launch_scatter_alt(const double *alt, int64_t alt_stride, const int *idx, const double *scale,
                               const int *list, int nlist, int batch, double *out, int nout, hipStream_t st);
 // FP64 product-Gram over bin fields in HBM (the refinement rows of
-// ill-conditioned triplets, any plan of up to 64 bins): same tables and
-// partial layout as launch_pgram_fields, one pair tile per wave, nblk blocks
-// of pgram_fields_chunk(n, nblk) points.
+// ill-conditioned triplets, any plan of up to 128 bins): same tables, column
+// groups and partial layout as launch_pgram_fields, one pair tile per wave,
+// nblk blocks of pgram_fields_chunk(n, nblk) points.
 hipError_t launch_pgram_fields_f64(const float *fields, int64_t npix, int nb, int batch, const uchar2 *pairs,
-                                   int n_mtile, int nblk, double *partial, hipStream_t st);
+                                   int n_mtile, int col0, int tile0, int tiles_total, int nblk, double *partial,
+                                   hipStream_t st);
 
 // out[map][g] = sum_{group[t] = g} count[t] B[map][t] / sum count[t] (NaN if empty).
 hipError_t launch_rebin(const double *B, int n_tri, const double *count, const int *group, int n_group, int batch,

@@ -454,46 +454,56 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MINW))) void
     st.write(partial, (int64_t)map * gridDim.x + blockIdx.x, n_mtile, col, half, reinterpret_cast<float *>(ubuf));
 }
 
-// Product-Gram over bin fields resident in HBM, for plans of 33..64 bins
-// (narrow shells): G[(x,y), z] = sum_n (F_x F_y)(n) F_z(n) in split-BF16,
-// with 64 columns (two 32-column MFMA tiles; columns >= nb are zero).  Block
-// (c, map, g) contracts the points [c chunk, (c+1) chunk) for the pair tiles
-// g PGF_TILES .. (g+1) PGF_TILES - 1; wave w owns the tiles g PGF_TILES + w +
-// r WAVES, r < PGF_MAXR.  Every step stages PGF_TK points of each field in
-// LDS, in FP32 for the row products and as bf16 halves for the columns, so
-// one split of a row product feeds both column tiles; the next step's
-// loads are in flight during a step's contraction.  A chunk is at most
-// 32768 points, the split-mode span of FP32 accumulation; the block writes
-// its FP64 tile partials [n_mtile][32][64] (its own tiles only).
+// Product-Gram over bin fields resident in HBM, for plans of 33..128 bins
+// (narrow shells): G[(x,y), z] = sum_n (F_x F_y)(n) F_z(n) in split-BF16.
+// One launch covers one group of 64 columns, fields col0 .. col0 + 63 (two
+// 32-column MFMA tiles; columns at or beyond nb are zero), and the pair rows
+// chosen for that group.  Block (c, map, g) contracts the points
+// [c chunk, (c+1) chunk) for the pair tiles g T .. (g+1) T - 1
+// of the group (T = pgf_tiles(ZR)); wave w owns the tiles g T + w + r WAVES,
+// r < pgf_maxr(ZR) (one tile per wave with ZR = 128, whose larger stage
+// leaves no registers for a second accumulator pair).
+// Every step stages PGF_TK points of each field in LDS, all nb in FP32 for
+// the row products and the group's columns as bf16 halves, so one split of a
+// row product feeds both column tiles; the next step's loads are in flight
+// during a step's contraction.  A chunk is at most 32768 points, the
+// split-mode span of FP32 accumulation; the block writes its FP64 tile
+// partials into tiles tile0 .. tile0 + n_mtile - 1 of its set of
+// tiles_total tiles (its own tiles only).  ZR: the zero row of the FP32
+// stage (64 for plans of up to 64 bins, else 128).
 // SQ: the product-Gram of the squares instead, rows (a,a) for a < nb (tile t
-// row r is a = 32 t + r) against the columns F_b^2, b < nb, and a column of
-// ones at b = nb (nb < 64): G[(a,a), b] = sum_n F_a^2 F_b^2 (the collapsed
-// p = 4 numerators) and G[(a,a), nb] = sum_n F_a^2 (the P numerators).
-// Its one or two row tiles would leave most waves idle, so the waves split
-// the K steps instead: wave w takes tile w % n_mtile and the steps
+// row r is a = 32 t + r) against the columns F_b^2 of the group, and a column
+// of ones at b = nb when nb - col0 < 64: G[(a,a), b] = sum_n F_a^2 F_b^2 (the
+// collapsed p = 4 numerators) and G[(a,a), nb] = sum_n F_a^2 (the P
+// numerators).  Its few row tiles would leave most waves idle, so the waves
+// split the K steps instead: wave w takes tile w % n_mtile and the steps
 // s = w / n_mtile (mod KS), KS = WAVES / n_mtile, and each K part writes its
-// own partial set (partial [batch][nblk][KS][n_mtile][32][64]); the
+// own partial set (partial [batch][nblk][KS][tiles_total][32][64]); the
 // fixed-order reduction over nblk KS sets adds them.
 constexpr int PGF_NT = 1024, PGF_MAXR = 2, PGF_TK = 128;
-constexpr int PGF_TILES = PGF_NT / 64 * PGF_MAXR;
+__host__ __device__ constexpr int pgf_maxr(int zr) { return zr == PGF_ROW_ZERO ? PGF_MAXR : 1; }
+__host__ __device__ constexpr int pgf_tiles(int zr) { return PGF_NT / 64 * pgf_maxr(zr); }
 
-template <bool SQ>
+template <bool SQ, int ZR>
 __global__ __launch_bounds__(PGF_NT) void k_pgram_fields(const float *__restrict__ fields, int64_t npix, int nb,
                                                          int64_t map_stride, const uchar2 *__restrict__ pairs,
-                                                         int n_mtile, int64_t chunk, double *__restrict__ partial) {
-    constexpr int TK = PGF_TK, FS = TK + 4, BS = TK + 8, WAVES = PGF_NT / 64, MAXR = PGF_MAXR;
-    __shared__ __attribute__((aligned(16))) float Ft[(PGF_ROW_ZERO + 1) * FS];   // field rows, then a row of zeros
+                                                         int n_mtile, int col0, int tile0, int tiles_total,
+                                                         int64_t chunk, double *__restrict__ partial) {
+    constexpr int TK = PGF_TK, FS = TK + 4, BS = TK + 8, WAVES = PGF_NT / 64, MAXR = pgf_maxr(ZR);
+    __shared__ __attribute__((aligned(16))) float Ft[(ZR + 1) * FS];   // field rows, then a row of zeros
     __shared__ __attribute__((aligned(16))) __bf16 Bh[64 * BS];
     __shared__ __attribute__((aligned(16))) __bf16 Bl[64 * BS];
     static_assert((BS * 2) % 16 == 0, "bf16 rows must keep 16-byte alignment");
     const int tid = threadIdx.x, lane = tid & 63, col = lane & 31, half = lane >> 5;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int map = blockIdx.y;
-    // rows nb..63 and the zero row are never loaded: zero them once (SQ:
-    // column nb is the ones column)
-    for (int i = tid; i < (PGF_ROW_ZERO + 1 - nb) * FS; i += PGF_NT) Ft[nb * FS + i] = 0.0f;
-    const int one_col = SQ && nb < 64 ? nb : -1;
-    const int zr = one_col >= 0 ? nb + 1 : nb;
+    // rows nb..ZR-1 and the zero row are never loaded: zero them once
+    for (int i = tid; i < (ZR + 1 - nb) * FS; i += PGF_NT) Ft[nb * FS + i] = 0.0f;
+    // the group's column fields col0 .. col0 + ncf - 1; SQ: column nb - col0
+    // is the ones column when it falls in the group
+    const int ncf = nb - col0 < 64 ? nb - col0 : 64;
+    const int one_col = SQ && nb - col0 < 64 ? nb - col0 : -1;
+    const int zr = one_col >= 0 ? ncf + 1 : ncf;
     for (int i = tid; i < (64 - zr) * BS; i += PGF_NT) {
         Bh[zr * BS + i] = (__bf16)0.0f;
         Bl[zr * BS + i] = (__bf16)0.0f;
@@ -513,11 +523,11 @@ __global__ __launch_bounds__(PGF_NT) void k_pgram_fields(const float *__restrict
         if constexpr (SQ) {
             const int t = wave % n_mtile, a = t * 32 + col;
             tile_of[r] = r == 0 ? t : -1;
-            rp[r] = a < nb ? uchar2{(unsigned char)a, (unsigned char)a} : uchar2{PGF_ROW_ZERO, PGF_ROW_ZERO};
+            rp[r] = a < nb ? uchar2{(unsigned char)a, (unsigned char)a} : uchar2{ZR, ZR};
         } else {
-            const int t = blockIdx.z * PGF_TILES + wave + r * WAVES;
+            const int t = blockIdx.z * pgf_tiles(ZR) + wave + r * WAVES;
             tile_of[r] = t < n_mtile ? t : -1;
-            rp[r] = t < n_mtile ? pairs[t * 32 + col] : uchar2{PGF_ROW_ZERO, PGF_ROW_ZERO};
+            rp[r] = t < n_mtile ? pairs[t * 32 + col] : uchar2{ZR, ZR};
         }
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
@@ -530,8 +540,8 @@ __global__ __launch_bounds__(PGF_NT) void k_pgram_fields(const float *__restrict
     const int64_t p1 = p0 + chunk < npix ? p0 + chunk : npix;
     // the loads of step p + TK are issued before step p's contraction and
     // land in registers; after the step they go to LDS
-    constexpr int LPT = 64 * (TK / 4) / PGF_NT;   // float4 per thread at 64 bins
-    static_assert(64 * (TK / 4) % PGF_NT == 0, "field loads must divide the block");
+    constexpr int LPT = ZR * (TK / 4) / PGF_NT;   // float4 per thread at ZR bins
+    static_assert(ZR * (TK / 4) % PGF_NT == 0, "field loads must divide the block");
     float4 pre[LPT];
     auto fetch = [&](int64_t p) {
 #pragma unroll
@@ -553,13 +563,15 @@ __global__ __launch_bounds__(PGF_NT) void k_pgram_fields(const float *__restrict
             const int b = e / (TK / 4), k = (e % (TK / 4)) * 4;
             const float4 v = pre[j];
             *reinterpret_cast<float4 *>(&Ft[b * FS + k]) = v;
+            const int c = b - col0;
+            if (c < 0 || c >= 64) continue;
             const float4 w = SQ ? float4{v.x * v.x, v.y * v.y, v.z * v.z, v.w * v.w} : v;
             bf16x2 h0, l0, h1, l1;
             split2(w.x, w.y, h0, l0);
             split2(w.z, w.w, h1, l1);
-            // 8-byte stores: (b BS + k) 2 bytes is a multiple of 8 (BS = 136, k = 0 mod 4)
-            *reinterpret_cast<bf16x4 *>(&Bh[b * BS + k]) = bf16x4{h0[0], h0[1], h1[0], h1[1]};
-            *reinterpret_cast<bf16x4 *>(&Bl[b * BS + k]) = bf16x4{l0[0], l0[1], l1[0], l1[1]};
+            // 8-byte stores: (c BS + k) 2 bytes is a multiple of 8 (BS = 136, k = 0 mod 4)
+            *reinterpret_cast<bf16x4 *>(&Bh[c * BS + k]) = bf16x4{h0[0], h0[1], h1[0], h1[1]};
+            *reinterpret_cast<bf16x4 *>(&Bl[c * BS + k]) = bf16x4{l0[0], l0[1], l1[0], l1[1]};
         }
         __syncthreads();
         if (p + TK < p1) fetch(p + TK);
@@ -590,7 +602,8 @@ __global__ __launch_bounds__(PGF_NT) void k_pgram_fields(const float *__restrict
             }
         }
     }
-    double *base = partial + (((int64_t)map * gridDim.x + blockIdx.x) * ks + kpart) * ((int64_t)n_mtile * 2048);
+    double *base = partial + (((int64_t)map * gridDim.x + blockIdx.x) * ks + kpart) * ((int64_t)tiles_total * 2048) +
+                   (int64_t)tile0 * 2048;
 #pragma unroll
     for (int r = 0; r < MAXR; ++r) {
         if (tile_of[r] < 0) continue;
@@ -608,30 +621,38 @@ __global__ __launch_bounds__(PGF_NT) void k_pgram_fields(const float *__restrict
 // that FP32 (or split-BF16) rounding of the products and their accumulation
 // would show: the pair product of two FP32 fields is exact in FP64, and so
 // are the products with the column fields up to FP64 rounding.  64 columns
-// (columns >= nb are zero).  Block (c, map, g) contracts the points
-// [c chunk, (c+1) chunk) for the 32-row pair tile g WAVES + w of wave w.
+// (fields col0 .. col0 + 63 of one column group; columns at or beyond nb are
+// zero).  Block (c, map, g) contracts the points [c chunk, (c+1) chunk) for
+// the 32-row pair tile g WAVES + w of wave w.
 // Each step stages PGF64_TK points of every field in LDS; one K step (4
 // points) is 8 MFMAs 16x16x4: row halves (lanes l % 16 and 16 + l % 16) times
 // the four 16-column quarters.  Lane layout (checked on the device): lane l
 // feeds A[l % 16][l / 16] and B[l / 16][l % 16], and holds
 // C[4 r + l / 16][l % 16] in accumulator register r.  Partials
-// [batch][nblk][n_mtile][32][64] FP64, as the split kernel writes them.
+// [batch][nblk][tiles_total][32][64] FP64 (this launch: tiles tile0 ..
+// tile0 + n_mtile - 1), as the split kernel writes them.
 constexpr int PGF64_NT = 256, PGF64_TK = 128;
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
+template <int ZR>
 __global__ __launch_bounds__(PGF64_NT) void k_pgram_fields_f64(const float *__restrict__ fields, int64_t npix,
                                                                int nb, int64_t map_stride,
                                                                const uchar2 *__restrict__ pairs, int n_mtile,
-                                                               int64_t chunk, double *__restrict__ partial) {
+                                                               int col0, int tile0, int tiles_total, int64_t chunk,
+                                                               double *__restrict__ partial) {
     constexpr int TK = PGF64_TK, FS = TK + 4, WAVES = PGF64_NT / 64;
-    __shared__ __attribute__((aligned(16))) float Ft[(PGF_ROW_ZERO + 1) * FS];
+    __shared__ __attribute__((aligned(16))) float Ft[(ZR + 1) * FS];
     const int tid = threadIdx.x, lane = tid & 63, r16 = lane & 15, kq = lane >> 4;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int map = blockIdx.y;
-    for (int i = tid; i < (PGF_ROW_ZERO + 1 - nb) * FS; i += PGF64_NT) Ft[nb * FS + i] = 0.0f;
+    for (int i = tid; i < (ZR + 1 - nb) * FS; i += PGF64_NT) Ft[nb * FS + i] = 0.0f;
     const int tile = blockIdx.z * WAVES + wave;
     const bool live = tile < n_mtile;
-    const uchar2 zero = uchar2{PGF_ROW_ZERO, PGF_ROW_ZERO};
+    const uchar2 zero = uchar2{ZR, ZR};
+    // column c of quarter q reads field row col0 + 16 q + c (the zero row past nb)
+    int brow[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) brow[q] = col0 + 16 * q + r16 < nb ? col0 + 16 * q + r16 : ZR;
     const uchar2 rp0 = live ? pairs[tile * 32 + r16] : zero;
     const uchar2 rp1 = live ? pairs[tile * 32 + 16 + r16] : zero;
     f64x4 c[2][4];
@@ -642,8 +663,8 @@ __global__ __launch_bounds__(PGF64_NT) void k_pgram_fields_f64(const float *__re
     const float *f = fields + (int64_t)map * map_stride;
     const int64_t p0 = (int64_t)blockIdx.x * chunk;
     const int64_t p1 = p0 + chunk < npix ? p0 + chunk : npix;
-    constexpr int LPT = 64 * (TK / 4) / PGF64_NT;   // float4 per thread at 64 bins
-    static_assert(64 * (TK / 4) % PGF64_NT == 0, "field loads must divide the block");
+    constexpr int LPT = ZR * (TK / 4) / PGF64_NT;   // float4 per thread at ZR bins
+    static_assert(ZR * (TK / 4) % PGF64_NT == 0, "field loads must divide the block");
     for (int64_t p = p0; p < p1; p += TK) {
         float4 v[LPT];
 #pragma unroll
@@ -672,14 +693,15 @@ __global__ __launch_bounds__(PGF64_NT) void k_pgram_fields_f64(const float *__re
             const double a1 = (double)Ft[rp1.x * FS + k] * (double)Ft[rp1.y * FS + k];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const double b = (double)Ft[(16 * q + r16) * FS + k];
+                const double b = (double)Ft[brow[q] * FS + k];
                 c[0][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b, c[0][q], 0, 0, 0);
                 c[1][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b, c[1][q], 0, 0, 0);
             }
         }
     }
     if (!live) return;
-    double *base = partial + ((int64_t)map * gridDim.x + blockIdx.x) * ((int64_t)n_mtile * 2048) + tile * 2048;
+    double *base = partial + ((int64_t)map * gridDim.x + blockIdx.x) * ((int64_t)tiles_total * 2048) +
+                   (int64_t)(tile0 + tile) * 2048;
 #pragma unroll
     for (int h = 0; h < 2; ++h)
 #pragma unroll
@@ -849,25 +871,43 @@ hipError_t launch_tail(int mode, bool want_t, const float2 *bc, const TailPairs 
 
 int pgram_fields_kparts(int n_mtile, bool squares) { return squares ? PGF_NT / 64 / n_mtile : 1; }
 
+int pgf_sq_tiles(int nb) {
+    const int t = (nb + 31) / 32;
+    return t <= 2 ? t : 4;
+}
+
 int64_t pgram_fields_chunk(int64_t npix, int nblk) {
     const int64_t c = (npix + nblk - 1) / nblk;
     return (c + PGF_TK - 1) / PGF_TK * PGF_TK;
 }
 
 hipError_t launch_pgram_fields(const float *fields, int64_t npix, int nb, int batch, const uchar2 *pairs, int n_mtile,
-                               int nblk, double *partial, hipStream_t st, bool squares) {
-    if (nb < 1 || nb > 64 || n_mtile < 1 || nblk < 1 || batch < 1) return hipErrorInvalidValue;
-    if (squares ? (nb > 63 || n_mtile != (nb + 31) / 32 || (PGF_NT / 64) % n_mtile != 0) : !pairs)
+                               int col0, int tile0, int tiles_total, int nblk, double *partial, hipStream_t st,
+                               bool squares) {
+    if (nb < 1 || nb > PGF_MAX_BINS || n_mtile < 1 || nblk < 1 || batch < 1) return hipErrorInvalidValue;
+    if (col0 < 0 || col0 % 64 != 0 || col0 >= nb || tile0 < 0 || tile0 + n_mtile > tiles_total)
         return hipErrorInvalidValue;
+    if (squares ? (n_mtile != pgf_sq_tiles(nb) || (PGF_NT / 64) % n_mtile != 0) : !pairs) return hipErrorInvalidValue;
     const int64_t chunk = pgram_fields_chunk(npix, nblk);
     if (npix % PGF_TK != 0 || chunk > PGF_MAX_CHUNK) return hipErrorInvalidValue;
-    const unsigned groups = squares ? 1u : (unsigned)((n_mtile + PGF_TILES - 1) / PGF_TILES);
-    if (squares)
-        hipLaunchKernelGGL(k_pgram_fields<true>, dim3(nblk, batch, groups), dim3(PGF_NT), 0, st, fields, npix, nb,
-                           (int64_t)nb * npix, pairs, n_mtile, chunk, partial);
-    else
-        hipLaunchKernelGGL(k_pgram_fields<false>, dim3(nblk, batch, groups), dim3(PGF_NT), 0, st, fields, npix, nb,
-                           (int64_t)nb * npix, pairs, n_mtile, chunk, partial);
+    const int per = pgf_tiles(pgf_row_zero(nb));
+    const unsigned groups = squares ? 1u : (unsigned)((n_mtile + per - 1) / per);
+    const int64_t ms = (int64_t)nb * npix;
+    if (nb <= PGF_ROW_ZERO) {
+        if (squares)
+            hipLaunchKernelGGL((k_pgram_fields<true, PGF_ROW_ZERO>), dim3(nblk, batch, groups), dim3(PGF_NT), 0, st,
+                               fields, npix, nb, ms, pairs, n_mtile, col0, tile0, tiles_total, chunk, partial);
+        else
+            hipLaunchKernelGGL((k_pgram_fields<false, PGF_ROW_ZERO>), dim3(nblk, batch, groups), dim3(PGF_NT), 0, st,
+                               fields, npix, nb, ms, pairs, n_mtile, col0, tile0, tiles_total, chunk, partial);
+    } else {
+        if (squares)
+            hipLaunchKernelGGL((k_pgram_fields<true, PGF_ROW_ZERO_XL>), dim3(nblk, batch, groups), dim3(PGF_NT), 0,
+                               st, fields, npix, nb, ms, pairs, n_mtile, col0, tile0, tiles_total, chunk, partial);
+        else
+            hipLaunchKernelGGL((k_pgram_fields<false, PGF_ROW_ZERO_XL>), dim3(nblk, batch, groups), dim3(PGF_NT), 0,
+                               st, fields, npix, nb, ms, pairs, n_mtile, col0, tile0, tiles_total, chunk, partial);
+    }
     return hipGetLastError();
 }
 
@@ -915,13 +955,21 @@ hipError_t launch_scatter_alt(const double *alt, int64_t alt_stride, const int *
 }
 
 hipError_t launch_pgram_fields_f64(const float *fields, int64_t npix, int nb, int batch, const uchar2 *pairs,
-                                   int n_mtile, int nblk, double *partial, hipStream_t st) {
-    if (nb < 1 || nb > 64 || n_mtile < 1 || nblk < 1 || batch < 1 || !pairs) return hipErrorInvalidValue;
+                                   int n_mtile, int col0, int tile0, int tiles_total, int nblk, double *partial,
+                                   hipStream_t st) {
+    if (nb < 1 || nb > PGF_MAX_BINS || n_mtile < 1 || nblk < 1 || batch < 1 || !pairs) return hipErrorInvalidValue;
+    if (col0 < 0 || col0 % 64 != 0 || col0 >= nb || tile0 < 0 || tile0 + n_mtile > tiles_total)
+        return hipErrorInvalidValue;
     const int64_t chunk = pgram_fields_chunk(npix, nblk);
     if (npix % PGF64_TK != 0 || chunk % PGF64_TK != 0) return hipErrorInvalidValue;
     const unsigned groups = (unsigned)((n_mtile + PGF64_NT / 64 - 1) / (PGF64_NT / 64));
-    hipLaunchKernelGGL(k_pgram_fields_f64, dim3(nblk, batch, groups), dim3(PGF64_NT), 0, st, fields, npix, nb,
-                       (int64_t)nb * npix, pairs, n_mtile, chunk, partial);
+    const int64_t ms = (int64_t)nb * npix;
+    if (nb <= PGF_ROW_ZERO)
+        hipLaunchKernelGGL(k_pgram_fields_f64<PGF_ROW_ZERO>, dim3(nblk, batch, groups), dim3(PGF64_NT), 0, st, fields,
+                           npix, nb, ms, pairs, n_mtile, col0, tile0, tiles_total, chunk, partial);
+    else
+        hipLaunchKernelGGL(k_pgram_fields_f64<PGF_ROW_ZERO_XL>, dim3(nblk, batch, groups), dim3(PGF64_NT), 0, st,
+                           fields, npix, nb, ms, pairs, n_mtile, col0, tile0, tiles_total, chunk, partial);
     return hipGetLastError();
 }
 

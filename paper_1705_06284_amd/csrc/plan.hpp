@@ -47,12 +47,22 @@ struct bispec_plan_s {
     int nblk = 1;                        // blocks of the term contraction
     std::vector<uchar4> terms;           // [triplets | (b,b) | quads]
     std::vector<double> scale;           // normalisation over the FFT count, per term
+    // The spectrum is computed from (delta - mean) 2^-spec_shift, with
+    // spec_shift = floor(log2 N_pix), so that bin fields are of the order of
+    // the map's r.m.s. and products of four of them stay inside the FP32
+    // range at any grid size (at 512^3, F^4 of a high shell reaches 1e39
+    // unscaled).  A power of two scales exactly; the per-term normalisation
+    // carries 2^(p spec_shift) back in FP64.
+    int spec_shift = 0;
     // product-Gram (MFMA) contraction
     bool mfma_ok = false;                // n_bins <= 32
     bool quads_collapsed = false;        // every quad is (a,a,b,b) up to order
-    bool pg_wide = false;                // 33..64 bins: product-Gram over the fields in HBM
+    bool pg_wide = false;                // 33..128 bins, general grids: product-Gram over the fields in HBM
     int nblk_wide = 1;                   // blocks per map of that product-Gram
-    int pg_sq_tiles = 0;                 // row tiles of its squares pass (P, collapsed T)
+    int n_cgroup = 1;                    // its groups of 64 columns
+    std::vector<int> pg_gtile;           // first row tile of each column group, and the total
+    int pg_sq_tiles = 0;                 // row tiles per group of its squares pass (P, collapsed T)
+    bool pg_sq_ok = false;               // the squares pass has a ones column (nb not a multiple of 64)
     int n_mtile = 0;                     // 32-row tiles of pair rows
     int nblk_pg = 1;                     // blocks of the product-Gram kernel (tuned)
     int nblk_pg_min = 1;                 // fewest blocks (chunk span limit)
@@ -66,6 +76,7 @@ struct bispec_plan_s {
     std::vector<unsigned char> refine;   // per triplet: 1 = read from the refinement tiles
     std::vector<int> refine_t;           // the indices of those triplets
     std::vector<uchar2> pg_pairs_r;      // [n_mtile_r*32] row factors of those rows
+    std::vector<int> pg_gtile_r;         // first refinement tile of each column group, and the total
     int n_mtile_r = 0;                   // 32-row tiles of refinement rows (0: none)
     int nblk_r = 1;                      // blocks per map of the refinement pass
     // stage timing: one event per stage boundary per call
@@ -100,7 +111,7 @@ struct Layout {
 };
 
 // Triplets with a condition number sqrt(M_i M_j M_k / (N_pix N_t)) above
-// this run on the FP32-mode refinement rows (split-BF16 rounding, about
+// this run on the FP64 refinement rows (split-BF16 rounding, about
 // 1.5e-5 kappa relative to the noise level, would pass 1e-4 beyond it).
 constexpr double kRefineKappa = 4.0;
 

@@ -322,3 +322,50 @@ def test_power_spectrum_parseval_and_pair_sum():
             s += Dg[v[0] % n, v[1] % n, v[2] % n] * Dg[w[0], w[1], w[2]]
         assert np.isclose(s.real / M[b] / n ** 3, P[b], rtol=1e-12)
     assert mask.dtype == np.uint64
+
+
+def test_more_than_64_bins_match_per_triplet_bruteforce():
+    """Plans beyond 64 bins: the direct sums take a bin-mask table per group
+    of closing bins.  96 narrow bins on 8^3 (one per sixteenth of k_f between
+    1 and 7, most of them empty); 40 closed and 10 open triplets whose bins
+    include one above 64, checked against an enumeration of their mode
+    triples."""
+    rng = np.random.default_rng(11)
+    n = 8
+    d = rng.standard_normal((n, n, n)).astype(np.float32)
+    edges = 1.0 + np.arange(97) / 16.0
+    lo, hi = edges[:-1], edges[1:]
+    D = np.fft.fftn(oracle.prepare(d))
+    m = _grid_modes(n, hi[-1])
+    mem = _membership(m, lo, hi)
+    occupied = [b for b in range(len(lo)) if mem[:, b].any()]
+    assert max(occupied) > 64
+
+    def brute(i, j, k):
+        a, b = m[mem[:, i]], m[mem[:, j]]
+        u = _wrap(-(a[:, None, :] + b[None, :, :]), n).reshape(-1, 3)
+        r2 = np.sum(u * u, axis=1).astype(np.float64)
+        inside = (r2 > 0) & (r2 >= lo[k] ** 2) & (r2 < hi[k] ** 2)
+        prod = (D[a[:, 0] % n, a[:, 1] % n, a[:, 2] % n][:, None]
+                * D[b[:, 0] % n, b[:, 1] % n, b[:, 2] % n][None, :]).ravel()
+        prod = prod * D[u[:, 0] % n, u[:, 1] % n, u[:, 2] % n]
+        return int(inside.sum()), prod[inside].sum(), np.abs(prod[inside]).sum()
+
+    closed, open_, ref = [], [], {}
+    for t in itertools.combinations_with_replacement(occupied, 3):
+        if t[2] <= 64 or (t[0] + 7 * t[1] + 13 * t[2]) % 3:
+            continue
+        c = brute(*t)
+        if c[0] > 0 and len(closed) < 40:
+            closed.append(t)
+            ref[t] = c
+        elif c[0] == 0 and len(open_) < 10:
+            open_.append(t)
+            ref[t] = c
+    assert len(closed) == 40 and len(open_) == 10
+    trip = closed + open_
+    res = oracle.bispectrum(d, lo, hi, trip)
+    for t, key in enumerate(trip):
+        cnt, s, mag = ref[key]
+        assert res.count[t] == cnt, key
+        assert abs(res.s[t] - s) <= 1e-12 * max(1.0, mag), key
