@@ -35,4 +35,6 @@ from .polyspec import (  # noqa: F401
     squared_edges,
     triangle_counts,
     trispectrum,
+    trispectrum_diag,
+    trispectrum_diag_connected,
 )

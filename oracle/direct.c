@@ -142,6 +142,64 @@ int orc_pair_sums(int nz, int ny, int nx, int sz, int sy, int sx, const double *
     return 0;
 }
 
+/* p = 4 with the diagonal fixed: ordered triples (m1 in A, m2 in B, m3 in C)
+ * closed by m4 = -(m1+m2+m3) mod N whose diagonal q = m1 + m2, reduced
+ * mod N, has (sz qz)^2 + (sy qy)^2 + (sx qx)^2 in [dlo2, dhi2) and is not 0
+ * (the diagonal-binned trispectrum; Section 2, Eq. Jeong_gen with p = 4 and
+ * the two-vector diagonal that four shells leave free). */
+int orc_triple_sums_diag(int nz, int ny, int nx, int sz, int sy, int sx, const double *re, const double *im,
+                         int na, const int32_t *ma, int nb_modes, const int32_t *mb,
+                         int nc, const int32_t *mc,
+                         const uint64_t *mask, int64_t mask_len, uint64_t want,
+                         double dlo2, double dhi2, int n_bins, double *out) {
+    if (nz <= 0 || ny <= 0 || nx <= 0 || n_bins <= 0 || n_bins > 64) return -1;
+    const grid_t G = {nz, ny, nx, sz, sy, sx};
+    const grid_t *g = &G;
+    int nt = threads_for((double)na * nb_modes * nc);
+    double *part = (double *)calloc((size_t)nt * n_bins * ORC_NACC, sizeof(double));
+    if (!part) return -2;
+#pragma omp parallel num_threads(nt)
+    {
+        double *acc = part + (size_t)omp_get_thread_num() * n_bins * ORC_NACC;
+#pragma omp for schedule(static)
+        for (int a = 0; a < na; ++a) {
+            int z1 = ma[3 * a], y1 = ma[3 * a + 1], x1 = ma[3 * a + 2];
+            double r1, i1;
+            amp(re, im, grid_index(z1, y1, x1, g), &r1, &i1);
+            for (int b = 0; b < nb_modes; ++b) {
+                int z2 = mb[3 * b], y2 = mb[3 * b + 1], x2 = mb[3 * b + 2];
+                const double dq = (double)grid_q(wrap_c(z1 + z2, nz), wrap_c(y1 + y2, ny), wrap_c(x1 + x2, nx), g);
+                if (dq <= 0.0 || dq < dlo2 || dq >= dhi2) continue;
+                double r2a, i2a;
+                amp(re, im, grid_index(z2, y2, x2, g), &r2a, &i2a);
+                double pr = r1 * r2a - i1 * i2a;
+                double pi = r1 * i2a + i1 * r2a;
+                for (int c = 0; c < nc; ++c) {
+                    int z3 = mc[3 * c], y3 = mc[3 * c + 1], x3 = mc[3 * c + 2];
+                    int uz = -(z1 + z2 + z3), uy = -(y1 + y2 + y3), ux = -(x1 + x2 + x3);
+                    int z4 = wrap_c(uz, nz), y4 = wrap_c(uy, ny), x4 = wrap_c(ux, nx);
+                    int64_t q = grid_q(z4, y4, x4, g);
+                    if (q >= mask_len) continue;
+                    uint64_t bits = mask[q] & want;
+                    if (!bits) continue;
+                    int strict = (z4 == uz) && (y4 == uy) && (x4 == ux);
+                    double r3a, i3a, r4a, i4a;
+                    amp(re, im, grid_index(z3, y3, x3, g), &r3a, &i3a);
+                    amp(re, im, grid_index(z4, y4, x4, g), &r4a, &i4a);
+                    double qr = pr * r3a - pi * i3a;
+                    double qi = pr * i3a + pi * r3a;
+                    double sr = qr * r4a - qi * i4a;
+                    double si = qr * i4a + qi * r4a;
+                    accumulate(acc, bits, sr, si, strict);
+                }
+            }
+        }
+    }
+    merge(out, part, nt, n_bins);
+    free(part);
+    return 0;
+}
+
 /* p = 4: ordered triples (m1 in A, m2 in B, m3 in C) closed by
  * m4 = -(m1+m2+m3) mod N. */
 int orc_triple_sums(int nz, int ny, int nx, int sz, int sy, int sx, const double *re, const double *im,

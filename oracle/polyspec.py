@@ -73,6 +73,10 @@ def _load():
                                               ctypes.c_int, ip, up, ctypes.c_int64, ctypes.c_uint64,
                                               ctypes.c_int, dp]
         lib.orc_triple_sums.restype = ctypes.c_int
+        lib.orc_triple_sums_diag.argtypes = six + [dp, dp, ctypes.c_int, ip, ctypes.c_int, ip,
+                                                   ctypes.c_int, ip, up, ctypes.c_int64, ctypes.c_uint64,
+                                                   ctypes.c_double, ctypes.c_double, ctypes.c_int, dp]
+        lib.orc_triple_sums_diag.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -438,6 +442,122 @@ def trispectrum_connected(delta, k_lo, k_hi, quads, box_len=None, delta_k=None):
     sd = disconnected_sums(d, k_lo, k_hi, quads, delta_k=delta_k)
     vol = _volume(n, box_len)
     npix = float(n) ** 3
+    with np.errstate(invalid="ignore", divide="ignore"):
+        val = vol ** 3 / npix ** 4 * (full.s - sd).real / full.count
+    return val, full, sd
+
+
+# ----------------------------------------------------------------------------
+# Diagonal-binned trispectrum
+# ----------------------------------------------------------------------------
+#
+# Four shells leave the quadrilateral k1 + k2 + k3 + k4 = 0 free to fold
+# along its diagonal q = k1 + k2 = -(k3 + k4); binning |q| as well fixes the
+# shape (Section 2, Eq. Jeong_gen with p = 4).  For a diagonal quad
+# (a, b, c, d, e) the sum runs over closed quadruples (modulo N) with k1 in
+# S_a, k2 in S_b, k3 in S_c, k4 in S_d and the reduced q in shell e (q = 0,
+# the pairing k2 = -k1, is in no shell).
+
+def _diag_order(counts, a, b, c, d):
+    """A slot order with the same sum: the pair (k1, k2) may swap with
+    (k3, k4) and each pair within itself; loop over the pair with fewer mode
+    combinations, then the smaller shell of the other, and close the last."""
+    if counts[c] * counts[d] < counts[a] * counts[b]:
+        a, b, c, d = c, d, a, b
+    if counts[d] < counts[c]:
+        c, d = d, c
+    return a, b, c, d
+
+
+def trispectrum_diag(delta, k_lo, k_hi, dquads, box_len=None, delta_k=None) -> Spectrum:
+    """Direct-sum diagonal-binned p = 4 polyspectrum for each (a, b, c, d, e):
+    (V^3 / N_pix^4) S / N_q over the closed quadruples whose diagonal
+    k1 + k2 lies in shell e."""
+    d = prepare(delta)
+    n = d.shape
+    if delta_k is None:
+        delta_k = dft3(d)
+    dq = np.asarray(dquads, dtype=np.int64).reshape(-1, 5)
+    lo2, hi2 = squared_edges(k_lo, k_hi, n)
+    counts = mode_counts(n, k_lo, k_hi)
+    modes = {}
+
+    def sh(b):
+        if b not in modes:
+            modes[b] = shell_modes(n, k_lo, k_hi, b)
+        return modes[b]
+
+    re, im = _grid_parts(delta_k)
+    acc = np.zeros((len(dq), _NACC))
+    lib = _load()
+    for t, (a, b, c, dd, e) in enumerate(dq):
+        a, b, c, dd = _diag_order(counts, int(a), int(b), int(c), int(dd))
+        mask = bin_mask_table(n, k_lo, k_hi, [dd])
+        out = np.zeros((1, _NACC), dtype=np.float64)
+        ma, mb, mc = sh(a), sh(b), sh(c)
+        rc = lib.orc_triple_sums_diag(*grid_shape(n), *q_scales(n), _ptr(re, ctypes.c_double),
+                                      _ptr(im, ctypes.c_double), len(ma), _ptr(ma, ctypes.c_int32),
+                                      len(mb), _ptr(mb, ctypes.c_int32), len(mc), _ptr(mc, ctypes.c_int32),
+                                      _ptr(mask, ctypes.c_uint64), len(mask), ctypes.c_uint64(1),
+                                      float(lo2[e]), float(hi2[e]), 1, _ptr(out, ctypes.c_double))
+        assert rc == 0, rc
+        acc[t] = out[0]
+    vol = _volume(n, box_len)
+    npix = float(np.prod(n))
+    return _finish(acc, vol ** 3 / npix ** 4)
+
+
+def diag_disconnected_sums(delta, k_lo, k_hi, dquads, delta_k=None):
+    """S_D per diagonal quad (a, b, c, d, e): the sum of D(k1) D(k2) D(k3) D(k4)
+    over the closed quadruples of the diagonal sum that split into two pairs
+    k_i = -k_j (Wick's pairings; k2 = -k1 has q = 0 and never enters), each
+    quadruple counted once: the pairings k3 = -k1, k4 = -k2 and k4 = -k1,
+    k3 = -k2 written out mode by mode as a set of quadruples."""
+    d = prepare(delta)
+    n = d.shape
+    if delta_k is None:
+        delta_k = dft3(d)
+    lo2, hi2 = squared_edges(k_lo, k_hi, n)
+    sc = q_scales(n)
+
+    def wrap(m):
+        return tuple(int(((m[i] + n[i] // 2) % n[i]) - n[i] // 2) if n[i] % 2 == 0
+                     else int(((m[i] + (n[i] - 1) // 2) % n[i]) - (n[i] - 1) // 2) for i in range(3))
+
+    def neg(m):
+        return wrap((-m[0], -m[1], -m[2]))
+
+    out = np.zeros(len(np.asarray(dquads).reshape(-1, 5)), dtype=np.complex128)
+    for t, (a, b, c, dd, e) in enumerate(np.asarray(dquads, dtype=np.int64).reshape(-1, 5)):
+        sets = [{tuple(int(x) for x in m) for m in shell_modes(n, k_lo, k_hi, int(x))} for x in (a, b, c, dd)]
+        sa, sb, scs, sd = sets
+        quadset = set()
+        for k1 in sa:
+            for k2 in sb:
+                q = wrap((k1[0] + k2[0], k1[1] + k2[1], k1[2] + k2[2]))
+                qq = float(_q_of(q[0], q[1], q[2], sc))
+                if qq <= 0 or qq < lo2[e] or qq >= hi2[e]:
+                    continue
+                if neg(k1) in scs and neg(k2) in sd:
+                    quadset.add((k1, k2, neg(k1), neg(k2)))       # k3 = -k1, k4 = -k2
+                if neg(k2) in scs and neg(k1) in sd:
+                    quadset.add((k1, k2, neg(k2), neg(k1)))       # k3 = -k2, k4 = -k1
+        amp = lambda m: delta_k[m[0] % n[0], m[1] % n[1], m[2] % n[2]]
+        out[t] = sum(amp(x[0]) * amp(x[1]) * amp(x[2]) * amp(x[3]) for x in quadset)
+    return out
+
+
+def trispectrum_diag_connected(delta, k_lo, k_hi, dquads, box_len=None, delta_k=None):
+    """Diagonal-binned T with the Gaussian pairings removed: (V^3 / N_pix^4)
+    Re(S - S_D) / N_q (diag_disconnected_sums).  Returns (value, raw
+    Spectrum, S_D)."""
+    d = prepare(delta)
+    if delta_k is None:
+        delta_k = dft3(d)
+    full = trispectrum_diag(d, k_lo, k_hi, dquads, box_len=box_len, delta_k=delta_k)
+    sd = diag_disconnected_sums(d, k_lo, k_hi, dquads, delta_k=delta_k)
+    vol = _volume(d.shape, box_len)
+    npix = float(np.prod(d.shape))
     with np.errstate(invalid="ignore", divide="ignore"):
         val = vol ** 3 / npix ** 4 * (full.s - sd).real / full.count
     return val, full, sd
