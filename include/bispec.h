@@ -119,6 +119,9 @@ typedef struct {
     void *stream;          /* hipStream_t for all work of this plan (NULL = default) */
     int32_t n_y;           /* N_y; 0 = n_side                                         */
     int32_t n_x;           /* N_x; 0 = n_side (edges: 0 <= k_lo < k_hi <= N_x / 2)    */
+    int32_t n_dquad;       /* diagonal-binned p = 4 configurations (0: none)          */
+    const int32_t *dquad;  /* [n_dquad][5] bin indices a, b, c, d, e (e: the shell of
+                              the diagonal k1 + k2); NULL when n_dquad = 0           */
 } bispec_plan_desc;
 
 /* Build a plan: validate the descriptor, tabulate the shells, evaluate the
@@ -178,11 +181,13 @@ bispec_status bispec_estimate(bispec_plan_t plan, const float *delta, int32_t ba
 bispec_status trispec_estimate(bispec_plan_t plan, const float *delta, int32_t batch,
                                double *T);
 
-/* Connected collapsed trispectrum (cubic power-of-two grids;
- * BISPEC_E_UNSUPPORTED_N on other grids): the raw T of Eq. Jeong_gen (p = 4) for
- * every quad (a,a,b,b), and Tc, the same estimate with the quadruples that
- * split into two pairs k_i = -k_j removed -- the Gaussian (disconnected)
- * pairings of Wick's theorem, measured on the map itself:
+/* Connected trispectrum (cubic power-of-two grids; BISPEC_E_UNSUPPORTED_N
+ * on other grids): the raw T of Eq. Jeong_gen (p = 4) for every planned quad,
+ * and Tc, the same estimate with the quadruples that split into two pairs
+ * k_i = -k_j removed -- the Gaussian (disconnected) pairings of Wick's
+ * theorem, measured on the map itself.  With the shells of each quad
+ * identical or disjoint only a collapsed quad (a,a,b,b) has such quadruples,
+ * so for any other quad Tc = T; for (a,a,b,b)
  *     Tc = T - V^3 / N_pix^4 * S_D / N_q,
  *     S_D = X_a X_b              (a != b, disjoint shells)
  *     S_D = 3 X_a^2 - 3 Y_a      (a = b; inclusion-exclusion over the three
@@ -192,11 +197,38 @@ bispec_status trispec_estimate(bispec_plan_t plan, const float *delta, int32_t b
  * over the FP32 spectrum.  For a Gaussian field Tc has zero mean.  The paper
  * names the trispectrum but evaluates none (Section 2); this removal of the
  * disconnected part is a reading of "connected".
- * T, Tc: device [batch][n_quad] FP64.  BISPEC_E_INVALID if a quad is not
- * collapsed, if the two shells of a quad (a,a,b,b), a != b, overlap, or for
- * NULL pointers. */
+ * T, Tc: device [batch][n_quad] FP64.  BISPEC_E_INVALID if two different
+ * shells of a quad overlap, or for NULL pointers. */
 bispec_status trispec_connected_estimate(bispec_plan_t plan, const float *delta, int32_t batch,
                                          double *T, double *Tc);
+
+/* Diagonal-binned trispectrum (Section 2, Eq. Jeong_gen with p = 4: four
+ * shells leave the quadrilateral k1 + k2 + k3 + k4 = 0 free to fold along its
+ * diagonal q = k1 + k2; binning |q| fixes it).  For each planned
+ * configuration (a, b, c, d, e) (bispec_plan_desc.dquad):
+ *     Td = V^3 / N_pix^4 * S / N_q(e),
+ *     S  = sum over closed quadruples (mod N) with k1..k4 in S_a..S_d and
+ *          k1 + k2, reduced mod N, in S_e of Delta(k1) Delta(k2) Delta(k3) Delta(k4),
+ * evaluated as N_pix^-2 sum_{q in S_e} Pi_ab(q) conj(Pi_cd(q)), Pi_ab the
+ * FP32 DFT of the pair-product field F_a F_b (mixed-radix transforms on any
+ * grid); N_q(e) from the FP64 unit fields at plan time (exact integers,
+ * bispec_plan_query_dquads).  Tdc (may be NULL): Td with the Gaussian
+ * pairings removed -- k3 = -k1, k4 = -k2 (a = c, b = d) and k4 = -k1,
+ * k3 = -k2 (a = d, b = c), sharing (k, k, -k, -k) when all four shells are
+ * one (k2 = -k1 has q = 0, in no shell):
+ *     Tdc = Td - V^3 / N_pix^4 * (c2 S2(a,b;e) - c4 S4(a;e)) / N_q(e),
+ *     S2 = sum_{k1 in S_a, k2 in S_b, k1 + k2 in S_e} |D(k1)|^2 |D(k2)|^2,
+ *     S4 = sum_{k in S_a, 2k in S_e} |D(k)|^4,
+ * c2 the number of the two pairings that apply, c4 = 1 if a = b = c = d.
+ * The paper defines no diagonal binning; this is a reading of its "and
+ * beyond" for p = 4.  Maps run one at a time.  Td, Tdc: device
+ * [batch][n_dquad] FP64.  BISPEC_E_INVALID if the plan has no dquads, if Tdc
+ * is requested and two different shells of a configuration overlap, or for
+ * NULL pointers. */
+bispec_status trispec_diag_estimate(bispec_plan_t plan, const float *delta, int32_t batch,
+                                    double *Td, double *Tdc);
+/* n_dquad and the counts N_q(e) (exact integers as double; either may be NULL). */
+bispec_status bispec_plan_query_dquads(bispec_plan_t plan, int32_t *n_dquad, double *counts_out);
 
 /* P, B and T from one set of bin fields (lower orders at no extra FFT cost,
  * Section 2 after Eq. Jeong_BI).  Any of P, B, T may be NULL. */

@@ -40,7 +40,8 @@ class PlanDesc(ctypes.Structure):
                 ("n_tri", ctypes.c_int32), ("tri", ctypes.POINTER(ctypes.c_int32)),
                 ("n_quad", ctypes.c_int32), ("quad", ctypes.POINTER(ctypes.c_int32)),
                 ("precision", ctypes.c_int32), ("max_batch", ctypes.c_int32), ("stream", ctypes.c_void_p),
-                ("n_y", ctypes.c_int32), ("n_x", ctypes.c_int32)]
+                ("n_y", ctypes.c_int32), ("n_x", ctypes.c_int32),
+                ("n_dquad", ctypes.c_int32), ("dquad", ctypes.POINTER(ctypes.c_int32))]
 
 
 _vp = ctypes.c_void_p
@@ -60,6 +61,8 @@ _SIGS = {
     "bispec_estimate": [_vp, _vp, _i32, _vp, _vp],
     "trispec_estimate": [_vp, _vp, _i32, _vp],
     "trispec_connected_estimate": [_vp, _vp, _i32, _vp, _vp],
+    "trispec_diag_estimate": [_vp, _vp, _i32, _vp, _vp],
+    "bispec_plan_query_dquads": [_vp, _ip, _dp],
     "polyspec_estimate": [_vp, _vp, _i32, _vp, _vp, _vp],
     "polyspec_estimate_noalloc": [_vp, _vp, _i32, _vp, _vp, _vp],
     "bispec_timing_enable": [_vp, _i32],
@@ -94,6 +97,8 @@ bispec_bin_fields = _lib.bispec_bin_fields
 bispec_estimate = _lib.bispec_estimate
 trispec_estimate = _lib.trispec_estimate
 trispec_connected_estimate = _lib.trispec_connected_estimate
+trispec_diag_estimate = _lib.trispec_diag_estimate
+bispec_plan_query_dquads = _lib.bispec_plan_query_dquads
 polyspec_estimate = _lib.polyspec_estimate
 polyspec_estimate_noalloc = _lib.polyspec_estimate_noalloc
 bispec_timing_enable = _lib.bispec_timing_enable
@@ -144,11 +149,12 @@ class Plan:
     n: the side N of a cubic grid, or its shape (N_z, N_y, N_x); k_lo, k_hi:
     shell edges in units of k_f (of the x axis); triplets: [n, 3] bin indices
     or None for every closed triplet; quads: [n, 4] or None for every
-    (a,a,b,b).
+    (a,a,b,b); dquads: [n, 5] diagonal-binned configurations (a, b, c, d, e)
+    or None.
     """
 
     def __init__(self, n, k_lo, k_hi, triplets=None, quads=None, box_len=None,
-                 precision="split_bf16", max_batch=1, stream=None, device="cuda"):
+                 precision="split_bf16", max_batch=1, stream=None, device="cuda", dquads=None):
         import torch
         self._torch = torch
         self.device = torch.device(device)
@@ -168,6 +174,7 @@ class Plan:
             raise ValueError("k_lo and k_hi differ in length")
         tri = None if triplets is None else _arr(triplets, np.int32).reshape(-1, 3)
         qd = None if quads is None else _arr(quads, np.int32).reshape(-1, 4)
+        dq = None if dquads is None else _arr(dquads, np.int32).reshape(-1, 5)
         self.max_batch = int(max_batch)
         if stream is None:
             stream = torch.cuda.current_stream(self.device)
@@ -176,6 +183,8 @@ class Plan:
         d.n_side = shape[0]
         d.n_y = shape[1]
         d.n_x = shape[2]
+        d.n_dquad = 0 if dq is None else len(dq)
+        d.dquad = dq.ctypes.data_as(_ip) if dq is not None else ctypes.cast(None, _ip)
         d.box_len = -1.0 if box_len is None else float(box_len)
         d.n_bins = self.n_bins
         d.k_lo = self.k_lo.ctypes.data_as(_dp)
@@ -197,6 +206,9 @@ class Plan:
         nq = ctypes.c_int32()
         check(bispec_plan_query_quads(h, ctypes.byref(nq), None), "bispec_plan_query_quads")
         self.n_quad = nq.value
+        ndq = ctypes.c_int32()
+        check(bispec_plan_query_dquads(h, ctypes.byref(ndq), None), "bispec_plan_query_dquads")
+        self.n_dquad = ndq.value
         sz = ctypes.c_size_t()
         check(bispec_plan_footprint(h, self.max_batch, ctypes.byref(sz)), "bispec_plan_footprint")
         self.workspace_bytes = sz.value
@@ -204,6 +216,13 @@ class Plan:
         check(bispec_set_workspace(h, _ptr(self.workspace), self.workspace_bytes), "bispec_set_workspace")
 
     # -- queries ------------------------------------------------------------
+    @property
+    def dquad_counts(self):
+        """N_q(e) of every diagonal-binned configuration (exact integers)."""
+        out = np.zeros(self.n_dquad, np.float64)
+        check(bispec_plan_query_dquads(self.handle, None, out.ctypes.data_as(_dp)), "bispec_plan_query_dquads")
+        return out
+
     @property
     def triplets(self):
         out = np.zeros((self.n_tri, 3), np.int32)
@@ -393,6 +412,21 @@ class Plan:
         check(trispec_connected_estimate(self.handle, _ptr(d), bsz, _ptr(T), _ptr(Tc)), "trispec_connected_estimate")
         self._leave(d, T, Tc)
         return T, Tc
+
+    def trispec_diag(self, delta, connected=True):
+        """(Td, Tdc) as in trispec_diag_estimate: the diagonal-binned
+        trispectrum of every planned (a, b, c, d, e) and, with connected, the
+        same with the Gaussian pairings removed (else None); device tensors
+        [batch, n_dquad]."""
+        d = self._input(delta)
+        bsz = d.shape[0]
+        Td = self._empty(bsz, self.n_dquad)
+        Tdc = self._empty(bsz, self.n_dquad) if connected else None
+        self._enter()
+        check(trispec_diag_estimate(self.handle, _ptr(d), bsz, _ptr(Td), _ptr(Tdc) if connected else None),
+              "trispec_diag_estimate")
+        self._leave(d, Td, *([Tdc] if connected else []))
+        return Td, Tdc
 
     def bin_fields(self, delta):
         d = self._input(delta)

@@ -20,6 +20,7 @@
 #include <vector>
 
 #include "../../include/bispec.h"
+#include "diagtri.hpp"
 #include "general.hpp"
 #include "launch.hpp"
 #include "moments.hpp"
@@ -31,6 +32,7 @@ using namespace bispec;
 namespace {
 
 constexpr int kMeanParts = 1024;
+constexpr int kDtBlocks = 64;            // blocks per shell sum of the diagonal-binned pass
 constexpr size_t kAlign = 256;
 
 inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
@@ -143,6 +145,23 @@ Layout make_layout(const bispec_plan_s &p, int batch) {
     // bin fields in HBM: only the vector-ALU contraction and general quads read them
     L.fields = off;
     if (needs_fields(p)) off = align_up(off + sizeof(float) * vol * p.nb * batch);
+    // the diagonal-binned trispectrum pass, one map at a time: the full
+    // spectrum, a transform scratch, the fields of its shells, a product
+    // field and the spectra of the pair products
+    const size_t ndq = p.dquad.size() / 5;
+    const size_t np = ndq ? (size_t)p.npix : 0;
+    const size_t ndtw = ndq && !p.general ? (size_t)(p.gd.nz + p.gd.ny + p.gd.nx) : 0;
+    L.dtw = off;          off = align_up(off + sizeof(float2) * ndtw);
+    L.dspec = off;        off = align_up(off + sizeof(float2) * np);
+    L.dwork = off;        off = align_up(off + sizeof(float2) * np);
+    L.dfields = off;      off = align_up(off + sizeof(float) * np * p.dbins.size());
+    L.dtmp = off;         off = align_up(off + sizeof(float) * np);
+    L.dpspec = off;       off = align_up(off + sizeof(float2) * np * std::max(p.dpairs.size(), p.dupairs.size()));
+    L.didx = off;         off = align_up(off + sizeof(int) * p.didx.size());
+    L.dtask = off;        off = align_up(off + sizeof(DtTask) * 3 * ndq);
+    L.dpart = off;        off = align_up(off + sizeof(double) * 3 * ndq * kDtBlocks);
+    L.dsums = off;        off = align_up(off + sizeof(double) * 3 * ndq);
+    L.dcoef = off;        off = align_up(off + sizeof(double) * 3 * ndq);
     L.total = off;
     return L;
 }
@@ -589,6 +608,207 @@ GenPair gen_pair(const bispec_plan_s &p, int b) {
     return GenPair{p.qlo[b], p.qhi[b], two ? p.qlo[b + 1] : 0, two ? p.qhi[b + 1] : 0};
 }
 
+// Diagonal-binned p = 4 configurations: the grid as the mixed-radix passes
+// see it, the shells whose fields the pass builds (slots), the pair products,
+// the pairing coefficients of the connected part and the mode lists of the
+// diagonal shells (and of the shells whose |D|^4 sum the connected part
+// needs).
+bispec_status build_dquads(bispec_plan_s &p, const bispec_plan_desc *d) {
+    p.dquad.clear();
+    p.dbins.clear();
+    p.dpairs.clear();
+    p.dq_pp.clear();
+    p.dupairs.clear();
+    p.dq_up.clear();
+    p.didx.clear();
+    p.dseg.assign(p.nb, int2{0, 0});
+    p.dq_coef.clear();
+    const int ndq = d->n_dquad;
+    if (ndq == 0) return BISPEC_OK;
+    p.dquad.assign(d->dquad, d->dquad + 5 * ndq);
+    if (p.general) {
+        p.gd = p.gg;
+    } else {
+        GenGrid g{};
+        int off = 0;
+        for (int a = 0; a < 3; ++a) {
+            if (!gen_factor(p.n, g.ax[a])) return BISPEC_E_UNSUPPORTED_N;
+            g.ax[a].tw_off = off;
+            off += p.n;
+        }
+        g.nz = g.ny = g.nx = p.n;
+        g.sz = g.sy = g.sx = 1;
+        g.npix = p.npix;
+        p.gd = g;
+    }
+    const int nb = p.nb;
+    std::vector<int> slot(nb, -1);
+    auto use = [&](int b) {
+        if (slot[b] < 0) {
+            slot[b] = (int)p.dbins.size();
+            p.dbins.push_back(b);
+        }
+        return slot[b];
+    };
+    auto pair_of = [&](std::vector<int2> &v, int x, int y) {
+        int sx = use(x), sy = use(y);
+        if (sx > sy) std::swap(sx, sy);
+        for (size_t i = 0; i < v.size(); ++i)
+            if (v[i].x == sx && v[i].y == sy) return (int)i;
+        v.push_back(int2{sx, sy});
+        return (int)v.size() - 1;
+    };
+    auto overlap = [&](int x, int y) { return x != y && p.qlo[x] < p.qhi[y] && p.qlo[y] < p.qhi[x]; };
+    p.dconn_ok = true;
+    std::vector<double> c2(ndq), c4(ndq);
+    std::vector<char> listed(nb, 0);
+    for (int t = 0; t < ndq; ++t) {
+        const int *q = &p.dquad[5 * t];
+        const int a = q[0], b = q[1], c = q[2], dd = q[3], e = q[4];
+        p.dq_pp.push_back(pair_of(p.dpairs, a, b));
+        p.dq_pp.push_back(pair_of(p.dpairs, c, dd));
+        const int sh[4] = {a, b, c, dd};
+        for (int i = 0; i < 4; ++i)
+            for (int j = i + 1; j < 4; ++j) p.dconn_ok = p.dconn_ok && !overlap(sh[i], sh[j]);
+        c2[t] = (a == c && b == dd ? 1.0 : 0.0) + (a == dd && b == c ? 1.0 : 0.0);
+        c4[t] = a == b && b == c && c == dd ? 1.0 : 0.0;
+        p.dq_up.push_back(c2[t] > 0 ? pair_of(p.dupairs, a, b) : -1);
+        listed[e] = 1;
+        if (c4[t] > 0) listed[a] = 1;
+    }
+    // mode lists of the listed shells, in grid order
+    std::vector<int> lb;
+    for (int b = 0; b < nb; ++b)
+        if (listed[b]) lb.push_back(b);
+    std::vector<std::vector<int>> lists(lb.size());
+    const GenGrid &g = p.gd;
+    auto fq = [](int i, int n) { return (long long)(i < n - n / 2 ? i : i - n); };
+    for (int z = 0; z < g.nz; ++z) {
+        const long long qz = g.sz * fq(z, g.nz);
+        for (int y = 0; y < g.ny; ++y) {
+            const long long qy = g.sy * fq(y, g.ny);
+            for (int x = 0; x < g.nx; ++x) {
+                const long long qx = g.sx * fq(x, g.nx);
+                const long long qq = qz * qz + qy * qy + qx * qx;
+                if (qq == 0) continue;
+                for (size_t i = 0; i < lb.size(); ++i)
+                    if (qq >= p.qlo[lb[i]] && qq < p.qhi[lb[i]])
+                        lists[i].push_back((int)(((int64_t)z * g.ny + y) * g.nx + x));
+            }
+        }
+    }
+    for (size_t i = 0; i < lb.size(); ++i) {
+        p.dseg[lb[i]] = int2{(int)p.didx.size(), (int)lists[i].size()};
+        p.didx.insert(p.didx.end(), lists[i].begin(), lists[i].end());
+    }
+    p.dq_coef.assign(3 * ndq, 0.0);
+    for (int t = 0; t < ndq; ++t) {
+        p.dq_coef[ndq + t] = c2[t];
+        p.dq_coef[2 * ndq + t] = c4[t];
+    }
+    return BISPEC_OK;
+}
+
+// Shell-sum tasks of the diagonal pass: [0, n) the pair-product dot products
+// over the diagonal shell, [n, 2n) the |D|^2 product sums, [2n, 3n) the |D|^4
+// sums over shell a with 2k in the diagonal shell.
+std::vector<DtTask> dquad_tasks(const bispec_plan_s &p) {
+    const int ndq = (int)p.dquad.size() / 5;
+    std::vector<DtTask> tk(3 * ndq);
+    for (int t = 0; t < ndq; ++t) {
+        const int a = p.dquad[5 * t], e = p.dquad[5 * t + 4];
+        const int2 se = p.dseg[e];
+        tk[t] = DtTask{se.x, se.y, p.dq_pp[2 * t], p.dq_pp[2 * t + 1], 0, 0};
+        tk[ndq + t] = p.dq_up[t] >= 0 ? DtTask{se.x, se.y, p.dq_up[t], 0, 0, 0} : DtTask{0, 0, 0, 0, 0, 0};
+        tk[2 * ndq + t] = p.dq_coef[2 * ndq + t] > 0
+                              ? DtTask{p.dseg[a].x, p.dseg[a].y, 0, 0, p.qlo[e], p.qhi[e]}
+                              : DtTask{0, 0, 0, 0, 0, 0};
+    }
+    return tk;
+}
+
+GenPair dquad_genpair(const bispec_plan_s &p, int i) {
+    const int b1 = p.dbins[i];
+    const bool two = i + 1 < (int)p.dbins.size();
+    const int b2 = two ? p.dbins[i + 1] : 0;
+    return GenPair{p.qlo[b1], p.qhi[b1], two ? p.qlo[b2] : 0, two ? p.qhi[b2] : 0};
+}
+
+// N_q(e) of every diagonal quad in FP64: the unit fields of the slots, their
+// pair products transformed to N_pix C_xy(q) and rounded to the integer pair
+// counts C_xy(q), then sum_{q in S_e} C_ab(q) C_cd(q).  Also the
+// normalisation V^3 / N_pix^4 / N_q, over N_pix^2 for the dot products and
+// times 2^(4 spec_shift) for the scaled fields.
+bispec_status compute_dquad_counts(bispec_plan_s &p) {
+    const int ndq = (int)p.dquad.size() / 5;
+    if (ndq == 0) return BISPEC_OK;
+    hipStream_t st = p.stream;
+    const int64_t np = p.npix;
+    const int nbd = (int)p.dbins.size(), npr = (int)p.dpairs.size();
+    const std::vector<double2> tw = gen_twiddles<double2, double>(p.gd);
+    const std::vector<DtTask> tk = dquad_tasks(p);
+    size_t off = 0;
+    const size_t o_tw = off;     off = align_up(off + sizeof(double2) * tw.size());
+    const size_t o_f = off;      off = align_up(off + sizeof(double) * (size_t)np * nbd);
+    const size_t o_tmp = off;    off = align_up(off + sizeof(double) * (size_t)np);
+    const size_t o_spec = off;   off = align_up(off + sizeof(double2) * (size_t)np);
+    const size_t o_work = off;   off = align_up(off + sizeof(double2) * (size_t)np);
+    const size_t o_cnt = off;    off = align_up(off + sizeof(double) * (size_t)np * npr);
+    const size_t o_idx = off;    off = align_up(off + sizeof(int) * p.didx.size());
+    const size_t o_task = off;   off = align_up(off + sizeof(DtTask) * ndq);
+    const size_t o_part = off;   off = align_up(off + sizeof(double) * (size_t)ndq * kDtBlocks);
+    const size_t o_sums = off;   off = align_up(off + sizeof(double) * ndq);
+    const size_t o_bad = off;    off = align_up(off + sizeof(unsigned int));
+    char *mem = nullptr;
+    {
+        const hipError_t e = hipMalloc((void **)&mem, off);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            char what[128];
+            std::snprintf(what, sizeof(what), "hipMalloc of %zu bytes for the diagonal count fields", off);
+            return record(BISPEC_E_OOM, what, e);
+        }
+    }
+    struct Free {
+        char *m;
+        ~Free() { (void)hipFree(m); }
+    } guard{mem};
+    const double2 *dtw = (const double2 *)(mem + o_tw);
+    double *f = (double *)(mem + o_f);
+    CK(hipMemcpyAsync(mem + o_tw, tw.data(), sizeof(double2) * tw.size(), hipMemcpyHostToDevice, st));
+    if (!p.didx.empty())
+        CK(hipMemcpyAsync(mem + o_idx, p.didx.data(), sizeof(int) * p.didx.size(), hipMemcpyHostToDevice, st));
+    CK(hipMemcpyAsync(mem + o_task, tk.data(), sizeof(DtTask) * ndq, hipMemcpyHostToDevice, st));
+    CK(hipMemsetAsync(mem + o_bad, 0, sizeof(unsigned int), st));
+    for (int i = 0; i < nbd; i += 2)
+        CK(gen_inverse_unit_f64((double2 *)(mem + o_work), p.gd, dquad_genpair(p, i), dtw, f + (int64_t)i * np,
+                                i + 1 < nbd ? f + (int64_t)(i + 1) * np : nullptr, st));
+    for (int i = 0; i < npr; ++i) {
+        CK(dt_mul_f64(f + (int64_t)p.dpairs[i].x * np, f + (int64_t)p.dpairs[i].y * np, (double *)(mem + o_tmp), np,
+                      st));
+        CK(gen_forward_f64((const double *)(mem + o_tmp), p.gd, dtw, (double2 *)(mem + o_spec), st));
+        CK(dt_round_counts((const double2 *)(mem + o_spec), (double *)(mem + o_cnt) + (int64_t)i * np, np,
+                           (double)np, (unsigned int *)(mem + o_bad), st));
+    }
+    CK(dt_shell_sums(1, mem + o_cnt, np, (const int *)(mem + o_idx), (const DtTask *)(mem + o_task), ndq, kDtBlocks,
+                     (double *)(mem + o_part), (double *)(mem + o_sums), st));
+    std::vector<double> sums(ndq);
+    unsigned int bad = 0;
+    CK(hipMemcpyAsync(sums.data(), mem + o_sums, sizeof(double) * ndq, hipMemcpyDeviceToHost, st));
+    CK(hipMemcpyAsync(&bad, mem + o_bad, sizeof(unsigned int), hipMemcpyDeviceToHost, st));
+    CK(hipStreamSynchronize(st));
+    if (bad) return record(BISPEC_E_NUMERIC, "a diagonal pair count was not within 0.01 of an integer", hipSuccess);
+    const double npix = (double)np;
+    const double V = p.box_len * p.box_len * p.box_len *
+                     (p.general ? ((double)p.gg.nz / p.gg.nx) * ((double)p.gg.ny / p.gg.nx) : 1.0);
+    const double u4 = std::ldexp(1.0, 4 * p.spec_shift);
+    p.dq_count = sums;
+    for (int t = 0; t < ndq; ++t)
+        p.dq_coef[t] = sums[t] > 0 ? V * V * V / (npix * npix * npix * npix) / sums[t] / (npix * npix) * u4
+                                   : std::numeric_limits<double>::quiet_NaN();
+    return BISPEC_OK;
+}
+
 // Count fields and sums of a general grid: unit-amplitude fields of every
 // bin in FP64 by the mixed-radix transforms, then the compensated FP64 term sums.
 bispec_status compute_counts_general(bispec_plan_s &p, std::vector<int> &cand_tri, std::vector<double> &tri_cnt,
@@ -789,6 +1009,9 @@ bispec_status plan_impl(const bispec_plan_desc *d, bispec_plan_t *out) {
         if (d->tri[t] < 0 || d->tri[t] >= nb) return BISPEC_E_INVALID;
     for (int t = 0; t < 4 * d->n_quad; ++t)
         if (d->quad[t] < 0 || d->quad[t] >= nb) return BISPEC_E_INVALID;
+    if (d->n_dquad < 0 || (d->n_dquad > 0 && !d->dquad)) return BISPEC_E_INVALID;
+    for (int t = 0; t < 5 * d->n_dquad; ++t)
+        if (d->dquad[t] < 0 || d->dquad[t] >= nb) return BISPEC_E_INVALID;
 
     static std::atomic<unsigned long long> next_uid{1};
     bispec_plan_s *p = new bispec_plan_s();
@@ -817,6 +1040,8 @@ bispec_status plan_impl(const bispec_plan_desc *d, bispec_plan_t *out) {
         } else {
             p->ilo2.push_back(std::max(1, ceil_int(p->lo[b] * p->lo[b])));
             p->ihi2.push_back(ceil_int(p->hi[b] * p->hi[b]));
+            p->qlo.push_back(p->ilo2.back());    // q = |m|^2 (the mixed-radix passes' test)
+            p->qhi.push_back(p->ihi2.back());
         }
     }
     struct Owner {
@@ -938,6 +1163,10 @@ bispec_status plan_impl(const bispec_plan_desc *d, bispec_plan_t *out) {
         p->nblk_pg_max = (int)std::min<int64_t>(tiles, std::max<int64_t>(lo, std::min<int64_t>(4 * lo, 2048)));
     }
     build_terms(*p);
+    s = build_dquads(*p, d);
+    if (s != BISPEC_OK) return s;
+    s = compute_dquad_counts(*p);
+    if (s != BISPEC_OK) return s;
     own.keep = true;
     *out = p;
     return BISPEC_OK;
@@ -984,7 +1213,79 @@ bispec_status upload_tables(bispec_plan_s &p) {
                               hipMemcpyHostToDevice, p.stream));
         }
     }
+    const int ndq = (int)p.dquad.size() / 5;
+    if (ndq > 0) {
+        if (!p.general) {
+            const std::vector<float2> dtw = gen_twiddles<float2, float>(p.gd);
+            CK(hipMemcpyAsync(ws + L.dtw, dtw.data(), sizeof(float2) * dtw.size(), hipMemcpyHostToDevice,
+                              p.stream));
+        }
+        const std::vector<DtTask> tk = dquad_tasks(p);
+        CK(hipMemcpyAsync(ws + L.dtask, tk.data(), sizeof(DtTask) * tk.size(), hipMemcpyHostToDevice, p.stream));
+        if (!p.didx.empty())
+            CK(hipMemcpyAsync(ws + L.didx, p.didx.data(), sizeof(int) * p.didx.size(), hipMemcpyHostToDevice,
+                              p.stream));
+        CK(hipMemcpyAsync(ws + L.dcoef, p.dq_coef.data(), sizeof(double) * p.dq_coef.size(), hipMemcpyHostToDevice,
+                          p.stream));
+    }
     CK(hipStreamSynchronize(p.stream));
+    return BISPEC_OK;
+}
+
+// The diagonal-binned trispectrum of batch maps, one map at a time: full
+// spectrum (mean removed, scaled by 2^-spec_shift), the fields of the slots,
+// each pair product's spectrum, the dot products over the diagonal shells;
+// for Tdc also the |D|^4 sums and the |D|^2 pair products.
+bispec_status run_trispec_diag(bispec_plan_s &p, const float *delta, int batch, double *Td, double *Tdc) {
+    const Layout L = make_layout(p, p.max_batch);
+    char *ws = (char *)p.ws;
+    hipStream_t st = p.stream;
+    const int ndq = (int)p.dquad.size() / 5;
+    const int64_t np = p.npix;
+    const GenGrid &g = p.gd;
+    const float2 *tw = (const float2 *)(ws + (p.general ? L.tw : L.dtw));
+    float2 *spec = (float2 *)(ws + L.dspec);
+    float2 *work = (float2 *)(ws + L.dwork);
+    float *f = (float *)(ws + L.dfields);
+    float *tmp = (float *)(ws + L.dtmp);
+    float2 *ps = (float2 *)(ws + L.dpspec);
+    const int *idx = (const int *)(ws + L.didx);
+    const DtTask *tk = (const DtTask *)(ws + L.dtask);
+    double *part = (double *)(ws + L.dpart);
+    double *sums = (double *)(ws + L.dsums);
+    double *mean = (double *)(ws + L.mean);
+    const int nbd = (int)p.dbins.size();
+    // fields of the slots from a spectrum, pair products to their spectra
+    auto pair_spectra = [&](const float2 *src, const std::vector<int2> &pairs) -> hipError_t {
+        for (int i = 0; i < nbd; i += 2) {
+            hipError_t e = gen_inverse_pair(src, work, g, dquad_genpair(p, i), 1, tw, f + (int64_t)i * np,
+                                            i + 1 < nbd ? f + (int64_t)(i + 1) * np : nullptr, 0, st);
+            if (e != hipSuccess) return e;
+        }
+        for (size_t i = 0; i < pairs.size(); ++i) {
+            hipError_t e = dt_mul_f32(f + (int64_t)pairs[i].x * np, f + (int64_t)pairs[i].y * np, tmp, np, st);
+            if (e == hipSuccess) e = gen_forward(tmp, nullptr, g, 1, tw, ps + (int64_t)i * np, st, 1.0);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    };
+    for (int m = 0; m < batch; ++m) {
+        const float *dm = delta + (int64_t)m * np;
+        CK(gen_mean(dm, g, 1, (double *)(ws + L.mean_partial), kMeanParts, mean, st));
+        CK(gen_forward(dm, mean, g, 1, tw, spec, st, spec_scale(p)));
+        CK(pair_spectra(spec, p.dpairs));
+        CK(dt_shell_sums(0, ps, np, idx, tk, ndq, kDtBlocks, part, sums, st));
+        if (Tdc) {
+            CK(dt_pow4_sums(spec, g, idx, tk + 2 * ndq, ndq, kDtBlocks, part, sums + 2 * ndq, st));
+            if (!p.dupairs.empty()) {
+                CK(dt_power(spec, spec, np, st));
+                CK(pair_spectra(spec, p.dupairs));
+                CK(dt_shell_sums(2, ps, np, idx, tk + ndq, ndq, kDtBlocks, part, sums + ndq, st));
+            }
+        }
+        CK(dt_finalize(sums, (const double *)(ws + L.dcoef), ndq, (double)np, Td + (int64_t)m * ndq,
+                       Tdc ? Tdc + (int64_t)m * ndq : nullptr, st));
+    }
     return BISPEC_OK;
 }
 
@@ -1031,7 +1332,6 @@ bispec_status run_fields(bispec_plan_s &p, const float *delta, int batch, float 
         return BISPEC_OK;
     }
     const int n = p.n;
-    const int64_t vol = (int64_t)n * n * n;
     const float2 *tw = (const float2 *)(ws + L.tw);
     double *mean = (double *)(ws + L.mean);
     float2 *spec = (float2 *)(ws + L.spec);
@@ -1645,13 +1945,14 @@ bispec_status trispec_connected_estimate(bispec_plan_t plan, const float *delta,
     bispec_plan_s &p = *plan;
     if (p.general) return BISPEC_E_UNSUPPORTED_N;   // the spectral moments run on the half spectrum of a cube
     const int nq = (int)p.quad.size() / 4, ntri = (int)p.tri.size() / 3;
-    for (int q = 0; q < nq; ++q) {
-        int a[4] = {p.quad[4 * q], p.quad[4 * q + 1], p.quad[4 * q + 2], p.quad[4 * q + 3]};
-        std::sort(a, a + 4);
-        if (a[0] != a[1] || a[2] != a[3]) return BISPEC_E_INVALID;                 // collapsed quads only
-        const int x = a[0], y = a[2];
-        if (x != y && p.ilo2[x] < p.ihi2[y] && p.ilo2[y] < p.ihi2[x]) return BISPEC_E_INVALID;   // shells overlap
-    }
+    // shells of a quad identical or disjoint: then only (a, a, b, b) has
+    // pairings, and the connected T of any other quad is its raw T
+    for (int q = 0; q < nq; ++q)
+        for (int i = 0; i < 4; ++i)
+            for (int j = i + 1; j < 4; ++j) {
+                const int x = p.quad[4 * q + i], y = p.quad[4 * q + j];
+                if (x != y && p.ilo2[x] < p.ihi2[y] && p.ilo2[y] < p.ihi2[x]) return BISPEC_E_INVALID;
+            }
     s = polyspec_estimate(plan, delta, batch, nullptr, nullptr, T);
     if (s != BISPEC_OK) return s;
     const Layout L = make_layout(p, p.max_batch);
@@ -1663,6 +1964,29 @@ bispec_status trispec_connected_estimate(bispec_plan_t plan, const float *delta,
                            (double *)(ws + L.mom), (double *)(ws + L.mom_tmp), p.stream));
     CK(launch_trispec_connected(T, (const double *)(ws + L.mom), (const uchar4 *)(ws + L.terms) + ntri + p.nb,
                                 (const double *)(ws + L.scale) + ntri + p.nb, npix, nq, p.nb, batch, Tc, p.stream));
+    return BISPEC_OK;
+}
+
+bispec_status trispec_diag_estimate(bispec_plan_t plan, const float *delta, int32_t batch, double *Td,
+                                    double *Tdc) {
+    if (!Td) return BISPEC_E_INVALID;
+    bispec_status s = check_call(plan, delta, batch);
+    if (s != BISPEC_OK) return s;
+    if (plan->dquad.empty()) return BISPEC_E_INVALID;
+    if (Tdc && !plan->dconn_ok) return BISPEC_E_INVALID;
+    try {
+        return run_trispec_diag(*plan, delta, batch, Td, Tdc);
+    } catch (...) {
+        return BISPEC_E_HIP;
+    }
+}
+
+bispec_status bispec_plan_query_dquads(bispec_plan_t plan, int32_t *n_dquad, double *counts_out) {
+    if (!plan) return BISPEC_E_INVALID;
+    const int ndq = (int)plan->dquad.size() / 5;
+    if (n_dquad) *n_dquad = ndq;
+    if (counts_out)
+        for (int t = 0; t < ndq; ++t) counts_out[t] = plan->dq_count[t];
     return BISPEC_OK;
 }
 

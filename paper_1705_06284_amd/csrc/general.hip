@@ -147,29 +147,31 @@ __device__ C *gen_fft(C *a, C *b, const C *tw, const GenAxis &ax, int G) {
     return a;
 }
 
-// Forward pass along x: real rows (minus the FP64 mean) to complex rows of
-// the full spectrum; block (x, map) holds rows x G .. x G + G - 1.
-__global__ __launch_bounds__(GEN_NT) void k_gen_fwd_x(const float *__restrict__ delta,
-                                                      const double *__restrict__ mean, float2 *__restrict__ spec,
-                                                      const float2 *__restrict__ tw, GenGrid g, int G,
-                                                      double scale) {
-    extern __shared__ __attribute__((aligned(16))) float2 gsm[];
+// Forward pass along x: real rows (minus the FP64 mean, if any, times
+// scale) to complex rows of the full spectrum; block (x, map) holds rows
+// x G .. x G + G - 1.
+template <typename C, typename Rr>
+__global__ __launch_bounds__(GEN_NT) void k_gen_fwd_x(const Rr *__restrict__ delta,
+                                                      const double *__restrict__ mean, C *__restrict__ spec,
+                                                      const C *__restrict__ tw, GenGrid g, int G, double scale) {
+    using R = decltype(C{}.x);
+    extern __shared__ __attribute__((aligned(16))) unsigned char gsm_raw[];
+    C *gsm = reinterpret_cast<C *>(gsm_raw);
     const GenAxis &ax = g.ax[2];
     const int n = ax.n;
-    float2 *a = gsm, *b = gsm + G * n;
+    C *a = gsm, *b = gsm + G * n;
     const int map = blockIdx.y;
     const int64_t rows = (int64_t)g.nz * g.ny;
     const int64_t r0 = (int64_t)blockIdx.x * G;
-    const float *src = delta + (int64_t)map * g.npix;
-    const double mu = mean[map];
+    const Rr *src = delta + (int64_t)map * g.npix;
+    const double mu = mean ? mean[map] : 0.0;
     for (int e = threadIdx.x; e < G * n; e += GEN_NT) {
         const int p = e / n, i = e % n;
-        a[e] = r0 + p < rows ? float2{(float)(((double)src[(r0 + p) * n + i] - mu) * scale), 0.0f}
-                             : float2{0.0f, 0.0f};
+        a[e] = r0 + p < rows ? C{(R)(((double)src[(r0 + p) * n + i] - mu) * scale), R(0)} : C{R(0), R(0)};
     }
     __syncthreads();
-    const float2 *res = gen_fft<-1>(a, b, tw + ax.tw_off, ax, G);
-    float2 *dst = spec + (int64_t)map * g.npix;
+    const C *res = gen_fft<-1>(a, b, tw + ax.tw_off, ax, G);
+    C *dst = spec + (int64_t)map * g.npix;
     for (int e = threadIdx.x; e < G * n; e += GEN_NT) {
         const int p = e / n, i = e % n;
         if (r0 + p < rows) dst[(r0 + p) * n + i] = res[e];
@@ -386,20 +388,30 @@ hipError_t gen_mean(const float *x, const GenGrid &g, int batch, double *part, i
     return hipGetLastError();
 }
 
+template <typename C, typename Rr>
+static hipError_t gen_forward_t(const Rr *delta, const double *mean, const GenGrid &g, int batch, const C *tw,
+                                C *spec, hipStream_t st, double scale) {
+    const int Gx = gen_pencils(g.nx, sizeof(C));
+    const int64_t rows = (int64_t)g.nz * g.ny;
+    hipLaunchKernelGGL((k_gen_fwd_x<C, Rr>), dim3((unsigned)((rows + Gx - 1) / Gx), batch), dim3(GEN_NT),
+                       gen_smem<C>(g.nx, Gx), st, delta, mean, spec, tw, g, Gx, scale);
+    const int Gy = gen_pencils(g.ny, sizeof(C));
+    hipLaunchKernelGGL((k_gen_axis<C, -1, 1>), dim3((unsigned)(g.nz * ((g.nx + Gy - 1) / Gy)), batch),
+                       dim3(GEN_NT), gen_smem<C>(g.ny, Gy), st, spec, tw, g, Gy);
+    const int Gz = gen_pencils(g.nz, sizeof(C));
+    const int64_t ncol = (int64_t)g.ny * g.nx;
+    hipLaunchKernelGGL((k_gen_axis<C, -1, 2>), dim3((unsigned)((ncol + Gz - 1) / Gz), batch), dim3(GEN_NT),
+                       gen_smem<C>(g.nz, Gz), st, spec, tw, g, Gz);
+    return hipGetLastError();
+}
+
 hipError_t gen_forward(const float *delta, const double *mean, const GenGrid &g, int batch, const float2 *tw,
                        float2 *spec, hipStream_t st, double scale) {
-    const int Gx = gen_pencils(g.nx, sizeof(float2));
-    const int64_t rows = (int64_t)g.nz * g.ny;
-    hipLaunchKernelGGL(k_gen_fwd_x, dim3((unsigned)((rows + Gx - 1) / Gx), batch), dim3(GEN_NT),
-                       gen_smem<float2>(g.nx, Gx), st, delta, mean, spec, tw, g, Gx, scale);
-    const int Gy = gen_pencils(g.ny, sizeof(float2));
-    hipLaunchKernelGGL((k_gen_axis<float2, -1, 1>), dim3((unsigned)(g.nz * ((g.nx + Gy - 1) / Gy)), batch),
-                       dim3(GEN_NT), gen_smem<float2>(g.ny, Gy), st, spec, tw, g, Gy);
-    const int Gz = gen_pencils(g.nz, sizeof(float2));
-    const int64_t ncol = (int64_t)g.ny * g.nx;
-    hipLaunchKernelGGL((k_gen_axis<float2, -1, 2>), dim3((unsigned)((ncol + Gz - 1) / Gz), batch), dim3(GEN_NT),
-                       gen_smem<float2>(g.nz, Gz), st, spec, tw, g, Gz);
-    return hipGetLastError();
+    return gen_forward_t<float2, float>(delta, mean, g, batch, tw, spec, st, scale);
+}
+
+hipError_t gen_forward_f64(const double *x, const GenGrid &g, const double2 *tw, double2 *spec, hipStream_t st) {
+    return gen_forward_t<double2, double>(x, nullptr, g, 1, tw, spec, st, 1.0);
 }
 
 template <typename C, typename Rr, bool UNIT>

@@ -47,6 +47,8 @@ hipError_t gen_mean(const float *x, const GenGrid &g, int batch, double *part, i
 // [batch][npix]; tw: the three axis tables.
 hipError_t gen_forward(const float *delta, const double *mean, const GenGrid &g, int batch, const float2 *tw,
                        float2 *spec, hipStream_t st, double scale);
+// The same in FP64 for one real map x [npix] (no mean, no scale).
+hipError_t gen_forward_f64(const double *x, const GenGrid &g, const double2 *tw, double2 *spec, hipStream_t st);
 // Inverse transform of one shell pair: work [batch][npix] complex scratch;
 // fields F_b1 to f1 and F_b2 to f2 (may be null), map m at m * map_stride.
 hipError_t gen_inverse_pair(const float2 *spec, float2 *work, const GenGrid &g, const GenPair &pr, int batch,

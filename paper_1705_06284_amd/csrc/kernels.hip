@@ -671,7 +671,7 @@ __global__ __launch_bounds__(256) void k_shell_moments(const float2 *__restrict_
     }
 }
 
-// Connected collapsed T: Tc = T - scale N_pix S_D for the quad (a,a,b,b),
+// Connected T: Tc = T - scale N_pix S_D; S_D = 0 unless the quad is (a,a,b,b),
 // S_D = X_a X_b, plus 2 X_a^2 - 3 Y_a when a = b (the three Gaussian
 // pairings of k1..k4, inclusion-exclusion over their common quadruples
 // (k,-k,-k,k) and the like; for disjoint shells a != b only k2 = -k1,
@@ -695,7 +695,9 @@ __global__ __launch_bounds__(256) void k_trispec_connected(const double *__restr
     const int a = s[0], b = s[2];
     const double *m = mom + (int64_t)map * nb * 2;
     const double xa = m[2 * a], xb = m[2 * b], ya = m[2 * a + 1];
-    const double sd = xa * xb + (a == b ? 2.0 * xa * xa - 3.0 * ya : 0.0);
+    // with identical or disjoint shells only (a, a, b, b) has pairings
+    const bool coll = s[0] == s[1] && s[2] == s[3];
+    const double sd = coll ? xa * xb + (a == b ? 2.0 * xa * xa - 3.0 * ya : 0.0) : 0.0;
     Tc[(int64_t)map * nq + q] = T[(int64_t)map * nq + q] - scale[q] * npix * sd;
 }
 

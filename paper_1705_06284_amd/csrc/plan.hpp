@@ -28,6 +28,20 @@ struct bispec_plan_s {
     std::vector<double> tri_count;       // N_t (exact integers)
     std::vector<int> quad;               // [n_quad][4]
     std::vector<double> quad_count;      // N_q
+    // diagonal-binned p = 4 configurations (a, b, c, d, e): shells of k1..k4
+    // and of the diagonal k1 + k2 (diagtri.hip), on the mixed-radix transforms
+    std::vector<int> dquad;              // [n_dquad][5]
+    std::vector<double> dq_count;        // N_q(e), exact integers
+    std::vector<double> dq_coef;         // [3][n_dquad]: normalisation, pairing coefficients c2, c4
+    std::vector<int> dbins;              // shells whose fields the pass builds; slot = position
+    std::vector<int2> dpairs;            // slot pairs (x <= y) of the pair products
+    std::vector<int> dq_pp;              // [n_dquad][2]: pair of (a,b), of (c,d)
+    std::vector<int2> dupairs;           // slot pairs of the |D|^2 products (connected part)
+    std::vector<int> dq_up;              // per dquad: index into dupairs, or -1
+    std::vector<int> didx;               // linear mode indices of the listed shells
+    std::vector<int2> dseg;              // per bin: (offset, length) in didx; length 0 if unlisted
+    bool dconn_ok = false;               // every dquad's shells are identical or disjoint
+    bispec::GenGrid gd{};                // the grid as the mixed-radix transforms see it
     int precision = 0;
     int max_batch = 1;
     hipStream_t stream = nullptr;
@@ -107,7 +121,9 @@ constexpr int kMomBlocks = 2048;
 struct Layout {
     size_t tw, terms, scale, tcount, thr, mom_partial, mom_tmp, mom, pg_pairs, pg_idx, pg_pairs_r, cols, pd, ztab,
         ytab, mean_partial, mean, spec, abox, bc, fields, partial, pg_partial, pg_dense, pg_tmp, pg_partial_r,
-        pg_dense_r, pg_tmp_r, refine_t, total;
+        pg_dense_r, pg_tmp_r, refine_t,
+        // diagonal-binned trispectrum pass (one map at a time)
+        dtw, dspec, dwork, dfields, dtmp, dpspec, didx, dtask, dpart, dsums, dcoef, total;
 };
 
 // Triplets with a condition number sqrt(M_i M_j M_k / (N_pix N_t)) above

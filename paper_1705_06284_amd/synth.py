@@ -164,9 +164,12 @@ WORKLOADS = {
                            bins=("linear", 24)),
     "c4_512_lognormal": dict(n=512, kind="lognormal", spectral_index=1.0, sigma=1.5,
                              seed=4, bins=("linear", 32)),
-    # one-pixel shells up to the 64-bin plan limit, for configuration binning
+    # one-pixel shells for configuration binning: every shell below the
+    # Nyquist mode at 128^3 (63) and at 256^3 (127)
     "onepix_128_lognormal": dict(n=128, kind="lognormal", spectral_index=1.5, sigma=1.0,
                                  seed=2, bins=("unit", 1, 63)),
+    "onepix_256_lognormal": dict(n=256, kind="lognormal", spectral_index=1.5, sigma=1.0,
+                                 seed=8, bins=("unit", 1, 127)),
     # the toy reionisation boxes of Section 3.3: 600^3 cells of 1 Mpc, spheres
     # of radius 10 Mpc at uniform random centres (overlap allowed, as in the
     # paper's boxes), neutral fractions 0.99 and 0.88; 61 shells of 2 k_f

@@ -58,14 +58,13 @@ def test_connected_trispectrum_32(binding, prec):
     assert np.array_equal(Tc0.cpu().numpy()[0], Tc.cpu().numpy()[0])
 
 
-def test_connected_trispectrum_rejects_general_and_overlapping(binding):
+def test_connected_trispectrum_general_quads_and_overlapping_shells(binding):
     n = 16
     lo, hi = synth.unit_bins(1, 4)
     d = synth.lognormal_field(n, 1.5, 1.0, 43).astype(np.float32)
     plan = binding.Plan(n, lo, hi, quads=[(0, 1, 2, 3)], precision="fp32")
-    with pytest.raises(binding.BispecError) as ex:
-        plan.trispec_connected(d)
-    assert ex.value.code == -1          # BISPEC_E_INVALID: not a collapsed quad
+    T, Tc = plan.trispec_connected(d)   # disjoint shells, no pairing: Tc = T
+    assert torch.equal(T, Tc)
     lo2, hi2 = np.array([1.0, 1.5]), np.array([2.5, 3.0])
     plan2 = binding.Plan(n, lo2, hi2, quads=[(0, 0, 1, 1)], precision="fp32")
     with pytest.raises(binding.BispecError) as ex:
