@@ -122,13 +122,13 @@ def timed_steps(torch, step, steps, stream):
     return t1 - t0, lat
 
 
-def onepixel_run(torch, binding, synth, np, dev, stream, steps):
-    """Narrow shells (one k_f, 63 bins at 128^3: the bin fields go to HBM; the
-    triplets run on the split-BF16 product-Gram over them, 64 columns, P and
-    the 2016 collapsed T on its pass over the squares), against the same plan
-    on the FP32 vector-ALU terms, and the table B(theta) at k2 = 2 k1 for
-    k1 = 2..21 (20 cos theta bins each) from bispec_rebin."""
-    wl = "onepix_128_lognormal"
+def onepixel_run(torch, binding, synth, np, dev, stream, steps, wl="onepix_128_lognormal"):
+    """Narrow shells (one k_f: 63 bins at 128^3, 127 at 256^3; the bin fields
+    go to HBM, the triplets run on the split-BF16 product-Gram over them in
+    groups of 64 columns, P and the collapsed T on its pass over the
+    squares), against the same plan on the FP32 vector-ALU terms, and the
+    table B(theta) at k2 = 2 k1 for k1 = 2..21 (20 cos theta bins each) from
+    bispec_rebin."""
     n = synth.WORKLOADS[wl]["n"]
     lo, hi = synth.workload_bins(wl)
     plan = binding.Plan(n, lo, hi, stream=stream, device=dev)
@@ -164,8 +164,8 @@ def onepixel_run(torch, binding, synth, np, dev, stream, steps):
     wr, _ = timed_steps(torch, rebin, k, stream)
     out = {"workload": wl, "n": n, "bins": plan.n_bins, "triplets": plan.n_tri, "quads": plan.n_quad,
            "outputs": "B, P, T",
-           "contraction": "split-BF16 MFMA product-Gram over the bin fields in HBM (64 columns), "
-                          "P and T from its pass over the squares",
+           "contraction": "split-BF16 MFMA product-Gram over the bin fields in HBM (%d group(s) of 64 "
+                          "columns), P and T from its pass over the squares" % ((plan.n_bins + 63) // 64),
            "ms_per_map": 1e3 * we / k, "triangles_per_s": plan.n_tri * k / we,
            "stages_ms": {key: v / max(calls, 1) for key, v in stages.items()},
            "theta_table": {"configs": "k2 = 2 k1, k1 = 2..21 k_f, 20 bins of cos theta",
@@ -446,6 +446,8 @@ def main():
 
     if not args.no_onepixel:
         out["onepixel_128"] = onepixel_run(torch, binding, synth, np, dev, stream, args.steps)
+        out["onepixel_256"] = onepixel_run(torch, binding, synth, np, dev, stream, args.steps,
+                                           wl="onepix_256_lognormal")
 
     if not args.no_serving:
         out["serving"] = serving_run(args.serving_requests)

@@ -465,11 +465,9 @@ void build_pgram_tables(bispec_plan_s &p) {
     const int64_t npix_i = field_len(p);
     p.nblk_r = (int)std::min<int64_t>(std::max<int64_t>(256, npix_i / 16384), npix_i / 128);
     if (wide) {
-        // with many row tiles the launch already has blocks to spare: fewer,
-        // longer chunks (within the FP32 accumulation span) keep the
-        // partials small
+        // blocks of at most PGF_MAX_CHUNK points, the FP32 accumulation span
         const int64_t need = (npix_i + PGF_MAX_CHUNK - 1) / PGF_MAX_CHUNK;
-        p.nblk_wide = p.n_mtile > 64 ? (int)std::max<int64_t>(need, std::min<int64_t>(p.nblk_r, 256)) : p.nblk_r;
+        p.nblk_wide = (int)std::max<int64_t>(need, std::min<int64_t>(p.nblk_r, 256));
         // P and collapsed quads from the product-Gram of the squares (rows
         // (a,a), columns F_b^2 of each group, ones at column nb): -1 leaves a
         // term to the vector ALUs (when nb is a multiple of 64, or general quads)

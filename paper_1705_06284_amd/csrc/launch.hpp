@@ -98,7 +98,11 @@ constexpr int PGF_ROW_ZERO = 64;        // zero row of plans of up to 64 bins
 constexpr int PGF_ROW_ZERO_XL = 128;    // and of 65..128 bins
 constexpr int PGF_MAX_BINS = 128;
 inline int pgf_row_zero(int nb) { return nb <= PGF_ROW_ZERO ? PGF_ROW_ZERO : PGF_ROW_ZERO_XL; }
-constexpr int64_t PGF_MAX_CHUNK = 32768;
+// Points one block contracts in FP32 accumulation: 512 split-mode MFMA
+// steps.  The matrix cores' FP32 accumulation drifts with the length of the
+// sum (on one-k_f shells at 256^3, spans of 2048 steps left errors of 5e-5 of
+// the noise level on equilateral triplets, 512 steps 2e-5).
+constexpr int64_t PGF_MAX_CHUNK = 8192;
 int64_t pgram_fields_chunk(int64_t npix, int nblk);
 int pgram_fields_kparts(int n_mtile, bool squares);
 int pgf_sq_tiles(int nb);               // 1, 2 or 4 row tiles of (a,a)

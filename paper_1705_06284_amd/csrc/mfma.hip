@@ -466,7 +466,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MINW))) void
 // Every step stages PGF_TK points of each field in LDS, all nb in FP32 for
 // the row products and the group's columns as bf16 halves, so one split of a
 // row product feeds both column tiles; the next step's loads are in flight
-// during a step's contraction.  A chunk is at most 32768 points, the
+// during a step's contraction.  A chunk is at most PGF_MAX_CHUNK points, the
 // split-mode span of FP32 accumulation; the block writes its FP64 tile
 // partials into tiles tile0 .. tile0 + n_mtile - 1 of its set of
 // tiles_total tiles (its own tiles only).  ZR: the zero row of the FP32

@@ -20,6 +20,10 @@ Configuration sets (Eq. Jeong_BI, Eq. Jeong_PS, Eq. Jeong_gen with p = 4):
   k_2 on 40, 60, 96 k_f, every closed third shell), P of every shell, and the
   Bharadwaj-Pandey theory averaged over the same configurations (the window
   moments of oracle/toymodel.py) with the sphere statistics of the map.
+* onepix_256_lognormal (127 one-k_f shells): a stratified sample over all
+  bins -- every equilateral, one seeded triplet per bin, the flattened
+  triplets k = i + j + 1 (in k_f) with k >= 125, 32 more seeded triplets --
+  and P of every shell.
 * c4_512_lognormal (32 bins): a stratified sample that touches every bin --
   every equilateral (b,b,b), one seeded triplet per bin, the triangle-edge
   triplets k = i + j + 1 with k >= 29 (the worst-conditioned ones), 16 more
@@ -42,7 +46,36 @@ from oracle import fftref, toymodel  # noqa: E402
 from paper_1705_06284_amd import synth  # noqa: E402
 
 WORKLOADS = ("c2_128_lognormal", "c3_256_bubbles", "onepix_128_lognormal", "c4_512_lognormal",
-             "toy600_xhi099", "toy600_xhi088")
+             "onepix_256_lognormal", "toy600_xhi099", "toy600_xhi088")
+
+
+def onepix_sample(nb, cand, seed=8):
+    """Unit shells centred on k = b + 1: equilaterals, one seeded triplet per
+    bin, the flattened triplets k3 = k1 + k2 + 1 with k3 >= 125, 32 more."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    cs = {tuple(int(x) for x in t) for t in cand}
+    pick = [(b, b, b) for b in range(nb) if (b, b, b) in cs]
+    by_bin = {b: [] for b in range(nb)}
+    for t in sorted(cs):
+        for b in set(t):
+            by_bin[b].append(t)
+    for b in range(nb):
+        pick.append(by_bin[b][int(rng.integers(len(by_bin[b])))])
+    for k in (124, 125, 126):               # bin k is k_f = k + 1
+        for i in range(k):
+            j = k - 2 - i                   # (i + 1) + (j + 1) + 1 = k + 1
+            if i <= j and (i, j, k) in cs:
+                pick.append((i, j, k))
+    allc = sorted(cs)
+    for _ in range(32):
+        pick.append(allc[int(rng.integers(len(allc)))])
+    out = []
+    seen = set()
+    for t in pick:
+        if t not in seen:
+            seen.add(t)
+            out.append(t)
+    return np.array(out, np.int32)
 
 
 def toy_configurations(nb):
@@ -140,9 +173,11 @@ def make(wl, cache_bytes):
     cand = oracle.candidate_triplets(lo, hi)
     if wl == "c4_512_lognormal":
         trip, quads = c4_sample(nb, cand)
+    elif wl == "onepix_256_lognormal":
+        trip, quads = onepix_sample(nb, cand), np.zeros((0, 4), np.int32)
     else:
         trip = cand
-        quads = oracle.collapsed_quads(nb) if wl != "onepix_128_lognormal" else np.zeros((0, 4), np.int32)
+        quads = oracle.collapsed_quads(nb) if not wl.startswith("onepix") else np.zeros((0, 4), np.int32)
     print("%s: %d triplets, %d quads" % (wl, len(trip), len(quads)), flush=True)
     fb = R.bispectrum(trip)
     keep = fb.count > 0
@@ -205,4 +240,4 @@ if __name__ == "__main__":
         if wl.startswith("toy"):
             make_toy(wl, cache_bytes=16 << 30)
         else:
-            make(wl, cache_bytes=(34 << 30) if wl.startswith("c4") else (16 << 30))
+            make(wl, cache_bytes=(34 << 30) if wl.startswith("c4") else (8 << 30))

@@ -236,3 +236,23 @@ def test_physical_box_length(binding, prec):
     assert np.allclose(B.cpu().numpy(), B1.cpu().numpy() * r ** 2, rtol=1e-12, atol=0)
     assert np.allclose(P.cpu().numpy(), P1.cpu().numpy() * r, rtol=1e-12, atol=0)
     assert np.allclose(T.cpu().numpy(), T1.cpu().numpy() * r ** 3, rtol=1e-12, atol=0)
+
+
+def test_onepix_256_sample_all_bins_both_precisions(binding):
+    """256^3 lognormal map, 127 one-k_f shells (every shell below the Nyquist
+    mode; two column groups of the fields product-Gram): the plan's whole
+    closed set, checked on a stored sample that touches every bin
+    (equilaterals, one seeded triplet per bin, the flattened k3 = k1 + k2 + 1
+    triplets at the top of the range, 32 seeded extras) and every P."""
+    wl = "onepix_256_lognormal"
+    z, d = _load(wl)
+    lo, hi = synth.workload_bins(wl)
+    _say("one-pixel 256^3, 127 bins, stored sample of %d triplets" % len(z["triplets"]))
+    assert set(np.unique(z["triplets"])) == set(range(127))
+    plan = binding.Plan(256, lo, hi, precision="split_bf16", quads=[(0, 0, 1, 1)])
+    assert plan.n_tri > 180000
+    _check_plan_sets(plan, z)
+    dt = torch.from_numpy(d).cuda()
+    for prec in ("split_bf16", "fp32"):
+        plan.set_precision(prec)
+        _check_all(plan, dt, z, prec, "one-pixel 256")
