@@ -124,6 +124,14 @@ typedef struct {
                               the diagonal k1 + k2); NULL when n_dquad = 0           */
 } bispec_plan_desc;
 
+/* Process-wide limit on the device memory a plan's count pass may hold in
+ * FP64 unit fields (8 N_pix bytes per bin); 0 (the default) means half the
+ * free device memory at plan time.  Beyond the limit the bins are taken in
+ * groups and the fields of every set of groups that some term touches are
+ * made in turn (more transforms, the same integer counts).  Affects plans
+ * built after the call. */
+bispec_status bispec_set_count_memory(size_t bytes);
+
 /* Build a plan: validate the descriptor, tabulate the shells, evaluate the
  * FFT counts (Eq. Jeong_BI denominator, Section 3: FFT-counted triangles) in
  * FP64 and, when n_tri = 0, keep every i<=j<=k whose shells admit a triangle

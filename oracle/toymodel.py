@@ -64,10 +64,10 @@ def kmod_grid(shape, box_len):
     return (2.0 * np.pi / float(box_len)) * np.sqrt(q.astype(np.float64)) / s[2]
 
 
-def binned_window_moments(shape, k_lo, k_hi, box_len, R, triplets, cache_bytes=16 << 30):
+def binned_window_moments(shape, k_lo, k_hi, box_len, R, triplets, cache_bytes=16 << 30, counts=None):
     """<W^2> over the modes of each shell and <W1 W2 W3> over the closed
     triangles of each triplet (closure modulo N, as the estimator counts them),
-    with the triangle counts."""
+    with the triangle counts (computed here unless given)."""
     kk = kmod_grid(shape, box_len)
     w = window(kk * R)
     lo2, hi2 = polyspec.squared_edges(k_lo, k_hi, shape)
@@ -82,5 +82,12 @@ def binned_window_moments(shape, k_lo, k_hi, box_len, R, triplets, cache_bytes=1
     ref = fftref.FFTReference.from_spectrum(w.astype(np.complex128), k_lo, k_hi, box_len=box_len,
                                             cache_bytes=cache_bytes)
     del w
-    sp = ref.bispectrum(triplets)
-    return w2, sp.s / sp.count, sp.count
+    if counts is None:
+        sp = ref.bispectrum(triplets)
+        return w2, sp.s / sp.count, sp.count
+    # the sums of W1 W2 W3 alone, in bin order so the field cache is reused
+    t = np.asarray(triplets, dtype=np.int64).reshape(-1, 3)
+    s = np.zeros(len(t))
+    for i in sorted(range(len(t)), key=lambda i: tuple(sorted(t[i]))):
+        s[i] = ref.grid_sum("F", t[i]) / ref.npix
+    return w2, s / np.asarray(counts, dtype=np.float64), np.asarray(counts, dtype=np.float64)

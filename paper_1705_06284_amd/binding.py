@@ -63,6 +63,7 @@ _SIGS = {
     "trispec_connected_estimate": [_vp, _vp, _i32, _vp, _vp],
     "trispec_diag_estimate": [_vp, _vp, _i32, _vp, _vp],
     "bispec_plan_query_dquads": [_vp, _ip, _dp],
+    "bispec_set_count_memory": [ctypes.c_size_t],
     "polyspec_estimate": [_vp, _vp, _i32, _vp, _vp, _vp],
     "polyspec_estimate_noalloc": [_vp, _vp, _i32, _vp, _vp, _vp],
     "bispec_timing_enable": [_vp, _i32],
@@ -99,6 +100,7 @@ trispec_estimate = _lib.trispec_estimate
 trispec_connected_estimate = _lib.trispec_connected_estimate
 trispec_diag_estimate = _lib.trispec_diag_estimate
 bispec_plan_query_dquads = _lib.bispec_plan_query_dquads
+bispec_set_count_memory = _lib.bispec_set_count_memory
 polyspec_estimate = _lib.polyspec_estimate
 polyspec_estimate_noalloc = _lib.polyspec_estimate_noalloc
 bispec_timing_enable = _lib.bispec_timing_enable

@@ -807,25 +807,68 @@ bispec_status compute_dquad_counts(bispec_plan_s &p) {
     return BISPEC_OK;
 }
 
-// Count fields and sums of a general grid: unit-amplitude fields of every
-// bin in FP64 by the mixed-radix transforms, then the compensated FP64 term sums.
-bispec_status compute_counts_general(bispec_plan_s &p, std::vector<int> &cand_tri, std::vector<double> &tri_cnt,
-                                     std::vector<double> &quad_cnt) {
-    const int nb = p.nb;
+// Temporary memory the count passes may hold in unit fields (0: half the
+// free device memory at plan time); bispec_set_count_memory.
+std::atomic<size_t> g_count_memory{0};
+
+// Grid sums sum_n prod I_b(n) of every term over the FP64 unit fields (field
+// length flen), the bins made in pairs (2q, 2q+1) by make_pair(q, f1, f2).
+// When the fields of all pairs fit the count memory they are made once and
+// every term is contracted over them.  Else the pairs go in groups of
+// g = (pairs that fit) / 4; for each set of at most four groups that some
+// term touches, in turn, the fields of its pairs are made and its terms
+// contracted -- the fields are made again for every set, the memory stays
+// within the limit.
+template <class MakePair>
+bispec_status count_term_sums(bispec_plan_s &p, const std::vector<uchar4> &terms, int64_t flen, MakePair make_pair,
+                              std::vector<double> &sums) {
     hipStream_t st = p.stream;
-    const std::vector<uchar4> terms = count_terms(p, cand_tri);
-    const int nterm = (int)terms.size(), ntri = (int)cand_tri.size() / 3;
-    const int64_t fs = p.fstride;
-    const int nblk = contract_blocks(fs);
-    const std::vector<double2> tw = gen_twiddles<double2, double>(p.gg);
+    const int nb = p.nb, npairs = (nb + 1) / 2, nterm = (int)terms.size();
+    const size_t pair_bytes = 2 * sizeof(double) * (size_t)flen;
+    size_t limit = g_count_memory.load();
+    if (limit == 0) {
+        size_t fr = 0, tot = 0;
+        if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
+            (void)hipGetLastError();
+            fr = 0;
+        }
+        limit = fr / 2;
+    }
+    const int cap = (int)std::min<size_t>((size_t)npairs, std::max<size_t>(1, limit / pair_bytes));
+    const int g = cap >= npairs ? npairs : std::max(1, cap / 4);
+    // terms by the set of pair groups they touch
+    std::vector<std::pair<std::vector<int>, std::vector<int>>> buckets;
+    {
+        std::vector<std::vector<int>> keys(nterm);
+        for (int t = 0; t < nterm; ++t) {
+            const unsigned char b[4] = {terms[t].x, terms[t].y, terms[t].z, terms[t].w};
+            for (int i = 0; i < 4; ++i)
+                if (b[i] != 0xFF) keys[t].push_back((b[i] / 2) / g);
+            std::sort(keys[t].begin(), keys[t].end());
+            keys[t].erase(std::unique(keys[t].begin(), keys[t].end()), keys[t].end());
+        }
+        std::vector<int> order(nterm);
+        std::iota(order.begin(), order.end(), 0);
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return keys[a] < keys[b]; });
+        for (int t : order) {
+            if (buckets.empty() || buckets.back().first != keys[t]) buckets.push_back({keys[t], {}});
+            buckets.back().second.push_back(t);
+        }
+    }
+    size_t max_terms = 0, max_pairs = 0;
+    for (const auto &bk : buckets) {
+        max_terms = std::max(max_terms, bk.second.size());
+        size_t np = 0;
+        for (int grp : bk.first) np += (size_t)std::min(g, npairs - grp * g);
+        max_pairs = std::max(max_pairs, np);
+    }
+    const int nblk = contract_blocks(flen);
     size_t off = 0;
-    const size_t o_tw = off;      off = align_up(off + sizeof(double2) * tw.size());
-    const size_t o_terms = off;   off = align_up(off + sizeof(uchar4) * nterm);
-    const size_t o_ones = off;    off = align_up(off + sizeof(double) * nterm);
-    const size_t o_sums = off;    off = align_up(off + sizeof(double) * nterm);
-    const size_t o_partial = off; off = align_up(off + sizeof(double) * (size_t)nblk * nterm);
-    const size_t o_work = off;    off = align_up(off + sizeof(double2) * (size_t)p.npix);
-    const size_t o_fields = off;  off = align_up(off + sizeof(double) * (size_t)fs * nb);
+    const size_t o_fields = off;  off = align_up(off + pair_bytes * max_pairs);
+    const size_t o_terms = off;   off = align_up(off + sizeof(uchar4) * max_terms);
+    const size_t o_ones = off;    off = align_up(off + sizeof(double) * max_terms);
+    const size_t o_out = off;     off = align_up(off + sizeof(double) * max_terms);
+    const size_t o_partial = off; off = align_up(off + sizeof(double) * (size_t)nblk * max_terms);
     char *mem = nullptr;
     {
         const hipError_t e = hipMalloc((void **)&mem, off);
@@ -840,58 +883,100 @@ bispec_status compute_counts_general(bispec_plan_s &p, std::vector<int> &cand_tr
         char *m;
         ~Free() { (void)hipFree(m); }
     } guard{mem};
-    std::vector<double> ones(nterm, 1.0);
-    CK(hipMemcpyAsync(mem + o_tw, tw.data(), sizeof(double2) * tw.size(), hipMemcpyHostToDevice, st));
-    CK(hipMemcpyAsync(mem + o_terms, terms.data(), sizeof(uchar4) * nterm, hipMemcpyHostToDevice, st));
-    CK(hipMemcpyAsync(mem + o_ones, ones.data(), sizeof(double) * nterm, hipMemcpyHostToDevice, st));
     double *fields = (double *)(mem + o_fields);
-    for (int b = 0; b < nb; b += 2)
-        CK(gen_inverse_unit_f64((double2 *)(mem + o_work), p.gg, gen_pair(p, b), (const double2 *)(mem + o_tw),
-                                fields + (int64_t)b * fs, b + 1 < nb ? fields + (int64_t)(b + 1) * fs : nullptr, st));
-    CK(gen_zero_pads_f64(fields, p.npix, fs, nb, st));
-    CK(launch_contract_terms_f64(fields, fs, nb, (const uchar4 *)(mem + o_terms), nterm, nblk,
-                                 (double *)(mem + o_partial), st));
-    CK(launch_finalize((const double *)(mem + o_partial), nblk, nterm, 1, (const double *)(mem + o_ones),
-                       (double *)(mem + o_sums), nterm, nullptr, 0, nullptr, 0, st));
-    std::vector<double> sums(nterm);
-    CK(hipMemcpyAsync(sums.data(), mem + o_sums, sizeof(double) * nterm, hipMemcpyDeviceToHost, st));
-    CK(hipStreamSynchronize(st));
+    const std::vector<double> ones(max_terms, 1.0);
+    CK(hipMemcpyAsync(mem + o_ones, ones.data(), sizeof(double) * max_terms, hipMemcpyHostToDevice, st));
+    sums.assign(nterm, 0.0);
+    std::vector<int> slot(npairs, -1);
+    std::vector<uchar4> mapped;
+    std::vector<double> out;
+    for (const auto &bk : buckets) {
+        std::fill(slot.begin(), slot.end(), -1);
+        int ns = 0;
+        for (int grp : bk.first)
+            for (int q = grp * g; q < std::min(npairs, (grp + 1) * g); ++q) {
+                slot[q] = ns;
+                CK(make_pair(q, fields + (int64_t)(2 * ns) * flen,
+                             2 * q + 1 < nb ? fields + (int64_t)(2 * ns + 1) * flen : nullptr));
+                ++ns;
+            }
+        const int n = (int)bk.second.size();
+        mapped.resize(n);
+        auto remap = [&](unsigned char b) {
+            return b == 0xFF ? b : (unsigned char)(2 * slot[b / 2] + (b % 2));
+        };
+        for (int i = 0; i < n; ++i) {
+            const uchar4 u = terms[bk.second[i]];
+            mapped[i] = uchar4{remap(u.x), remap(u.y), remap(u.z), remap(u.w)};
+        }
+        CK(hipMemcpyAsync(mem + o_terms, mapped.data(), sizeof(uchar4) * n, hipMemcpyHostToDevice, st));
+        CK(launch_contract_terms_f64(fields, flen, 2 * ns, (const uchar4 *)(mem + o_terms), n, nblk,
+                                     (double *)(mem + o_partial), st));
+        CK(launch_finalize((const double *)(mem + o_partial), nblk, n, 1, (const double *)(mem + o_ones),
+                           (double *)(mem + o_out), n, nullptr, 0, nullptr, 0, st));
+        out.resize(n);
+        CK(hipMemcpyAsync(out.data(), mem + o_out, sizeof(double) * n, hipMemcpyDeviceToHost, st));
+        CK(hipStreamSynchronize(st));
+        for (int i = 0; i < n; ++i) sums[bk.second[i]] = out[i];
+    }
+    return BISPEC_OK;
+}
+
+// Count fields and sums of a general grid: unit-amplitude fields of every
+// bin in FP64 by the mixed-radix transforms, then the compensated FP64 term sums.
+bispec_status compute_counts_general(bispec_plan_s &p, std::vector<int> &cand_tri, std::vector<double> &tri_cnt,
+                                     std::vector<double> &quad_cnt) {
+    hipStream_t st = p.stream;
+    const std::vector<uchar4> terms = count_terms(p, cand_tri);
+    const int ntri = (int)cand_tri.size() / 3;
+    const int64_t fs = p.fstride;
+    const std::vector<double2> tw = gen_twiddles<double2, double>(p.gg);
+    size_t off = 0;
+    const size_t o_tw = off;      off = align_up(off + sizeof(double2) * tw.size());
+    const size_t o_work = off;    off = align_up(off + sizeof(double2) * (size_t)p.npix);
+    char *mem = nullptr;
+    {
+        const hipError_t e = hipMalloc((void **)&mem, off);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return record(BISPEC_E_OOM, "hipMalloc for the count transforms", e);
+        }
+    }
+    struct Free {
+        char *m;
+        ~Free() { (void)hipFree(m); }
+    } guard{mem};
+    CK(hipMemcpyAsync(mem + o_tw, tw.data(), sizeof(double2) * tw.size(), hipMemcpyHostToDevice, st));
+    auto make_pair = [&](int q, double *f1, double *f2) -> hipError_t {
+        hipError_t e = gen_inverse_unit_f64((double2 *)(mem + o_work), p.gg, gen_pair(p, 2 * q),
+                                            (const double2 *)(mem + o_tw), f1, f2, st);
+        if (e == hipSuccess) e = gen_zero_pads_f64(f1, p.npix, fs, 1, st);
+        if (e == hipSuccess && f2) e = gen_zero_pads_f64(f2, p.npix, fs, 1, st);
+        return e;
+    };
+    std::vector<double> sums;
+    bispec_status s = count_term_sums(p, terms, fs, make_pair, sums);
+    if (s != BISPEC_OK) return s;
     return counts_from_sums(p, sums, ntri, (double)p.npix, tri_cnt, quad_cnt);
 }
 
 // FP64 count fields I_b and their product sums, evaluated on the device.
 bispec_status compute_counts(bispec_plan_s &p, std::vector<int> &cand_tri, std::vector<double> &tri_cnt,
                              std::vector<double> &quad_cnt) {
-    const int n = p.n, nb = p.nb;
+    const int n = p.n;
     const int64_t vol = (int64_t)n * n * n;
     hipStream_t st = p.stream;
-
     // term list: candidate triplets, (b,b) for the mode-count check, quads
-    std::vector<uchar4> terms;
+    const std::vector<uchar4> terms = count_terms(p, cand_tri);
     const int ntri = (int)cand_tri.size() / 3;
-    for (int t = 0; t < ntri; ++t)
-        terms.push_back(uchar4{(unsigned char)cand_tri[3 * t], (unsigned char)cand_tri[3 * t + 1],
-                               (unsigned char)cand_tri[3 * t + 2], 0xFF});
-    for (int b = 0; b < nb; ++b) terms.push_back(uchar4{(unsigned char)b, (unsigned char)b, 0xFF, 0xFF});
-    const int nq = (int)p.quad.size() / 4;
-    for (int q = 0; q < nq; ++q)
-        terms.push_back(uchar4{(unsigned char)p.quad[4 * q], (unsigned char)p.quad[4 * q + 1],
-                               (unsigned char)p.quad[4 * q + 2], (unsigned char)p.quad[4 * q + 3]});
-    const int nterm = (int)terms.size();
-    const int nblk = contract_blocks(vol);
 
     std::vector<double2> tw(n);
     for (int i = 0; i < n; ++i) {
         const double a = 2.0 * M_PI * (double)i / (double)n;
         tw[i] = double2{std::cos(a), -std::sin(a)};
     }
-
     size_t off = 0;
     const size_t o_tw = off;      off = align_up(off + sizeof(double2) * n);
-    const size_t o_terms = off;   off = align_up(off + sizeof(uchar4) * nterm);
-    const size_t o_ones = off;    off = align_up(off + sizeof(double) * nterm);
-    const size_t o_sums = off;    off = align_up(off + sizeof(double) * nterm);
-    const size_t o_partial = off; off = align_up(off + sizeof(double) * (size_t)nblk * nterm);
     const size_t o_cols = off;    off = align_up(off + sizeof(int) * p.cols.size());
     const size_t o_abox = off;    off = align_up(off + sizeof(double2) * (size_t)n * p.wmax * p.wpmax);
     const size_t o_bc = off;      off = align_up(off + sizeof(double2) * (size_t)n * n * p.wpmax);
@@ -902,66 +987,49 @@ bispec_status compute_counts(bispec_plan_s &p, std::vector<int> &cand_tri, std::
         max_tab = std::max(max_tab, (size_t)(p.col_n[q] + G64 - 1) / G64 + (size_t)(n * p.pairs[q].Wp + G64 - 1) / G64);
     const size_t o_pd = off;      off = align_up(off + sizeof(PairDev) * p.pairs.size());
     const size_t o_tab = off;     off = align_up(off + sizeof(int2) * max_tab * p.pairs.size());
-    const size_t o_fields = off;  off = align_up(off + sizeof(double) * vol * nb);
     char *mem = nullptr;
     {
         const hipError_t e = hipMalloc((void **)&mem, off);
         if (e != hipSuccess) {
             (void)hipGetLastError();
-            char what[128];
-            std::snprintf(what, sizeof(what), "hipMalloc of %zu bytes for the count fields", off);
-            return record(BISPEC_E_OOM, what, e);
+            return record(BISPEC_E_OOM, "hipMalloc for the count transforms", e);
         }
     }
     struct Free {
         char *m;
         ~Free() { (void)hipFree(m); }
     } guard{mem};
-
-    std::vector<double> ones(nterm, 1.0);
     CK(hipMemcpyAsync(mem + o_tw, tw.data(), sizeof(double2) * n, hipMemcpyHostToDevice, st));
-    CK(hipMemcpyAsync(mem + o_terms, terms.data(), sizeof(uchar4) * nterm, hipMemcpyHostToDevice, st));
-    CK(hipMemcpyAsync(mem + o_ones, ones.data(), sizeof(double) * nterm, hipMemcpyHostToDevice, st));
     CK(hipMemcpyAsync(mem + o_cols, p.cols.data(), sizeof(int) * p.cols.size(), hipMemcpyHostToDevice, st));
-    double *fields = (double *)(mem + o_fields);
-    {
-        std::vector<PairDev> pd;
-        std::vector<int2> tabs;
-        std::vector<size_t> ztab_at, ytab_at;
-        std::vector<int> nz, ny;
-        for (size_t q = 0; q < p.pairs.size(); ++q) {
-            PairDev d{};
-            d.g = p.pairs[q];
-            d.col_off = p.col_off[q];
-            d.ncols = p.col_n[q];
-            pd.push_back(d);                    // boxes shared by all pairs: offsets 0
-            ztab_at.push_back(tabs.size());
-            for (int c0 = 0; c0 < d.ncols; c0 += G64) tabs.push_back(int2{(int)q, c0});
-            nz.push_back((int)(tabs.size() - ztab_at.back()));
-            ytab_at.push_back(tabs.size());
-            for (int c0 = 0; c0 < n * d.g.Wp; c0 += G64) tabs.push_back(int2{(int)q, c0});
-            ny.push_back((int)(tabs.size() - ytab_at.back()));
-        }
-        CK(hipMemcpyAsync(mem + o_pd, pd.data(), sizeof(PairDev) * pd.size(), hipMemcpyHostToDevice, st));
-        CK(hipMemcpyAsync(mem + o_tab, tabs.data(), sizeof(int2) * tabs.size(), hipMemcpyHostToDevice, st));
-        const int2 *tab = (const int2 *)(mem + o_tab);
-        for (size_t q = 0; q < p.pairs.size(); ++q) {
-            const int b = 2 * (int)q;
-            CK(launch_inverse_unit_f64(n, (const double2 *)(mem + o_tw), (const PairDev *)(mem + o_pd), p.pairs[q],
-                                       tab + ztab_at[q], nz[q], tab + ytab_at[q], ny[q], (const int *)(mem + o_cols),
-                                       (double2 *)(mem + o_abox), (double2 *)(mem + o_bc),
-                                       fields + (int64_t)b * vol,
-                                       b + 1 < nb ? fields + (int64_t)(b + 1) * vol : nullptr, st));
-        }
-        CK(hipStreamSynchronize(st));   // host vectors above must outlive the copies
+    std::vector<PairDev> pd;
+    std::vector<int2> tabs;
+    std::vector<size_t> ztab_at, ytab_at;
+    std::vector<int> nz, ny;
+    for (size_t q = 0; q < p.pairs.size(); ++q) {
+        PairDev d{};
+        d.g = p.pairs[q];
+        d.col_off = p.col_off[q];
+        d.ncols = p.col_n[q];
+        pd.push_back(d);                    // boxes shared by all pairs: offsets 0
+        ztab_at.push_back(tabs.size());
+        for (int c0 = 0; c0 < d.ncols; c0 += G64) tabs.push_back(int2{(int)q, c0});
+        nz.push_back((int)(tabs.size() - ztab_at.back()));
+        ytab_at.push_back(tabs.size());
+        for (int c0 = 0; c0 < n * d.g.Wp; c0 += G64) tabs.push_back(int2{(int)q, c0});
+        ny.push_back((int)(tabs.size() - ytab_at.back()));
     }
-    CK(launch_contract_terms_f64(fields, vol, nb, (const uchar4 *)(mem + o_terms), nterm, nblk,
-                                 (double *)(mem + o_partial), st));
-    CK(launch_finalize((const double *)(mem + o_partial), nblk, nterm, 1, (const double *)(mem + o_ones),
-                       (double *)(mem + o_sums), nterm, nullptr, 0, nullptr, 0, st));
-    std::vector<double> sums(nterm);
-    CK(hipMemcpyAsync(sums.data(), mem + o_sums, sizeof(double) * nterm, hipMemcpyDeviceToHost, st));
-    CK(hipStreamSynchronize(st));
+    CK(hipMemcpyAsync(mem + o_pd, pd.data(), sizeof(PairDev) * pd.size(), hipMemcpyHostToDevice, st));
+    CK(hipMemcpyAsync(mem + o_tab, tabs.data(), sizeof(int2) * tabs.size(), hipMemcpyHostToDevice, st));
+    CK(hipStreamSynchronize(st));   // host vectors above must outlive the copies
+    const int2 *tab = (const int2 *)(mem + o_tab);
+    auto make_pair = [&](int q, double *f1, double *f2) -> hipError_t {
+        return launch_inverse_unit_f64(n, (const double2 *)(mem + o_tw), (const PairDev *)(mem + o_pd), p.pairs[q],
+                                       tab + ztab_at[q], nz[q], tab + ytab_at[q], ny[q], (const int *)(mem + o_cols),
+                                       (double2 *)(mem + o_abox), (double2 *)(mem + o_bc), f1, f2, st);
+    };
+    std::vector<double> sums;
+    bispec_status s = count_term_sums(p, terms, vol, make_pair, sums);
+    if (s != BISPEC_OK) return s;
     return counts_from_sums(p, sums, ntri, (double)vol, tri_cnt, quad_cnt);
 }
 
@@ -1977,6 +2045,11 @@ bispec_status trispec_diag_estimate(bispec_plan_t plan, const float *delta, int3
     } catch (...) {
         return BISPEC_E_HIP;
     }
+}
+
+bispec_status bispec_set_count_memory(size_t bytes) {
+    g_count_memory.store(bytes);
+    return BISPEC_OK;
 }
 
 bispec_status bispec_plan_query_dquads(bispec_plan_t plan, int32_t *n_dquad, double *counts_out) {

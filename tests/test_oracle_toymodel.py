@@ -60,6 +60,9 @@ def test_bin_averages_match_brute_force(shape, L):
     res = oracle.bispectrum(np.zeros(shape, np.float32), lo, hi, trip, box_len=L, delta_k=W.astype(complex))
     assert np.array_equal(cnt.astype(np.int64), res.count)
     assert np.allclose(www, res.s.real / res.count, rtol=1e-12, atol=1e-15)
+    # the same with the counts given (the sums of W1 W2 W3 alone)
+    w2g, wwwg, _ = toymodel.binned_window_moments(shape, lo, hi, L, R, trip, counts=res.count)
+    assert np.allclose(wwwg, www, rtol=1e-13, atol=1e-16) and np.array_equal(w2g, w2)
     # shell means of W^2 by enumeration of the shell modes
     for b in range(3):
         md = oracle.shell_modes(shape, lo, hi, b)
