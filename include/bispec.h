@@ -172,7 +172,13 @@ bispec_status bispec_plan_mode_counts(bispec_plan_t plan, int64_t *modes_out /*[
 
 /* The bin fields F_b(n) of Eq. (delta_nr): fields is a device buffer
  * [batch][n_bins][N^3] FP32 (unnormalised inverse transform, so
- * sum_n F_b(n)^2 = N_pix sum_{m in S_b} |Delta_fft(m)|^2). */
+ * sum_n F_b(n)^2 = N_pix sum_{m in S_b} |Delta_fft(m)|^2).
+ * fields = NULL keeps them resident instead, in the plan's workspace (plans
+ * whose workspace holds the field region: more than 32 bins, general grids,
+ * general quads, ill-conditioned triplets or BISPEC_FP32_VALU; else
+ * BISPEC_E_NO_WORKSPACE), for polyspec_estimate with delta = NULL.  Any
+ * polyspec_estimate with a map on such a plan also leaves that map's fields
+ * resident. */
 bispec_status bispec_bin_fields(bispec_plan_t plan, const float *delta, int32_t batch,
                                 float *fields);
 
@@ -239,7 +245,11 @@ bispec_status trispec_diag_estimate(bispec_plan_t plan, const float *delta, int3
 bispec_status bispec_plan_query_dquads(bispec_plan_t plan, int32_t *n_dquad, double *counts_out);
 
 /* P, B and T from one set of bin fields (lower orders at no extra FFT cost,
- * Section 2 after Eq. Jeong_BI).  Any of P, B, T may be NULL. */
+ * Section 2 after Eq. Jeong_BI).  Any of P, B, T may be NULL.  delta = NULL
+ * contracts the fields resident in the workspace (the last
+ * bispec_bin_fields(fields = NULL) or estimate on a field-region plan, of
+ * the same batch; BISPEC_E_INVALID otherwise, and on plans whose contraction
+ * is fused with the last transform). */
 bispec_status polyspec_estimate(bispec_plan_t plan, const float *delta, int32_t batch,
                                 double *P, double *B, double *T);
 

@@ -368,10 +368,15 @@ class Plan:
             if t is not None:
                 t.record_stream(self.stream)
 
-    def polyspec(self, delta, want_p=True, want_b=True, want_t=True, out=None):
-        """(P, B, T) device tensors [batch, ...]; entries not wanted are None."""
-        d = self._input(delta)
-        bsz = d.shape[0]
+    def polyspec(self, delta, want_p=True, want_b=True, want_t=True, out=None, batch=None):
+        """(P, B, T) device tensors [batch, ...]; entries not wanted are None.
+        delta None: the bin fields resident in the workspace (of ``batch``
+        maps; see bin_fields(keep=True))."""
+        if delta is None:
+            d, bsz = None, int(batch or 1)
+        else:
+            d = self._input(delta)
+            bsz = d.shape[0]
         if out is None:
             P = self._empty(bsz, self.n_bins) if want_p else None
             B = self._empty(bsz, self.n_tri) if want_b else None
@@ -380,7 +385,7 @@ class Plan:
             P, B, T = out
         self._enter()
         check(polyspec_estimate(self.handle, _ptr(d), bsz, _ptr(P), _ptr(B), _ptr(T)), "polyspec_estimate")
-        self._leave(d, P, B, T)
+        self._leave(*[x for x in (d, P, B, T) if x is not None])
         return P, B, T
 
     def estimate(self, delta, want_p=True):
@@ -430,9 +435,16 @@ class Plan:
         self._leave(d, Td, *([Tdc] if connected else []))
         return Td, Tdc
 
-    def bin_fields(self, delta):
+    def bin_fields(self, delta, keep=False):
+        """Device tensor [batch, n_bins, *shape] of the bin fields; keep=True
+        leaves them in the workspace instead (returns None)."""
         d = self._input(delta)
         bsz = d.shape[0]
+        if keep:
+            self._enter()
+            check(bispec_bin_fields(self.handle, _ptr(d), bsz, None), "bispec_bin_fields")
+            self._leave(d)
+            return None
         f = self._torch.empty((bsz, self.n_bins) + self.shape, dtype=self._torch.float32, device=self.device)
         self._enter()
         check(bispec_bin_fields(self.handle, _ptr(d), bsz, _ptr(f)), "bispec_bin_fields")

@@ -1509,8 +1509,15 @@ bispec_status run_estimate_body(bispec_plan_s &p, const float *delta, int batch,
     if (!mfma) {
         float *fields = (float *)(ws + L.fields);
         const int64_t fl = field_len(p);
-        bispec_status s = run_fields(p, delta, batch, fields, fl, true, spec_scale(p));
-        if (s != BISPEC_OK) return s;
+        bispec_status s = BISPEC_OK;
+        if (delta) {
+            p.resident = 0;
+            s = run_fields(p, delta, batch, fields, fl, true, spec_scale(p));
+            if (s != BISPEC_OK) return s;
+            p.resident = batch;          // these maps' fields stay in the workspace
+        } else if (p.resident != batch) {
+            return BISPEC_E_INVALID;
+        }
         // split mode over the fields in HBM (33..128 bins, general grids):
         // the triplets on MFMA; then P and collapsed quads from the
         // product-Gram of the squares (nb not a multiple of 64); what is left
@@ -1674,6 +1681,7 @@ bispec_status bispec_set_workspace(bispec_plan_t plan, void *dev_ptr, size_t byt
     plan->drop_graphs();
     plan->ws = dev_ptr;
     plan->ws_bytes = bytes;
+    plan->resident = 0;
     plan->ws_fields = needs_fields(*plan);
     try {
         bispec_status s = upload_tables(*plan);
@@ -1728,7 +1736,21 @@ bispec_status bispec_plan_mode_counts(bispec_plan_t plan, int64_t *modes_out) {
 bispec_status bispec_bin_fields(bispec_plan_t plan, const float *delta, int32_t batch, float *fields) {
     bispec_status s = check_call(plan, delta, batch);
     if (s != BISPEC_OK) return s;
-    if (!fields) return BISPEC_E_INVALID;
+    if (!fields) {
+        // keep the fields resident in the workspace for polyspec_estimate(delta = NULL)
+        if (!plan->ws_fields) return BISPEC_E_NO_WORKSPACE;
+        try {
+            const Layout L = make_layout(*plan, plan->max_batch);
+            plan->resident = 0;
+            bispec_status st = run_fields(*plan, delta, batch, (float *)((char *)plan->ws + L.fields),
+                                          field_len(*plan), true, spec_scale(*plan));
+            stamp_rest(*plan, 3);
+            if (st == BISPEC_OK) plan->resident = batch;
+            return st;
+        } catch (...) {
+            return BISPEC_E_HIP;
+        }
+    }
     try {
         const int64_t len = plan->general ? plan->npix : (int64_t)plan->n * plan->n * plan->n;
         bispec_status st = run_fields(*plan, delta, batch, fields, len, false, 1.0);   // the fields as defined
@@ -1741,8 +1763,11 @@ bispec_status bispec_bin_fields(bispec_plan_t plan, const float *delta, int32_t 
 
 bispec_status polyspec_estimate(bispec_plan_t plan, const float *delta, int32_t batch, double *P, double *B,
                                 double *T) {
-    bispec_status s = check_call(plan, delta, batch);
+    // delta = NULL: contract the bin fields resident in the workspace
+    bispec_status s = check_call(plan, delta ? delta : (const float *)plan, batch);
     if (s != BISPEC_OK) return s;
+    if (!delta && (plan->resident != batch || (plan->mfma_ok && plan->precision != BISPEC_FP32_VALU)))
+        return BISPEC_E_INVALID;
     try {
         bispec_plan_s &p = *plan;
         if (!p.use_graph || p.timing || p.stream == nullptr) return run_estimate(p, delta, batch, P, B, T);

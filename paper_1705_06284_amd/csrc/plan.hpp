@@ -48,6 +48,7 @@ struct bispec_plan_s {
     void *ws = nullptr;
     size_t ws_bytes = 0;
     bool ws_fields = false;              // workspace holds the bin-field region
+    int resident = 0;                    // maps whose bin fields the region holds (0: none)
     // pruned inverse transform: bins paired (2q, 2q+1)
     std::vector<bispec::PairGeom> pairs;
     std::vector<int> cols;               // active z-pass columns of all pairs

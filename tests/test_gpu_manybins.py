@@ -108,3 +108,31 @@ def test_bin_fields_beyond_64(binding):
         M = (q > 0) & (q >= lo[b] ** 2) & (q < hi[b] ** 2)
         ref = np.fft.ifftn(D * M).real * 32 ** 3
         assert np.max(np.abs(F[b] - ref)) <= 2e-6 * max(np.max(np.abs(ref)), 1e-30), b
+
+
+def test_resident_bin_fields(binding):
+    """bin_fields(keep=True) leaves the fields in the workspace and
+    polyspec(None) contracts them: bitwise the same P, B, T as from the map;
+    an estimate from a map leaves its fields resident too.  Plans whose
+    contraction is fused with the last transform have no field region."""
+    shape, nb = (32, 32, 32), 70
+    lo, hi = _one_radius_bins(32, nb)
+    maps = np.stack([_field(shape, seed=s) for s in (21, 22)])
+    plan = binding.Plan(shape, lo, hi, precision="split_bf16", max_batch=2)
+    ref = plan.polyspec(maps)
+    plan.bin_fields(maps[:1], keep=True)
+    with pytest.raises(binding.BispecError) as ei:
+        plan.polyspec(None, batch=2)             # one map resident, not two
+    assert ei.value.code == -1
+    one = plan.polyspec(None, batch=1)
+    plan.polyspec(maps)                           # leaves both maps' fields resident
+    two = plan.polyspec(None, batch=2)
+    for a, b, c in zip(ref, one, two):
+        assert torch.equal(a[:1], b) and torch.equal(a, c)
+    fused = binding.Plan(32, *synth.linear_bins(32, 8), precision="split_bf16")
+    with pytest.raises(binding.BispecError) as ei:
+        fused.bin_fields(maps[0], keep=True)
+    assert ei.value.code == -5
+    with pytest.raises(binding.BispecError) as ei:
+        fused.polyspec(None)
+    assert ei.value.code == -1
