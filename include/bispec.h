@@ -78,7 +78,7 @@ typedef enum {
  * F_b^2 and ones); general quads, and P and T when n_bins is 64 or 128, run
  * on the vector ALUs.  Mode 0 runs as mode 2 there.
  * In modes 0 and 1, triplets whose condition number
- * kappa_t = sqrt(M_i M_j M_k / (N_pix N_t)) exceeds 2 (shells narrower than
+ * kappa_t = sqrt(M_i M_j M_k / (N_pix N_t)) exceeds 2.5 (shells narrower than
  * k_f near the edge of the triangle inequality; bispec_plan_condition) are
  * read instead from product-Gram rows of their own on the FP64 matrix cores,
  * over the bin fields in HBM, so their error stays at the level of the FP32

@@ -54,8 +54,8 @@ constexpr int PG_TK_TAIL = 512;           // grid points per LDS tile of the fus
 // LDS tile; tiles are at least one x-row of N points):
 //   wide: 1024 threads, one tile per wave, 512 points (up to 16 pair
 //         tiles, 4 waves per SIMD);
-//   deep: 512 threads, up to three tiles per wave, 512 points, next tile
-//         prefetched into registers;
+//   deep: 512 threads, up to three tiles per wave, 512 points (no prefetch:
+//         its registers spilled, and without them the shape is 15 % faster);
 //   twin: 512 threads, one tile per wave, 256 points (N <= 256, up to 8
 //         pair tiles): half the LDS of the others, so two blocks share a CU
 //         and one block's transforms overlap the other's contraction.
@@ -830,7 +830,7 @@ hipError_t launch_tail_m(const float2 *bc, const TailPairs &tp, int n, int nb, i
             hipLaunchKernelGGL((k_tail<MODE, WANT_T, NN, PG_NT_WIDE, PG_MAXT_WIDE, PG_TK_TAIL, 4, PG_WIDE_PREFETCH>), dim3(nblk, batch),
                                dim3(PG_NT_WIDE), 0, st, bc, tp, nb, pairs, n_mtile, tw, per_w, ks, partial);
         else if (sh == PG_SHAPE_DEEP)
-            hipLaunchKernelGGL((k_tail<MODE, WANT_T, NN, PG_NT_DEEP, PG_MAXT_DEEP, PG_TK_TAIL, 2, true>), dim3(nblk, batch),
+            hipLaunchKernelGGL((k_tail<MODE, WANT_T, NN, PG_NT_DEEP, PG_MAXT_DEEP, PG_TK_TAIL, 2, false>), dim3(nblk, batch),
                                dim3(PG_NT_DEEP), 0, st, bc, tp, nb, pairs, n_mtile, tw, per_w, ks, partial);
         else if constexpr (NN <= PG_TK_TWIN) {
             constexpr int TKT = NN >= PG_TK_TWIN ? NN : PG_TK_TWIN;

@@ -131,8 +131,9 @@ struct Layout {
 // this run on the FP64 refinement rows: split-BF16 rounding measures up to
 // about 3e-5 kappa relative to the noise level on narrow shells (plus a
 // kappa-independent part from the FP32 accumulation), so the bar of 1e-4
-// keeps a margin of about 1.5 only below kappa = 2.
-constexpr double kRefineKappa = 2.0;
+// keeps a margin of about 1.3 at kappa = 2.5.  Linear bins of a few k_f
+// stay below it (max 2.03 at 256^3 with 24 bins, 2.07 at 512^3 with 32).
+constexpr double kRefineKappa = 2.5;
 
 // Doubles of the refinement pass's dense tiles per map.
 size_t refine_dense_doubles(const bispec_plan_s &p);

@@ -256,3 +256,25 @@ def test_onepix_256_sample_all_bins_both_precisions(binding):
     for prec in ("split_bf16", "fp32"):
         plan.set_precision(prec)
         _check_all(plan, dt, z, prec, "one-pixel 256")
+
+
+@pytest.mark.parametrize("wl", ["toy600_xhi099", "toy600_xhi088"])
+def test_toy600_sample(binding, wl):
+    """The ionised-sphere boxes of Section 3.3 on the mixed-radix path: 600^3
+    cells of 1 Mpc, 61 shells of 2 k_f, every equilateral and the k2 = 2 k1
+    families of the paper's figure, and P of every shell, in both
+    precisions."""
+    path = os.path.join(HERE, "golden", "%s.fftref.npz" % wl)
+    if not os.path.exists(path):
+        pytest.skip("no stored values for %s" % wl)
+    z, d = _load(wl)
+    lo, hi = synth.workload_bins(wl)
+    L = float(z["box_len"])
+    _say("%s: 600^3, %d triplets" % (wl, len(z["triplets"])))
+    plan = binding.Plan(600, lo, hi, triplets=z["triplets"], quads=[(0, 0, 1, 1)], box_len=L,
+                        precision="split_bf16")
+    _check_plan_sets(plan, z)
+    dt = torch.from_numpy(d).cuda()
+    for prec in ("split_bf16", "fp32"):
+        plan.set_precision(prec)
+        _check_all(plan, dt, z, prec, wl)
