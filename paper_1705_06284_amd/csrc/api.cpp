@@ -77,7 +77,7 @@ bool needs_fields(const bispec_plan_s &p) {
     return p.general || !p.mfma_ok || !p.quads_collapsed || p.precision == BISPEC_FP32_VALU || p.n_mtile_r > 0;
 }
 
-size_t refine_dense_doubles(const bispec_plan_s &p) { return (size_t)p.n_mtile_r * 2048; }
+size_t refine_dense_doubles(const bispec_plan_s &p) { return p.refine_valu ? 0 : (size_t)p.n_mtile_r * 2048; }
 
 // Dense tile entries of the fields product-Gram (33..128 bins, general
 // grids): [n_mtile][32][64], or the squares pass's [n_cgroup*sq_tiles][32][64].
@@ -142,6 +142,10 @@ Layout make_layout(const bispec_plan_s &p, int batch) {
     L.pg_dense_r = off;   off = align_up(off + sizeof(double) * rd * batch);
     L.pg_tmp_r = off;     off = align_up(off + sizeof(double) * rd * PG_REDUCE_SEGS * batch);
     L.refine_t = off;     off = align_up(off + sizeof(int) * p.refine_t.size());
+    L.ref_terms = off;    off = align_up(off + sizeof(uchar4) * p.refine_terms.size());
+    L.ref_scale = off;    off = align_up(off + sizeof(double) * p.refine_scale.size());
+    L.ref_out = off;      off = align_up(off + sizeof(double) * p.refine_terms.size() * batch);
+    L.ref_tmp = off;      off = align_up(off + sizeof(double) * p.refine_terms.size() * PG_REDUCE_SEGS * batch);
     // bin fields in HBM: only the vector-ALU contraction and general quads read them
     L.fields = off;
     if (needs_fields(p)) off = align_up(off + sizeof(float) * vol * p.nb * batch);
@@ -444,6 +448,18 @@ void build_pgram_tables(bispec_plan_s &p) {
     p.n_mtile = (int)p.pg_pairs.size() / 32;
     lay_out(grp_r, Gr, row_of_r, p.pg_pairs_r, p.pg_gtile_r, zero2r);
     p.n_mtile_r = (int)p.pg_pairs_r.size() / 32;
+    // an FP64 tile computes 32 x 64 sums per point at a third of the vector
+    // ALUs' cost per sum; with fewer than a third of them wanted (one-k_f
+    // shells: about one flattened triplet per row) the vector ALUs are cheaper
+    p.refine_valu = !ref_t.empty() && (double)ref_t.size() < (2048.0 / 3.0) * p.n_mtile_r;
+    p.refine_terms.clear();
+    p.refine_scale.clear();
+    if (p.refine_valu)
+        for (int t : ref_t) {
+            p.refine_terms.push_back(uchar4{(unsigned char)p.tri[3 * t], (unsigned char)p.tri[3 * t + 1],
+                                            (unsigned char)p.tri[3 * t + 2], 0xFF});
+            p.refine_scale.push_back(p.scale.empty() ? 0.0 : p.scale[t]);
+        }
     const int ncol = wide ? 64 : 32;
     auto dense = [ncol](int row, int c) { return (row / 32) * 32 * ncol + (row % 32) * ncol + c; };
     for (int t = 0; t < ntri; ++t) {
@@ -451,6 +467,7 @@ void build_pgram_tables(bispec_plan_s &p) {
         const std::vector<int> &ro = r ? row_of_r : row_of;
         const std::vector<int> &it = r ? tp_r : tp;
         int idx = -1;
+        if (r && p.refine_valu) idx = 0;   // written over afterwards (the vector-ALU terms)
         for (int k = 0; k < 3 && idx < 0; ++k)
             if (ro[it[3 * t + k]] >= 0) {
                 const int row = ro[it[3 * t + k]], c = rest[3 * t + k];
@@ -1278,6 +1295,12 @@ bispec_status upload_tables(bispec_plan_s &p) {
             CK(hipMemcpyAsync(ws + L.refine_t, p.refine_t.data(), sizeof(int) * p.refine_t.size(),
                               hipMemcpyHostToDevice, p.stream));
         }
+        if (p.refine_valu) {
+            CK(hipMemcpyAsync(ws + L.ref_terms, p.refine_terms.data(), sizeof(uchar4) * p.refine_terms.size(),
+                              hipMemcpyHostToDevice, p.stream));
+            CK(hipMemcpyAsync(ws + L.ref_scale, p.refine_scale.data(), sizeof(double) * p.refine_scale.size(),
+                              hipMemcpyHostToDevice, p.stream));
+        }
     }
     const int ndq = (int)p.dquad.size() / 5;
     if (ndq > 0) {
@@ -1480,6 +1503,30 @@ bispec_status finalize_range(bispec_plan_s &p, bool gather, const double *partia
     return BISPEC_OK;
 }
 
+// The ill-conditioned triplets as FP64-product terms on the vector ALUs
+// over the bin fields, written over their entries of B (after B's own
+// finalisation).
+bispec_status refine_valu_run(bispec_plan_s &p, const float *fields, int64_t fl, int batch, double *B) {
+    const Layout L = make_layout(p, p.max_batch);
+    char *ws = (char *)p.ws;
+    const int n = (int)p.refine_terms.size();
+    const int ntri = (int)p.tri.size() / 3;
+    double *partial = (double *)(ws + L.partial);
+    // few terms per thread: more, shorter blocks (about 1024 points each)
+    // hide the latency of each term's dependent sum; within the partial
+    // buffer, which holds n_blk x n_terms sums
+    const int64_t want = std::max<int64_t>(p.nblk, std::min<int64_t>(8192, fl / 1024));
+    const int nblk = (int)std::min<int64_t>(want, (int64_t)p.nblk * (int64_t)p.terms.size() / std::max(n, 1));
+    CK(launch_contract_terms_f32x64(fields, fl, p.nb, (int64_t)p.nb * fl, batch, (const uchar4 *)(ws + L.ref_terms),
+                                    n, nblk, partial, p.stream));
+    // fixed-order segmented sums over the blocks, then scale and scatter
+    CK(launch_reduce_dense(partial, nblk, n, batch, (double *)(ws + L.ref_out), (double *)(ws + L.ref_tmp),
+                           p.stream));
+    CK(launch_scatter_list((const double *)(ws + L.ref_out), n, (const int *)(ws + L.refine_t),
+                           (const double *)(ws + L.ref_scale), batch, B, ntri, p.stream));
+    return BISPEC_OK;
+}
+
 // VALU contraction of terms [first, last) followed by their reduction.
 bispec_status valu_terms(bispec_plan_s &p, const float *fields, int first, int last, int batch, double *P, double *B,
                          double *T) {
@@ -1532,7 +1579,7 @@ bispec_status run_estimate_body(bispec_plan_s &p, const float *delta, int batch,
             CK(pgram_groups(p, fields, fl, batch, (const uchar2 *)(ws + L.pg_pairs), p.pg_gtile, false, p.nblk_wide,
                             pg));
             CK(launch_reduce_dense(pg, p.nblk_wide, n_dense, batch, dense, (double *)(ws + L.pg_tmp), p.stream));
-            if (p.n_mtile_r > 0) {
+            if (p.n_mtile_r > 0 && !p.refine_valu) {
                 // ill-conditioned triplets: FP64 product-Gram rows of their own
                 double *pr = (double *)(ws + L.pg_partial_r);
                 CK(pgram_groups(p, fields, fl, batch, (const uchar2 *)(ws + L.pg_pairs_r), p.pg_gtile_r, true,
@@ -1542,6 +1589,10 @@ bispec_status run_estimate_body(bispec_plan_s &p, const float *delta, int batch,
             }
             s = finalize_range(p, true, dense, 1, n_dense, 0, ntri, batch, P, B, T);
             if (s != BISPEC_OK) return s;
+            if (p.refine_valu) {
+                s = refine_valu_run(p, fields, fl, batch, B);
+                if (s != BISPEC_OK) return s;
+            }
             first = ntri;
             if (first == last && !T) return BISPEC_OK;
         }
@@ -1569,6 +1620,8 @@ bispec_status run_estimate_body(bispec_plan_s &p, const float *delta, int batch,
         if (s != BISPEC_OK) return s;
         // ill-conditioned triplets of the vector-ALU route (FP32 mode): the
         // FP64 refinement rows, written over the vector-ALU values
+        if (B && first == 0 && ntri > 0 && p.n_mtile_r > 0 && p.precision != BISPEC_FP32_VALU && p.refine_valu)
+            return refine_valu_run(p, fields, fl, batch, B);
         if (B && first == 0 && ntri > 0 && p.n_mtile_r > 0 && p.precision != BISPEC_FP32_VALU) {
             double *pr = (double *)(ws + L.pg_partial_r);
             CK(pgram_groups(p, fields, fl, batch, (const uchar2 *)(ws + L.pg_pairs_r), p.pg_gtile_r, true, p.nblk_r,
@@ -1607,23 +1660,29 @@ bispec_status run_estimate_body(bispec_plan_s &p, const float *delta, int batch,
                        (const uchar2 *)(ws + L.pg_pairs), p.n_mtile, tw, p.nblk_pg, pg, p.stream, p.tail_shape));
         const int64_t n_dense = (int64_t)pgram_partial_doubles(p.n_mtile, t_mfma);
         const bool refine = first < ntri && p.n_mtile_r > 0;
+        float *rfields = (float *)(ws + L.fields);
         if (refine) {
             // ill-conditioned triplets: the bin fields from the compact rows
-            // (still in place), then FP64 product-Gram rows of their own
-            float *fields = (float *)(ws + L.fields);
+            // (still in place), then FP64 product-Gram rows of their own (or
+            // FP64-product terms on the vector ALUs, after the finalisation)
             CK(launch_inverse_x_pairs((const float2 *)(ws + L.bc), n, batch, tw, (const PairDev *)(ws + L.pd),
-                                      (int)p.pairs.size(), p.nb, fields, p.stream));
-            CK(pgram_groups(p, fields, (int64_t)n * n * n, batch, (const uchar2 *)(ws + L.pg_pairs_r), p.pg_gtile_r,
-                            true, p.nblk_r, (double *)(ws + L.pg_partial_r)));
+                                      (int)p.pairs.size(), p.nb, rfields, p.stream));
+            if (!p.refine_valu)
+                CK(pgram_groups(p, rfields, (int64_t)n * n * n, batch, (const uchar2 *)(ws + L.pg_pairs_r),
+                                p.pg_gtile_r, true, p.nblk_r, (double *)(ws + L.pg_partial_r)));
         }
         stamp(p, 3);
         CK(launch_reduce_dense(pg, p.nblk_pg, n_dense, batch, dense, (double *)(ws + L.pg_tmp), p.stream));
-        if (refine)
+        if (refine && !p.refine_valu)
             CK(launch_reduce_dense((const double *)(ws + L.pg_partial_r), p.nblk_r,
                                    (int64_t)refine_dense_doubles(p), batch, (double *)(ws + L.pg_dense_r),
                                    (double *)(ws + L.pg_tmp_r), p.stream));
         if (first < last) {
             s = finalize_range(p, true, dense, 1, n_dense, first, last, batch, P, B, T);
+            if (s != BISPEC_OK) return s;
+        }
+        if (refine && p.refine_valu && B) {
+            s = refine_valu_run(p, rfields, (int64_t)n * n * n, batch, B);
             if (s != BISPEC_OK) return s;
         }
         if (t_mfma) {

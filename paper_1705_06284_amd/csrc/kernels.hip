@@ -465,13 +465,16 @@ __device__ __forceinline__ void comp_add(double &s, double &c, double x) {
 // FP32 fields: products and per-tile (64 point) sums in FP32, then FP64.
 // FP64 fields (the count fields of the plan): every product is added with
 // compensated FP64 summation, so sums of integer-valued count products stay
-// exact well beyond 2^53 / N_pix.
-template <typename R>
+// exact well beyond 2^53 / N_pix.  FP32 fields with X64 set (the
+// ill-conditioned triplets): products formed in FP64, per-tile sums in
+// FP64, then compensated.
+template <typename R, bool X64>
 __global__ __launch_bounds__(256) void k_contract_terms(const R *__restrict__ fields, int64_t npix, int nb,
                                                         int64_t map_stride, const uchar4 *__restrict__ terms,
                                                         int t0, int nterm_launch, int nterm_total,
                                                         int64_t chunk, double *__restrict__ partial) {
     constexpr bool F64 = sizeof(R) == 8;
+    using P = typename std::conditional<F64 || X64, double, R>::type;   // product and tile-sum type
     extern __shared__ unsigned char smem_raw[];
     R *tile = reinterpret_cast<R *>(smem_raw);   // [CT_TILE][nb]
     const int map = blockIdx.y;
@@ -505,16 +508,18 @@ __global__ __launch_bounds__(256) void k_contract_terms(const R *__restrict__ fi
         for (int q = 0; q < CT_MAXT; ++q) {
             if (q >= nmine) break;
             const uchar4 tm = my_terms[q];
-            R s = R(0);
+            P s = P(0);
             for (int pt = 0; pt < CT_TILE; ++pt) {
                 const R *row = tile + pt * nb;
-                R v = row[tm.x] * row[tm.y];
-                if (tm.z != 0xFF) v *= row[tm.z];
-                if (tm.w != 0xFF) v *= row[tm.w];
+                P v = (P)row[tm.x] * (P)row[tm.y];
+                if (tm.z != 0xFF) v *= (P)row[tm.z];
+                if (tm.w != 0xFF) v *= (P)row[tm.w];
                 if constexpr (F64) comp_add(acc[q], comp[q], v);
                 else s += v;
             }
-            if constexpr (!F64) acc[q] += (double)s;
+            if constexpr (X64) comp_add(acc[q], comp[q], s);
+            else if constexpr (!F64) acc[q] += (double)s;
+            (void)s;
         }
     }
     double *out = partial + ((int64_t)map * gridDim.x + blockIdx.x) * nterm_total + t0;
@@ -849,15 +854,15 @@ int fft_pencils_per_block(int n, bool fp64) {
     return g;
 }
 
-template <typename R>
+template <typename R, bool X64 = false>
 hipError_t launch_contract_terms_t(const R *fields, int64_t npix, int nb, int64_t map_stride, int batch,
                                    const uchar4 *terms, int nterm, int nblk, double *partial, hipStream_t st) {
     const int64_t chunk = ((npix + nblk - 1) / nblk + CT_TILE - 1) / CT_TILE * CT_TILE;
     const size_t smem = (size_t)CT_TILE * nb * sizeof(R);
     for (int t0 = 0; t0 < nterm; t0 += 256 * CT_MAXT) {
         const int nt = nterm - t0 < 256 * CT_MAXT ? nterm - t0 : 256 * CT_MAXT;
-        hipLaunchKernelGGL(k_contract_terms<R>, dim3(nblk, batch), dim3(256), smem, st, fields, npix, nb, map_stride,
-                           terms, t0, nt, nterm, chunk, partial);
+        hipLaunchKernelGGL((k_contract_terms<R, X64>), dim3(nblk, batch), dim3(256), smem, st, fields, npix, nb,
+                           map_stride, terms, t0, nt, nterm, chunk, partial);
     }
     return hipGetLastError();
 }
@@ -865,6 +870,27 @@ hipError_t launch_contract_terms_t(const R *fields, int64_t npix, int nb, int64_
 hipError_t launch_contract_terms_f32(const float *fields, int64_t npix, int nb, int64_t map_stride, int batch,
                                      const uchar4 *terms, int nterm, int nblk, double *partial, hipStream_t st) {
     return launch_contract_terms_t<float>(fields, npix, nb, map_stride, batch, terms, nterm, nblk, partial, st);
+}
+
+hipError_t launch_contract_terms_f32x64(const float *fields, int64_t npix, int nb, int64_t map_stride, int batch,
+                                        const uchar4 *terms, int nterm, int nblk, double *partial, hipStream_t st) {
+    return launch_contract_terms_t<float, true>(fields, npix, nb, map_stride, batch, terms, nterm, nblk, partial, st);
+}
+
+// out[map][list[i]] = scale[i] src[map][i]
+__global__ __launch_bounds__(256) void k_scatter_list(const double *__restrict__ src, int n,
+                                                      const int *__restrict__ list, const double *__restrict__ scale,
+                                                      double *__restrict__ out, int nout) {
+    const int i = blockIdx.x * 256 + threadIdx.x, map = blockIdx.y;
+    if (i < n) out[(int64_t)map * nout + list[i]] = scale[i] * src[(int64_t)map * n + i];
+}
+
+hipError_t launch_scatter_list(const double *src, int n, const int *list, const double *scale, int batch,
+                               double *out, int nout, hipStream_t st) {
+    if (n < 1) return hipSuccess;
+    hipLaunchKernelGGL(k_scatter_list, dim3((n + 255) / 256, batch), dim3(256), 0, st, src, n, list, scale, out,
+                       nout);
+    return hipGetLastError();
 }
 
 hipError_t launch_contract_terms_f64(const double *fields, int64_t npix, int nb, const uchar4 *terms, int nterm,

@@ -40,6 +40,13 @@ int fft_pencils_per_block(int n, bool fp64);
 
 hipError_t launch_contract_terms_f32(const float *fields, int64_t npix, int nb, int64_t map_stride, int batch,
                                      const uchar4 *terms, int nterm, int nblk, double *partial, hipStream_t st);
+// FP32 fields with the products formed and summed in FP64 (the
+// ill-conditioned triplets on the vector ALUs).
+hipError_t launch_contract_terms_f32x64(const float *fields, int64_t npix, int nb, int64_t map_stride, int batch,
+                                        const uchar4 *terms, int nterm, int nblk, double *partial, hipStream_t st);
+// out[map][list[i]] = scale[i] src[map][i], i < n (src [batch][n], out [batch][nout]).
+hipError_t launch_scatter_list(const double *src, int n, const int *list, const double *scale, int batch,
+                               double *out, int nout, hipStream_t st);
 hipError_t launch_contract_terms_f64(const double *fields, int64_t npix, int nb, const uchar4 *terms, int nterm,
                                      int nblk, double *partial, hipStream_t st);
 

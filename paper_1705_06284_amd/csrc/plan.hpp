@@ -93,6 +93,11 @@ struct bispec_plan_s {
     std::vector<uchar2> pg_pairs_r;      // [n_mtile_r*32] row factors of those rows
     std::vector<int> pg_gtile_r;         // first refinement tile of each column group, and the total
     int n_mtile_r = 0;                   // 32-row tiles of refinement rows (0: none)
+    // when those rows would use few of their 2048 entries per tile, the
+    // triplets run instead as FP64-product terms on the vector ALUs
+    bool refine_valu = false;
+    std::vector<uchar4> refine_terms;    // their terms, and the normalisation of each
+    std::vector<double> refine_scale;
     int nblk_r = 1;                      // blocks per map of the refinement pass
     // stage timing: one event per stage boundary per call
     bool timing = false;
@@ -122,7 +127,7 @@ constexpr int kMomBlocks = 2048;
 struct Layout {
     size_t tw, terms, scale, tcount, thr, mom_partial, mom_tmp, mom, pg_pairs, pg_idx, pg_pairs_r, cols, pd, ztab,
         ytab, mean_partial, mean, spec, abox, bc, fields, partial, pg_partial, pg_dense, pg_tmp, pg_partial_r,
-        pg_dense_r, pg_tmp_r, refine_t,
+        pg_dense_r, pg_tmp_r, refine_t, ref_terms, ref_scale, ref_out, ref_tmp,
         // diagonal-binned trispectrum pass (one map at a time)
         dtw, dspec, dwork, dfields, dtmp, dpspec, didx, dtask, dpart, dsums, dcoef, total;
 };
