@@ -17,6 +17,7 @@
 #include <limits>
 #include <new>
 #include <numeric>
+#include <tuple>
 #include <vector>
 
 #include "../../include/bispec.h"
@@ -144,6 +145,10 @@ Layout make_layout(const bispec_plan_s &p, int batch) {
     L.refine_t = off;     off = align_up(off + sizeof(int) * p.refine_t.size());
     L.ref_terms = off;    off = align_up(off + sizeof(uchar4) * p.refine_terms.size());
     L.ref_scale = off;    off = align_up(off + sizeof(double) * p.refine_scale.size());
+    L.ref_list = off;     off = align_up(off + sizeof(int) * p.refine_list.size());
+    L.ref_bins = off;     off = align_up(off + sizeof(int) * p.refine_bins.size());
+    L.ref_partial = off;
+    off = align_up(off + sizeof(double) * p.refine_terms.size() * (p.refine_valu ? p.refine_nblk : 0) * batch);
     L.ref_out = off;      off = align_up(off + sizeof(double) * p.refine_terms.size() * batch);
     L.ref_tmp = off;      off = align_up(off + sizeof(double) * p.refine_terms.size() * PG_REDUCE_SEGS * batch);
     // bin fields in HBM: only the vector-ALU contraction and general quads read them
@@ -327,6 +332,81 @@ void greedy_cover(int nitem, const std::vector<int> &tp, const std::vector<int> 
     }
 }
 
+// Slot table of the vector-ALU refinement (k_refine_terms): the refined
+// triplets in bin order, in launches of refine_slots_per_launch slots split
+// evenly over the waves, each launch staging the bins its slots read.
+void build_refine_slots(bispec_plan_s &p, const std::vector<int> &ref_t) {
+    p.refine_terms.clear();
+    p.refine_scale.clear();
+    p.refine_list.clear();
+    p.refine_bins.clear();
+    p.refine_bins_off.assign(1, 0);
+    p.refine_nbs = 0;
+    if (!p.refine_valu) return;
+    const int nb = p.nb;
+    struct Entry { int x, y, z, t; };
+    std::vector<Entry> es;
+    for (int t : ref_t) {
+        int a[3] = {p.tri[3 * t], p.tri[3 * t + 1], p.tri[3 * t + 2]};
+        std::sort(a, a + 3);
+        es.push_back(Entry{a[0], a[1], a[2], t});
+    }
+    std::sort(es.begin(), es.end(), [](const Entry &a, const Entry &b) {
+        return std::make_tuple(a.x, a.y, a.z, a.t) < std::make_tuple(b.x, b.y, b.z, b.t);
+    });
+    // the most bins any launch stages fixes the slots per wave; a launch of
+    // the larger size can only stage more, so settle it from the top
+    int nbs_plan = 128;
+    for (int pass = 0; pass < 2; ++pass) {
+        const int spl = refine_slots_per_launch(nbs_plan);
+        int most = 0;
+        for (size_t l0 = 0; l0 < es.size(); l0 += spl) {
+            std::vector<char> used(nb, 0);
+            for (size_t i = l0; i < std::min(es.size(), l0 + spl); ++i) used[es[i].x] = used[es[i].y] = used[es[i].z] = 1;
+            most = std::max(most, (int)std::count(used.begin(), used.end(), 1));
+        }
+        if (refine_rows_bucket(most) == refine_rows_bucket(nbs_plan)) break;
+        nbs_plan = most;
+    }
+    // (every launch of spl slots stages at most refine_rows_bucket(nbs_plan)
+    // bins: either the last pass confirmed it, or that bucket is 128 >= nb)
+    p.refine_nbs = nbs_plan;
+    const int spw = refine_slots_per_wave(nbs_plan), spl = refine_slots_per_launch(nbs_plan);
+    const int waves = spl / spw;
+    for (size_t l0 = 0; l0 < es.size(); l0 += spl) {
+        const int m = (int)std::min<size_t>(spl, es.size() - l0);
+        std::vector<int> row(nb, -1);
+        for (int i = 0; i < m; ++i)
+            for (int b : {es[l0 + i].x, es[l0 + i].y, es[l0 + i].z}) row[b] = 0;
+        const int off = (int)p.refine_bins.size();
+        for (int b = 0; b < nb; ++b)
+            if (row[b] == 0) {
+                row[b] = (int)p.refine_bins.size() - off;
+                p.refine_bins.push_back(b);
+            }
+        p.refine_bins_off.push_back((int)p.refine_bins.size());
+        for (int w = 0; w < waves; ++w) {
+            const int i0 = (int)((int64_t)m * w / waves), i1 = (int)((int64_t)m * (w + 1) / waves);
+            for (int q = 0; q < spw; ++q) {
+                if (i0 + q < i1) {
+                    const Entry &e = es[l0 + i0 + q];
+                    p.refine_terms.push_back(uchar4{(unsigned char)row[e.x], (unsigned char)row[e.y],
+                                                    (unsigned char)row[e.z], 0});
+                    p.refine_scale.push_back(p.scale.empty() ? 0.0 : p.scale[e.t]);
+                    p.refine_list.push_back(e.t);
+                } else {
+                    p.refine_terms.push_back(uchar4{0, 0, 0, 0x80});   // empty: reads row 0, not written
+                    p.refine_scale.push_back(0.0);
+                    p.refine_list.push_back(-1);
+                }
+            }
+        }
+    }
+    // about 32 tiles of 256 points per block, at most 1024 blocks per map
+    const int64_t fl = field_len(p);
+    p.refine_nblk = (int)std::max<int64_t>(1, std::min<int64_t>(1024, (fl + 8191) / 8192));
+}
+
 // Rows of the product-Gram.  Fused tail (up to 32 bins): every (b,b) row is
 // kept (rows 0..nb-1, so pair tile 0 holds row (r,r) in lane r, which the
 // p = 4 tile relies on); when nb < 32 column nb is a field of ones, so
@@ -452,14 +532,7 @@ void build_pgram_tables(bispec_plan_s &p) {
     // ALUs' cost per sum; with fewer than a third of them wanted (one-k_f
     // shells: about one flattened triplet per row) the vector ALUs are cheaper
     p.refine_valu = !ref_t.empty() && (double)ref_t.size() < (2048.0 / 3.0) * p.n_mtile_r;
-    p.refine_terms.clear();
-    p.refine_scale.clear();
-    if (p.refine_valu)
-        for (int t : ref_t) {
-            p.refine_terms.push_back(uchar4{(unsigned char)p.tri[3 * t], (unsigned char)p.tri[3 * t + 1],
-                                            (unsigned char)p.tri[3 * t + 2], 0xFF});
-            p.refine_scale.push_back(p.scale.empty() ? 0.0 : p.scale[t]);
-        }
+    build_refine_slots(p, ref_t);
     const int ncol = wide ? 64 : 32;
     auto dense = [ncol](int row, int c) { return (row / 32) * 32 * ncol + (row % 32) * ncol + c; };
     for (int t = 0; t < ntri; ++t) {
@@ -1300,6 +1373,10 @@ bispec_status upload_tables(bispec_plan_s &p) {
                               hipMemcpyHostToDevice, p.stream));
             CK(hipMemcpyAsync(ws + L.ref_scale, p.refine_scale.data(), sizeof(double) * p.refine_scale.size(),
                               hipMemcpyHostToDevice, p.stream));
+            CK(hipMemcpyAsync(ws + L.ref_list, p.refine_list.data(), sizeof(int) * p.refine_list.size(),
+                              hipMemcpyHostToDevice, p.stream));
+            CK(hipMemcpyAsync(ws + L.ref_bins, p.refine_bins.data(), sizeof(int) * p.refine_bins.size(),
+                              hipMemcpyHostToDevice, p.stream));
         }
     }
     const int ndq = (int)p.dquad.size() / 5;
@@ -1504,25 +1581,27 @@ bispec_status finalize_range(bispec_plan_s &p, bool gather, const double *partia
 }
 
 // The ill-conditioned triplets as FP64-product terms on the vector ALUs
-// over the bin fields, written over their entries of B (after B's own
-// finalisation).
+// over the bin fields (k_refine_terms, one launch per slot batch), written
+// over their entries of B (after B's own finalisation).
 bispec_status refine_valu_run(bispec_plan_s &p, const float *fields, int64_t fl, int batch, double *B) {
     const Layout L = make_layout(p, p.max_batch);
     char *ws = (char *)p.ws;
-    const int n = (int)p.refine_terms.size();
+    const int nslot = (int)p.refine_terms.size();
     const int ntri = (int)p.tri.size() / 3;
-    double *partial = (double *)(ws + L.partial);
-    // few terms per thread: more, shorter blocks (about 1024 points each)
-    // hide the latency of each term's dependent sum; within the partial
-    // buffer, which holds n_blk x n_terms sums
-    const int64_t want = std::max<int64_t>(p.nblk, std::min<int64_t>(8192, fl / 1024));
-    const int nblk = (int)std::min<int64_t>(want, (int64_t)p.nblk * (int64_t)p.terms.size() / std::max(n, 1));
-    CK(launch_contract_terms_f32x64(fields, fl, p.nb, (int64_t)p.nb * fl, batch, (const uchar4 *)(ws + L.ref_terms),
-                                    n, nblk, partial, p.stream));
+    const int spl = refine_slots_per_launch(p.refine_nbs);
+    double *partial = (double *)(ws + L.ref_partial);
+    const int nl = (int)p.refine_bins_off.size() - 1;
+    if (nslot != nl * spl) return BISPEC_E_INVALID;
+    for (int l = 0; l < nl; ++l) {
+        const int b0 = p.refine_bins_off[l], nbs = p.refine_bins_off[l + 1] - b0;
+        CK(launch_refine_terms(fields, fl, (int64_t)p.nb * fl, batch, (const int *)(ws + L.ref_bins) + b0, nbs,
+                               p.refine_nbs, (const uchar4 *)(ws + L.ref_terms), l * spl, nslot, p.refine_nblk,
+                               partial, p.stream));
+    }
     // fixed-order segmented sums over the blocks, then scale and scatter
-    CK(launch_reduce_dense(partial, nblk, n, batch, (double *)(ws + L.ref_out), (double *)(ws + L.ref_tmp),
-                           p.stream));
-    CK(launch_scatter_list((const double *)(ws + L.ref_out), n, (const int *)(ws + L.refine_t),
+    CK(launch_reduce_dense(partial, p.refine_nblk, nslot, batch, (double *)(ws + L.ref_out),
+                           (double *)(ws + L.ref_tmp), p.stream));
+    CK(launch_scatter_list((const double *)(ws + L.ref_out), nslot, (const int *)(ws + L.ref_list),
                            (const double *)(ws + L.ref_scale), batch, B, ntri, p.stream));
     return BISPEC_OK;
 }

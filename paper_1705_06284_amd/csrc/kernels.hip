@@ -465,16 +465,14 @@ __device__ __forceinline__ void comp_add(double &s, double &c, double x) {
 // FP32 fields: products and per-tile (64 point) sums in FP32, then FP64.
 // FP64 fields (the count fields of the plan): every product is added with
 // compensated FP64 summation, so sums of integer-valued count products stay
-// exact well beyond 2^53 / N_pix.  FP32 fields with X64 set (the
-// ill-conditioned triplets): products formed in FP64, per-tile sums in
-// FP64, then compensated.
-template <typename R, bool X64>
+// exact well beyond 2^53 / N_pix.
+template <typename R>
 __global__ __launch_bounds__(256) void k_contract_terms(const R *__restrict__ fields, int64_t npix, int nb,
                                                         int64_t map_stride, const uchar4 *__restrict__ terms,
                                                         int t0, int nterm_launch, int nterm_total,
                                                         int64_t chunk, double *__restrict__ partial) {
     constexpr bool F64 = sizeof(R) == 8;
-    using P = typename std::conditional<F64 || X64, double, R>::type;   // product and tile-sum type
+    using P = R;                                   // product and tile-sum type
     extern __shared__ unsigned char smem_raw[];
     R *tile = reinterpret_cast<R *>(smem_raw);   // [CT_TILE][nb]
     const int map = blockIdx.y;
@@ -517,8 +515,7 @@ __global__ __launch_bounds__(256) void k_contract_terms(const R *__restrict__ fi
                 if constexpr (F64) comp_add(acc[q], comp[q], v);
                 else s += v;
             }
-            if constexpr (X64) comp_add(acc[q], comp[q], s);
-            else if constexpr (!F64) acc[q] += (double)s;
+            if constexpr (!F64) acc[q] += (double)s;
             (void)s;
         }
     }
@@ -528,6 +525,112 @@ __global__ __launch_bounds__(256) void k_contract_terms(const R *__restrict__ fi
         const int t = threadIdx.x + q * 256;
         if (t < nterm_launch) out[t] = acc[q] + comp[q];
     }
+}
+
+// ---------------------------------------------------------------------------
+// Ill-conditioned triplets on the vector ALUs (narrow shells near the
+// triangle edge): sum_n F_x F_y F_z with the products formed in FP64 (the
+// pair product of two FP32 values is exact) and FP64 sums.
+//
+// A block of RF_WAVES waves takes a span of grid points in tiles of RF_TP
+// points.  The fields the launch reads (bins[r], r < nbs) are staged per
+// tile into LDS as rows of RF_TP floats; lane l reads points 4l..4l+3 of a
+// row with one 16-byte load, so a wave's reads cover a row without bank
+// conflicts.  Wave w owns the slots [w*S, (w+1)*S) of the launch's slot
+// table (S = SLOTS), one per lane of a register, read out with v_readlane:
+// slot x | y << 8 | z << 16 | f << 24 adds F_x F_y F_z (staged rows) to its
+// sum; f = 0x80 marks an empty slot (rows 0, not written).  The slots carry
+// no branches, so the loads of later slots overlap the products of earlier
+// ones.  Each lane keeps one FP64 running sum per slot over all its points;
+// at the end the lanes' sums are added in a fixed order and the block
+// writes one FP64 partial per slot, partial[map][block][slot0 + slot].  The
+// next tile's global loads are issued into registers before the current
+// tile's products.
+// ---------------------------------------------------------------------------
+constexpr int RF_WAVES = 16;
+constexpr int RF_TP = 256;
+
+template <int NBS, int SLOTS>
+__global__ __launch_bounds__(RF_WAVES * 64) void k_refine_terms(const float *__restrict__ fields, int64_t fl,
+                                                                int64_t map_stride, const int *__restrict__ bins,
+                                                                int nbs, const uchar4 *__restrict__ slots, int slot0,
+                                                                int nslot_total, int64_t chunk,
+                                                                double *__restrict__ partial) {
+    constexpr int PF = NBS / RF_WAVES;             // staged rows per wave
+    static_assert(SLOTS <= 64, "one slot per lane");
+    __shared__ __attribute__((aligned(16))) float tile[NBS * RF_TP];
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const float *f = fields + (int64_t)blockIdx.y * map_stride;
+    const int64_t p_begin = (int64_t)blockIdx.x * chunk;
+    const int64_t p_end = p_begin + chunk < fl ? p_begin + chunk : fl;
+    const unsigned *tab = reinterpret_cast<const unsigned *>(slots + slot0) + w * SLOTS;
+    const unsigned desc = lane < SLOTS ? tab[lane] : 0u;
+    float4 pf[PF];
+    auto load = [&](int64_t p) {
+        const int64_t pt = p + 4 * lane;
+#pragma unroll
+        for (int j = 0; j < PF; ++j) {
+            const int r = w + RF_WAVES * j;
+            if (r < nbs)
+                pf[j] = pt < p_end ? *reinterpret_cast<const float4 *>(f + (int64_t)bins[r] * fl + pt)
+                                   : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+    };
+    auto row = [&](unsigned r) { return *reinterpret_cast<const float4 *>(&tile[r * RF_TP + 4 * lane]); };
+    double acc[SLOTS];
+#pragma unroll
+    for (int q = 0; q < SLOTS; ++q) acc[q] = 0.0;
+    if (p_begin < p_end) load(p_begin);
+    for (int64_t p = p_begin; p < p_end; p += RF_TP) {
+        __syncthreads();                           // the previous tile is read
+#pragma unroll
+        for (int j = 0; j < PF; ++j) {
+            const int r = w + RF_WAVES * j;
+            if (r < nbs) *reinterpret_cast<float4 *>(&tile[r * RF_TP + 4 * lane]) = pf[j];
+        }
+        __syncthreads();
+        if (p + RF_TP < p_end) load(p + RF_TP);
+#pragma unroll
+        for (int q = 0; q < SLOTS; ++q) {
+            const unsigned d = __builtin_amdgcn_readlane(desc, q);
+            const float4 a = row(d & 0xFF), b = row((d >> 8) & 0xFF), c = row((d >> 16) & 0xFF);
+            acc[q] = fma((double)a.x * (double)b.x, (double)c.x, acc[q]);
+            acc[q] = fma((double)a.y * (double)b.y, (double)c.y, acc[q]);
+            acc[q] = fma((double)a.z * (double)b.z, (double)c.z, acc[q]);
+            acc[q] = fma((double)a.w * (double)b.w, (double)c.w, acc[q]);
+        }
+    }
+    double *out = partial + ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * nslot_total + slot0 + w * SLOTS;
+#pragma unroll
+    for (int q = 0; q < SLOTS; ++q) {
+        const double v = wave_sum(acc[q]);
+        if (lane == 0 && !(__builtin_amdgcn_readlane(desc, q) >> 31)) out[q] = v;
+    }
+}
+
+int refine_rows_bucket(int nbs) { return nbs <= 32 ? 32 : nbs <= 64 ? 64 : 128; }
+int refine_slots_per_wave(int nbs) { return refine_rows_bucket(nbs) <= 64 ? 32 : 24; }
+int refine_slots_per_launch(int nbs) { return RF_WAVES * refine_slots_per_wave(nbs); }
+int64_t refine_chunk(int64_t fl, int nblk) { return ((fl + nblk - 1) / nblk + RF_TP - 1) / RF_TP * RF_TP; }
+
+hipError_t launch_refine_terms(const float *fields, int64_t fl, int64_t map_stride, int batch, const int *bins,
+                               int nbs, int nbs_plan, const uchar4 *slots, int slot0, int nslot_total, int nblk,
+                               double *partial, hipStream_t st) {
+    const int bucket = refine_rows_bucket(nbs_plan);
+    if (fl % 4 || nblk < 1 || nbs < 1 || nbs > bucket || nbs_plan > 128) return hipErrorInvalidValue;
+    const int64_t chunk = refine_chunk(fl, nblk);
+    const dim3 grid(nblk, batch), block(RF_WAVES * 64);
+    if (bucket == 32)
+        hipLaunchKernelGGL((k_refine_terms<32, 32>), grid, block, 0, st, fields, fl, map_stride, bins, nbs, slots,
+                           slot0, nslot_total, chunk, partial);
+    else if (bucket == 64)
+        hipLaunchKernelGGL((k_refine_terms<64, 32>), grid, block, 0, st, fields, fl, map_stride, bins, nbs, slots,
+                           slot0, nslot_total, chunk, partial);
+    else
+        hipLaunchKernelGGL((k_refine_terms<128, 24>), grid, block, 0, st, fields, fl, map_stride, bins, nbs, slots,
+                           slot0, nslot_total, chunk, partial);
+    return hipGetLastError();
 }
 
 // Fixed-order compensated FP64 sum over blocks, then scale: out = scale[t] * sum.
@@ -854,14 +957,14 @@ int fft_pencils_per_block(int n, bool fp64) {
     return g;
 }
 
-template <typename R, bool X64 = false>
+template <typename R>
 hipError_t launch_contract_terms_t(const R *fields, int64_t npix, int nb, int64_t map_stride, int batch,
                                    const uchar4 *terms, int nterm, int nblk, double *partial, hipStream_t st) {
     const int64_t chunk = ((npix + nblk - 1) / nblk + CT_TILE - 1) / CT_TILE * CT_TILE;
     const size_t smem = (size_t)CT_TILE * nb * sizeof(R);
     for (int t0 = 0; t0 < nterm; t0 += 256 * CT_MAXT) {
         const int nt = nterm - t0 < 256 * CT_MAXT ? nterm - t0 : 256 * CT_MAXT;
-        hipLaunchKernelGGL((k_contract_terms<R, X64>), dim3(nblk, batch), dim3(256), smem, st, fields, npix, nb,
+        hipLaunchKernelGGL((k_contract_terms<R>), dim3(nblk, batch), dim3(256), smem, st, fields, npix, nb,
                            map_stride, terms, t0, nt, nterm, chunk, partial);
     }
     return hipGetLastError();
@@ -872,17 +975,13 @@ hipError_t launch_contract_terms_f32(const float *fields, int64_t npix, int nb, 
     return launch_contract_terms_t<float>(fields, npix, nb, map_stride, batch, terms, nterm, nblk, partial, st);
 }
 
-hipError_t launch_contract_terms_f32x64(const float *fields, int64_t npix, int nb, int64_t map_stride, int batch,
-                                        const uchar4 *terms, int nterm, int nblk, double *partial, hipStream_t st) {
-    return launch_contract_terms_t<float, true>(fields, npix, nb, map_stride, batch, terms, nterm, nblk, partial, st);
-}
 
 // out[map][list[i]] = scale[i] src[map][i]
 __global__ __launch_bounds__(256) void k_scatter_list(const double *__restrict__ src, int n,
                                                       const int *__restrict__ list, const double *__restrict__ scale,
                                                       double *__restrict__ out, int nout) {
     const int i = blockIdx.x * 256 + threadIdx.x, map = blockIdx.y;
-    if (i < n) out[(int64_t)map * nout + list[i]] = scale[i] * src[(int64_t)map * n + i];
+    if (i < n && list[i] >= 0) out[(int64_t)map * nout + list[i]] = scale[i] * src[(int64_t)map * n + i];
 }
 
 hipError_t launch_scatter_list(const double *src, int n, const int *list, const double *scale, int batch,

@@ -95,9 +95,16 @@ struct bispec_plan_s {
     int n_mtile_r = 0;                   // 32-row tiles of refinement rows (0: none)
     // when those rows would use few of their 2048 entries per tile, the
     // triplets run instead as FP64-product terms on the vector ALUs
+    // (k_refine_terms): a slot table of launches of
+    // refine_slots_per_launch(refine_nbs) slots each
     bool refine_valu = false;
-    std::vector<uchar4> refine_terms;    // their terms, and the normalisation of each
-    std::vector<double> refine_scale;
+    std::vector<uchar4> refine_terms;    // per slot: staged rows x, y, z and 0x80 if empty
+    std::vector<double> refine_scale;    // per slot: the triplet's normalisation (0: empty)
+    std::vector<int> refine_list;        // per slot: the triplet (-1: empty)
+    std::vector<int> refine_bins;        // each launch's staged bins, concatenated
+    std::vector<int> refine_bins_off;    // launch l stages refine_bins[off[l] .. off[l+1])
+    int refine_nbs = 0;                  // most bins a launch stages
+    int refine_nblk = 1;                 // blocks per map of each launch
     int nblk_r = 1;                      // blocks per map of the refinement pass
     // stage timing: one event per stage boundary per call
     bool timing = false;
@@ -127,7 +134,7 @@ constexpr int kMomBlocks = 2048;
 struct Layout {
     size_t tw, terms, scale, tcount, thr, mom_partial, mom_tmp, mom, pg_pairs, pg_idx, pg_pairs_r, cols, pd, ztab,
         ytab, mean_partial, mean, spec, abox, bc, fields, partial, pg_partial, pg_dense, pg_tmp, pg_partial_r,
-        pg_dense_r, pg_tmp_r, refine_t, ref_terms, ref_scale, ref_out, ref_tmp,
+        pg_dense_r, pg_tmp_r, refine_t, ref_terms, ref_scale, ref_list, ref_bins, ref_partial, ref_out, ref_tmp,
         // diagonal-binned trispectrum pass (one map at a time)
         dtw, dspec, dwork, dfields, dtmp, dpspec, didx, dtask, dpart, dsums, dcoef, total;
 };
