@@ -460,9 +460,11 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MINW))) void
 // 32-column MFMA tiles; columns at or beyond nb are zero), and the pair rows
 // chosen for that group.  Block (c, map, g) contracts the points
 // [c chunk, (c+1) chunk) for the pair tiles g T .. (g+1) T - 1
-// of the group (T = pgf_tiles(ZR)); wave w owns the tiles g T + w + r WAVES,
-// r < pgf_maxr(ZR) (one tile per wave with ZR = 128, whose larger stage
-// leaves no registers for a second accumulator pair).
+// of the group (T = PGF_TILES = 32); wave w owns the tiles g T + w + r WAVES,
+// r < pgf_maxr(ZR, SQ): 16 waves of two tiles with ZR = 64, and with
+// ZR = 128, whose larger stage leaves 1024-thread blocks registers for one
+// accumulator pair, 8 waves of four tiles (each block re-reads the fields,
+// so fewer, larger tile sets halve that traffic).
 // Every step stages PGF_TK points of each field in LDS, all nb in FP32 for
 // the row products and the group's columns as bf16 halves, so one split of a
 // row product feeds both column tiles; the next step's loads are in flight
@@ -480,16 +482,21 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MINW))) void
 // s = w / n_mtile (mod KS), KS = WAVES / n_mtile, and each K part writes its
 // own partial set (partial [batch][nblk][KS][tiles_total][32][64]); the
 // fixed-order reduction over nblk KS sets adds them.
-constexpr int PGF_NT = 1024, PGF_MAXR = 2, PGF_TK = 128;
-__host__ __device__ constexpr int pgf_maxr(int zr) { return zr == PGF_ROW_ZERO ? PGF_MAXR : 1; }
-__host__ __device__ constexpr int pgf_tiles(int zr) { return PGF_NT / 64 * pgf_maxr(zr); }
+constexpr int PGF_NT = 1024, PGF_TK = 128, PGF_TILES = 32;
+__host__ __device__ constexpr int pgf_nt(int zr, bool sq) { return zr == PGF_ROW_ZERO_XL && !sq ? 512 : PGF_NT; }
+__host__ __device__ constexpr int pgf_maxr(int zr, bool sq) { return zr == PGF_ROW_ZERO ? 2 : sq ? 1 : 4; }
+static_assert(pgf_nt(PGF_ROW_ZERO, false) / 64 * pgf_maxr(PGF_ROW_ZERO, false) == PGF_TILES &&
+                  pgf_nt(PGF_ROW_ZERO_XL, false) / 64 * pgf_maxr(PGF_ROW_ZERO_XL, false) == PGF_TILES,
+              "every triplet-pass block holds PGF_TILES pair tiles");
 
 template <bool SQ, int ZR>
-__global__ __launch_bounds__(PGF_NT) void k_pgram_fields(const float *__restrict__ fields, int64_t npix, int nb,
-                                                         int64_t map_stride, const uchar2 *__restrict__ pairs,
-                                                         int n_mtile, int col0, int tile0, int tiles_total,
-                                                         int64_t chunk, double *__restrict__ partial) {
-    constexpr int TK = PGF_TK, FS = TK + 4, BS = TK + 8, WAVES = PGF_NT / 64, MAXR = pgf_maxr(ZR);
+__global__ __launch_bounds__(pgf_nt(ZR, SQ)) void k_pgram_fields(const float *__restrict__ fields, int64_t npix,
+                                                                 int nb, int64_t map_stride,
+                                                                 const uchar2 *__restrict__ pairs, int n_mtile,
+                                                                 int col0, int tile0, int tiles_total, int64_t chunk,
+                                                                 double *__restrict__ partial) {
+    constexpr int NT = pgf_nt(ZR, SQ);
+    constexpr int TK = PGF_TK, FS = TK + 4, BS = TK + 8, WAVES = NT / 64, MAXR = pgf_maxr(ZR, SQ);
     __shared__ __attribute__((aligned(16))) float Ft[(ZR + 1) * FS];   // field rows, then a row of zeros
     __shared__ __attribute__((aligned(16))) __bf16 Bh[64 * BS];
     __shared__ __attribute__((aligned(16))) __bf16 Bl[64 * BS];
@@ -498,18 +505,18 @@ __global__ __launch_bounds__(PGF_NT) void k_pgram_fields(const float *__restrict
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int map = blockIdx.y;
     // rows nb..ZR-1 and the zero row are never loaded: zero them once
-    for (int i = tid; i < (ZR + 1 - nb) * FS; i += PGF_NT) Ft[nb * FS + i] = 0.0f;
+    for (int i = tid; i < (ZR + 1 - nb) * FS; i += NT) Ft[nb * FS + i] = 0.0f;
     // the group's column fields col0 .. col0 + ncf - 1; SQ: column nb - col0
     // is the ones column when it falls in the group
     const int ncf = nb - col0 < 64 ? nb - col0 : 64;
     const int one_col = SQ && nb - col0 < 64 ? nb - col0 : -1;
     const int zr = one_col >= 0 ? ncf + 1 : ncf;
-    for (int i = tid; i < (64 - zr) * BS; i += PGF_NT) {
+    for (int i = tid; i < (64 - zr) * BS; i += NT) {
         Bh[zr * BS + i] = (__bf16)0.0f;
         Bl[zr * BS + i] = (__bf16)0.0f;
     }
     if (one_col >= 0)
-        for (int i = tid; i < BS; i += PGF_NT) {
+        for (int i = tid; i < BS; i += NT) {
             Bh[one_col * BS + i] = (__bf16)1.0f;
             Bl[one_col * BS + i] = (__bf16)0.0f;
         }
@@ -525,7 +532,7 @@ __global__ __launch_bounds__(PGF_NT) void k_pgram_fields(const float *__restrict
             tile_of[r] = r == 0 ? t : -1;
             rp[r] = a < nb ? uchar2{(unsigned char)a, (unsigned char)a} : uchar2{ZR, ZR};
         } else {
-            const int t = blockIdx.z * pgf_tiles(ZR) + wave + r * WAVES;
+            const int t = blockIdx.z * PGF_TILES + wave + r * WAVES;
             tile_of[r] = t < n_mtile ? t : -1;
             rp[r] = t < n_mtile ? pairs[t * 32 + col] : uchar2{ZR, ZR};
         }
@@ -540,13 +547,13 @@ __global__ __launch_bounds__(PGF_NT) void k_pgram_fields(const float *__restrict
     const int64_t p1 = p0 + chunk < npix ? p0 + chunk : npix;
     // the loads of step p + TK are issued before step p's contraction and
     // land in registers; after the step they go to LDS
-    constexpr int LPT = ZR * (TK / 4) / PGF_NT;   // float4 per thread at ZR bins
-    static_assert(ZR * (TK / 4) % PGF_NT == 0, "field loads must divide the block");
+    constexpr int LPT = ZR * (TK / 4) / NT;   // float4 per thread at ZR bins
+    static_assert(ZR * (TK / 4) % NT == 0, "field loads must divide the block");
     float4 pre[LPT];
     auto fetch = [&](int64_t p) {
 #pragma unroll
         for (int j = 0; j < LPT; ++j) {
-            const int e = tid + j * PGF_NT;
+            const int e = tid + j * NT;
             if (e < nb * (TK / 4)) {
                 const int b = e / (TK / 4), k = (e % (TK / 4)) * 4;
                 pre[j] = *reinterpret_cast<const float4 *>(f + (int64_t)b * npix + p + k);
@@ -558,7 +565,7 @@ __global__ __launch_bounds__(PGF_NT) void k_pgram_fields(const float *__restrict
         __syncthreads();   // the previous step's reads are done
 #pragma unroll
         for (int j = 0; j < LPT; ++j) {
-            const int e = tid + j * PGF_NT;
+            const int e = tid + j * NT;
             if (e >= nb * (TK / 4)) continue;
             const int b = e / (TK / 4), k = (e % (TK / 4)) * 4;
             const float4 v = pre[j];
@@ -890,8 +897,7 @@ hipError_t launch_pgram_fields(const float *fields, int64_t npix, int nb, int ba
     if (squares ? (n_mtile != pgf_sq_tiles(nb) || (PGF_NT / 64) % n_mtile != 0) : !pairs) return hipErrorInvalidValue;
     const int64_t chunk = pgram_fields_chunk(npix, nblk);
     if (npix % PGF_TK != 0 || chunk > PGF_MAX_CHUNK) return hipErrorInvalidValue;
-    const int per = pgf_tiles(pgf_row_zero(nb));
-    const unsigned groups = squares ? 1u : (unsigned)((n_mtile + per - 1) / per);
+    const unsigned groups = squares ? 1u : (unsigned)((n_mtile + PGF_TILES - 1) / PGF_TILES);
     const int64_t ms = (int64_t)nb * npix;
     if (nb <= PGF_ROW_ZERO) {
         if (squares)
@@ -905,7 +911,8 @@ hipError_t launch_pgram_fields(const float *fields, int64_t npix, int nb, int ba
             hipLaunchKernelGGL((k_pgram_fields<true, PGF_ROW_ZERO_XL>), dim3(nblk, batch, groups), dim3(PGF_NT), 0,
                                st, fields, npix, nb, ms, pairs, n_mtile, col0, tile0, tiles_total, chunk, partial);
         else
-            hipLaunchKernelGGL((k_pgram_fields<false, PGF_ROW_ZERO_XL>), dim3(nblk, batch, groups), dim3(PGF_NT), 0,
+            hipLaunchKernelGGL((k_pgram_fields<false, PGF_ROW_ZERO_XL>), dim3(nblk, batch, groups),
+                               dim3(pgf_nt(PGF_ROW_ZERO_XL, false)), 0,
                                st, fields, npix, nb, ms, pairs, n_mtile, col0, tile0, tiles_total, chunk, partial);
     }
     return hipGetLastError();
