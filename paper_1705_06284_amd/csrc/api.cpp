@@ -1580,9 +1580,10 @@ bispec_status finalize_range(bispec_plan_s &p, bool gather, const double *partia
     return BISPEC_OK;
 }
 
-// The ill-conditioned triplets as FP64-product terms on the vector ALUs
-// over the bin fields (k_refine_terms, one launch per slot batch), written
-// over their entries of B (after B's own finalisation).
+// The ill-conditioned triplets as terms on the vector ALUs over the bin
+// fields (k_refine_terms, one launch per slot batch; FP32 products in
+// split-BF16 mode, FP64 otherwise, FP64 sums), written over their entries
+// of B (after B's own finalisation).
 bispec_status refine_valu_run(bispec_plan_s &p, const float *fields, int64_t fl, int batch, double *B) {
     const Layout L = make_layout(p, p.max_batch);
     char *ws = (char *)p.ws;
@@ -1596,7 +1597,7 @@ bispec_status refine_valu_run(bispec_plan_s &p, const float *fields, int64_t fl,
         const int b0 = p.refine_bins_off[l], nbs = p.refine_bins_off[l + 1] - b0;
         CK(launch_refine_terms(fields, fl, (int64_t)p.nb * fl, batch, (const int *)(ws + L.ref_bins) + b0, nbs,
                                p.refine_nbs, (const uchar4 *)(ws + L.ref_terms), l * spl, nslot, p.refine_nblk,
-                               partial, p.stream));
+                               partial, p.stream, p.precision != BISPEC_SPLIT_BF16));
     }
     // fixed-order segmented sums over the blocks, then scale and scatter
     CK(launch_reduce_dense(partial, p.refine_nblk, nslot, batch, (double *)(ws + L.ref_out),

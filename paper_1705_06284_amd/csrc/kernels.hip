@@ -529,8 +529,12 @@ __global__ __launch_bounds__(256) void k_contract_terms(const R *__restrict__ fi
 
 // ---------------------------------------------------------------------------
 // Ill-conditioned triplets on the vector ALUs (narrow shells near the
-// triangle edge): sum_n F_x F_y F_z with the products formed in FP64 (the
-// pair product of two FP32 values is exact) and FP64 sums.
+// triangle edge): sum_n F_x F_y F_z with FP64 sums.  F64P: the products are
+// formed in FP64 (the pair product of two FP32 values is exact), for plans in
+// FP32 mode, whose bar is tighter; otherwise in FP32 with a 4-point FP32 sum
+// per lane before the FP64 one: a relative rounding of a few 2^-24 per
+// product, far below the 2^-9..2^-17 of the split-BF16 operands the
+// refinement replaces, at half the vector-ALU work.
 //
 // A block of RF_WAVES waves takes a span of grid points in tiles of RF_TP
 // points.  The fields the launch reads (bins[r], r < nbs) are staged per
@@ -550,7 +554,7 @@ __global__ __launch_bounds__(256) void k_contract_terms(const R *__restrict__ fi
 constexpr int RF_WAVES = 16;
 constexpr int RF_TP = 256;
 
-template <int NBS, int SLOTS>
+template <int NBS, int SLOTS, bool F64P>
 __global__ __launch_bounds__(RF_WAVES * 64) void k_refine_terms(const float *__restrict__ fields, int64_t fl,
                                                                 int64_t map_stride, const int *__restrict__ bins,
                                                                 int nbs, const uchar4 *__restrict__ slots, int slot0,
@@ -595,10 +599,18 @@ __global__ __launch_bounds__(RF_WAVES * 64) void k_refine_terms(const float *__r
         for (int q = 0; q < SLOTS; ++q) {
             const unsigned d = __builtin_amdgcn_readlane(desc, q);
             const float4 a = row(d & 0xFF), b = row((d >> 8) & 0xFF), c = row((d >> 16) & 0xFF);
-            acc[q] = fma((double)a.x * (double)b.x, (double)c.x, acc[q]);
-            acc[q] = fma((double)a.y * (double)b.y, (double)c.y, acc[q]);
-            acc[q] = fma((double)a.z * (double)b.z, (double)c.z, acc[q]);
-            acc[q] = fma((double)a.w * (double)b.w, (double)c.w, acc[q]);
+            if constexpr (F64P) {
+                acc[q] = fma((double)a.x * (double)b.x, (double)c.x, acc[q]);
+                acc[q] = fma((double)a.y * (double)b.y, (double)c.y, acc[q]);
+                acc[q] = fma((double)a.z * (double)b.z, (double)c.z, acc[q]);
+                acc[q] = fma((double)a.w * (double)b.w, (double)c.w, acc[q]);
+            } else {
+                float t = (a.x * b.x) * c.x;
+                t = fmaf(a.y * b.y, c.y, t);
+                t = fmaf(a.z * b.z, c.z, t);
+                t = fmaf(a.w * b.w, c.w, t);
+                acc[q] += (double)t;
+            }
         }
     }
     double *out = partial + ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * nslot_total + slot0 + w * SLOTS;
@@ -616,20 +628,25 @@ int64_t refine_chunk(int64_t fl, int nblk) { return ((fl + nblk - 1) / nblk + RF
 
 hipError_t launch_refine_terms(const float *fields, int64_t fl, int64_t map_stride, int batch, const int *bins,
                                int nbs, int nbs_plan, const uchar4 *slots, int slot0, int nslot_total, int nblk,
-                               double *partial, hipStream_t st) {
+                               double *partial, hipStream_t st, bool f64_products) {
     const int bucket = refine_rows_bucket(nbs_plan);
     if (fl % 4 || nblk < 1 || nbs < 1 || nbs > bucket || nbs_plan > 128) return hipErrorInvalidValue;
     const int64_t chunk = refine_chunk(fl, nblk);
     const dim3 grid(nblk, batch), block(RF_WAVES * 64);
-    if (bucket == 32)
-        hipLaunchKernelGGL((k_refine_terms<32, 32>), grid, block, 0, st, fields, fl, map_stride, bins, nbs, slots,
-                           slot0, nslot_total, chunk, partial);
-    else if (bucket == 64)
-        hipLaunchKernelGGL((k_refine_terms<64, 32>), grid, block, 0, st, fields, fl, map_stride, bins, nbs, slots,
-                           slot0, nslot_total, chunk, partial);
-    else
-        hipLaunchKernelGGL((k_refine_terms<128, 24>), grid, block, 0, st, fields, fl, map_stride, bins, nbs, slots,
-                           slot0, nslot_total, chunk, partial);
+    auto go = [&](auto f64c) {
+        constexpr bool F = decltype(f64c)::value;
+        if (bucket == 32)
+            hipLaunchKernelGGL((k_refine_terms<32, 32, F>), grid, block, 0, st, fields, fl, map_stride, bins, nbs,
+                               slots, slot0, nslot_total, chunk, partial);
+        else if (bucket == 64)
+            hipLaunchKernelGGL((k_refine_terms<64, 32, F>), grid, block, 0, st, fields, fl, map_stride, bins, nbs,
+                               slots, slot0, nslot_total, chunk, partial);
+        else
+            hipLaunchKernelGGL((k_refine_terms<128, 24, F>), grid, block, 0, st, fields, fl, map_stride, bins, nbs,
+                               slots, slot0, nslot_total, chunk, partial);
+    };
+    if (f64_products) go(std::true_type{});
+    else go(std::false_type{});
     return hipGetLastError();
 }
 

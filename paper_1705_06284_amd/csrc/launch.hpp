@@ -40,8 +40,9 @@ int fft_pencils_per_block(int n, bool fp64);
 
 hipError_t launch_contract_terms_f32(const float *fields, int64_t npix, int nb, int64_t map_stride, int batch,
                                      const uchar4 *terms, int nterm, int nblk, double *partial, hipStream_t st);
-// Ill-conditioned triplets on the vector ALUs (k_refine_terms): FP64
-// products and sums over FP32 fields [batch][*][fl] (fl a multiple of 4).
+// Ill-conditioned triplets on the vector ALUs (k_refine_terms): FP64 sums
+// over FP32 fields [batch][*][fl] (fl a multiple of 4), the products in FP64
+// (f64_products) or FP32.
 // One launch contracts the slots [slot0, slot0 + refine_slots_per_launch)
 // of the slot table (uchar4 (x, y, z, f): staged rows x, y, z; f = 0x80 an
 // empty slot, which reads rows 0 and is not written),
@@ -54,7 +55,7 @@ int refine_slots_per_wave(int nbs_plan);
 int refine_slots_per_launch(int nbs_plan);
 hipError_t launch_refine_terms(const float *fields, int64_t fl, int64_t map_stride, int batch, const int *bins,
                                int nbs, int nbs_plan, const uchar4 *slots, int slot0, int nslot_total, int nblk,
-                               double *partial, hipStream_t st);
+                               double *partial, hipStream_t st, bool f64_products);
 // out[map][list[i]] = scale[i] src[map][i], i < n, list[i] >= 0 (src [batch][n], out [batch][nout]).
 hipError_t launch_scatter_list(const double *src, int n, const int *list, const double *scale, int batch,
                                double *out, int nout, hipStream_t st);
