@@ -17,7 +17,10 @@ window does not blow up a relative error.  Sample variance makes k below
   15 % of the envelope everywhere, both with medians below 3 % -- the
   paper's "follows the theoretical predictions very closely".
 * x_HI = 0.88 (6615 spheres, overlapping): the model, which has no overlap,
-  fits worse below 0.2 Mpc^-1, as the paper finds at z = 11.
+  fits worse below 0.2 Mpc^-1, as the paper finds at z = 11 on its
+  equilateral configurations: there the median deviation is ten times the
+  0.99 box's (0.42 against 0.04 of the envelope), while above 0.2 Mpc^-1
+  the 0.88 box stays near the model (median 0.07).
 """
 import os
 
@@ -67,10 +70,15 @@ def test_toy_box_099_follows_the_model():
 
 def test_overlap_at_088_departs_from_the_model_below_0p2():
     z99, z88 = _load("toy600_xhi099"), _load("toy600_xhi088")
-    assert int(z88["spheres"]) == 6615
+    assert int(z88["spheres"]) == 6615 and abs(float(z88["ionized_fraction"]) - 0.12) < 1e-4
     kc, kf, t, _, db99 = _deviations(z99)
     _, _, t88, _, db88 = _deviations(z88)
     assert np.array_equal(t, t88)
-    low = (kc[t].max(axis=1) * kf < 0.2) & (kc[t].min(axis=1) >= 100.0 / 6.0)
-    assert low.sum() >= 3
-    assert np.median(db88[low]) > 2.0 * np.median(db99[low])
+    k = kc[t] * kf
+    equilateral = (t[:, 0] == t[:, 1]) & (t[:, 1] == t[:, 2])
+    low = equilateral & (k.max(axis=1) < 0.2)
+    assert low.sum() == 9
+    assert np.median(db88[low]) > 5.0 * np.median(db99[low])
+    high = k.min(axis=1) >= 0.2
+    assert high.sum() > 100
+    assert np.median(db88[high]) < 0.1 < np.median(db88[low])
