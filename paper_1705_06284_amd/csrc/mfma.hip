@@ -460,12 +460,11 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MINW))) void
 // 32-column MFMA tiles; columns at or beyond nb are zero), and the pair rows
 // chosen for that group.  Block (c, map, g) contracts the points
 // [c chunk, (c+1) chunk) for the pair tiles g T .. (g+1) T - 1
-// of the group (T = PGF_TILES = 32); wave w owns the tiles g T + w + r WAVES,
-// r < pgf_maxr(ZR, SQ): 16 waves of two tiles with ZR = 64, and with
-// ZR = 128, whose larger stage leaves 1024-thread blocks registers for one
-// accumulator pair, 8 waves of four tiles (each block re-reads the fields,
-// so fewer, larger tile sets halve that traffic).
-// Every step stages PGF_TK points of each field in LDS, all nb in FP32 for
+// of the group (T = PGF_TILES = 32); each of the 16 waves owns the tiles
+// g T + w + r WAVES, r < 2.  With ZR = 128 a step stages pgf_tk(ZR, SQ) = 64
+// points (the stage of 128 fields at 128 points would leave the registers
+// for one accumulator pair only).
+// Every step stages pgf_tk points of each field in LDS, all nb in FP32 for
 // the row products and the group's columns as bf16 halves, so one split of a
 // row product feeds both column tiles; the next step's loads are in flight
 // during a step's contraction.  A chunk is at most PGF_MAX_CHUNK points, the
@@ -483,20 +482,20 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MINW))) void
 // own partial set (partial [batch][nblk][KS][tiles_total][32][64]); the
 // fixed-order reduction over nblk KS sets adds them.
 constexpr int PGF_NT = 1024, PGF_TK = 128, PGF_TILES = 32;
-__host__ __device__ constexpr int pgf_nt(int zr, bool sq) { return zr == PGF_ROW_ZERO_XL && !sq ? 512 : PGF_NT; }
-__host__ __device__ constexpr int pgf_maxr(int zr, bool sq) { return zr == PGF_ROW_ZERO ? 2 : sq ? 1 : 4; }
-static_assert(pgf_nt(PGF_ROW_ZERO, false) / 64 * pgf_maxr(PGF_ROW_ZERO, false) == PGF_TILES &&
-                  pgf_nt(PGF_ROW_ZERO_XL, false) / 64 * pgf_maxr(PGF_ROW_ZERO_XL, false) == PGF_TILES,
+__host__ __device__ constexpr int pgf_maxr(int zr, bool sq) { return sq && zr == PGF_ROW_ZERO_XL ? 1 : 2; }
+__host__ __device__ constexpr int pgf_tk(int zr, bool sq) { return zr == PGF_ROW_ZERO_XL && !sq ? 64 : PGF_TK; }
+static_assert(PGF_NT / 64 * pgf_maxr(PGF_ROW_ZERO, false) == PGF_TILES &&
+                  PGF_NT / 64 * pgf_maxr(PGF_ROW_ZERO_XL, false) == PGF_TILES,
               "every triplet-pass block holds PGF_TILES pair tiles");
 
 template <bool SQ, int ZR>
-__global__ __launch_bounds__(pgf_nt(ZR, SQ)) void k_pgram_fields(const float *__restrict__ fields, int64_t npix,
-                                                                 int nb, int64_t map_stride,
-                                                                 const uchar2 *__restrict__ pairs, int n_mtile,
-                                                                 int col0, int tile0, int tiles_total, int64_t chunk,
-                                                                 double *__restrict__ partial) {
-    constexpr int NT = pgf_nt(ZR, SQ);
-    constexpr int TK = PGF_TK, FS = TK + 4, BS = TK + 8, WAVES = NT / 64, MAXR = pgf_maxr(ZR, SQ);
+__global__ __launch_bounds__(PGF_NT) void k_pgram_fields(const float *__restrict__ fields, int64_t npix, int nb,
+                                                         int64_t map_stride, const uchar2 *__restrict__ pairs,
+                                                         int n_mtile, int col0, int tile0, int tiles_total,
+                                                         int64_t chunk, double *__restrict__ partial) {
+    constexpr int NT = PGF_NT;
+    constexpr int TK = pgf_tk(ZR, SQ), FS = TK + 4, BS = TK + 8, WAVES = NT / 64, MAXR = pgf_maxr(ZR, SQ);
+    static_assert(PGF_TK % TK == 0, "a chunk holds whole steps");
     __shared__ __attribute__((aligned(16))) float Ft[(ZR + 1) * FS];   // field rows, then a row of zeros
     __shared__ __attribute__((aligned(16))) __bf16 Bh[64 * BS];
     __shared__ __attribute__((aligned(16))) __bf16 Bl[64 * BS];
@@ -576,7 +575,7 @@ __global__ __launch_bounds__(pgf_nt(ZR, SQ)) void k_pgram_fields(const float *__
             bf16x2 h0, l0, h1, l1;
             split2(w.x, w.y, h0, l0);
             split2(w.z, w.w, h1, l1);
-            // 8-byte stores: (c BS + k) 2 bytes is a multiple of 8 (BS = 136, k = 0 mod 4)
+            // 8-byte stores: (c BS + k) 2 bytes is a multiple of 8 (BS = TK + 8, k = 0 mod 4)
             *reinterpret_cast<bf16x4 *>(&Bh[c * BS + k]) = bf16x4{h0[0], h0[1], h1[0], h1[1]};
             *reinterpret_cast<bf16x4 *>(&Bl[c * BS + k]) = bf16x4{l0[0], l0[1], l1[0], l1[1]};
         }
@@ -911,8 +910,7 @@ hipError_t launch_pgram_fields(const float *fields, int64_t npix, int nb, int ba
             hipLaunchKernelGGL((k_pgram_fields<true, PGF_ROW_ZERO_XL>), dim3(nblk, batch, groups), dim3(PGF_NT), 0,
                                st, fields, npix, nb, ms, pairs, n_mtile, col0, tile0, tiles_total, chunk, partial);
         else
-            hipLaunchKernelGGL((k_pgram_fields<false, PGF_ROW_ZERO_XL>), dim3(nblk, batch, groups),
-                               dim3(pgf_nt(PGF_ROW_ZERO_XL, false)), 0,
+            hipLaunchKernelGGL((k_pgram_fields<false, PGF_ROW_ZERO_XL>), dim3(nblk, batch, groups), dim3(PGF_NT), 0,
                                st, fields, npix, nb, ms, pairs, n_mtile, col0, tile0, tiles_total, chunk, partial);
     }
     return hipGetLastError();
