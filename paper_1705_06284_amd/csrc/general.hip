@@ -16,13 +16,19 @@
 // exactly reduced argument (the inverse direction conjugates it).
 //
 // The forward transform keeps the full complex spectrum [m_z][m_y][m_x]
-// (Eq. DeltaFFTtoDelta).  Each shell pair (b1, b2) is transformed back
-// without pruning: pass Z gathers [m in S_b1] Delta + i [m in S_b2] Delta
+// (Eq. DeltaFFTtoDelta).  Each shell pair (b1, b2) is transformed back in the
+// full work volume: pass Z gathers [m in S_b1] Delta + i [m in S_b2] Delta
 // (both masked spectra are Hermitian, so the inverse is F_b1 + i F_b2,
 // Eq. delta_nr), passes Y and X follow, and the last pass writes the real and
 // imaginary parts as the two bin fields.  Membership is the integer test
 // qlo <= q < qhi on q = (s_z m_z)^2 + (s_y m_y)^2 + (s_x m_x)^2, s_i = P / N_i
 // with P the lcm of the sides.
+// The passes are pruned to the pair's reach, qmax = max(hi1, hi2): pass Z
+// runs on the columns of the disk (s_y m_y)^2 + (s_x m_x)^2 < qmax only (a
+// column outside it holds no shell mode) and writes nothing elsewhere; pass
+// Y runs on the columns (n_z, x) with (s_x m_x)^2 < qmax and reads the
+// entries outside the disk as zeros; pass X reads only those x, the rest of
+// each row as zeros.  Blocks whose pencils all fall outside return at once.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -38,6 +44,17 @@ constexpr int GEN_NT = 256;
 // Signed frequency of index i on an axis of n points: 0..n - n/2 - 1, then
 // -(n/2)..-1.
 __device__ __forceinline__ int gen_freq(int i, int n) { return i < n - n / 2 ? i : i - n; }
+
+// q contributions of the y and x frequencies, and the pair's reach.
+__device__ __forceinline__ int64_t gen_qy(const GenGrid &g, int y) {
+    const int64_t m = g.sy * gen_freq(y, g.ny);
+    return m * m;
+}
+__device__ __forceinline__ int64_t gen_qx(const GenGrid &g, int x) {
+    const int64_t m = g.sx * gen_freq(x, g.nx);
+    return m * m;
+}
+__device__ __forceinline__ int64_t gen_reach(const GenPair &pr) { return pr.hi1 > pr.hi2 ? pr.hi1 : pr.hi2; }
 
 template <int DIR, typename C> __device__ __forceinline__ C gen_tw(const C *tw, int j) {
     C w = tw[j];
@@ -235,6 +252,13 @@ __global__ __launch_bounds__(GEN_NT) void k_gen_inv_z(const C *__restrict__ spec
     const C *sp = UNIT ? nullptr : spec + (int64_t)map * g.npix;
     C *w = work + (int64_t)map * g.npix;
     using Rr = decltype(C{}.x);
+    const int64_t reach = gen_reach(pr);
+    auto in_disk = [&](int64_t c) {
+        return c < ncol && gen_qy(g, (int)(c / g.nx)) + gen_qx(g, (int)(c % g.nx)) < reach;
+    };
+    // the block's columns all outside the disk: nothing to do (block-uniform)
+    const int64_t cfirst = (int64_t)blockIdx.x * G;
+    if (!__syncthreads_or(threadIdx.x < G && in_disk(cfirst + threadIdx.x))) return;
     for (int e = threadIdx.x; e < G * n; e += GEN_NT) {
         const int p = e % G, i = e / G;
         const int64_t c = (int64_t)blockIdx.x * G + p;
@@ -259,7 +283,38 @@ __global__ __launch_bounds__(GEN_NT) void k_gen_inv_z(const C *__restrict__ spec
     for (int e = threadIdx.x; e < G * n; e += GEN_NT) {
         const int p = e % G, i = e / G;
         const int64_t c = (int64_t)blockIdx.x * G + p;
-        if (c < ncol) w[(int64_t)i * ncol + c] = res[p * n + i];
+        if (in_disk(c)) w[(int64_t)i * ncol + c] = res[p * n + i];
+    }
+}
+
+// Pass Y of the inverse transform of one shell pair, in place on the work
+// volume: block (z, x group) transforms the columns (z, x) with
+// (s_x m_x)^2 < reach along y, reading the entries outside the disk as zeros
+// (pass Z left them unwritten).
+template <typename C>
+__global__ __launch_bounds__(GEN_NT) void k_gen_inv_y(C *__restrict__ work, const C *__restrict__ tw, GenGrid g,
+                                                      GenPair pr, int G) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char gsm_raw[];
+    C *a = reinterpret_cast<C *>(gsm_raw);
+    const GenAxis &ax = g.ax[1];
+    const int n = ax.n;
+    C *b = a + G * n;
+    C *v = work + (int64_t)blockIdx.y * g.npix;
+    const int gx = (g.nx + G - 1) / G;
+    const int z = blockIdx.x / gx, x0 = (blockIdx.x % gx) * G;
+    const int64_t reach = gen_reach(pr);
+    auto live = [&](int x) { return x < g.nx && gen_qx(g, x) < reach; };
+    if (!__syncthreads_or(threadIdx.x < G && live(x0 + threadIdx.x))) return;
+    for (int e = threadIdx.x; e < G * n; e += GEN_NT) {
+        const int p = e % G, i = e / G, x = x0 + p;
+        const bool ok = live(x) && gen_qy(g, i) + gen_qx(g, x) < reach;
+        a[p * n + i] = ok ? v[((int64_t)z * g.ny + i) * g.nx + x] : C{0, 0};
+    }
+    __syncthreads();
+    const C *res = gen_fft<+1>(a, b, tw + ax.tw_off, ax, G);
+    for (int e = threadIdx.x; e < G * n; e += GEN_NT) {
+        const int p = e % G, i = e / G, x = x0 + p;
+        if (live(x)) v[((int64_t)z * g.ny + i) * g.nx + x] = res[p * n + i];
     }
 }
 
@@ -269,7 +324,7 @@ __global__ __launch_bounds__(GEN_NT) void k_gen_inv_z(const C *__restrict__ spec
 template <typename C, typename Rr>
 __global__ __launch_bounds__(GEN_NT) void k_gen_inv_x(const C *__restrict__ work, Rr *__restrict__ f1,
                                                       Rr *__restrict__ f2, int64_t map_stride,
-                                                      const C *__restrict__ tw, GenGrid g, int G) {
+                                                      const C *__restrict__ tw, GenGrid g, GenPair pr, int G) {
     extern __shared__ __attribute__((aligned(16))) unsigned char gsm_raw[];
     C *a = reinterpret_cast<C *>(gsm_raw);
     const GenAxis &ax = g.ax[2];
@@ -279,9 +334,10 @@ __global__ __launch_bounds__(GEN_NT) void k_gen_inv_x(const C *__restrict__ work
     const int64_t rows = (int64_t)g.nz * g.ny;
     const int64_t r0 = (int64_t)blockIdx.x * G;
     const C *src = work + (int64_t)map * g.npix;
+    const int64_t reach = gen_reach(pr);
     for (int e = threadIdx.x; e < G * n; e += GEN_NT) {
         const int p = e / n, i = e % n;
-        a[e] = r0 + p < rows ? src[(r0 + p) * n + i] : C{0, 0};
+        a[e] = r0 + p < rows && gen_qx(g, i) < reach ? src[(r0 + p) * n + i] : C{0, 0};
     }
     __syncthreads();
     const C *res = gen_fft<+1>(a, b, tw + ax.tw_off, ax, G);
@@ -422,11 +478,11 @@ static hipError_t gen_inverse_t(const C *spec, C *work, const GenGrid &g, const 
     hipLaunchKernelGGL((k_gen_inv_z<C, UNIT>), dim3((unsigned)((ncol + Gz - 1) / Gz), batch), dim3(GEN_NT),
                        gen_smem<C>(g.nz, Gz), st, spec, work, tw, g, pr, Gz);
     const int Gy = gen_pencils(g.ny, sizeof(C));
-    hipLaunchKernelGGL((k_gen_axis<C, +1, 1>), dim3((unsigned)(g.nz * ((g.nx + Gy - 1) / Gy)), batch),
-                       dim3(GEN_NT), gen_smem<C>(g.ny, Gy), st, work, tw, g, Gy);
+    hipLaunchKernelGGL((k_gen_inv_y<C>), dim3((unsigned)(g.nz * ((g.nx + Gy - 1) / Gy)), batch), dim3(GEN_NT),
+                       gen_smem<C>(g.ny, Gy), st, work, tw, g, pr, Gy);
     const int Gx = gen_pencils(g.nx, sizeof(C));
     hipLaunchKernelGGL((k_gen_inv_x<C, Rr>), dim3((unsigned)((rows + Gx - 1) / Gx), batch), dim3(GEN_NT),
-                       gen_smem<C>(g.nx, Gx), st, work, f1, f2, map_stride, tw, g, Gx);
+                       gen_smem<C>(g.nx, Gx), st, work, f1, f2, map_stride, tw, g, pr, Gx);
     return hipGetLastError();
 }
 
