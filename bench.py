@@ -42,6 +42,8 @@ def parse():
     ap.add_argument("--inverse-batch", type=int, default=4,
                     help="maps per call of the inverse-stage measurement (0: skip)")
     ap.add_argument("--no-serving", action="store_true", help="skip the request-stream measurement")
+    ap.add_argument("--toy600", action="store_true",
+                    help="also time the 600^3 toy reionisation box (mixed-radix transforms, 61 shells)")
     ap.add_argument("--no-onepixel", action="store_true",
                     help="skip the one-pixel-shell measurement with configuration binning")
     ap.add_argument("--serving-requests", type=int, default=2000)
@@ -185,6 +187,38 @@ def onepixel_run(torch, binding, synth, np, dev, stream, steps, wl="onepix_128_l
     out["fp32_valu"] = {"ms_per_map": 1e3 * wv / kv, "triangles_per_s": plan.n_tri * kv / wv,
                         "kind": "simple vector-ALU kernel, not tuned (a reference point, not a competitor)"}
     return out
+
+
+def toy600_run(torch, binding, synth, dev, stream, steps, wl="toy600_xhi099"):
+    """The 600^3 toy box of Section 3.3 (cells of 1 Mpc, 61 shells of 2 k_f,
+    every closed triplet, P and the collapsed T) on the mixed-radix
+    transforms and the fields product-Gram, split-BF16."""
+    w = synth.WORKLOADS[wl]
+    lo, hi = synth.workload_bins(wl)
+    t0 = time.perf_counter()
+    plan = binding.Plan((w["n"],) * 3, lo, hi, box_len=w["box_len"], stream=stream, device=dev)
+    torch.cuda.synchronize()
+    t_plan = time.perf_counter() - t0
+    d = torch.from_numpy(synth.workload_field(wl)).to(dev).unsqueeze(0)
+    P = torch.empty(1, plan.n_bins, dtype=torch.float64, device=dev)
+    B = torch.empty(1, plan.n_tri, dtype=torch.float64, device=dev)
+    T = torch.empty(1, plan.n_quad, dtype=torch.float64, device=dev)
+
+    def est():
+        binding.check(binding.polyspec_estimate(plan.handle, binding._ptr(d), 1, binding._ptr(P), binding._ptr(B),
+                                                binding._ptr(T)), "polyspec_estimate")
+
+    est()
+    k = max(2, steps // 4)
+    plan.timing_read()
+    plan.timing(True)
+    we, _ = timed_steps(torch, est, k, stream)
+    plan.timing(False)
+    stages, calls = plan.timing_read()
+    return {"workload": wl, "shape": [w["n"]] * 3, "bins": plan.n_bins, "triplets": plan.n_tri,
+            "quads": plan.n_quad, "outputs": "B, P, T", "plan_s": t_plan, "ms_per_map": 1e3 * we / k,
+            "triangles_per_s": plan.n_tri * k / we,
+            "stages_ms": {key: v / max(calls, 1) for key, v in stages.items()}}
 
 
 def percentile(xs, q):
@@ -448,6 +482,9 @@ def main():
         out["onepixel_128"] = onepixel_run(torch, binding, synth, np, dev, stream, args.steps)
         out["onepixel_256"] = onepixel_run(torch, binding, synth, np, dev, stream, args.steps,
                                            wl="onepix_256_lognormal")
+
+    if args.toy600:
+        out["toy600"] = toy600_run(torch, binding, synth, dev, stream, args.steps)
 
     if not args.no_serving:
         out["serving"] = serving_run(args.serving_requests)
