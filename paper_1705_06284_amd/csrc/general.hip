@@ -100,22 +100,43 @@ template <int R, int DIR, typename C> __device__ __forceinline__ void gen_dft(C 
     else if constexpr (R == 8) dft8<DIR>(v);
 }
 
+// q = a / b and r = a % b for 0 <= a < 2^24 and b >= 1, given rcp = 1 / b in
+// FP32: the FP32 quotient is off by at most one and is corrected once (the
+// divisors vary per pass, so the integer division would not be strength-
+// reduced by the compiler).
+__device__ __forceinline__ int gen_divmod(int a, int b, float rcp, int &r) {
+    int q = (int)((float)a * rcp);
+    r = a - q * b;
+    if (r < 0) {
+        --q;
+        r += b;
+    } else if (r >= b) {
+        ++q;
+        r -= b;
+    }
+    return q;
+}
+
 // One pass of radix R (2, 3, 4, 5 or 8) from src to dst over G pencils of n
-// points (pencil stride n).
+// points (pencil stride n).  The twiddle exponent t k n / (ns R) stays
+// below n (t < R, k < ns), so it needs no reduction.
 template <int R, int DIR, typename C>
 __device__ void gen_pass(const C *src, C *dst, const C *tw, int n, int ns, int G) {
     const int nb = n / R, tstep = n / (ns * R);
+    const float rnb = 1.0f / (float)nb, rns = 1.0f / (float)ns;
     for (int task = threadIdx.x; task < G * nb; task += GEN_NT) {
-        const int p = task / nb, jj = task % nb, k = jj % ns;
+        int jj, k;
+        const int p = gen_divmod(task, nb, rnb, jj);
+        const int blk = gen_divmod(jj, ns, rns, k);
         const C *s = src + p * n;
         C v[R];
 #pragma unroll
         for (int t = 0; t < R; ++t) {
             v[t] = s[jj + t * nb];
-            if (t > 0 && ns > 1) v[t] = cmul(v[t], gen_tw<DIR>(tw, (t * k * tstep) % n));
+            if (t > 0 && ns > 1) v[t] = cmul(v[t], gen_tw<DIR>(tw, t * k * tstep));
         }
         gen_dft<R, DIR>(v);
-        C *d = dst + p * n + (jj / ns) * ns * R + k;
+        C *d = dst + p * n + blk * ns * R + k;
 #pragma unroll
         for (int u = 0; u < R; ++u) d[u * ns] = v[u];
     }
@@ -126,17 +147,23 @@ __device__ void gen_pass(const C *src, C *dst, const C *tw, int n, int ns, int G
 template <int DIR, typename C>
 __device__ void gen_pass_prime(const C *src, C *dst, const C *tw, int n, int ns, int R, int G) {
     const int nb = n / R, tstep = n / (ns * R), step_r = n / R;
+    const float rn = 1.0f / (float)n, rr = 1.0f / (float)R, rns = 1.0f / (float)ns;
     for (int task = threadIdx.x; task < G * n; task += GEN_NT) {
-        const int p = task / n, rem = task % n;
-        const int jj = rem / R, u = rem % R, k = jj % ns;
+        int rem, u, k;
+        const int p = gen_divmod(task, n, rn, rem);
+        const int jj = gen_divmod(rem, R, rr, u);
+        const int blk = gen_divmod(jj, ns, rns, k);
         const C *s = src + p * n;
         C acc = C{0, 0};
+        int tu = 0;                                  // t u mod R
         for (int t = 0; t < R; ++t) {
             C x = s[jj + t * nb];
-            if (t > 0 && ns > 1) x = cmul(x, gen_tw<DIR>(tw, (t * k * tstep) % n));
-            acc = cadd(acc, cmul(x, gen_tw<DIR>(tw, ((t * u) % R) * step_r)));
+            if (t > 0 && ns > 1) x = cmul(x, gen_tw<DIR>(tw, t * k * tstep));
+            acc = cadd(acc, cmul(x, gen_tw<DIR>(tw, tu * step_r)));
+            tu += u;
+            if (tu >= R) tu -= R;
         }
-        dst[p * n + (jj / ns) * ns * R + k + u * ns] = acc;
+        dst[p * n + blk * ns * R + k + u * ns] = acc;
     }
 }
 
