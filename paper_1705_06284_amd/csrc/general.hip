@@ -507,7 +507,9 @@ static hipError_t gen_inverse_t(const C *spec, C *work, const GenGrid &g, const 
     const int Gy = gen_pencils(g.ny, sizeof(C));
     hipLaunchKernelGGL((k_gen_inv_y<C>), dim3((unsigned)(g.nz * ((g.nx + Gy - 1) / Gy)), batch), dim3(GEN_NT),
                        gen_smem<C>(g.ny, Gy), st, work, tw, g, pr, Gy);
-    const int Gx = gen_pencils(g.nx, sizeof(C));
+    // pass X: rows are contiguous, so fewer rows per block cost no coalescing
+    // and buy occupancy (at 600 points, 2 rows in 19 KiB: eight blocks per CU)
+    const int gpx = gen_pencils(g.nx, sizeof(C)), Gx = gpx >= 4 ? gpx / 2 : gpx;
     hipLaunchKernelGGL((k_gen_inv_x<C, Rr>), dim3((unsigned)((rows + Gx - 1) / Gx), batch), dim3(GEN_NT),
                        gen_smem<C>(g.nx, Gx), st, work, f1, f2, map_stride, tw, g, pr, Gx);
     return hipGetLastError();
