@@ -474,7 +474,9 @@ hipError_t gen_mean(const float *x, const GenGrid &g, int batch, double *part, i
 template <typename C, typename Rr>
 static hipError_t gen_forward_t(const Rr *delta, const double *mean, const GenGrid &g, int batch, const C *tw,
                                 C *spec, hipStream_t st, double scale) {
-    const int Gx = gen_pencils(g.nx, sizeof(C));
+    // rows are contiguous: half the rows per block, for occupancy (as in pass X
+    // of the inverse)
+    const int gpx = gen_pencils(g.nx, sizeof(C)), Gx = gpx >= 4 ? gpx / 2 : gpx;
     const int64_t rows = (int64_t)g.nz * g.ny;
     hipLaunchKernelGGL((k_gen_fwd_x<C, Rr>), dim3((unsigned)((rows + Gx - 1) / Gx), batch), dim3(GEN_NT),
                        gen_smem<C>(g.nx, Gx), st, delta, mean, spec, tw, g, Gx, scale);
