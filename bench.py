@@ -42,8 +42,8 @@ def parse():
     ap.add_argument("--inverse-batch", type=int, default=4,
                     help="maps per call of the inverse-stage measurement (0: skip)")
     ap.add_argument("--no-serving", action="store_true", help="skip the request-stream measurement")
-    ap.add_argument("--toy600", action="store_true",
-                    help="also time the 600^3 toy reionisation box (mixed-radix transforms, 61 shells)")
+    ap.add_argument("--no-toy600", action="store_true",
+                    help="skip the 600^3 toy reionisation box (mixed-radix transforms, 61 shells)")
     ap.add_argument("--no-onepixel", action="store_true",
                     help="skip the one-pixel-shell measurement with configuration binning")
     ap.add_argument("--serving-requests", type=int, default=2000)
@@ -483,7 +483,7 @@ def main():
         out["onepixel_256"] = onepixel_run(torch, binding, synth, np, dev, stream, args.steps,
                                            wl="onepix_256_lognormal")
 
-    if args.toy600:
+    if not args.no_toy600:
         out["toy600"] = toy600_run(torch, binding, synth, dev, stream, args.steps)
 
     if not args.no_serving:
