@@ -136,3 +136,30 @@ def test_resident_bin_fields(binding):
     with pytest.raises(binding.BispecError) as ei:
         fused.polyspec(None)
     assert ei.value.code == -1
+
+
+@pytest.mark.parametrize("shape,nb", [((32, 32, 32), 96), ((24, 24, 24), 80), ((64, 64, 64), 40)],
+                         ids=["32cube-96", "24cube-80", "64cube-40-narrow"])
+def test_batch_of_two_equals_single_maps(binding, shape, nb):
+    """Every kernel indexes maps by grid.y and reduces each map in a fixed
+    order, so a map's results do not depend on the batch it runs in: the
+    column groups, the squares pass, the refinement of ill-conditioned
+    triplets (40 shells of 0.75 k_f at 64^3 reach kappa ~ 100) and (24^3)
+    the pruned mixed-radix transforms, bit for bit."""
+    if nb == 40:
+        lo = 1.0 + 0.75 * np.arange(nb)
+        hi = lo + 0.75
+    else:
+        lo, hi = _one_radius_bins(shape[0], nb)
+    maps = np.stack([_field(shape, seed=s) for s in (3, 4)])
+    for prec in ("fp32", "split_bf16"):
+        plan = binding.Plan(shape, lo, hi, precision=prec, max_batch=2)
+        kappa = plan.condition
+        _say("%s, %d bins, %s: batch of 2 vs single (%d triplets above kappa 2.5)"
+             % (shape, nb, prec, int((kappa > 2.5).sum())))
+        if nb == 40:
+            assert (kappa > 2.5).sum() > 0          # the refinement runs
+        P, B, T = plan.polyspec(maps)
+        for i in range(2):
+            p1, b1, t1 = plan.polyspec(maps[i])
+            assert torch.equal(B[i], b1[0]) and torch.equal(P[i], p1[0]) and torch.equal(T[i], t1[0]), prec
