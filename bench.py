@@ -44,6 +44,8 @@ def parse():
     ap.add_argument("--no-serving", action="store_true", help="skip the request-stream measurement")
     ap.add_argument("--no-toy600", action="store_true",
                     help="skip the 600^3 toy reionisation box (mixed-radix transforms, 61 shells)")
+    ap.add_argument("--no-diag", action="store_true",
+                    help="skip the diagonal-binned trispectrum on the 128^3 lognormal map")
     ap.add_argument("--no-onepixel", action="store_true",
                     help="skip the one-pixel-shell measurement with configuration binning")
     ap.add_argument("--serving-requests", type=int, default=2000)
@@ -219,6 +221,30 @@ def toy600_run(torch, binding, synth, dev, stream, steps, wl="toy600_xhi099"):
             "quads": plan.n_quad, "outputs": "B, P, T", "plan_s": t_plan, "ms_per_map": 1e3 * we / k,
             "triangles_per_s": plan.n_tri * k / we,
             "stages_ms": {key: v / max(calls, 1) for key, v in stages.items()}}
+
+
+def diag_run(torch, binding, synth, dev, stream, steps, wl="c2_128_lognormal"):
+    """The diagonal-binned trispectrum T(a, b, c, d; e) on the 128^3 lognormal
+    map with 16 linear bins: (a, b, a, b; e) and (a, a, b, b; e) for
+    a <= b < 4 and diagonal shells e < 8, raw and with the Gaussian pairings
+    removed (one map at a time: the fields of the shells used, the pair
+    products and their transforms, the shell sums)."""
+    n = synth.WORKLOADS[wl]["n"]
+    lo, hi = synth.workload_bins(wl)
+    dq = [(a, b, a, b, e) for a in range(4) for b in range(a, 4) for e in range(8)]
+    dq += [(a, a, b, b, e) for a in range(4) for b in range(a, 4) for e in range(8)]
+    plan = binding.Plan(n, lo, hi, dquads=dq, stream=stream, device=dev)
+    d = torch.from_numpy(synth.workload_field(wl)).to(dev).unsqueeze(0)
+
+    def step():
+        plan.trispec_diag(d, connected=True)
+
+    step()
+    k = max(3, steps // 4)
+    w, _ = timed_steps(torch, step, k, stream)
+    return {"workload": wl, "n": n, "bins": plan.n_bins, "configs": len(dq),
+            "kinds": "(a,b,a,b;e) and (a,a,b,b;e), a <= b < 4, e < 8; raw and connected",
+            "ms_per_map": 1e3 * w / k, "configs_per_s": len(dq) * k / w}
 
 
 def percentile(xs, q):
@@ -485,6 +511,9 @@ def main():
 
     if not args.no_toy600:
         out["toy600"] = toy600_run(torch, binding, synth, dev, stream, args.steps)
+
+    if not args.no_diag:
+        out["diag_T"] = diag_run(torch, binding, synth, dev, stream, args.steps)
 
     if not args.no_serving:
         out["serving"] = serving_run(args.serving_requests)
