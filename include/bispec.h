@@ -80,10 +80,13 @@ typedef enum {
  * In modes 0 and 1, triplets whose condition number
  * kappa_t = sqrt(M_i M_j M_k / (N_pix N_t)) exceeds 2.5 (shells narrower than
  * k_f near the edge of the triangle inequality; bispec_plan_condition) are
- * read instead from product-Gram rows of their own on the FP64 matrix cores,
- * over the bin fields in HBM, so their error stays at the level of the FP32
- * FFTs (about 2.5e-7 kappa relative to the noise level of B).  Such plans
- * keep the bin fields in the workspace (bispec_plan_footprint). */
+ * computed again over the bin fields in HBM with FP64 sums: on product-Gram
+ * rows of their own on the FP64 matrix cores, or, when those rows would be
+ * sparse (about one such triplet per pair, as with one-pixel shells), as
+ * terms on the vector ALUs with FP64 products in mode 0 and FP32 products in
+ * mode 1.  Their error stays near that of the FP32 FFTs (about 2.5e-7 kappa
+ * relative to the noise level of B).  Such plans keep the bin fields in the
+ * workspace (bispec_plan_footprint). */
 enum {
     BISPEC_FP32 = 0,        /* product-Gram, FP32 MFMA, FP32 accumulation            */
     BISPEC_SPLIT_BF16 = 1,  /* product-Gram, BF16 MFMA on hi/lo splits (3 products),
